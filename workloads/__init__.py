@@ -1,0 +1,118 @@
+"""Seeded synthetic inputs for the Kronecker-regression workloads.
+
+This module only draws random inputs (NumPy PCG64, one data seed per workload)
+and assembles the synthetic response b = K x_true + sigma * e; it holds none of
+the method's steps (no leverage scores, sampling, sketching or solves).  The same
+arrays feed the CPU oracle and the GPU library.
+
+Workloads (sizes as named in the tests and the benchmark):
+  small_regression  N=2, factors 64x8, m=2048 (K is 4096 x 64)
+  skewed_regression N=3, factors 512x16 with 26 rows per mode scaled by 100,
+                    K is 1.34e8 x 4096, m = ceil(R ln R / eps) = 340,696
+  tucker_tensor     400^3 FP32 tensor = rank-(16,16,16) core times orthonormal
+                    factors plus 1% Gaussian noise, with seeded initial factors
+  paper_e1          the paper's synthetic Kronecker regression: two n x d factors
+                    with entries N(1, 0.001^2), b = 1, lam = 1e-3
+  random_problem    any shapes, for parity sweeps and edge cases
+"""
+
+import math
+
+import numpy as np
+
+
+def _design_apply(As, x):
+    """K x for K = A(1) kron ... kron A(N) (row-major vec), used only to synthesise b."""
+    T = np.asarray(x, dtype=np.float64).reshape([A.shape[1] for A in As])
+    for n, A in enumerate(As):
+        T = np.moveaxis(np.tensordot(A, T, axes=([1], [n])), 0, n)
+    return T.reshape(-1)
+
+
+def m_rule(R, eps):
+    """m = ceil(R ln R / eps), the explicit sample count of the large workloads."""
+    return int(math.ceil(R * math.log(R) / eps))
+
+
+def small_regression(seed=1):
+    """N=2, A(n) 64x8 i.i.d. N(0,1), b = K x_true + 0.01 e, m = 2048, eps = 0.1."""
+    rng = np.random.default_rng(seed)
+    As = [rng.standard_normal((64, 8)) for _ in range(2)]
+    x_true = rng.standard_normal(64)
+    e = rng.standard_normal(64 * 64)
+    b = _design_apply(As, x_true) + 0.01 * e
+    return dict(name="small_regression N=2 I=64x64 R=8x8 m=2048", As=As, b=b,
+                x_true=x_true, lam=0.0, eps=0.1, m=2048, seed=0)
+
+
+def skewed_regression(seed=2, I=512, R=16, N=3, heavy_frac=0.05, scale=100.0, sigma=0.1):
+    """N=3, A(n) 512x16 N(0,1) with 26 random rows per mode scaled x100.
+
+    b = K x_true + 0.1 e (1.34e8 float64 entries, 1.07 GB); m = ceil(R ln R/eps).
+    """
+    rng = np.random.default_rng(seed)
+    As = []
+    nheavy = int(round(heavy_frac * I))
+    for _ in range(N):
+        A = rng.standard_normal((I, R))
+        heavy = rng.choice(I, size=nheavy, replace=False)
+        A[heavy] *= scale
+        As.append(A)
+    x_true = rng.standard_normal(R**N)
+    b = _design_apply(As, x_true)
+    b += sigma * rng.standard_normal(b.size)
+    eps = 0.1
+    return dict(name="skewed_regression N=%d I=%d^%d R=%d^%d" % (N, I, N, R, N), As=As, b=b,
+                x_true=x_true, lam=0.0, eps=eps, m=m_rule(R**N, eps), seed=0)
+
+
+def tucker_tensor(seed=3, I=400, R=16, N=3, noise=0.01):
+    """Dense FP32 tensor = core x_n orthonormal factors + noise, and an initial guess.
+
+    Noise is i.i.d. Gaussian scaled so that ||E||_F = noise * ||X_clean||_F.
+    """
+    rng = np.random.default_rng(seed)
+    G0 = rng.standard_normal((R,) * N)
+    Qs = [np.linalg.qr(rng.standard_normal((I, R)))[0] for _ in range(N)]
+    X = G0
+    for n, Q in enumerate(Qs):
+        X = np.moveaxis(np.tensordot(Q, X, axes=([1], [n])), 0, n)
+    E = rng.standard_normal(X.shape)
+    E *= noise * np.linalg.norm(X) / np.linalg.norm(E)
+    X = (X + E).astype(np.float32)
+    G_init = rng.standard_normal((R,) * N)
+    A_init = [rng.standard_normal((I, R)) for _ in range(N)]
+    eps = 0.1
+    return dict(name="tucker_tensor %d^%d rank %d^%d" % (I, N, R, N), X=X, G0=G0, Qs=Qs,
+                G_init=G_init, A_init=A_init, lam=1e-3, eps=eps,
+                m_core=m_rule(R**N, eps), m_factor=m_rule(R ** (N - 1), eps), sweeps=10,
+                seed=0)
+
+
+def paper_e1(n, d, seed=0):
+    """The paper's synthetic workload: A(1), A(2) n x d with entries N(1, 0.001^2), b = 1."""
+    rng = np.random.default_rng(seed)
+    As = [1.0 + 0.001 * rng.standard_normal((n, d)) for _ in range(2)]
+    return dict(name="paper_e1 n=%d d=%d" % (n, d), As=As, b=np.ones(n * n), lam=1e-3, eps=0.1)
+
+
+def random_problem(I, R, seed=0, sigma=0.01, nrhs=1, heavy=0, scale=100.0):
+    """Factors A(n) I_n x R_n i.i.d. N(0,1) (optionally `heavy` rows per mode scaled),
+    x_true ~ N(0,1), b = K x_true + sigma e.  With nrhs > 1, b and x_true have
+    nrhs columns (row-major: row index major, right-hand side minor)."""
+    rng = np.random.default_rng(seed)
+    As = []
+    for In, Rn in zip(I, R):
+        A = rng.standard_normal((In, Rn))
+        if heavy:
+            A[rng.choice(In, size=min(heavy, In), replace=False)] *= scale
+        As.append(A)
+    Rtot = int(np.prod(R))
+    Itot = int(np.prod(I))
+    x_true = rng.standard_normal((Rtot, nrhs))
+    b = np.stack([_design_apply(As, x_true[:, k]) for k in range(nrhs)], axis=1)
+    b += sigma * rng.standard_normal(b.shape)
+    if nrhs == 1:
+        x_true, b = x_true[:, 0], b[:, 0]
+    assert b.shape[0] == Itot
+    return dict(name="random I=%s R=%s" % (list(I), list(R)), As=As, b=b, x_true=x_true)
