@@ -1,0 +1,146 @@
+/*
+ * kron_regress.h -- C ABI of the MI355X (gfx950) library for subquadratic
+ * Kronecker regression (Fahrbach, Fu, Ghadiri, NeurIPS 2022).
+ *
+ * The library solves, to a (1+eps) approximation,
+ *     min_x ||K x - b||_2^2 + lambda ||x||_2^2,   K = A(1) kron A(2) kron ... kron A(N)
+ * by Algorithm 2 (FastKroneckerRegression): factor leverage scores, i.i.d. row
+ * sampling from their product distribution (Lemma kronecker_cross_leverage_scores),
+ * and preconditioned Richardson iteration on the sketched problem (Lemma
+ * richardson_iteration) with M^+ = (kron V) D (kron V)^T applied by KronMatMul
+ * mode products (Lemma kron_mat_mul) and the sampled products K~ x, K~^T r computed
+ * level by level over the distinct sampled rows (Theorem kron_mat_mul_sqrt_decomp).
+ *
+ * Conventions (all entry points)
+ *   - Row-major, last index fastest.  Row (i_1..i_N) of K is the linear index
+ *     sum_n i_n prod_{k>n} I_k; column (r_1..r_N) likewise; x is the row-major vec
+ *     of an R_1 x .. x R_N tensor; b has prod(I_n) rows.  With nrhs > 1, b is
+ *     prod(I) x nrhs and x is prod(R) x nrhs, both row-major.
+ *   - Pointers named d_* (and the A[], b, x members) are DEVICE pointers owned by
+ *     the caller; the library never frees them.  Host pointers are named h_*.
+ *   - Every call runs on the handle's HIP stream.  Calls that return kr_info or a
+ *     host value synchronise that stream before returning; others are
+ *     asynchronous.  Workspace belongs to the handle; a handle must not be used
+ *     from two host threads at once.
+ *   - Errors are returned as kr_status; kr_last_error() gives a message.  On an
+ *     error no output is guaranteed.  No C++ exception crosses this ABI.
+ *   - Sampling randomness: Philox4x64-10 (Salmon et al., SC'11) with key
+ *     (seed, stream) and counter (t, n/4, row, 0) for sample t, mode n, sketch
+ *     row (0 here); mode n uses output word n%4 and its top 32 bits u pick the
+ *     index i with C_{i-1} <= u < C_i on the inclusive CDF of integer weights
+ *     Q_i = max(1, floor(2^32 l_i / sum l)) (largest weight absorbs the rounding
+ *     deficit so sum Q = 2^32).  The sketch weight of a sample is
+ *     omega = 1/(m prod_n Q_{i_n} 2^-32).
+ */
+#ifndef KRON_REGRESS_H
+#define KRON_REGRESS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KR_MAX_MODES 8
+
+typedef enum {
+  KR_OK = 0,
+  KR_WMAXITER = 1,       /* iteration limit reached; x holds the last iterate          */
+  KR_EINVAL = -1,        /* invalid argument (shape, range, NaN/Inf input)             */
+  KR_ENOMEM = -2,        /* device allocation failed                                   */
+  KR_EHIP = -3,          /* HIP runtime error                                          */
+  KR_ESINGULAR = -4,     /* lambda = 0 and a factor Gram matrix is singular            */
+  KR_EDIVERGED = -5,     /* Richardson produced a non-finite or exploding update       */
+  KR_EUNSUPPORTED = -6   /* shape outside the implemented limits                       */
+} kr_status;
+
+typedef enum { KR_F64 = 0, KR_F32 = 1 } kr_dtype;
+
+typedef struct kr_handle_s* kr_handle;
+
+/* One Kronecker regression problem.  A[n] points to an I[n] x R[n] row-major
+ * matrix of dtype a_dtype; b to prod(I) x nrhs entries of dtype b_dtype. */
+typedef struct {
+  int32_t N;                       /* number of factors, 1..KR_MAX_MODES            */
+  int32_t nrhs;                    /* right-hand sides sharing the sketch (>= 1)    */
+  int64_t I[KR_MAX_MODES];         /* rows of each factor (I_n >= R_n)              */
+  int64_t R[KR_MAX_MODES];         /* columns of each factor                        */
+  const void* A[KR_MAX_MODES];     /* device pointers                                */
+  int32_t a_dtype;                 /* kr_dtype                                       */
+  int32_t b_dtype;                 /* kr_dtype                                       */
+  const void* b;                   /* device pointer                                 */
+} kr_problem;
+
+typedef struct {
+  int64_t m;          /* number of row samples; 0 selects Algorithm 2's
+                         ceil(1680 R ln(40R) ln(1/delta)/eps)                         */
+  int32_t max_iter;   /* Richardson iteration limit (default 200 when <= 0)           */
+  int32_t check_every;/* iterations between convergence checks (default 8 when <= 0) */
+  double tol;         /* stop when (1-sqrt(eps)) ||d|| <= tol ||x||, per RHS
+                         (default 1e-12 when <= 0)                                    */
+  uint64_t seed;      /* Philox key word 0                                            */
+  uint64_t stream;    /* Philox key word 1                                            */
+} kr_opts;
+
+typedef struct {
+  int32_t iters;          /* Richardson iterations performed (max over RHS)          */
+  int32_t status;         /* kr_status of the solve                                   */
+  int64_t m;              /* samples drawn                                            */
+  int64_t distinct_rows;  /* distinct sampled rows of K                               */
+  double rel_update;      /* final (1-sqrt(eps))||d|| / ||x|| (max over RHS)          */
+} kr_info;
+
+/* Handle lifetime.  `hip_stream` is a hipStream_t (NULL = default stream). */
+kr_status kr_create(kr_handle* h, void* hip_stream);
+kr_status kr_destroy(kr_handle h);
+kr_status kr_set_stream(kr_handle h, void* hip_stream);
+const char* kr_last_error(kr_handle h);
+const char* kr_version(void);
+
+/* Algorithm 2, FastKroneckerRegression, with lambda = 0 (Theorem
+ * fast_kronecker_regression).  Writes d_x (prod(R) x nrhs, float64).
+ * eps in (0, 1/4]; delta in (0, 1) (used only when opts->m == 0).
+ * Returns KR_ESINGULAR if a factor Gram matrix is numerically singular. */
+kr_status kron_regress(kr_handle h, const kr_problem* p, double eps, double delta,
+                       const kr_opts* opts, void* d_x, kr_info* h_info);
+
+/* Algorithm 2 with L2 regularisation lambda >= 0 (Corollary
+ * approximate_ridge_regression); sampling uses the statistical leverage scores of
+ * K, the preconditioner is (K^T K + lambda I)^+.  Writes d_x (float64). */
+kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps,
+                     double delta, const kr_opts* opts, void* d_x, kr_info* h_info);
+
+/* f(x) = ||K x - b||^2 + lambda ||x||^2 in float64 (the quantity of the
+ * guarantee of Theorem fast_kronecker_regression), streaming b once.  x is
+ * float64 prod(R) x nrhs; h_loss receives nrhs values. */
+kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void* d_x,
+                    double* h_loss);
+
+/* The exact minimiser via the factor thin SVDs and KronMatMul (the paper's
+ * exact baseline): x* = (kron V) diag(kron s / (kron s^2 + lambda)) (kron U)^T b.
+ * Writes d_x (float64, prod(R) x nrhs). */
+kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x);
+
+/* Test support: copy the last solve's sketch to host memory.  Any pointer may be
+ * NULL.  h_Q: sum_n I_n uint64 integer weights (mode-major); h_keys: distinct
+ * rows as per-mode indices, D x N int32 (sorted by linear row index); h_Omega: D
+ * float64 merged weights; h_counts: D int32 multiplicities.  cap is the capacity
+ * in distinct rows; *h_D receives D. */
+kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega,
+                           int32_t* h_counts, int64_t cap, int64_t* h_D);
+
+/* Measurement support: when enabled, every kernel launch of the handle whose
+ * name contains `filter` (NULL or "" = every kernel) is bracketed by a pair of
+ * HIP events on the handle's stream (adds a little launch overhead per bracketed
+ * launch).  kr_profile_enable clears earlier records.
+ * kr_profile_query synchronises on the recorded events and returns the number
+ * of launches of the named kernel (e.g. "k_stream_loss<16>") and their summed
+ * device time in milliseconds (0 launches when the name is unknown). */
+kr_status kr_profile_enable(kr_handle h, int32_t enable, const char* filter);
+kr_status kr_profile_query(kr_handle h, const char* kernel, int64_t* h_launches, double* h_total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRON_REGRESS_H */

@@ -1,0 +1,267 @@
+"""Python binding of libkron_regress (gfx950): subquadratic Kronecker regression.
+
+Argument marshalling only: every step runs in the HIP library behind the C ABI
+declared in include/kron_regress.h.  Tensors are torch tensors on the GPU
+(PyTorch supplies device memory and the current HIP stream).  There is no CPU
+fallback: when the library or a GPU is missing the calls raise.
+
+Functions mirror the C entry points:
+  kron_regress(As, b, eps, ...)            Algorithm 2 with lambda = 0
+  kron_ridge(As, b, lam, eps, ...)         Algorithm 2 with L2 regularisation
+  kron_loss(As, b, x, lam)                 ||K x - b||^2 + lam ||x||^2 (float64)
+  kron_exact(As, b, lam)                   exact KronMatMul optimum
+  export_sketch(handle)                    last solve's sketch (tests)
+"""
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkron_regress.so")
+MAX_MODES = 8
+
+KR_OK, KR_WMAXITER = 0, 1
+STATUS_NAMES = {0: "OK", 1: "WMAXITER", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR",
+                -5: "EDIVERGED", -6: "EUNSUPPORTED"}
+KR_F64, KR_F32 = 0, 1
+
+
+class KronRegressError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("nrhs", ctypes.c_int32),
+                ("I", ctypes.c_int64 * MAX_MODES), ("R", ctypes.c_int64 * MAX_MODES),
+                ("A", ctypes.c_void_p * MAX_MODES), ("a_dtype", ctypes.c_int32),
+                ("b_dtype", ctypes.c_int32), ("b", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("distinct_rows", ctypes.c_int64), ("rel_update", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "status": STATUS_NAMES.get(self.status, self.status),
+                "m": self.m, "distinct_rows": self.distinct_rows, "rel_update": self.rel_update}
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libkron_regress.so (built by build.py) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libkron_regress.so is not built; run paper_2209_04876_amd/build.py")
+    lib = ctypes.CDLL(path)
+    c_p, c_i, c_d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.kr_create.argtypes = [ctypes.POINTER(c_p), c_p]
+    lib.kr_destroy.argtypes = [c_p]
+    lib.kr_set_stream.argtypes = [c_p, c_p]
+    lib.kr_last_error.argtypes = [c_p]
+    lib.kr_last_error.restype = ctypes.c_char_p
+    lib.kr_version.restype = ctypes.c_char_p
+    P, O, IN = ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.POINTER(Info)
+    lib.kron_regress.argtypes = [c_p, P, c_d, c_d, O, c_p, IN]
+    lib.kron_ridge.argtypes = [c_p, P, c_d, c_d, c_d, O, c_p, IN]
+    lib.kron_loss.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d)]
+    lib.kron_exact.argtypes = [c_p, P, c_d, c_p]
+    lib.kr_export_sketch.argtypes = [c_p, c_p, c_p, c_p, c_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.kr_profile_enable.argtypes = [c_p, ctypes.c_int32, ctypes.c_char_p]
+    lib.kr_profile_query.argtypes = [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(c_d)]
+    for name in ("kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_loss",
+                 "kron_exact", "kr_export_sketch"):
+        getattr(lib, name).restype = c_i
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("a ROCm GPU is required: the library has no CPU path")
+    return torch
+
+
+class Handle:
+    """A library handle bound to a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.ptr = ctypes.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        self._check(self.lib.kr_create(ctypes.byref(self.ptr), ctypes.c_void_p(s.cuda_stream)))
+
+    def _check(self, status):
+        if status < 0:
+            msg = self.lib.kr_last_error(self.ptr).decode() if self.ptr else ""
+            raise KronRegressError(status, msg)
+        return status
+
+    def close(self):
+        if self.ptr:
+            self.lib.kr_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def default_handle():
+    torch = _torch()
+    key = (torch.cuda.current_device(), torch.cuda.current_stream().cuda_stream)
+    h = _default.get(key)
+    if h is None:
+        h = _default[key] = Handle()
+    return h
+
+
+def _problem(As, b):
+    torch = _torch()
+    if not 1 <= len(As) <= MAX_MODES:
+        raise ValueError("need 1..%d factors" % MAX_MODES)
+    p = Problem()
+    p.N = len(As)
+    keep = []
+    adt = As[0].dtype
+    for n, A in enumerate(As):
+        if not (A.is_cuda and A.dim() == 2 and A.is_contiguous() and A.dtype == adt):
+            raise ValueError("factor %d must be a contiguous 2-D CUDA tensor of one dtype" % n)
+        p.I[n], p.R[n] = A.shape
+        p.A[n] = A.data_ptr()
+        keep.append(A)
+    p.a_dtype = {torch.float64: KR_F64, torch.float32: KR_F32}[adt]
+    if b is not None:
+        if not (b.is_cuda and b.is_contiguous() and b.dim() in (1, 2)):
+            raise ValueError("b must be a contiguous 1-D or 2-D CUDA tensor")
+        p.nrhs = 1 if b.dim() == 1 else b.shape[1]
+        p.b = b.data_ptr()
+        p.b_dtype = {torch.float64: KR_F64, torch.float32: KR_F32}[b.dtype]
+    else:
+        p.nrhs = 1
+    return p, keep
+
+
+def _x_like(As, nrhs, one_dim):
+    torch = _torch()
+    R = 1
+    for A in As:
+        R *= A.shape[1]
+    shape = (R,) if one_dim else (R, nrhs)
+    return torch.empty(shape, dtype=torch.float64, device=As[0].device)
+
+
+def _opts(m, max_iter, tol, seed, stream, check_every):
+    o = Opts()
+    o.m, o.max_iter, o.tol, o.seed, o.stream, o.check_every = m, max_iter, tol, seed, stream, check_every
+    return o
+
+
+def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=1e-12,
+               check_every=8, handle=None, x=None, allow_maxiter=True):
+    """Algorithm 2 with regularisation lam.  Returns (x float64, info dict)."""
+    h = handle or default_handle()
+    p, _keep = _problem(As, b)
+    if x is None:
+        x = _x_like(As, p.nrhs, b.dim() == 1)
+    info = Info()
+    st = h.lib.kron_ridge(h.ptr, ctypes.byref(p), lam, eps, delta,
+                          ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every)),
+                          ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
+    h._check(st)
+    if st == KR_WMAXITER and not allow_maxiter:
+        raise KronRegressError(st, "iteration limit reached")
+    return x, info.as_dict()
+
+
+def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=1e-12,
+                 check_every=8, handle=None, x=None, allow_maxiter=True):
+    """Algorithm 2 (lambda = 0).  Returns (x float64, info dict)."""
+    h = handle or default_handle()
+    p, _keep = _problem(As, b)
+    if x is None:
+        x = _x_like(As, p.nrhs, b.dim() == 1)
+    info = Info()
+    st = h.lib.kron_regress(h.ptr, ctypes.byref(p), eps, delta,
+                            ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every)),
+                            ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
+    h._check(st)
+    if st == KR_WMAXITER and not allow_maxiter:
+        raise KronRegressError(st, "iteration limit reached")
+    return x, info.as_dict()
+
+
+def kron_loss(As, b, x, lam=0.0, handle=None):
+    """||K x - b||^2 + lam ||x||^2 per right-hand side (list of floats)."""
+    h = handle or default_handle()
+    p, _keep = _problem(As, b)
+    if x.dtype != _torch().float64 or not x.is_contiguous():
+        raise ValueError("x must be contiguous float64")
+    out = (ctypes.c_double * p.nrhs)()
+    h._check(h.lib.kron_loss(h.ptr, ctypes.byref(p), lam, ctypes.c_void_p(x.data_ptr()), out))
+    return list(out)
+
+
+def kron_exact(As, b, lam=0.0, handle=None):
+    """The exact minimiser via factor SVDs and KronMatMul (float64)."""
+    h = handle or default_handle()
+    p, _keep = _problem(As, b)
+    x = _x_like(As, p.nrhs, b.dim() == 1)
+    h._check(h.lib.kron_exact(h.ptr, ctypes.byref(p), lam, ctypes.c_void_p(x.data_ptr())))
+    return x
+
+
+def profile_enable(enable=True, kernel_filter="", handle=None):
+    """Bracket kernel launches whose name contains kernel_filter ("" = all) with HIP
+    events on the handle's stream (clears old records)."""
+    h = handle or default_handle()
+    h._check(h.lib.kr_profile_enable(h.ptr, 1 if enable else 0, kernel_filter.encode()))
+
+
+def profile_query(kernel, handle=None):
+    """(launches, total device ms) recorded for a kernel name since profile_enable."""
+    h = handle or default_handle()
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    h._check(h.lib.kr_profile_query(h.ptr, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def export_sketch(sizes, handle=None, cap=None):
+    """The last solve's sketch: Q tables per mode, distinct rows (D x N), Omega, counts."""
+    import numpy as np
+    h = handle or default_handle()
+    D = ctypes.c_int64()
+    h._check(h.lib.kr_export_sketch(h.ptr, None, None, None, None, 0, ctypes.byref(D)))
+    D = D.value
+    N = len(sizes)
+    Q = np.zeros(int(sum(sizes)), dtype=np.uint64)
+    rows = np.zeros((D, N), dtype=np.int32)
+    Omega = np.zeros(D, dtype=np.float64)
+    counts = np.zeros(D, dtype=np.int32)
+    h._check(h.lib.kr_export_sketch(h.ptr, Q.ctypes.data, rows.ctypes.data, Omega.ctypes.data,
+                                    counts.ctypes.data, D, ctypes.byref(ctypes.c_int64())))
+    offs = np.cumsum([0] + list(sizes))
+    return {"Q": [Q[offs[n]:offs[n + 1]] for n in range(N)], "rows": rows.astype(np.int64),
+            "Omega": Omega, "counts": counts.astype(np.int64)}
+
+
+__all__ = ["Handle", "KronRegressError", "kron_regress", "kron_ridge", "kron_loss", "kron_exact",
+           "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query"]

@@ -1,0 +1,713 @@
+// C ABI of the library: handles, workspace, validation and the launch sequence
+// of Algorithm 2 (FastKroneckerRegression) and of the exact KronMatMul
+// baseline and loss.  Single translation unit: the kernel files are included.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kr_internal.h"
+#include "kr_setup.hip"
+#include "kr_sketch.hip"
+#include "kr_iter.hip"
+#include "kr_stream.hip"
+
+using namespace kr;
+
+namespace {
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct kr_handle_s {
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* aux = nullptr;
+  size_t aux_bytes = 0;
+  IterState* h_state = nullptr;   // pinned
+  int64_t* h_small = nullptr;     // pinned scratch (flags, counts)
+  // last sketch, for kr_export_sketch
+  bool has_sketch = false;
+  Geom g{};
+  ModeTables T{};
+  Tree tr{};
+  double* Omega = nullptr;
+  int32_t* counts = nullptr;
+  // optional per-kernel timing with HIP events on the handle's stream
+  bool prof_on = false;
+  std::string prof_filter;
+  std::vector<hipEvent_t> ev_pool;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
+};
+
+namespace {
+
+hipEvent_t pool_event(kr_handle h) {
+  if (h->ev_pool.empty()) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+  }
+  hipEvent_t e = h->ev_pool.back();
+  h->ev_pool.pop_back();
+  return e;
+}
+
+// Records an event pair around one launch when profiling is enabled.
+struct ProfScope {
+  kr_handle h;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(kr_handle h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) {
+    if (h->prof_on && (h->prof_filter.empty() || std::strstr(n, h->prof_filter.c_str()))) {
+      a = pool_event(h);
+      hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = pool_event(h);
+      hipEventRecord(b, s);
+      h->prof[name].push_back({a, b});
+    }
+  }
+};
+
+void prof_clear(kr_handle h) {
+  for (auto& kv : h->prof)
+    for (auto& pr : kv.second) {
+      h->ev_pool.push_back(pr.first);
+      h->ev_pool.push_back(pr.second);
+    }
+  h->prof.clear();
+}
+
+}  // namespace
+
+#define KL(h, kern, ...)                      \
+  do {                                        \
+    ProfScope _ps((h), #kern, (h)->stream);   \
+    hipLaunchKernelGGL(kern, __VA_ARGS__);    \
+  } while (0)
+
+#define KR_FAIL(h, code, ...)                                   \
+  do {                                                          \
+    char _b[512];                                               \
+    snprintf(_b, sizeof(_b), __VA_ARGS__);                      \
+    (h)->err = _b;                                              \
+    return (code);                                              \
+  } while (0)
+
+#define HIPCHK(h, expr)                                                          \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess)                                                        \
+      KR_FAIL(h, KR_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e));        \
+  } while (0)
+
+static int ceil_log2(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+static int64_t grid_for(int64_t work, int64_t threads, int64_t cap = 4096) {
+  int64_t b = (work + threads - 1) / threads;
+  return std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+static kr_status ensure(kr_handle h, void** buf, size_t* cap, size_t need) {
+  if (need <= *cap) return KR_OK;
+  if (*buf) {
+    hipStreamSynchronize(h->stream);
+    hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+  }
+  size_t want = std::max(need, size_t(64) << 20);
+  if (hipMalloc(buf, want) != hipSuccess) {
+    *buf = nullptr;
+    KR_FAIL(h, KR_ENOMEM, "device workspace of %zu bytes could not be allocated", want);
+  }
+  *cap = want;
+  h->has_sketch = false;
+  return KR_OK;
+}
+
+// Validate a problem and fill the geometry (m set by the caller).
+static kr_status make_geom(kr_handle h, const kr_problem* p, Geom* g) {
+  if (!p) KR_FAIL(h, KR_EINVAL, "problem is NULL");
+  if (p->N < 1 || p->N > KR_MAX_MODES) KR_FAIL(h, KR_EINVAL, "N=%d outside 1..%d", p->N, KR_MAX_MODES);
+  if (p->nrhs < 1 || p->nrhs > KR_MAX_RHS) KR_FAIL(h, KR_EINVAL, "nrhs=%d outside 1..%d", p->nrhs, KR_MAX_RHS);
+  if (p->a_dtype != KR_F64 && p->a_dtype != KR_F32) KR_FAIL(h, KR_EINVAL, "bad a_dtype");
+  if (p->b_dtype != KR_F64 && p->b_dtype != KR_F32) KR_FAIL(h, KR_EINVAL, "bad b_dtype");
+  std::memset(g, 0, sizeof(*g));
+  g->N = p->N;
+  g->nrhs = p->nrhs;
+  int64_t Rtot = 1, Itot = 1;
+  for (int n = 0; n < p->N; ++n) {
+    if (!p->A[n]) KR_FAIL(h, KR_EINVAL, "A[%d] is NULL", n);
+    if (p->R[n] < 1 || p->R[n] > 64) KR_FAIL(h, KR_EUNSUPPORTED, "R[%d]=%lld outside 1..64", n, (long long)p->R[n]);
+    if (p->I[n] < p->R[n]) KR_FAIL(h, KR_EINVAL, "I[%d]=%lld < R[%d]=%lld", n, (long long)p->I[n], n, (long long)p->R[n]);
+    if (p->I[n] > (int64_t(1) << 24)) KR_FAIL(h, KR_EUNSUPPORTED, "I[%d] > 2^24", n);
+    g->I[n] = (int)p->I[n];
+    g->R[n] = (int)p->R[n];
+    Rtot *= p->R[n];
+    Itot *= p->I[n];
+    if (Itot > (int64_t(1) << 46)) KR_FAIL(h, KR_EUNSUPPORTED, "prod(I) too large");
+  }
+  if (Rtot * p->nrhs > (int64_t(1) << 26)) KR_FAIL(h, KR_EUNSUPPORTED, "prod(R)*nrhs too large");
+  g->Rtot = Rtot;
+  g->Itot = Itot;
+  g->rsuf[p->N] = 1;
+  for (int k = p->N - 1; k >= 0; --k) g->rsuf[k] = g->rsuf[k + 1] * g->R[k];
+  int kb = 0;
+  for (int n = 0; n < p->N; ++n) {
+    g->bits[n] = std::max(1, ceil_log2(g->I[n]));
+    kb += g->bits[n];
+  }
+  if (kb > 64) KR_FAIL(h, KR_EUNSUPPORTED, "packed row key needs %d > 64 bits", kb);
+  g->keybits = kb;
+  g->shift[p->N - 1] = 0;
+  for (int n = p->N - 2; n >= 0; --n) g->shift[n] = g->shift[n + 1] + g->bits[n + 1];
+  for (int k = 1; k <= p->N; ++k) g->lshift[k] = g->shift[k - 1];
+  g->lshift[0] = kb;
+  return KR_OK;
+}
+
+extern "C" {
+
+const char* kr_version(void) { return "kron_regress gfx950 0.1"; }
+
+kr_status kr_create(kr_handle* out, void* stream) {
+  if (!out) return KR_EINVAL;
+  kr_handle h = new kr_handle_s();
+  h->stream = (hipStream_t)stream;
+  if (hipHostMalloc((void**)&h->h_state, sizeof(IterState)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_small, 64 * sizeof(int64_t)) != hipSuccess) {
+    delete h;
+    return KR_ENOMEM;
+  }
+  *out = h;
+  return KR_OK;
+}
+
+kr_status kr_destroy(kr_handle h) {
+  if (!h) return KR_EINVAL;
+  hipStreamSynchronize(h->stream);
+  prof_clear(h);
+  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+  if (h->ws) hipFree(h->ws);
+  if (h->aux) hipFree(h->aux);
+  if (h->h_state) hipHostFree(h->h_state);
+  if (h->h_small) hipHostFree(h->h_small);
+  delete h;
+  return KR_OK;
+}
+
+kr_status kr_set_stream(kr_handle h, void* stream) {
+  if (!h) return KR_EINVAL;
+  h->stream = (hipStream_t)stream;
+  return KR_OK;
+}
+
+const char* kr_last_error(kr_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+kr_status kr_profile_enable(kr_handle h, int32_t enable, const char* filter) {
+  if (!h) return KR_EINVAL;
+  hipStreamSynchronize(h->stream);
+  prof_clear(h);
+  h->prof_on = enable != 0;
+  h->prof_filter = filter ? filter : "";
+  return KR_OK;
+}
+
+kr_status kr_profile_query(kr_handle h, const char* kernel, int64_t* launches, double* total_ms) {
+  if (!h || !kernel) return KR_EINVAL;
+  auto it = h->prof.find(kernel);
+  int64_t n = 0;
+  double tot = 0.0;
+  if (it != h->prof.end()) {
+    for (auto& pr : it->second) {
+      HIPCHK(h, hipEventSynchronize(pr.second));
+      float ms = 0.f;
+      HIPCHK(h, hipEventElapsedTime(&ms, pr.first, pr.second));
+      tot += ms;
+      ++n;
+    }
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = tot;
+  return KR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Setup shared by the solvers and the exact baseline: FP64 factors, Gram
+// eigen-decompositions, leverage scores, quantised weights and CDFs.
+// ---------------------------------------------------------------------------
+struct SetupBufs {
+  double* A64[KR_MAXN];
+  double* gram;
+  int32_t* flags;
+};
+
+static void carve_setup(Arena& a, const Geom& g, ModeTables* T, SetupBufs* s) {
+  for (int n = 0; n < g.N; ++n) {
+    s->A64[n] = a.take<double>((size_t)g.I[n] * g.R[n]);
+    T->A[n] = s->A64[n];
+    T->V[n] = a.take<double>((size_t)g.R[n] * g.R[n]);
+    T->evals[n] = a.take<double>(g.R[n]);
+    T->Ginv[n] = a.take<double>((size_t)g.R[n] * g.R[n]);
+    T->lev[n] = a.take<double>(g.I[n]);
+    T->Q[n] = a.take<uint64_t>(g.I[n]);
+    T->C[n] = a.take<uint64_t>(g.I[n]);
+  }
+  s->gram = a.take<double>((size_t)g.N * 64 * 64);
+  s->flags = a.take<int32_t>(64);
+}
+
+static size_t setup_bytes(const Geom& g) {
+  size_t b = 0;
+  for (int n = 0; n < g.N; ++n)
+    b += 8 * ((size_t)g.I[n] * g.R[n] + 2 * (size_t)g.R[n] * g.R[n] + g.R[n] + 3 * (size_t)g.I[n]) + 7 * 256;
+  return b + 8 * (size_t)g.N * 4096 + 1024;
+}
+
+static kr_status launch_setup(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T,
+                              const SetupBufs& s, bool leverage) {
+  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, h->stream, (uint32_t*)s.flags, (int64_t)64);
+  for (int n = 0; n < g.N; ++n) {
+    const int64_t cnt = (int64_t)g.I[n] * g.R[n];
+    KL(h, k_promote, dim3(grid_for(cnt, 256, 1024)), dim3(256), 0, h->stream, p->A[n], p->a_dtype,
+                       s.A64[n], cnt, s.flags);
+  }
+  KL(h, k_gram, dim3(g.N), dim3(256), 0, h->stream, T, g, s.gram);
+  KL(h, k_eig, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+  if (leverage) KL(h, k_leverage, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
+  HIPCHK(h, hipGetLastError());
+  return KR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2
+// ---------------------------------------------------------------------------
+struct SolveBufs {
+  SetupBufs s;
+  uint64_t* keys;
+  uint64_t* keys_alt;
+  uint32_t* hist;
+  int64_t* tiletot;
+  double* Omega;
+  double* bD;
+  int32_t* counts;
+  double* P[KR_MAXN + 1];
+  double* Q[KR_MAXN + 1];
+  double* t0;
+  double* t1;
+  IterState* state;
+};
+
+static int64_t level_cap(const Geom& g, int k) {
+  // level k holds distinct prefixes of length k: at most min(m, prod_{n<k} I_n)
+  if (k == 0) return 1;
+  double prod = 1.0;
+  for (int n = 0; n < k; ++n) prod *= (double)g.I[n];
+  return (int64_t)std::min<double>((double)g.m, prod);
+}
+
+static size_t solve_bytes(const Geom& g, int ntiles, int nblocks) {
+  size_t b = setup_bytes(g);
+  b += 2 * 8 * (size_t)g.m + 4 * 256 * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
+  const int64_t D = level_cap(g, g.N);
+  b += (size_t)D * (8 + 8 * g.nrhs + 4);
+  for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2);
+  b += 4 * (size_t)(D + 2) + 8 * (size_t)D;
+  for (int k = 1; k < g.N; ++k) b += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs;
+  b += 3 * 8 * (size_t)g.Rtot * g.nrhs + sizeof(IterState) + 8 * (KR_MAXN + 1);
+  return b + 64 * 256 + 4096;
+}
+
+static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
+                       const kr_opts* opts, void* d_x, kr_info* info) {
+  if (!h) return KR_EINVAL;
+  Geom g;
+  kr_status st = make_geom(h, p, &g);
+  if (st != KR_OK) return st;
+  if (!p->b || !d_x) KR_FAIL(h, KR_EINVAL, "b or x is NULL");
+  if (!(eps > 0.0 && eps < 1.0)) KR_FAIL(h, KR_EINVAL, "eps=%g outside (0, 1)", eps);
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda=%g invalid", lambda);
+  kr_opts o{};
+  if (opts) o = *opts;
+  int64_t m = o.m;
+  if (m <= 0) {
+    if (!(delta > 0.0 && delta < 1.0)) KR_FAIL(h, KR_EINVAL, "delta=%g outside (0, 1)", delta);
+    const double R = (double)g.Rtot;
+    const double s = std::ceil(1680.0 * R * std::log(40.0 * R) * std::log(1.0 / delta) / eps);
+    if (s > 2.0e9) KR_FAIL(h, KR_EUNSUPPORTED, "theory sample count %.3g too large; pass opts.m", s);
+    m = (int64_t)s;
+  }
+  if (m > (int64_t(1) << 31) - 2) KR_FAIL(h, KR_EUNSUPPORTED, "m=%lld too large", (long long)m);
+  g.m = m;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  const int check_every = o.check_every > 0 ? o.check_every : 8;
+  const double tol = o.tol > 0.0 ? o.tol : 1e-12;
+  const double eta = 1.0 - std::sqrt(eps);
+
+  const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
+  const int ntiles = nblocks;
+  st = ensure(h, &h->ws, &h->ws_bytes, solve_bytes(g, ntiles, nblocks));
+  if (st != KR_OK) return st;
+  Arena a{(char*)h->ws, h->ws_bytes, 0};
+  ModeTables T{};
+  SolveBufs B{};
+  carve_setup(a, g, &T, &B.s);
+  B.keys = a.take<uint64_t>(m);
+  B.keys_alt = a.take<uint64_t>(m);
+  B.hist = a.take<uint32_t>((size_t)256 * nblocks);
+  B.tiletot = a.take<int64_t>((size_t)ntiles * (KR_MAXN + 1));
+  Tree tr{};
+  for (int k = 1; k <= g.N; ++k) {
+    const int64_t c = level_cap(g, k);
+    tr.idx[k] = a.take<int32_t>(c + 2);
+    tr.parent[k] = a.take<int32_t>(c + 2);
+    tr.fchild[k] = a.take<int32_t>(c + 2);
+  }
+  tr.fchild[0] = a.take<int32_t>(4);
+  const int64_t Dcap = level_cap(g, g.N);
+  tr.rstart = a.take<int32_t>(Dcap + 2);
+  tr.rkey = a.take<uint64_t>(Dcap + 1);
+  tr.cnt = a.take<int64_t>(KR_MAXN + 1);
+  B.Omega = a.take<double>(Dcap);
+  B.counts = a.take<int32_t>(Dcap);
+  B.bD = a.take<double>((size_t)Dcap * g.nrhs);
+  B.P[0] = (double*)d_x;
+  for (int k = 1; k < g.N; ++k) {
+    B.P[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
+    B.Q[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
+  }
+  B.Q[0] = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B.t0 = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B.t1 = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B.state = a.take<IterState>(1);
+  if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
+
+  hipStream_t s = h->stream;
+  // -- setup: leverage, quantised weights, CDFs
+  st = launch_setup(h, p, g, T, B.s, true);
+  if (st != KR_OK) return st;
+  // -- sampling
+  int64_t sumI = 0;
+  for (int n = 0; n < g.N; ++n) sumI += g.I[n];
+  const int in_lds = sumI * 8 <= 48 * 1024;
+  KL(h, k_sample, dim3(grid_for(m, 256, 2048)), dim3(256), in_lds ? sumI * 8 : 0, s, T, g, o.seed,
+                     o.stream, (uint64_t)0, in_lds, B.keys);
+  // -- stable LSD radix sort of the packed keys
+  uint64_t* kin = B.keys;
+  uint64_t* kout = B.keys_alt;
+  for (int sh = 0; sh < g.keybits; sh += 8) {
+    KL(h, k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, B.hist, nblocks);
+    KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, B.hist, (int64_t)256 * nblocks);
+    KL(h, k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, B.hist,
+                       nblocks);
+    std::swap(kin, kout);
+  }
+  // -- sample tree (distinct prefixes per level)
+  KL(h, k_tree_count, dim3(ntiles), dim3(SORT_THREADS), 0, s, kin, g, B.tiletot);
+  KL(h, k_tree_scan, dim3(1), dim3(64), 0, s, B.tiletot, ntiles, g, tr);
+  KL(h, k_tree_sentinels, dim3(1), dim3(64), 0, s, g, tr);
+  KL(h, k_tree_emit, dim3(ntiles), dim3(SORT_THREADS), 0, s, kin, g, B.tiletot, tr);
+  KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype,
+                     B.Omega, B.bD, B.counts, B.s.flags);
+  // -- Richardson
+  KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, (double*)d_x,
+                     g.Rtot * g.nrhs, 0.0);
+  KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state,
+                     (int64_t)(sizeof(IterState) / 4));
+  HIPCHK(h, hipGetLastError());
+  const int Rl = g.R[g.N - 1];
+  const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
+  const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
+  int iters_enqueued = 0;
+  bool flags_checked = false;
+  kr_status result = KR_OK;
+  while (iters_enqueued < max_iter) {
+    const int chunk = std::min(check_every, max_iter - iters_enqueued);
+    for (int it = 0; it < chunk; ++it) {
+      for (int k = 1; k < g.N; ++k) {
+        const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
+        KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
+                           (const double*)B.P[k - 1], B.P[k], (const IterState*)B.state);
+      }
+      double* qlast = g.N == 1 ? B.Q[0] : B.Q[g.N - 1];
+      const dim3 rg(grid_for(rows_threads, 256));
+      switch (G) {
+        case 8: KL(h, k_rows_adj<8>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                   (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+        case 16: KL(h, k_rows_adj<16>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                    (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+        case 32: KL(h, k_rows_adj<32>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                    (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+        default: KL(h, k_rows_adj<64>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                    (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+      }
+      for (int k = g.N - 1; k >= 1; --k) {
+        const int64_t work = level_cap(g, k - 1) * g.rsuf[k - 1] * g.nrhs;
+        KL(h, k_adj_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
+                           (const double*)B.Q[k], B.Q[k - 1], (const IterState*)B.state);
+      }
+      KL(h, k_precond_update, dim3(1), dim3(1024), 0, s, T, g, (const double*)B.Q[0], (double*)d_x,
+                         B.t0, B.t1, lambda, eta, tol, max_iter, lambda == 0.0 ? 1 : 0, B.state);
+    }
+    iters_enqueued += chunk;
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(h->h_state, B.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
+    if (!flags_checked) {
+      HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (!flags_checked) {
+      flags_checked = true;
+      const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
+      if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A or b");
+      if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
+      if ((fl & KR_FLAG_SINGULAR) && lambda == 0.0)
+        KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
+    }
+    if (h->h_state->all_done) break;
+  }
+  HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  const IterState& S = *h->h_state;
+  double rel = 0.0;
+  bool all = true;
+  for (int q = 0; q < g.nrhs; ++q) {
+    rel = std::max(rel, S.rel[q]);
+    all = all && S.done[q];
+  }
+  if (S.diverged) {
+    result = KR_EDIVERGED;
+    h->err = "Richardson iteration diverged (non-finite or exploding update)";
+  } else if (!all) {
+    result = KR_WMAXITER;
+    h->err = "iteration limit reached before the stopping rule was met";
+  }
+  if (info) {
+    info->iters = S.iters;
+    info->status = result;
+    info->m = m;
+    info->distinct_rows = h->h_small[8 + g.N];
+    info->rel_update = rel;
+  }
+  h->has_sketch = true;
+  h->g = g;
+  h->T = T;
+  h->tr = tr;
+  h->Omega = B.Omega;
+  h->counts = B.counts;
+  return result;
+}
+
+extern "C" {
+
+kr_status kron_regress(kr_handle h, const kr_problem* p, double eps, double delta, const kr_opts* opts,
+                       void* d_x, kr_info* info) {
+  return solve(h, p, 0.0, eps, delta, opts, d_x, info);
+}
+
+kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
+                     const kr_opts* opts, void* d_x, kr_info* info) {
+  return solve(h, p, lambda, eps, delta, opts, d_x, info);
+}
+
+kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega, int32_t* h_counts,
+                           int64_t cap, int64_t* h_D) {
+  if (!h) return KR_EINVAL;
+  if (!h->has_sketch) KR_FAIL(h, KR_EINVAL, "no sketch to export");
+  const Geom& g = h->g;
+  int64_t D = 0;
+  HIPCHK(h, hipMemcpy(&D, h->tr.cnt + g.N, sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (h_D) *h_D = D;
+  if (h_Q) {
+    int64_t off = 0;
+    for (int n = 0; n < g.N; ++n) {
+      HIPCHK(h, hipMemcpy(h_Q + off, h->T.Q[n], g.I[n] * sizeof(uint64_t), hipMemcpyDeviceToHost));
+      off += g.I[n];
+    }
+  }
+  if (D > cap) {
+    if (h_rows || h_Omega || h_counts) KR_FAIL(h, KR_EINVAL, "capacity %lld < D=%lld", (long long)cap, (long long)D);
+    return KR_OK;
+  }
+  if (h_rows) {
+    std::vector<uint64_t> keys(D);
+    HIPCHK(h, hipMemcpy(keys.data(), h->tr.rkey, D * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < D; ++j)
+      for (int n = 0; n < g.N; ++n)
+        h_rows[j * g.N + n] = (int32_t)((keys[j] >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+  }
+  if (h_Omega) HIPCHK(h, hipMemcpy(h_Omega, h->Omega, D * sizeof(double), hipMemcpyDeviceToHost));
+  if (h_counts) HIPCHK(h, hipMemcpy(h_counts, h->counts, D * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return KR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Loss and exact baseline
+// ---------------------------------------------------------------------------
+static int rm_bucket(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64; }
+
+kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void* d_x, double* h_loss) {
+  if (!h) return KR_EINVAL;
+  Geom g;
+  kr_status st = make_geom(h, p, &g);
+  if (st != KR_OK) return st;
+  if (!p->b || !d_x || !h_loss) KR_FAIL(h, KR_EINVAL, "b, x or loss is NULL");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
+  // largest intermediate of the expansion x x_{N-1} A_{N-1} .. x_1 A_1
+  int64_t dims[KR_MAXN];
+  for (int n = 0; n < g.N; ++n) dims[n] = g.R[n];
+  int64_t maxsz = g.Rtot * g.nrhs;
+  for (int n = g.N - 1; n >= 1; --n) {
+    dims[n] = g.I[n];
+    int64_t sz = g.nrhs;
+    for (int k = 0; k < g.N; ++k) sz *= dims[k];
+    maxsz = std::max(maxsz, sz);
+  }
+  const int64_t C = (g.Itot / g.I[0]) * g.nrhs;
+  size_t need = setup_bytes(g) + 2 * 8 * (size_t)maxsz + 8 * (size_t)C + 8 * 64 + 4096;
+  st = ensure(h, &h->aux, &h->aux_bytes, need);
+  if (st != KR_OK) return st;
+  Arena a{(char*)h->aux, h->aux_bytes, 0};
+  ModeTables T{};
+  SetupBufs S{};
+  carve_setup(a, g, &T, &S);
+  double* buf0 = a.take<double>(maxsz);
+  double* buf1 = a.take<double>(maxsz);
+  double* partial = a.take<double>(C);
+  double* out = a.take<double>(64);
+  hipStream_t s = h->stream;
+  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)S.flags, (int64_t)64);
+  for (int n = 0; n < g.N; ++n) {
+    const int64_t cnt = (int64_t)g.I[n] * g.R[n];
+    KL(h, k_promote, dim3(grid_for(cnt, 256, 1024)), dim3(256), 0, s, p->A[n], p->a_dtype, S.A64[n],
+                       cnt, S.flags);
+  }
+  const double* cur = (const double*)d_x;
+  for (int n = 0; n < g.N; ++n) dims[n] = g.R[n];
+  double* dst = buf0;
+  for (int n = g.N - 1; n >= 1; --n) {
+    int64_t pre = 1, post = g.nrhs;
+    for (int k = 0; k < n; ++k) pre *= dims[k];
+    for (int k = n + 1; k < g.N; ++k) post *= dims[k];
+    KL(h, k_mode_product, dim3(grid_for(pre * g.I[n] * post, 256)), dim3(256), 0, s, cur, dst, pre,
+                       g.R[n], g.I[n], post, (const double*)S.A64[n], 0);
+    dims[n] = g.I[n];
+    cur = dst;
+    dst = dst == buf0 ? buf1 : buf0;
+  }
+  const dim3 sg(grid_for(C, 256, int64_t(1) << 30));
+  switch (rm_bucket(g.R[0])) {
+    case 8: KL(h, k_stream_loss<8>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
+    case 16: KL(h, k_stream_loss<16>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
+    case 32: KL(h, k_stream_loss<32>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
+    default: KL(h, k_stream_loss<64>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
+  }
+  KL(h, k_finish_loss, dim3(g.nrhs), dim3(1024), 0, s, (const double*)partial, C, (const double*)d_x,
+                     g.Rtot, g.nrhs, lambda, out);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h_loss, out, g.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(h->h_small, S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if ((int32_t)(h->h_small[0] & 0xFFFFFFFF) & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A");
+  return KR_OK;
+}
+
+kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x) {
+  if (!h) return KR_EINVAL;
+  Geom g;
+  kr_status st = make_geom(h, p, &g);
+  if (st != KR_OK) return st;
+  if (!p->b || !d_x) KR_FAIL(h, KR_EINVAL, "b or x is NULL");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
+  const int64_t C = (g.Itot / g.I[0]) * g.nrhs;
+  int64_t maxsz = (int64_t)g.R[0] * C;
+  size_t need = setup_bytes(g) + 2 * 8 * (size_t)maxsz + 4096;
+  for (int n = 0; n < g.N; ++n) need += 8 * (size_t)g.I[n] * g.R[n] + 256;
+  st = ensure(h, &h->aux, &h->aux_bytes, need);
+  if (st != KR_OK) return st;
+  Arena a{(char*)h->aux, h->aux_bytes, 0};
+  ModeTables T{};
+  SetupBufs S{};
+  carve_setup(a, g, &T, &S);
+  double* U[KR_MAXN];
+  for (int n = 0; n < g.N; ++n) U[n] = a.take<double>((size_t)g.I[n] * g.R[n]);
+  double* buf0 = a.take<double>(maxsz);
+  double* buf1 = a.take<double>(maxsz);
+  hipStream_t s = h->stream;
+  st = launch_setup(h, p, g, T, S, false);
+  if (st != KR_OK) return st;
+  for (int n = 0; n < g.N; ++n)
+    KL(h, k_left_singular, dim3(grid_for((int64_t)g.I[n] * g.R[n], 256, 1024)), dim3(256), 0, s,
+                       (const double*)S.A64[n], (const double*)T.V[n], (const double*)T.evals[n], g.I[n], g.R[n],
+                       U[n]);
+  const dim3 sg(grid_for(C, 256, int64_t(1) << 30));
+  switch (rm_bucket(g.R[0])) {
+    case 8: KL(h, k_stream_contract0<8>, sg, dim3(256), 0, s, (const double*)U[0], g.I[0], g.R[0], p->b, p->b_dtype, C, buf0); break;
+    case 16: KL(h, k_stream_contract0<16>, sg, dim3(256), 0, s, (const double*)U[0], g.I[0], g.R[0], p->b, p->b_dtype, C, buf0); break;
+    case 32: KL(h, k_stream_contract0<32>, sg, dim3(256), 0, s, (const double*)U[0], g.I[0], g.R[0], p->b, p->b_dtype, C, buf0); break;
+    default: KL(h, k_stream_contract0<64>, sg, dim3(256), 0, s, (const double*)U[0], g.I[0], g.R[0], p->b, p->b_dtype, C, buf0); break;
+  }
+  int64_t dims[KR_MAXN];
+  dims[0] = g.R[0];
+  for (int n = 1; n < g.N; ++n) dims[n] = g.I[n];
+  double* cur = buf0;
+  double* dst = buf1;
+  for (int n = 1; n < g.N; ++n) {
+    int64_t pre = 1, post = g.nrhs;
+    for (int k = 0; k < n; ++k) pre *= dims[k];
+    for (int k = n + 1; k < g.N; ++k) post *= dims[k];
+    KL(h, k_mode_product, dim3(grid_for(pre * g.R[n] * post, 256)), dim3(256), 0, s,
+                       (const double*)cur, dst, pre, g.I[n], g.R[n], post, (const double*)U[n], 1);
+    dims[n] = g.R[n];
+    std::swap(cur, dst);
+  }
+  KL(h, k_exact_scale, dim3(grid_for(g.Rtot * g.nrhs, 256)), dim3(256), 0, s, T, g, lambda, cur);
+  for (int n = 0; n < g.N; ++n) {
+    int64_t pre = 1, post = g.nrhs;
+    for (int k = 0; k < n; ++k) pre *= g.R[k];
+    for (int k = n + 1; k < g.N; ++k) post *= g.R[k];
+    double* o = (n == g.N - 1) ? (double*)d_x : dst;
+    KL(h, k_mode_product, dim3(grid_for(pre * g.R[n] * post, 256)), dim3(256), 0, s,
+                       (const double*)cur, o, pre, g.R[n], g.R[n], post, (const double*)T.V[n], 0);
+    if (n != g.N - 1) std::swap(cur, dst);
+  }
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_small, S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if ((int32_t)(h->h_small[0] & 0xFFFFFFFF) & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A");
+  return KR_OK;
+}
+
+}  // extern "C"

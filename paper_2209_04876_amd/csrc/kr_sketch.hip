@@ -1,0 +1,311 @@
+// RowSampling on the product distribution and the merge of duplicate samples
+// (Definition of leverage score sampling; Algorithm 2 sampling lines; the
+// diagonal view of S and the distinct prefix sets of Theorem
+// kron_mat_mul_sqrt_decomp).
+//
+//   k_sample        Philox4x64-10 words -> per-mode inverse-CDF draws -> packed key
+//   k_radix_*       stable LSD radix sort of the packed keys (8-bit digits)
+//   k_tree_*        run-length encoding of the sorted keys at every prefix length:
+//                   the nodes of level k are the distinct (i_0..i_{k-1})
+//   k_rows          per distinct row: multiplicity, merged weight
+//                   Omega_j = count_j / (m prod_n p'_{i_n}), gathered response b_j
+//
+// The packed key stores mode n's index in bits [shift[n], shift[n] + bits[n]),
+// mode 0 most significant, so sorting keys sorts rows by their linear index and
+// every prefix of modes is a contiguous key range.
+#include "kr_internal.h"
+
+namespace kr {
+
+#define SORT_THREADS 256
+#define SORT_ITEMS 16
+#define SORT_TILE (SORT_THREADS * SORT_ITEMS)
+
+// ---------------------------------------------------------------------------
+// Sampling.  CDF tables are staged in LDS when they fit (cdf_in_lds != 0).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_sample(ModeTables T, Geom g, uint64_t seed, uint64_t stream,
+                                                uint64_t row, int cdf_in_lds,
+                                                uint64_t* __restrict__ keys) {
+  extern __shared__ uint64_t lds_cdf[];
+  const uint64_t* C[KR_MAXN];
+  int off = 0;
+  for (int n = 0; n < g.N; ++n) {
+    if (cdf_in_lds) {
+      for (int i = threadIdx.x; i < g.I[n]; i += blockDim.x) lds_cdf[off + i] = T.C[n][i];
+      C[n] = lds_cdf + off;
+    } else {
+      C[n] = T.C[n];
+    }
+    off += g.I[n];
+  }
+  __syncthreads();
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t key = 0;
+    for (int grp = 0; grp * 4 < g.N; ++grp) {
+      const u64x4 w = philox4x64_10((uint64_t)t, (uint64_t)grp, row, 0ull, seed, stream);
+      for (int k = 0; k < 4 && grp * 4 + k < g.N; ++k) {
+        const int n = grp * 4 + k;
+        const uint64_t u = w.v[k] >> 32;
+        // number of CDF entries <= u  (index i with C_{i-1} <= u < C_i)
+        int lo = 0, hi = g.I[n];
+        const uint64_t* c = C[n];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (c[mid] <= u) lo = mid + 1; else hi = mid;
+        }
+        key |= (uint64_t)lo << g.shift[n];
+      }
+    }
+    keys[t] = key;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits.  hist is digit-major: hist[d * nblocks + b].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
+                                                            int shift, uint32_t* __restrict__ hist,
+                                                            int nblocks) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+  for (int k = 0; k < SORT_ITEMS; ++k) {
+    const int64_t t = base + (int64_t)k * SORT_THREADS + threadIdx.x;
+    if (t < m) atomicAdd(&cnt[(keys[t] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of n uint32 values in place, one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int64_t n) {
+  __shared__ uint32_t s[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t x = i < n ? v[i] : 0u;
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < n) v[i] = carry + s[threadIdx.x] - x;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += s[1023];
+    __syncthreads();
+  }
+}
+
+// Stable scatter.  The tile is processed in rounds of 256 consecutive keys; in a
+// round, a key's rank among equal digits is (earlier waves' counts) + (earlier
+// lanes in its wave with the same digit, found by ballot matching).
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t* __restrict__ in,
+                                                               uint64_t* __restrict__ out, int64_t m,
+                                                               int shift, const uint32_t* __restrict__ hist,
+                                                               int nblocks) {
+  __shared__ uint32_t base_[256];
+  __shared__ uint32_t wcnt[SORT_THREADS / 64][257];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  base_[threadIdx.x] = hist[(size_t)threadIdx.x * nblocks + blockIdx.x];
+  for (int k = 0; k < SORT_THREADS / 64; ++k) wcnt[k][threadIdx.x] = 0;
+  if (threadIdx.x < SORT_THREADS / 64) wcnt[threadIdx.x][256] = 0;
+  __syncthreads();
+  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  const int64_t tbase = (int64_t)blockIdx.x * SORT_TILE;
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    const int64_t t = tbase + (int64_t)r * SORT_THREADS + threadIdx.x;
+    const bool valid = t < m;
+    const uint64_t key = valid ? in[t] : 0ull;
+    const uint32_t d = valid ? (uint32_t)((key >> shift) & 255u) : 256u;
+    unsigned long long peers = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    if (rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base_[d] + rank;
+      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+      out[pos] = key;
+    }
+    __syncthreads();
+    {
+      uint32_t add = 0;
+      for (int k = 0; k < SORT_THREADS / 64; ++k) { add += wcnt[k][threadIdx.x]; wcnt[k][threadIdx.x] = 0; }
+      base_[threadIdx.x] += add;
+      if (threadIdx.x < SORT_THREADS / 64) wcnt[threadIdx.x][256] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tree build: flag_k[t] = (t == 0) or prefix_k(key[t]) != prefix_k(key[t-1]).
+// Pass 1 counts flags per tile and level; pass 2 scans tile totals; pass 3
+// assigns node ids and writes node arrays.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t level_flags(const uint64_t* keys, int64_t t, const Geom& g) {
+  if (t == 0) return (1u << (g.N + 1)) - 2u;  // levels 1..N
+  const uint64_t a = keys[t], b = keys[t - 1];
+  uint32_t f = 0;
+  for (int k = 1; k <= g.N; ++k)
+    if ((a >> g.lshift[k]) != (b >> g.lshift[k])) f |= 1u << k;
+  return f;
+}
+
+__global__ void __launch_bounds__(SORT_THREADS) k_tree_count(const uint64_t* __restrict__ keys, Geom g,
+                                                            int64_t* __restrict__ tiletot) {
+  __shared__ int64_t red[SORT_THREADS / 64][KR_MAXN + 1];
+  int cnt[KR_MAXN + 1];
+  for (int k = 0; k <= KR_MAXN; ++k) cnt[k] = 0;
+  const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)threadIdx.x * SORT_ITEMS;
+  for (int e = 0; e < SORT_ITEMS; ++e) {
+    const int64_t t = t0 + e;
+    if (t < g.m) {
+      const uint32_t f = level_flags(keys, t, g);
+      for (int k = 1; k <= g.N; ++k) cnt[k] += (f >> k) & 1u;
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k = 1; k <= g.N; ++k) {
+    int v = cnt[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[w][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x <= (unsigned)g.N && threadIdx.x >= 1) {
+    int64_t s = 0;
+    for (int k = 0; k < SORT_THREADS / 64; ++k) s += red[k][threadIdx.x];
+    tiletot[(size_t)blockIdx.x * (KR_MAXN + 1) + threadIdx.x] = s;
+  }
+}
+
+// Exclusive scan of tile totals per level (one thread per level), node counts,
+// and the sentinels of the child-range arrays.
+__global__ void k_tree_scan(int64_t* __restrict__ tiletot, int ntiles, Geom g, Tree tr) {
+  const int k = threadIdx.x;
+  if (k == 0) {
+    tr.cnt[0] = 1;
+    return;
+  }
+  if (k > g.N) return;
+  int64_t run = 0;
+  for (int b = 0; b < ntiles; ++b) {
+    const int64_t v = tiletot[(size_t)b * (KR_MAXN + 1) + k];
+    tiletot[(size_t)b * (KR_MAXN + 1) + k] = run;
+    run += v;
+  }
+  tr.cnt[k] = run;
+}
+
+__global__ void k_tree_sentinels(Geom g, Tree tr) {
+  const int k = threadIdx.x;
+  if (k < g.N) tr.fchild[k][tr.cnt[k]] = (int32_t)tr.cnt[k + 1];
+  if (k == 0) {
+    tr.fchild[0][0] = 0;
+    tr.rstart[tr.cnt[g.N]] = (int32_t)g.m;
+  }
+}
+
+__global__ void __launch_bounds__(SORT_THREADS) k_tree_emit(const uint64_t* __restrict__ keys, Geom g,
+                                                           const int64_t* __restrict__ tiletot, Tree tr) {
+  __shared__ int64_t wsum[SORT_THREADS / 64][KR_MAXN + 1];
+  int cnt[KR_MAXN + 1];
+  uint32_t fl[SORT_ITEMS];
+  for (int k = 0; k <= KR_MAXN; ++k) cnt[k] = 0;
+  const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)threadIdx.x * SORT_ITEMS;
+  for (int e = 0; e < SORT_ITEMS; ++e) {
+    const int64_t t = t0 + e;
+    fl[e] = t < g.m ? level_flags(keys, t, g) : 0u;
+    for (int k = 1; k <= g.N; ++k) cnt[k] += (fl[e] >> k) & 1u;
+  }
+  // block-exclusive prefix per level: wave inclusive scan then wave offsets
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t excl[KR_MAXN + 1];
+  for (int k = 1; k <= g.N; ++k) {
+    int v = cnt[k];
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(v, o, 64);
+      if (lane >= o) v += y;
+    }
+    excl[k] = v - cnt[k];
+    if (lane == 63) wsum[w][k] = v;
+  }
+  __syncthreads();
+  for (int k = 1; k <= g.N; ++k) {
+    int64_t off = tiletot[(size_t)blockIdx.x * (KR_MAXN + 1) + k];
+    for (int q = 0; q < w; ++q) off += wsum[q][k];
+    excl[k] += off;
+  }
+  // walk the items: excl[k] is the number of level-k flags before item t
+  for (int e = 0; e < SORT_ITEMS; ++e) {
+    const int64_t t = t0 + e;
+    if (t >= g.m) break;
+    const uint32_t f = fl[e];
+    const uint64_t key = keys[t];
+    for (int k = 1; k <= g.N; ++k) {
+      if ((f >> k) & 1u) {
+        const int64_t s = excl[k];
+        const int n = k - 1;
+        tr.idx[k][s] = (int32_t)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+        // parent: the level-(k-1) node containing t (inclusive count - 1)
+        tr.parent[k][s] = k == 1 ? 0 : (int32_t)(excl[k - 1] + ((f >> (k - 1)) & 1u) - 1);
+        if (k < g.N) tr.fchild[k][s] = (int32_t)excl[k + 1];
+        if (k == g.N) {
+          tr.rstart[s] = (int32_t)t;
+          tr.rkey[s] = key;
+        }
+      }
+    }
+    for (int k = 1; k <= g.N; ++k) excl[k] += (f >> k) & 1u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Distinct rows: multiplicity, Omega_j = count_j * omega_j with
+// omega_j = 1 / (m prod_n Q_n[i_n] 2^-32) multiplied in mode order, gathered b.
+// b is row-major (prod I) x nrhs of dtype b_dtype; bD is D x nrhs float64.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rows(ModeTables T, Geom g, Tree tr, const void* __restrict__ b,
+                                             int b_dtype, double* __restrict__ Omega,
+                                             double* __restrict__ bD, int32_t* __restrict__ counts,
+                                             int32_t* __restrict__ flags) {
+  const int64_t D = tr.cnt[g.N];
+  int bad = 0;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < D;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = tr.rstart[j + 1] - tr.rstart[j];
+    const uint64_t key = tr.rkey[j];
+    double den = (double)g.m;
+    int64_t lin = 0;
+    for (int n = 0; n < g.N; ++n) {
+      const int i = (int)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+      den = den * ((double)T.Q[n][i] * 0x1p-32);
+      lin = lin * g.I[n] + i;
+    }
+    const double om = 1.0 / den;
+    Omega[j] = (double)c * om;
+    counts[j] = c;
+    for (int q = 0; q < g.nrhs; ++q) {
+      const int64_t e = lin * g.nrhs + q;
+      const double v = b_dtype == KR_F32 ? (double)((const float*)b)[e] : ((const double*)b)[e];
+      bD[j * g.nrhs + q] = v;
+      bad |= !isfinite(v);
+    }
+  }
+  if (bad) atomicOr(flags, KR_FLAG_NONFINITE);
+}
+
+}  // namespace kr
