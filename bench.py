@@ -102,14 +102,7 @@ def main():
     # one fully profiled step (outside the timed region) for the kernel breakdown
     kr.profile_enable(True, "")
     step()
-    names = ["k_stream_loss<16>", "k_precond_update", "k_adj_level", "k_fwd_level", "k_rows_adj<16>",
-             "k_sample", "k_radix_scatter", "k_radix_hist", "k_scan_u32", "k_tree_emit", "k_tree_count",
-             "k_rows", "k_mode_product", "k_finish_loss", "k_gram", "k_eig", "k_leverage", "k_promote"]
-    breakdown = {}
-    for nm in names:
-        n, ms = kr.profile_query(nm)
-        if n:
-            breakdown[nm] = {"launches": n, "ms": round(ms, 4)}
+    breakdown = {k: {"launches": n, "ms": round(ms, 4)} for k, (n, ms) in kr.profile_breakdown().items()}
     dominant = max(breakdown, key=lambda k: breakdown[k]["ms"])
     log("kernel breakdown (one step):", json.dumps(breakdown))
 

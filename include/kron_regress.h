@@ -28,7 +28,7 @@
  *     (seed, stream) and counter (t, n/4, row, 0) for sample t, mode n, sketch
  *     row (0 here); mode n uses output word n%4 and its top 32 bits u pick the
  *     index i with C_{i-1} <= u < C_i on the inclusive CDF of integer weights
- *     Q_i = max(1, floor(2^32 l_i / sum l)) (largest weight absorbs the rounding
+ *     Q_i = max(1, round(2^32 l_i / sum l)) (largest weight absorbs the rounding
  *     deficit so sum Q = 2^32).  The sketch weight of a sample is
  *     omega = 1/(m prod_n Q_{i_n} 2^-32).
  */
@@ -80,7 +80,15 @@ typedef struct {
                          (default 1e-12 when <= 0)                                    */
   uint64_t seed;      /* Philox key word 0                                            */
   uint64_t stream;    /* Philox key word 1                                            */
+  int32_t flags;      /* KR_OPT_* bits                                                */
+  int32_t workgroups; /* workgroups of the cooperative iteration (0 = automatic)      */
 } kr_opts;
+
+/* kr_opts.flags: run the whole iteration as one cooperative launch with grid
+ * barriers (N >= 2 and the iterate small enough to fit in LDS; otherwise the
+ * flag is ignored) instead of one kernel launch per phase with host
+ * convergence checks every check_every iterations. */
+#define KR_OPT_COOPERATIVE 1
 
 typedef struct {
   int32_t iters;          /* Richardson iterations performed (max over RHS)          */
@@ -138,6 +146,9 @@ kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* 
  * device time in milliseconds (0 launches when the name is unknown). */
 kr_status kr_profile_enable(kr_handle h, int32_t enable, const char* filter);
 kr_status kr_profile_query(kr_handle h, const char* kernel, int64_t* h_launches, double* h_total_ms);
+/* Newline-separated names of the kernels recorded since kr_profile_enable,
+ * NUL-terminated in h_buf (KR_EINVAL when cap is too small; the list is cut). */
+kr_status kr_profile_list(kr_handle h, char* h_buf, int64_t cap);
 
 #ifdef __cplusplus
 }

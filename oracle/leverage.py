@@ -3,7 +3,7 @@
 Statistical and ridge leverage scores follow Section 3 (definition of the
 lambda-ridge leverage score and its compact-SVD form).  The sampling
 distribution p_i = l_i / sum(l) of each factor (Algorithm 2, product
-distribution data structure) is quantised to integers on a 2^32 grid so that the
+distribution data structure) is quantised to the nearest integers on a 2^32 grid so that the
 CPU and GPU samplers agree bit for bit; the realised probabilities p'_i = Q_i/2^32
 are what the sketch weights use, which keeps the sketch unbiased for p' and makes
 p' a beta-overestimate of p (Section 3, definition of beta-overestimate).
@@ -46,7 +46,10 @@ def leverage_scores(A):
 def quantize(lev):
     """Integer weights Q on the 2^32 grid for p = lev / sum(lev).
 
-    Q_i = max(1, floor(p_i * 2^32)) where lev_i > 0, and 0 where lev_i == 0.
+    Q_i = max(1, floor(p_i * 2^32 + 1/2)) (nearest integer) where lev_i > 0, and 0
+    where lev_i == 0.  Rounding to nearest keeps exactly representable
+    probabilities (uniform leverage over 2^k rows, as for square factors) away
+    from the quantisation boundaries, which sit at half-integers.
     The difference 2^32 - sum(Q) is added to the largest Q (lowest index on ties)
     so that sum(Q) == 2^32 exactly.  Returns uint64.
     """
@@ -57,7 +60,7 @@ def quantize(lev):
     if total <= 0.0:
         raise ValueError("all leverage scores are zero")
     p = lev / total
-    q = np.floor(p * float(GRID)).astype(np.int64)
+    q = np.floor(p * float(GRID) + 0.5).astype(np.int64)
     q = np.where(lev > 0.0, np.maximum(q, 1), 0)
     j = int(np.argmax(q))
     q[j] += GRID - int(np.sum(q))

@@ -40,7 +40,11 @@ class Problem(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint64)]
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint64),
+                ("flags", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
+
+
+OPT_COOPERATIVE = 1
 
 
 class Info(ctypes.Structure):
@@ -79,7 +83,8 @@ def load_library(path=LIB_PATH):
     lib.kr_profile_enable.argtypes = [c_p, ctypes.c_int32, ctypes.c_char_p]
     lib.kr_profile_query.argtypes = [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(c_d)]
-    for name in ("kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_loss",
+    lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
+    for name in ("kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_loss",
                  "kron_exact", "kr_export_sketch"):
         getattr(lib, name).restype = c_i
     _lib = lib
@@ -169,14 +174,16 @@ def _x_like(As, nrhs, one_dim):
     return torch.empty(shape, dtype=torch.float64, device=As[0].device)
 
 
-def _opts(m, max_iter, tol, seed, stream, check_every):
+def _opts(m, max_iter, tol, seed, stream, check_every, flags=0, workgroups=0):
     o = Opts()
     o.m, o.max_iter, o.tol, o.seed, o.stream, o.check_every = m, max_iter, tol, seed, stream, check_every
+    o.flags, o.workgroups = flags, workgroups
     return o
 
 
 def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=1e-12,
-               check_every=8, handle=None, x=None, allow_maxiter=True):
+               check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
+               workgroups=0):
     """Algorithm 2 with regularisation lam.  Returns (x float64, info dict)."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
@@ -184,7 +191,8 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
         x = _x_like(As, p.nrhs, b.dim() == 1)
     info = Info()
     st = h.lib.kron_ridge(h.ptr, ctypes.byref(p), lam, eps, delta,
-                          ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every)),
+                          ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
+                                             OPT_COOPERATIVE if cooperative else 0, workgroups)),
                           ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:
@@ -193,7 +201,8 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
 
 
 def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=1e-12,
-                 check_every=8, handle=None, x=None, allow_maxiter=True):
+                 check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
+                 workgroups=0):
     """Algorithm 2 (lambda = 0).  Returns (x float64, info dict)."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
@@ -201,7 +210,8 @@ def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200
         x = _x_like(As, p.nrhs, b.dim() == 1)
     info = Info()
     st = h.lib.kron_regress(h.ptr, ctypes.byref(p), eps, delta,
-                            ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every)),
+                            ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
+                                               OPT_COOPERATIVE if cooperative else 0, workgroups)),
                             ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:
@@ -244,6 +254,19 @@ def profile_query(kernel, handle=None):
     return n.value, ms.value
 
 
+def profile_names(handle=None):
+    """Kernel names recorded since profile_enable."""
+    h = handle or default_handle()
+    buf = ctypes.create_string_buffer(65536)
+    h._check(h.lib.kr_profile_list(h.ptr, buf, len(buf)))
+    return [n for n in buf.value.decode().split("\n") if n]
+
+
+def profile_breakdown(handle=None):
+    """{kernel: (launches, total ms)} for every kernel recorded since profile_enable."""
+    return {n: profile_query(n, handle) for n in profile_names(handle)}
+
+
 def export_sketch(sizes, handle=None, cap=None):
     """The last solve's sketch: Q tables per mode, distinct rows (D x N), Omega, counts."""
     import numpy as np
@@ -264,4 +287,5 @@ def export_sketch(sizes, handle=None, cap=None):
 
 
 __all__ = ["Handle", "KronRegressError", "kron_regress", "kron_ridge", "kron_loss", "kron_exact",
-           "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query"]
+           "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query",
+           "profile_names", "profile_breakdown"]

@@ -17,6 +17,7 @@
 #include "kr_sketch.hip"
 #include "kr_iter.hip"
 #include "kr_stream.hip"
+#include "kr_persist.hip"
 
 using namespace kr;
 
@@ -243,6 +244,19 @@ kr_status kr_profile_enable(kr_handle h, int32_t enable, const char* filter) {
   return KR_OK;
 }
 
+kr_status kr_profile_list(kr_handle h, char* h_buf, int64_t cap) {
+  if (!h || !h_buf || cap < 1) return KR_EINVAL;
+  std::string all;
+  for (auto& kv : h->prof) {
+    all += kv.first;
+    all += '\n';
+  }
+  const size_t n = std::min<size_t>(all.size(), (size_t)cap - 1);
+  std::memcpy(h_buf, all.data(), n);
+  h_buf[n] = 0;
+  return all.size() + 1 > (size_t)cap ? KR_EINVAL : KR_OK;
+}
+
 kr_status kr_profile_query(kr_handle h, const char* kernel, int64_t* launches, double* total_ms) {
   if (!h || !kernel) return KR_EINVAL;
   auto it = h->prof.find(kernel);
@@ -327,6 +341,9 @@ struct SolveBufs {
   double* Q[KR_MAXN + 1];
   double* t0;
   double* t1;
+  double* wrow;
+  double* part;
+  int64_t* rs1;
   IterState* state;
 };
 
@@ -343,10 +360,12 @@ static size_t solve_bytes(const Geom& g, int ntiles, int nblocks) {
   b += 2 * 8 * (size_t)g.m + 4 * 256 * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
   const int64_t D = level_cap(g, g.N);
   b += (size_t)D * (8 + 8 * g.nrhs + 4);
-  for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2);
+  for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
   b += 4 * (size_t)(D + 2) + 8 * (size_t)D;
   for (int k = 1; k < g.N; ++k) b += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs;
-  b += 3 * 8 * (size_t)g.Rtot * g.nrhs + sizeof(IterState) + 8 * (KR_MAXN + 1);
+  b += 3 * 8 * (size_t)g.Rtot * g.nrhs + sizeof(IterState) + 8 * (KR_MAXN + 1) + 512;
+  b += 8 * (size_t)D * g.nrhs + 8 * (size_t)(level_cap(g, 1) + 2) + 512;
+  b += 8 * (size_t)((level_cap(g, 1) + 31) / 32) * g.Rtot * g.nrhs + 512;
   return b + 64 * 256 + 4096;
 }
 
@@ -371,6 +390,9 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   }
   if (m > (int64_t(1) << 31) - 2) KR_FAIL(h, KR_EUNSUPPORTED, "m=%lld too large", (long long)m);
   g.m = m;
+  for (int k = 0; k <= g.N; ++k)
+    if ((double)level_cap(g, k) * (double)g.rsuf[k] * g.nrhs >= 2147483647.0)
+      KR_FAIL(h, KR_EUNSUPPORTED, "level %d of the sample tree needs more than 2^31 entries", k);
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
   const int check_every = o.check_every > 0 ? o.check_every : 8;
   const double tol = o.tol > 0.0 ? o.tol : 1e-12;
@@ -394,6 +416,7 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     tr.idx[k] = a.take<int32_t>(c + 2);
     tr.parent[k] = a.take<int32_t>(c + 2);
     tr.fchild[k] = a.take<int32_t>(c + 2);
+    tr.arow[k] = a.take<double>((size_t)c * g.R[k - 1]);
   }
   tr.fchild[0] = a.take<int32_t>(4);
   const int64_t Dcap = level_cap(g, g.N);
@@ -411,7 +434,11 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   B.Q[0] = a.take<double>((size_t)g.Rtot * g.nrhs);
   B.t0 = a.take<double>((size_t)g.Rtot * g.nrhs);
   B.t1 = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B.wrow = a.take<double>((size_t)Dcap * g.nrhs);
+  B.part = a.take<double>((size_t)((level_cap(g, 1) + RA_NODES - 1) / RA_NODES) * g.Rtot * g.nrhs);
+  B.rs1 = a.take<int64_t>(level_cap(g, 1) + 2);
   B.state = a.take<IterState>(1);
+  unsigned* bar = a.take<unsigned>(64);
   if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
 
   hipStream_t s = h->stream;
@@ -439,6 +466,7 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   KL(h, k_tree_scan, dim3(1), dim3(64), 0, s, B.tiletot, ntiles, g, tr);
   KL(h, k_tree_sentinels, dim3(1), dim3(64), 0, s, g, tr);
   KL(h, k_tree_emit, dim3(ntiles), dim3(SORT_THREADS), 0, s, kin, g, B.tiletot, tr);
+  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
   KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype,
                      B.Omega, B.bD, B.counts, B.s.flags);
   // -- Richardson
@@ -449,54 +477,125 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   HIPCHK(h, hipGetLastError());
   const int Rl = g.R[g.N - 1];
   const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
-  const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
-  int iters_enqueued = 0;
-  bool flags_checked = false;
+  const int64_t RT = g.Rtot * g.nrhs;
+  size_t mats = 0;
+  for (int n = 0; n < g.N; ++n) mats += (size_t)g.R[n] * g.R[n];
+  const int PT = 1024;   // threads per workgroup of the cooperative iteration
+  const size_t plds = 8 * (3 * (size_t)std::max<int64_t>(RT, PT) + (lambda > 0.0 ? (size_t)RT : 0) + mats);
   kr_status result = KR_OK;
-  while (iters_enqueued < max_iter) {
-    const int chunk = std::min(check_every, max_iter - iters_enqueued);
-    for (int it = 0; it < chunk; ++it) {
-      for (int k = 1; k < g.N; ++k) {
-        const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
-        KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
-                           (const double*)B.P[k - 1], B.P[k], (const IterState*)B.state);
-      }
-      double* qlast = g.N == 1 ? B.Q[0] : B.Q[g.N - 1];
-      const dim3 rg(grid_for(rows_threads, 256));
-      switch (G) {
-        case 8: KL(h, k_rows_adj<8>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                   (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-        case 16: KL(h, k_rows_adj<16>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                    (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-        case 32: KL(h, k_rows_adj<32>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                    (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-        default: KL(h, k_rows_adj<64>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                    (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-      }
-      for (int k = g.N - 1; k >= 1; --k) {
-        const int64_t work = level_cap(g, k - 1) * g.rsuf[k - 1] * g.nrhs;
-        KL(h, k_adj_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
-                           (const double*)B.Q[k], B.Q[k - 1], (const IterState*)B.state);
-      }
-      KL(h, k_precond_update, dim3(1), dim3(1024), 0, s, T, g, (const double*)B.Q[0], (double*)d_x,
-                         B.t0, B.t1, lambda, eta, tol, max_iter, lambda == 0.0 ? 1 : 0, B.state);
+  if (g.N >= 2 && plds <= 150 * 1024 && (o.flags & KR_OPT_COOPERATIVE)) {
+    // one cooperative launch runs every iteration
+    PArgs pa{};
+    pa.T = T;
+    pa.g = g;
+    pa.tr = tr;
+    pa.Omega = B.Omega;
+    pa.bD = B.bD;
+    for (int k = 1; k < g.N; ++k) { pa.P[k] = B.P[k]; pa.Q[k] = B.Q[k]; }
+    pa.gp = B.t0;
+    pa.wrow = B.wrow;
+    pa.rs1 = B.rs1;
+    KL(h, k_level1_rows, dim3(grid_for(level_cap(g, 1) + 1, 256, 1024)), dim3(256), 0, s, g, tr, B.rs1);
+    pa.xout = (double*)d_x;
+    pa.st = B.state;
+    pa.bar = bar;
+    pa.abortf = (int32_t*)(bar + 16);
+    pa.setup_flags = B.s.flags;
+    pa.lambda = lambda;
+    pa.eta = eta;
+    pa.tol = tol;
+    pa.max_iter = max_iter;
+    pa.use_ginv = lambda == 0.0 ? 1 : 0;
+    KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)bar, (int64_t)64);
+    const void* fn = G == 8 ? (const void*)k_richardson_persistent<8>
+                   : G == 16 ? (const void*)k_richardson_persistent<16>
+                   : G == 32 ? (const void*)k_richardson_persistent<32>
+                             : (const void*)k_richardson_persistent<64>;
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIPCHK(h, hipGetDevice(&dev));
+    HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
+    HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PT, plds));
+    if (per_cu < 1) KR_FAIL(h, KR_EUNSUPPORTED, "persistent kernel does not fit on a compute unit");
+    // fences of the grid barrier cost grow with the number of workgroups; 16
+    // workgroups of 1024 threads keep a barrier near 3 us
+    const int64_t CE = g.R[0] >= PT ? 1 : PT / g.R[0];
+    const int64_t want = std::max<int64_t>(level_cap(g, 1), (g.rsuf[1] * g.nrhs + CE - 1) / CE);
+    const int64_t cap = o.workgroups > 0 ? o.workgroups : 16;
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((int64_t)per_cu * ncu, want), cap));
+    void* args[] = {&pa};
+    {
+      ProfScope ps(h, "k_richardson_persistent", s);
+      HIPCHK(h, hipLaunchCooperativeKernel(fn, dim3(nblk), dim3(PT), args, (unsigned)plds, s));
     }
-    iters_enqueued += chunk;
-    HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(h->h_state, B.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
-    if (!flags_checked) {
-      HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    }
+    HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
-    if (!flags_checked) {
-      flags_checked = true;
-      const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
-      if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A or b");
-      if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
-      if ((fl & KR_FLAG_SINGULAR) && lambda == 0.0)
-        KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
+    const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
+    if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A or b");
+    if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
+    if ((fl & KR_FLAG_SINGULAR) && lambda == 0.0)
+      KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
+    if (h->h_state->diverged == 2) KR_FAIL(h, KR_EHIP, "grid barrier timed out in the persistent iteration");
+  } else {
+    const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
+    int iters_enqueued = 0;
+    bool flags_checked = false;
+    while (iters_enqueued < max_iter) {
+      const int chunk = std::min(check_every, max_iter - iters_enqueued);
+      for (int it = 0; it < chunk; ++it) {
+        for (int k = 1; k < g.N; ++k) {
+          const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
+          KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
+                             (const double*)B.P[k - 1], B.P[k], (const IterState*)B.state);
+        }
+        double* qlast = g.N == 1 ? B.Q[0] : B.Q[g.N - 1];
+        const dim3 rg(grid_for(rows_threads, 256));
+        switch (G) {
+          case 8: KL(h, k_rows_adj<8>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                     (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+          case 16: KL(h, k_rows_adj<16>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                      (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+          case 32: KL(h, k_rows_adj<32>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                      (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+          default: KL(h, k_rows_adj<64>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
+                                      (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
+        }
+        for (int k = g.N - 1; k >= 2; --k) {
+          const int64_t work = level_cap(g, k - 1) * g.rsuf[k - 1] * g.nrhs;
+          KL(h, k_adj_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
+                             (const double*)B.Q[k], B.Q[k - 1], (const IterState*)B.state);
+        }
+        if (g.N >= 2) {
+          const int64_t CEr = g.R[0] >= 256 ? 1 : 256 / g.R[0];
+          const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
+          const int64_t nnb = (level_cap(g, 1) + RA_NODES - 1) / RA_NODES;
+          KL(h, k_adj_root_partial, dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr,
+             (const double*)B.Q[1], B.part, (const IterState*)B.state);
+          KL(h, k_adj_root_sum, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr,
+             (const double*)B.part, B.Q[0], (const IterState*)B.state);
+        }
+        KL(h, k_precond_update, dim3(1), dim3(1024), 0, s, T, g, (const double*)B.Q[0], (double*)d_x,
+                           B.t0, B.t1, lambda, eta, tol, max_iter, lambda == 0.0 ? 1 : 0, B.state);
+      }
+      iters_enqueued += chunk;
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(h->h_state, B.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
+      if (!flags_checked) {
+        HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(h, hipStreamSynchronize(s));
+      if (!flags_checked) {
+        flags_checked = true;
+        const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
+        if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A or b");
+        if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
+        if ((fl & KR_FLAG_SINGULAR) && lambda == 0.0)
+          KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
+      }
+      if (h->h_state->all_done) break;
     }
-    if (h->h_state->all_done) break;
+
   }
   HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));

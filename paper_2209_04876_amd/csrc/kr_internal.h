@@ -51,10 +51,13 @@ struct ModeTables {
 //   fchild[k][s] first level-(k+1) child of s, with fchild[k][S_k] = S_{k+1}
 //                (k = 0..N-1; fchild[0] = {0, S_1})
 //   cnt[k]       S_k (device side; cnt[0] = 1)
+//   arow[k]      the factor row a_{k-1}[i_{k-1}(s)] of every level-k node, gathered
+//                once so the iteration reads node data contiguously
 // Level N nodes are the distinct rows; rstart[j] is the first sorted sample of
 // row j and rstart[D] = m.
 struct Tree {
   int32_t* idx[KR_MAXN + 1];
+  double* arow[KR_MAXN + 1];    // arow[k][s][r] = A_{k-1}[idx[k][s]][r], contiguous per node
   int32_t* parent[KR_MAXN + 1];
   int32_t* fchild[KR_MAXN + 1];
   int32_t* rstart;

@@ -21,32 +21,47 @@
 
 namespace kr {
 
+// (q, r) = divmod(e, W) for a grid-stride loop without dividing inside the loop.
+struct GDiv {
+  unsigned q, r, dq, dr, W;
+  __device__ __forceinline__ GDiv(unsigned e0, unsigned W_, unsigned step) : W(W_) {
+    q = e0 / W; r = e0 - q * W; dq = step / W; dr = step - dq * W;
+  }
+  __device__ __forceinline__ void next() {
+    q += dq; r += dr;
+    if (r >= W) { r -= W; ++q; }
+  }
+};
+
 __global__ void __launch_bounds__(256) k_fwd_level(ModeTables T, Geom g, Tree tr, int k,
                                                   const double* __restrict__ Pprev,
                                                   double* __restrict__ Pout,
                                                   const IterState* __restrict__ st) {
   if (st->all_done) return;
-  const int64_t S = tr.cnt[k];
-  const int64_t W = g.rsuf[k] * g.nrhs;         // entries per level-k node
-  const int64_t Wp = g.rsuf[k - 1] * g.nrhs;    // entries per parent
+  const unsigned S = (unsigned)tr.cnt[k];
+  const unsigned W = (unsigned)(g.rsuf[k] * g.nrhs);         // entries per level-k node
+  const unsigned Wp = (unsigned)(g.rsuf[k - 1] * g.nrhs);    // entries per parent
   const int Rk = g.R[k - 1];
-  const double* __restrict__ A = T.A[k - 1];
-  const int64_t total = S * W;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = e / W, cq = e - s * W;
-    const int p = k == 1 ? 0 : tr.parent[k][s];
-    const double* a = A + (int64_t)tr.idx[k][s] * Rk;
-    const double* src = Pprev + (int64_t)p * Wp + cq;
+  const double* __restrict__ arow = tr.arow[k];
+  const unsigned total = S * W;
+  const unsigned step = gridDim.x * blockDim.x;
+  const unsigned e0 = blockIdx.x * blockDim.x + threadIdx.x;
+  GDiv di(e0, W, step);
+  for (unsigned e = e0; e < total; e += step, di.next()) {
+    const unsigned s = di.q, cq = di.r;
+    const unsigned p = k == 1 ? 0u : (unsigned)tr.parent[k][s];
+    const double* a = arow + (size_t)s * Rk;
+    const double* src = Pprev + (size_t)p * Wp + cq;
     double acc = 0.0;
-    for (int r = 0; r < Rk; ++r) acc = fma(a[r], src[(int64_t)r * W], acc);
+#pragma unroll 4
+    for (int r = 0; r < Rk; ++r) acc = fma(a[r], src[r * W], acc);
     Pout[e] = acc;
   }
 }
 
 // Rows and the last adjoint level, fused.  A group of G lanes (power of two
 // >= R_{N-1}) owns one (level-(N-1) node p, rhs q); lane r keeps P[p][r][q] and
-// accumulates Q[p][r][q] over the children rows of p.
+// accumulates Q[p][r][q] over the children rows of p, four rows per step.
 template <int G>
 __global__ void __launch_bounds__(256) k_rows_adj(ModeTables T, Geom g, Tree tr,
                                                  const double* __restrict__ Pprev,
@@ -57,7 +72,7 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables T, Geom g, Tree tr,
   if (st->all_done) return;
   const int N = g.N, nrhs = g.nrhs;
   const int R = g.R[N - 1];
-  const double* __restrict__ A = T.A[N - 1];
+  const double* __restrict__ AL = tr.arow[N];
   const int64_t Sp = tr.cnt[N - 1];
   const int lane = threadIdx.x & (G - 1);
   const int64_t ngroups_total = Sp * nrhs;
@@ -67,96 +82,196 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables T, Geom g, Tree tr,
     const bool active = grp < ngroups_total;
     const int64_t p = active ? grp / nrhs : 0;
     const int q = active ? (int)(grp - p * nrhs) : 0;
-    const double pv = (active && lane < R) ? Pprev[(p * R + lane) * nrhs + q] : 0.0;
+    const bool ln = active && lane < R;
+    const double pv = ln ? Pprev[(p * R + lane) * nrhs + q] : 0.0;
     double acc = 0.0;
     const int j0 = active ? tr.fchild[N - 1][p] : 0;
     const int j1 = active ? tr.fchild[N - 1][p + 1] : 0;
-    for (int j = j0; j < j1; ++j) {
-      const double a = lane < R ? A[(int64_t)tr.idx[N][j] * R + lane] : 0.0;
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      double av[4], y[4], om[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = ln ? AL[(int64_t)(j + u) * R + lane] : 0.0;
+        om[u] = Omega[j + u];
+        bb[u] = bD[(int64_t)(j + u) * nrhs + q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = av[u] * pv;
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, G);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = fma(om[u] * (y[u] - bb[u]), av[u], acc);
+    }
+    for (; j < j1; ++j) {
+      const double a = ln ? AL[(int64_t)j * R + lane] : 0.0;
       double y = a * pv;
 #pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, G);
-      const double w = Omega[j] * (y - bD[(int64_t)j * nrhs + q]);
-      acc = fma(w, a, acc);
+      acc = fma(Omega[j] * (y - bD[(int64_t)j * nrhs + q]), a, acc);
     }
-    if (active && lane < R) Qout[(p * R + lane) * nrhs + q] = acc;
+    if (ln) Qout[(p * R + lane) * nrhs + q] = acc;
   }
 }
 
-// Adjoint level k (k = N-1 .. 1): Q_{k-1}[p][r][c][q] = sum_s a_{k-1}[i(s)][r] Q_k[s][c][q].
+// Adjoint level k (k = N-1 .. 2): Q_{k-1}[p][r][c][q] = sum_s a_{k-1}[i(s)][r] Q_k[s][c][q].
 __global__ void __launch_bounds__(256) k_adj_level(ModeTables T, Geom g, Tree tr, int k,
                                                   const double* __restrict__ Qk,
                                                   double* __restrict__ Qout,
                                                   const IterState* __restrict__ st) {
   if (st->all_done) return;
-  const int64_t Sp = tr.cnt[k - 1];
-  const int64_t W = g.rsuf[k] * g.nrhs;
-  const int64_t Wp = g.rsuf[k - 1] * g.nrhs;
+  const unsigned Sp = (unsigned)tr.cnt[k - 1];
+  const unsigned W = (unsigned)(g.rsuf[k] * g.nrhs);
+  const unsigned Wp = (unsigned)(g.rsuf[k - 1] * g.nrhs);
   const int Rk = g.R[k - 1];
-  const double* __restrict__ A = T.A[k - 1];
-  const int64_t total = Sp * Wp;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = e / Wp, rem = e - p * Wp;
-    const int r = (int)(rem / W);
-    const int64_t cq = rem - (int64_t)r * W;
+  const double* __restrict__ arow = tr.arow[k];
+  const unsigned total = Sp * Wp;
+  const unsigned step = gridDim.x * blockDim.x;
+  const unsigned e0 = blockIdx.x * blockDim.x + threadIdx.x;
+  GDiv di(e0, Wp, step);
+  for (unsigned e = e0; e < total; e += step, di.next()) {
+    const unsigned p = di.q, rem = di.r;
+    const unsigned r = rem / W, cq = rem - r * W;
     const int s0 = tr.fchild[k - 1][p], s1 = tr.fchild[k - 1][p + 1];
     double acc = 0.0;
-    for (int s = s0; s < s1; ++s)
-      acc = fma(A[(int64_t)tr.idx[k][s] * Rk + r], Qk[(int64_t)s * W + cq], acc);
+    int s = s0;
+    for (; s + 4 <= s1; s += 4) {
+      double av[4], qv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = arow[(size_t)(s + u) * Rk + r];
+        qv[u] = Qk[(size_t)(s + u) * W + cq];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = fma(av[u], qv[u], acc);
+    }
+    for (; s < s1; ++s) acc = fma(arow[(size_t)s * Rk + r], Qk[(size_t)s * W + cq], acc);
     Qout[e] = acc;
   }
 }
 
+// Root adjoint, split over blocks of level-1 nodes: partial[b][r0][c] =
+// sum_{s in block b} a_0[i(s)][r0] Q_1[s][c].  Workgroup (column block, node block)
+// stages its node block's factor rows and Q_1 columns in LDS.
+#define RA_NODES 32
+__global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const double* __restrict__ Q1,
+                                                         double* __restrict__ partial,
+                                                         const IterState* __restrict__ st) {
+  if (st->all_done) return;
+  __shared__ double as[RA_NODES * 64];
+  __shared__ double qs[RA_NODES * 256];
+  const unsigned S1 = (unsigned)tr.cnt[1];
+  const int R0 = g.R[0];
+  const unsigned W1 = (unsigned)(g.rsuf[1] * g.nrhs);
+  const unsigned CE = R0 >= 256 ? 1u : 256u / (unsigned)R0;
+  const unsigned ncb = (W1 + CE - 1) / CE;
+  const unsigned nnb = (S1 + RA_NODES - 1) / RA_NODES;
+  for (unsigned task = blockIdx.x; task < ncb * nnb; task += gridDim.x) {
+    const unsigned cb = task % ncb, nbk = task / ncb;
+    const unsigned e0 = cb * CE, s0 = nbk * RA_NODES;
+    const unsigned ns = (S1 - s0) < RA_NODES ? (S1 - s0) : RA_NODES;
+    for (unsigned i = threadIdx.x; i < ns * (unsigned)R0; i += blockDim.x) as[i] = tr.arow[1][(size_t)s0 * R0 + i];
+    for (unsigned i = threadIdx.x; i < ns * CE; i += blockDim.x) {
+      const unsigned sn = i / CE, c = i - sn * CE;
+      qs[i] = e0 + c < W1 ? Q1[(size_t)(s0 + sn) * W1 + e0 + c] : 0.0;
+    }
+    __syncthreads();
+    const unsigned r0 = threadIdx.x / CE, c = threadIdx.x - r0 * CE;
+    if (r0 < (unsigned)R0 && e0 + c < W1) {
+      double acc = 0.0;
+      for (unsigned sn = 0; sn < ns; ++sn) acc = fma(as[sn * R0 + r0], qs[sn * CE + c], acc);
+      partial[(size_t)nbk * g.Rtot * g.nrhs + (size_t)r0 * W1 + e0 + c] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// g = sum over node blocks of the partials, in block order (deterministic).
+__global__ void __launch_bounds__(256) k_adj_root_sum(Geom g, Tree tr, const double* __restrict__ partial,
+                                                     double* __restrict__ grad, const IterState* __restrict__ st) {
+  if (st->all_done) return;
+  const unsigned S1 = (unsigned)tr.cnt[1];
+  const unsigned nnb = (S1 + RA_NODES - 1) / RA_NODES;
+  const size_t RT = (size_t)g.Rtot * g.nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < RT; e += (size_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (unsigned b = 0; b < nnb; ++b) acc += partial[(size_t)b * RT + e];
+    grad[e] = acc;
+  }
+}
+
 // Mode product inside one workgroup: out = in x_n M, M is R_n x R_n (M[a][b]),
-// transposed when trans != 0.  Tensor layout [R_0..R_{N-1}][nrhs].
+// transposed when trans != 0.  Tensor layout [R_0..R_{N-1}][nrhs].  Each thread
+// owns whole mode-n fibres: it reads the fibre once into registers and forms all
+// R_n outputs.
+template <int RM>
+__device__ void wg_mode_fibre(const Geom& g, int n, const double* __restrict__ M, int trans,
+                              const double* in, double* out) {
+  const int Rn = g.R[n];
+  const unsigned post = (unsigned)(g.rsuf[n + 1] * g.nrhs);
+  const unsigned nfib = (unsigned)(g.Rtot * g.nrhs) / (unsigned)Rn;
+  GDiv di(threadIdx.x, post, blockDim.x);
+  for (unsigned f = threadIdx.x; f < nfib; f += blockDim.x, di.next()) {
+    const size_t base = (size_t)di.q * Rn * post + di.r;
+    double v[RM];
+#pragma unroll
+    for (int b = 0; b < RM; ++b) v[b] = b < Rn ? in[base + (size_t)b * post] : 0.0;
+    for (int a = 0; a < Rn; ++a) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < RM; ++b)
+        if (b < Rn) acc = fma(trans ? M[b * Rn + a] : M[a * Rn + b], v[b], acc);
+      out[base + (size_t)a * post] = acc;
+    }
+  }
+}
+
 __device__ void wg_mode_product(const Geom& g, int n, const double* __restrict__ M, int trans,
                                 const double* in, double* out) {
   const int Rn = g.R[n];
-  const int64_t post = g.rsuf[n + 1] * g.nrhs;
-  const int64_t total = g.Rtot * g.nrhs;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int64_t blk = e / (Rn * post);
-    const int64_t rem = e - blk * Rn * post;
-    const int a = (int)(rem / post);
-    const int64_t c = rem - (int64_t)a * post;
-    const double* src = in + blk * Rn * post + c;
-    double acc = 0.0;
-    for (int b = 0; b < Rn; ++b) {
-      const double mab = trans ? M[b * Rn + a] : M[a * Rn + b];
-      acc = fma(mab, src[(int64_t)b * post], acc);
-    }
-    out[e] = acc;
-  }
+  if (Rn <= 8) wg_mode_fibre<8>(g, n, M, trans, in, out);
+  else if (Rn <= 16) wg_mode_fibre<16>(g, n, M, trans, in, out);
+  else if (Rn <= 32) wg_mode_fibre<32>(g, n, M, trans, in, out);
+  else wg_mode_fibre<64>(g, n, M, trans, in, out);
 }
 
 // d = M^+ (g + lambda x); x <- x - eta d for right-hand sides not yet converged;
 // per-RHS norms, stopping rule eta ||d|| <= tol ||x||, divergence test.
-// One workgroup of 1024 threads.  t0/t1 are Rtot x nrhs scratch buffers.
+// One workgroup of 1024 threads.  t0/t1 are Rtot x nrhs scratch buffers; each
+// factor matrix is staged in LDS before its mode product.
 __global__ void __launch_bounds__(1024) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
                                                         double* __restrict__ x, double* __restrict__ t0,
                                                         double* __restrict__ t1, double lambda, double eta,
                                                         double tol, int max_iter, int use_ginv,
                                                         IterState* __restrict__ st) {
   __shared__ double red[16];
+  __shared__ double ms[64 * 64];
   if (st->all_done) return;
   const int64_t total = g.Rtot * g.nrhs;
   for (int64_t e = threadIdx.x; e < total; e += blockDim.x) t0[e] = grad[e] + lambda * x[e];
-  __syncthreads();
   double* cur = t0;
   double* nxt = t1;
+  auto stage = [&](const double* M, int n) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < g.R[n] * g.R[n]; e += blockDim.x) ms[e] = M[e];
+    __syncthreads();
+  };
   if (use_ginv) {
     for (int n = 0; n < g.N; ++n) {
-      wg_mode_product(g, n, T.Ginv[n], 0, cur, nxt);
-      __syncthreads();
+      stage(T.Ginv[n], n);
+      wg_mode_product(g, n, ms, 0, cur, nxt);
       double* tmp = cur; cur = nxt; nxt = tmp;
     }
   } else {
     for (int n = 0; n < g.N; ++n) {
-      wg_mode_product(g, n, T.V[n], 1, cur, nxt);
-      __syncthreads();
+      stage(T.V[n], n);
+      wg_mode_product(g, n, ms, 1, cur, nxt);
       double* tmp = cur; cur = nxt; nxt = tmp;
     }
+    __syncthreads();
     for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
       int64_t r = e / g.nrhs;
       double prod = 1.0;
@@ -168,13 +283,13 @@ __global__ void __launch_bounds__(1024) k_precond_update(ModeTables T, Geom g, c
       const double den = prod + lambda;
       cur[e] = den > 0.0 ? cur[e] / den : 0.0;
     }
-    __syncthreads();
     for (int n = 0; n < g.N; ++n) {
-      wg_mode_product(g, n, T.V[n], 0, cur, nxt);
-      __syncthreads();
+      stage(T.V[n], n);
+      wg_mode_product(g, n, ms, 0, cur, nxt);
       double* tmp = cur; cur = nxt; nxt = tmp;
     }
   }
+  __syncthreads();
   // cur = d.  Update and norms per right-hand side.
   const int it = st->iters;
   int all = 1, div = 0;

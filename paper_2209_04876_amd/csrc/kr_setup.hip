@@ -57,14 +57,17 @@ __global__ void __launch_bounds__(256) k_gram(ModeTables T, Geom g, double* __re
   for (int pq = threadIdx.x; pq < R * R && k < npair; pq += blockDim.x, ++k) G[pq] = acc[k];
 }
 
-// One wave per mode.  Cyclic-by-row Jacobi rotations on the symmetric Gram
-// matrix held in LDS; lanes update the rows/columns touched by a rotation in
-// parallel.  A rotation is skipped when |a_pq| is below rounding relative to
+// One wave per mode.  Two-sided Jacobi with the round-robin (tournament)
+// ordering: each round applies floor(R/2) disjoint rotations at once (columns
+// A <- A J and V <- V J, then rows A <- J^T A); R-1 rounds make a sweep.  A
+// rotation is skipped when |a_pq| is below rounding relative to
 // sqrt(|a_pp a_qq|); sweeps stop when a sweep performs no rotation.
 __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* __restrict__ gram,
                                             int32_t* __restrict__ flags) {
   __shared__ double a[KR_RMAX * KR_RMAX];
   __shared__ double v[KR_RMAX * KR_RMAX];
+  __shared__ double cs_c[KR_RMAX / 2], cs_s[KR_RMAX / 2];
+  __shared__ int cs_p[KR_RMAX / 2], cs_q[KR_RMAX / 2];
   __shared__ int rotated;
   const int n = blockIdx.x;
   const int R = g.R[n], I = g.I[n];
@@ -74,40 +77,64 @@ __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* 
     a[e] = G[e];
     v[e] = (e / R == e % R) ? 1.0 : 0.0;
   }
+  const int mpl = (R & 1) ? R + 1 : R;   // players in the round-robin (dummy = R when odd)
+  const int npair = mpl / 2;
   __syncthreads();
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  for (int sweep = 0; sweep < 60 && R > 1; ++sweep) {
     if (lane == 0) rotated = 0;
     __syncthreads();
-    for (int p = 0; p < R - 1; ++p) {
-      for (int q = p + 1; q < R; ++q) {
-        const double apq = a[p * R + q], app = a[p * R + p], aqq = a[q * R + q];
-        const bool skip = fabs(apq) <= 1e-17 * sqrt(fabs(app * aqq)) || apq == 0.0;
-        __syncthreads();
-        if (skip) continue;
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = lane; k < R; k += 64) {
-          if (k != p && k != q) {
-            const double akp = a[k * R + p], akq = a[k * R + q];
-            const double nkp = c * akp - s * akq, nkq = s * akp + c * akq;
-            a[k * R + p] = nkp; a[p * R + k] = nkp;
-            a[k * R + q] = nkq; a[q * R + k] = nkq;
+    for (int round = 0; round < mpl - 1; ++round) {
+      if (lane < npair) {
+        int p, q;
+        if (lane == 0) { p = mpl - 1; q = round; }
+        else { p = (round + lane) % (mpl - 1); q = (round - lane + (mpl - 1)) % (mpl - 1); }
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, sn = 0.0;
+        bool act = q < R;
+        if (act) {
+          const double apq = a[p * R + q], app = a[p * R + p], aqq = a[q * R + q];
+          if (apq == 0.0 || fabs(apq) <= 1e-17 * sqrt(fabs(app * aqq))) {
+            act = false;
+          } else {
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+            rotated = 1;
           }
-          const double vkp = v[k * R + p], vkq = v[k * R + q];
-          v[k * R + p] = c * vkp - s * vkq;
-          v[k * R + q] = s * vkp + c * vkq;
         }
-        if (lane == 0) {
-          a[p * R + p] = app - t * apq;
-          a[q * R + q] = aqq + t * apq;
-          a[p * R + q] = 0.0; a[q * R + p] = 0.0;
-          rotated = 1;
-        }
-        __syncthreads();
+        cs_c[lane] = c; cs_s[lane] = sn;
+        cs_p[lane] = act ? p : -1; cs_q[lane] = q;
       }
+      __syncthreads();
+      // columns of A and V: for row i and pair k
+      for (int e = lane; e < R * npair; e += 64) {
+        const int k = e % npair, i = e / npair;
+        const int p = cs_p[k];
+        if (p < 0) continue;
+        const int q = cs_q[k];
+        const double c = cs_c[k], sn = cs_s[k];
+        const double aip = a[i * R + p], aiq = a[i * R + q];
+        a[i * R + p] = c * aip - sn * aiq;
+        a[i * R + q] = sn * aip + c * aiq;
+        const double vip = v[i * R + p], viq = v[i * R + q];
+        v[i * R + p] = c * vip - sn * viq;
+        v[i * R + q] = sn * vip + c * viq;
+      }
+      __syncthreads();
+      // rows of A: for column j and pair k
+      for (int e = lane; e < R * npair; e += 64) {
+        const int k = e % npair, j = e / npair;
+        const int p = cs_p[k];
+        if (p < 0) continue;
+        const int q = cs_q[k];
+        const double c = cs_c[k], sn = cs_s[k];
+        const double apj = a[p * R + j], aqj = a[q * R + j];
+        a[p * R + j] = c * apj - sn * aqj;
+        a[q * R + j] = sn * apj + c * aqj;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (!rotated) break;
   }
   __syncthreads();
@@ -185,13 +212,13 @@ __global__ void __launch_bounds__(256) k_leverage(ModeTables T, Geom g, int32_t*
     if (threadIdx.x == 0) atomicOr(flags, KR_FLAG_QUANT);
     return;
   }
-  // Q_i = max(1, floor(2^32 l_i / S)) for l_i > 0; exact integer sum and argmax
+  // Q_i = max(1, nearest integer to 2^32 l_i / S) for l_i > 0; exact integer sum and argmax
   unsigned long long qsum = 0ull, best = 0ull;
   for (int i = threadIdx.x; i < I; i += blockDim.x) {
     const double l = lev[i];
     uint64_t q = 0;
     if (l > 0.0) {
-      q = (uint64_t)floor((l / S) * 4294967296.0);
+      q = (uint64_t)floor((l / S) * 4294967296.0 + 0.5);
       if (q < 1) q = 1;
     }
     Q[i] = q;

@@ -80,27 +80,28 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __r
   hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of n uint32 values in place, one workgroup of 1024 threads.
+// Exclusive scan of n uint32 values in place, one workgroup of 1024 threads:
+// each thread scans a contiguous chunk, chunk totals are scanned in LDS.
 __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int64_t n) {
   __shared__ uint32_t s[1024];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t b = (int64_t)threadIdx.x * chunk;
+  const int64_t e = b + chunk < n ? b + chunk : n;
+  uint32_t tot = 0;
+  for (int64_t i = b; i < e; ++i) tot += v[i];
+  s[threadIdx.x] = tot;
   __syncthreads();
-  for (int64_t base = 0; base < n; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t x = i < n ? v[i] : 0u;
-    s[threadIdx.x] = x;
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (i < n) v[i] = carry + s[threadIdx.x] - x;
+    s[threadIdx.x] += add;
     __syncthreads();
-    if (threadIdx.x == 0) carry += s[1023];
-    __syncthreads();
+  }
+  uint32_t run = s[threadIdx.x] - tot;
+  for (int64_t i = b; i < e; ++i) {
+    const uint32_t x = v[i];
+    v[i] = run;
+    run += x;
   }
 }
 
@@ -270,6 +271,20 @@ __global__ void __launch_bounds__(SORT_THREADS) k_tree_emit(const uint64_t* __re
       }
     }
     for (int k = 1; k <= g.N; ++k) excl[k] += (f >> k) & 1u;
+  }
+}
+
+// Gather the factor row of every tree node: arow[k][s][r] = A_{k-1}[idx[k][s]][r].
+__global__ void __launch_bounds__(256) k_node_rows(ModeTables T, Geom g, Tree tr) {
+  for (int k = 1; k <= g.N; ++k) {
+    const int R = g.R[k - 1];
+    const int64_t total = tr.cnt[k] * R;
+    const double* __restrict__ A = T.A[k - 1];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t s = e / R;
+      tr.arow[k][e] = A[(int64_t)tr.idx[k][s] * R + (e - s * R)];
+    }
   }
 }
 

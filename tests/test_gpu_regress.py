@@ -153,3 +153,18 @@ def test_sketch_failure_detected(gpu_lib):
     with pytest.raises(gpu_lib.KronRegressError) as e:
         gpu_lib.kron_regress(tA, tb, m=1)
     assert e.value.status == -5
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[6], CASES[8], CASES[9]], ids=lambda c: c[0])
+def test_cooperative_iteration_matches(gpu_lib, case):
+    # the single cooperative launch (grid barriers) reaches the same sketched
+    # minimiser as the one-kernel-per-phase iteration
+    name, I, R, m, nrhs, lam, heavy = case
+    print("case cooperative", name, flush=True)
+    w = workloads.random_problem(I, R, seed=zlib.crc32(name.encode()) % 1000, nrhs=nrhs, heavy=heavy)
+    tA, tb = _torch_inputs(w["As"], w["b"])
+    xm, im = gpu_lib.kron_ridge(tA, tb, lam, m=m, seed=7, stream=3, tol=1e-12, max_iter=400,
+                                cooperative=True)
+    xp, ip = gpu_lib.kron_ridge(tA, tb, lam, m=m, seed=7, stream=3, tol=1e-12, max_iter=400)
+    assert im["status"] == ip["status"] == "OK"
+    assert rel_l2(xm.cpu().numpy(), xp.cpu().numpy()) < 1e-11
