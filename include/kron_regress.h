@@ -129,11 +129,29 @@ kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void*
  * Writes d_x (float64, prod(R) x nrhs). */
 kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x);
 
+/* Algorithm 3 (FastFactorMatrixUpdate): the ALS update of factor `mode` of a
+ * Tucker decomposition (Theorem fast_factor_matrix_update).  p->A[0..N-1] are the
+ * current factors (A[mode] supplies only its shape), p->b is the tensor X
+ * (row-major I_1..I_N, dtype p->b_dtype), p->nrhs must be 1; d_core is the core
+ * G (float64, row-major R_1..R_N).  Every row i of the new factor is the
+ * (1+eps)-approximate solution of min_y ||K G_(n)^T y - X_(n)[i]||^2 + lambda ||y||^2
+ * (K = Kronecker product of the other factors) from its own leverage sketch of K
+ * with opts->m samples (0 selects ceil(1680 R' ln(40 R') ln(I_n/delta)/eps),
+ * R' = prod_{m != n} R_m), drawn with Philox counter word 2 = row.  Writes
+ * d_A_out (I_mode x R_mode float64; may alias p->A[mode]).  h_info: iters = max
+ * over rows, distinct_rows = sum over rows.  KR_ESINGULAR when G_(n) G_(n)^T is
+ * singular.  eps in (0, 1/3) for the guarantee.  Limits: prod_{m != n} R_m <= 2048. */
+kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode,
+                               double lambda, double eps, double delta, const kr_opts* opts,
+                               void* d_A_out, kr_info* h_info);
+
 /* Test support: copy the last solve's sketch to host memory.  Any pointer may be
- * NULL.  h_Q: sum_n I_n uint64 integer weights (mode-major); h_keys: distinct
+ * NULL.  h_Q: sum_n I_n uint64 integer weights (mode-major); h_rows: distinct
  * rows as per-mode indices, D x N int32 (sorted by linear row index); h_Omega: D
  * float64 merged weights; h_counts: D int32 multiplicities.  cap is the capacity
- * in distinct rows; *h_D receives D. */
+ * in distinct rows; *h_D receives D.  After tucker_factor_update the first
+ * index of every distinct row is the factor row it belongs to and h_Q holds the
+ * weights of the other modes (entries of the row pseudo-mode are zero). */
 kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega,
                            int32_t* h_counts, int64_t cap, int64_t* h_D);
 

@@ -10,6 +10,7 @@ Functions mirror the C entry points:
   kron_ridge(As, b, lam, eps, ...)         Algorithm 2 with L2 regularisation
   kron_loss(As, b, x, lam)                 ||K x - b||^2 + lam ||x||^2 (float64)
   kron_exact(As, b, lam)                   exact KronMatMul optimum
+  tucker_factor_update(X, As, G, mode, lam) Algorithm 3 (Tucker ALS factor update)
   export_sketch(handle)                    last solve's sketch (tests)
 """
 
@@ -79,13 +80,14 @@ def load_library(path=LIB_PATH):
     lib.kron_ridge.argtypes = [c_p, P, c_d, c_d, c_d, O, c_p, IN]
     lib.kron_loss.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d)]
     lib.kron_exact.argtypes = [c_p, P, c_d, c_p]
+    lib.tucker_factor_update.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_d, c_d, O, c_p, IN]
     lib.kr_export_sketch.argtypes = [c_p, c_p, c_p, c_p, c_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.kr_profile_enable.argtypes = [c_p, ctypes.c_int32, ctypes.c_char_p]
     lib.kr_profile_query.argtypes = [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(c_d)]
     lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
     for name in ("kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_loss",
-                 "kron_exact", "kr_export_sketch"):
+                 "kron_exact", "kr_export_sketch", "tucker_factor_update"):
         getattr(lib, name).restype = c_i
     _lib = lib
     return lib
@@ -239,6 +241,27 @@ def kron_exact(As, b, lam=0.0, handle=None):
     return x
 
 
+def tucker_factor_update(X, As, G, mode, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=400,
+                         tol=1e-12, check_every=8, handle=None, out=None):
+    """Algorithm 3: the new factor `mode` (float64 I_mode x R_mode) and an info dict.
+
+    X: contiguous CUDA tensor with the full tensor (row-major); As: the N current
+    factors (A[mode] supplies its shape); G: the core, float64, shape R_1..R_N."""
+    torch = _torch()
+    h = handle or default_handle()
+    p, _keep = _problem(As, X.reshape(-1))
+    if G.dtype != torch.float64 or not G.is_contiguous() or not G.is_cuda:
+        raise ValueError("core must be a contiguous float64 CUDA tensor")
+    if out is None:
+        out = torch.empty(As[mode].shape, dtype=torch.float64, device=As[mode].device)
+    info = Info()
+    st = h.lib.tucker_factor_update(h.ptr, ctypes.byref(p), ctypes.c_void_p(G.data_ptr()), mode, lam, eps, delta,
+                                    ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every)),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.byref(info))
+    h._check(st)
+    return out, info.as_dict()
+
+
 def profile_enable(enable=True, kernel_filter="", handle=None):
     """Bracket kernel launches whose name contains kernel_filter ("" = all) with HIP
     events on the handle's stream (clears old records)."""
@@ -287,5 +310,6 @@ def export_sketch(sizes, handle=None, cap=None):
 
 
 __all__ = ["Handle", "KronRegressError", "kron_regress", "kron_ridge", "kron_loss", "kron_exact",
+           "tucker_factor_update",
            "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query",
            "profile_names", "profile_breakdown"]

@@ -18,6 +18,7 @@
 #include "kr_iter.hip"
 #include "kr_stream.hip"
 #include "kr_persist.hip"
+#include "kr_tucker.hip"
 
 using namespace kr;
 
@@ -369,6 +370,67 @@ static size_t solve_bytes(const Geom& g, int ntiles, int nblocks) {
   return b + 64 * 256 + 4096;
 }
 
+
+// Stable LSD radix sort of the g.m packed keys (8-bit digits over g.keybits) and
+// the per-level run-length encoding into the sample tree.
+static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_t* keys_alt, uint32_t* hist,
+                             int64_t* tiletot, int nblocks, const Tree& tr) {
+  hipStream_t s = h->stream;
+  const int64_t m = g.m;
+  uint64_t* kin = keys;
+  uint64_t* kout = keys_alt;
+  for (int sh = 0; sh < g.keybits; sh += 8) {
+    KL(h, k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
+    KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
+    KL(h, k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist, nblocks);
+    std::swap(kin, kout);
+  }
+  KL(h, k_tree_count, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot);
+  KL(h, k_tree_scan, dim3(1), dim3(64), 0, s, tiletot, nblocks, g, tr);
+  KL(h, k_tree_sentinels, dim3(1), dim3(64), 0, s, g, tr);
+  KL(h, k_tree_emit, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot, tr);
+}
+
+// One pass of the sampled products K~^T Omega (K~ x - b~) down and up the sample
+// tree: forward levels 1..N-1, the rows with the last adjoint level, adjoint
+// levels N-1..2, and (without segment roots) the root adjoint into Q[0].
+// P[0] is the iterate; Q[k] receives level-k results.
+static void launch_level_products(kr_handle h, const ModeTables& T, const Geom& g, const Tree& tr, double* const* P,
+                                  double* const* Q, const double* Omega, const double* bD, double* part,
+                                  const IterState* state) {
+  hipStream_t s = h->stream;
+  for (int k = 1; k < g.N; ++k) {
+    const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
+    KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k, (const double*)P[k - 1], P[k],
+       state);
+  }
+  const int Rl = g.R[g.N - 1];
+  const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
+  const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
+  double* qlast = Q[g.N - 1];
+  const double* plast = P[g.N - 1];
+  const dim3 rg(grid_for(rows_threads, 256));
+  switch (G) {
+    case 8: KL(h, k_rows_adj<8>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
+    case 16: KL(h, k_rows_adj<16>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
+    case 32: KL(h, k_rows_adj<32>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
+    default: KL(h, k_rows_adj<64>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
+  }
+  for (int k = g.N - 1; k >= 2; --k) {
+    const int64_t work = level_cap(g, k - 1) * g.rsuf[k - 1] * g.nrhs;
+    KL(h, k_adj_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k, (const double*)Q[k], Q[k - 1], state);
+  }
+  if (g.N >= 2 && !g.seg_root) {
+    const int64_t CEr = g.R[0] >= 256 ? 1 : 256 / g.R[0];
+    const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
+    const int64_t nnb = (level_cap(g, 1) + RA_NODES - 1) / RA_NODES;
+    KL(h, k_adj_root_partial, dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr, (const double*)Q[1], part,
+       state);
+    KL(h, k_adj_root_sum, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr, (const double*)part, Q[0],
+       state);
+  }
+}
+
 static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
                        const kr_opts* opts, void* d_x, kr_info* info) {
   if (!h) return KR_EINVAL;
@@ -451,21 +513,8 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   const int in_lds = sumI * 8 <= 48 * 1024;
   KL(h, k_sample, dim3(grid_for(m, 256, 2048)), dim3(256), in_lds ? sumI * 8 : 0, s, T, g, o.seed,
                      o.stream, (uint64_t)0, in_lds, B.keys);
-  // -- stable LSD radix sort of the packed keys
-  uint64_t* kin = B.keys;
-  uint64_t* kout = B.keys_alt;
-  for (int sh = 0; sh < g.keybits; sh += 8) {
-    KL(h, k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, B.hist, nblocks);
-    KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, B.hist, (int64_t)256 * nblocks);
-    KL(h, k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, B.hist,
-                       nblocks);
-    std::swap(kin, kout);
-  }
-  // -- sample tree (distinct prefixes per level)
-  KL(h, k_tree_count, dim3(ntiles), dim3(SORT_THREADS), 0, s, kin, g, B.tiletot);
-  KL(h, k_tree_scan, dim3(1), dim3(64), 0, s, B.tiletot, ntiles, g, tr);
-  KL(h, k_tree_sentinels, dim3(1), dim3(64), 0, s, g, tr);
-  KL(h, k_tree_emit, dim3(ntiles), dim3(SORT_THREADS), 0, s, kin, g, B.tiletot, tr);
+  // -- stable radix sort and the sample tree (distinct prefixes per level)
+  launch_sort_tree(h, g, B.keys, B.keys_alt, B.hist, B.tiletot, nblocks, tr);
   KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
   KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype,
                      B.Omega, B.bD, B.counts, B.s.flags);
@@ -538,43 +587,12 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
       KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
     if (h->h_state->diverged == 2) KR_FAIL(h, KR_EHIP, "grid barrier timed out in the persistent iteration");
   } else {
-    const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
     int iters_enqueued = 0;
     bool flags_checked = false;
     while (iters_enqueued < max_iter) {
       const int chunk = std::min(check_every, max_iter - iters_enqueued);
       for (int it = 0; it < chunk; ++it) {
-        for (int k = 1; k < g.N; ++k) {
-          const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
-          KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
-                             (const double*)B.P[k - 1], B.P[k], (const IterState*)B.state);
-        }
-        double* qlast = g.N == 1 ? B.Q[0] : B.Q[g.N - 1];
-        const dim3 rg(grid_for(rows_threads, 256));
-        switch (G) {
-          case 8: KL(h, k_rows_adj<8>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                     (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-          case 16: KL(h, k_rows_adj<16>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                      (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-          case 32: KL(h, k_rows_adj<32>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                      (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-          default: KL(h, k_rows_adj<64>, rg, dim3(256), 0, s, T, g, tr, (const double*)B.P[g.N - 1],
-                                      (const double*)B.Omega, (const double*)B.bD, qlast, (const IterState*)B.state); break;
-        }
-        for (int k = g.N - 1; k >= 2; --k) {
-          const int64_t work = level_cap(g, k - 1) * g.rsuf[k - 1] * g.nrhs;
-          KL(h, k_adj_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k,
-                             (const double*)B.Q[k], B.Q[k - 1], (const IterState*)B.state);
-        }
-        if (g.N >= 2) {
-          const int64_t CEr = g.R[0] >= 256 ? 1 : 256 / g.R[0];
-          const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
-          const int64_t nnb = (level_cap(g, 1) + RA_NODES - 1) / RA_NODES;
-          KL(h, k_adj_root_partial, dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr,
-             (const double*)B.Q[1], B.part, (const IterState*)B.state);
-          KL(h, k_adj_root_sum, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr,
-             (const double*)B.part, B.Q[0], (const IterState*)B.state);
-        }
+        launch_level_products(h, T, g, tr, B.P, B.Q, B.Omega, B.bD, B.part, (const IterState*)B.state);
         KL(h, k_precond_update, dim3(1), dim3(1024), 0, s, T, g, (const double*)B.Q[0], (double*)d_x,
                            B.t0, B.t1, lambda, eta, tol, max_iter, lambda == 0.0 ? 1 : 0, B.state);
       }
@@ -652,7 +670,10 @@ kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* 
   if (h_Q) {
     int64_t off = 0;
     for (int n = 0; n < g.N; ++n) {
-      HIPCHK(h, hipMemcpy(h_Q + off, h->T.Q[n], g.I[n] * sizeof(uint64_t), hipMemcpyDeviceToHost));
+      if (h->T.Q[n])
+        HIPCHK(h, hipMemcpy(h_Q + off, h->T.Q[n], g.I[n] * sizeof(uint64_t), hipMemcpyDeviceToHost));
+      else
+        std::memset(h_Q + off, 0, g.I[n] * sizeof(uint64_t));
       off += g.I[n];
     }
   }
@@ -807,6 +828,232 @@ kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x)
   HIPCHK(h, hipStreamSynchronize(s));
   if ((int32_t)(h->h_small[0] & 0xFFFFFFFF) & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A");
   return KR_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Algorithm 3 (FastFactorMatrixUpdate) for one mode of Tucker ALS
+// ---------------------------------------------------------------------------
+kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode, double lambda,
+                               double eps, double delta, const kr_opts* opts, void* d_A_out, kr_info* info) {
+  if (!h) return KR_EINVAL;
+  Geom gx;   // the tensor X with its factors (validated like a regression problem)
+  kr_status st = make_geom(h, p, &gx);
+  if (st != KR_OK) return st;
+  if (p->N < 2) KR_FAIL(h, KR_EINVAL, "a factor update needs N >= 2");
+  if (mode < 0 || mode >= p->N) KR_FAIL(h, KR_EINVAL, "mode %d outside 0..%d", mode, p->N - 1);
+  if (p->nrhs != 1) KR_FAIL(h, KR_EINVAL, "the tensor is a single right-hand side");
+  if (!p->b || !d_core || !d_A_out) KR_FAIL(h, KR_EINVAL, "X, core or output is NULL");
+  if (!(eps > 0.0 && eps < 1.0)) KR_FAIL(h, KR_EINVAL, "eps=%g outside (0, 1)", eps);
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda=%g invalid", lambda);
+  const int N = p->N;
+  const int In = (int)p->I[mode], Rn = (int)p->R[mode];
+  // problem of the other factors (setup) and the sample-tree geometry (row first)
+  kr_problem po = *p;
+  po.N = N - 1;
+  TuckerGeom tg{};
+  tg.Nx = N;
+  tg.mode = mode;
+  tg.Rn = Rn;
+  for (int m = 0; m < N; ++m) tg.Ix[m] = (int)p->I[m];
+  tg.tmode[0] = mode;
+  int Rr = 1;
+  for (int m = 0, k = 0; m < N; ++m) {
+    if (m == mode) continue;
+    po.I[k] = p->I[m];
+    po.R[k] = p->R[m];
+    po.A[k] = p->A[m];
+    tg.tmode[k + 1] = m;
+    Rr *= (int)p->R[m];
+    ++k;
+  }
+  tg.Rr = Rr;
+  if (Rr > 2048) KR_FAIL(h, KR_EUNSUPPORTED, "prod_{m != n} R_m = %d > 2048", Rr);
+  Geom go;
+  st = make_geom(h, &po, &go);
+  if (st != KR_OK) return st;
+  kr_problem pt = po;  // tree geometry: pseudo-mode 0 = row, then the other modes
+  pt.N = N;
+  for (int k = N - 1; k >= 1; --k) { pt.I[k] = po.I[k - 1]; pt.R[k] = po.R[k - 1]; pt.A[k] = po.A[k - 1]; }
+  pt.I[0] = In;
+  pt.R[0] = 1;
+  pt.A[0] = p->A[mode];
+  Geom g;
+  st = make_geom(h, &pt, &g);
+  if (st != KR_OK) return st;
+  g.seg_root = 1;
+  kr_opts o{};
+  if (opts) o = *opts;
+  int64_t mrow = o.m;
+  if (mrow <= 0) {
+    if (!(delta > 0.0 && delta < 1.0)) KR_FAIL(h, KR_EINVAL, "delta=%g outside (0, 1)", delta);
+    const double Rd = (double)Rr;
+    const double sc = std::ceil(1680.0 * Rd * std::log(40.0 * Rd) * std::log((double)In / delta) / eps);
+    if (sc * In > 2.0e9) KR_FAIL(h, KR_EUNSUPPORTED, "theory sample count %.3g per row too large; pass opts.m", sc);
+    mrow = (int64_t)sc;
+  }
+  if ((double)mrow * In > 2.0e9) KR_FAIL(h, KR_EUNSUPPORTED, "rows x samples = %.3g too large", (double)mrow * In);
+  tg.m_row = mrow;
+  g.m = mrow * In;
+  go.m = g.m;
+  for (int k = 0; k <= g.N; ++k)
+    if ((double)level_cap(g, k) * (double)g.rsuf[k] >= 2147483647.0)
+      KR_FAIL(h, KR_EUNSUPPORTED, "level %d of the sample tree needs more than 2^31 entries", k);
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  const int check_every = o.check_every > 0 ? o.check_every : 8;
+  const double tol = o.tol > 0.0 ? o.tol : 1e-12;
+  const double eta = 1.0 - std::sqrt(eps);
+  const int64_t m = g.m;
+  const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
+
+  // workspace
+  size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * 256 * (size_t)nblocks +
+                8 * (size_t)nblocks * (KR_MAXN + 1) + 4096;
+  const int64_t Dcap = level_cap(g, g.N);
+  for (int k = 1; k <= g.N; ++k) need += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
+  need += (size_t)Dcap * (8 + 8 + 4) + 4 * (size_t)(Dcap + 2) + 8 * (size_t)Dcap + 2048;
+  for (int k = 1; k < g.N; ++k) need += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] + 512;
+  need += 8 * ((size_t)In * Rr + 3 * (size_t)Rn * Rr + (size_t)Rr * Rn + (size_t)Rn * Rn + 8) + 4 * 4 * (size_t)In +
+          8 * 2 * (size_t)In + sizeof(IterState) + 16 * 256;
+  st = ensure(h, &h->ws, &h->ws_bytes, need);
+  if (st != KR_OK) return st;
+  Arena a{(char*)h->ws, h->ws_bytes, 0};
+  ModeTables To{};
+  SetupBufs S{};
+  carve_setup(a, go, &To, &S);
+  uint64_t* keys = a.take<uint64_t>(m);
+  uint64_t* keys_alt = a.take<uint64_t>(m);
+  uint32_t* hist = a.take<uint32_t>((size_t)256 * nblocks);
+  int64_t* tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
+  Tree tr{};
+  for (int k = 1; k <= g.N; ++k) {
+    const int64_t c = level_cap(g, k);
+    tr.idx[k] = a.take<int32_t>(c + 2);
+    tr.parent[k] = a.take<int32_t>(c + 2);
+    tr.fchild[k] = a.take<int32_t>(c + 2);
+    tr.arow[k] = a.take<double>((size_t)c * g.R[k - 1]);
+  }
+  tr.fchild[0] = a.take<int32_t>(4);
+  tr.rstart = a.take<int32_t>(Dcap + 2);
+  tr.rkey = a.take<uint64_t>(Dcap + 1);
+  tr.cnt = a.take<int64_t>(KR_MAXN + 1);
+  double* Omega = a.take<double>(Dcap);
+  int32_t* counts = a.take<int32_t>(Dcap);
+  double* bD = a.take<double>(Dcap);
+  double* P[KR_MAXN + 1] = {};
+  double* Q[KR_MAXN + 1] = {};
+  for (int k = 1; k < g.N; ++k) {
+    P[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k]);
+    Q[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k]);
+  }
+  double* Z = a.take<double>((size_t)In * Rr);
+  P[0] = Z;
+  double* Gn = a.take<double>((size_t)Rn * Rr);
+  double* GtP = a.take<double>((size_t)Rn * Rr);
+  double* Vw = a.take<double>((size_t)Rn * Rr);
+  double* AinvU = a.take<double>((size_t)Rr * Rn);
+  double* Cinv = a.take<double>((size_t)Rn * Rn);
+  double* wbuf = a.take<double>(8);
+  int32_t* seg_done = a.take<int32_t>(In);
+  int32_t* seg_iters = a.take<int32_t>(In);
+  int32_t* counters = a.take<int32_t>(64);   // [0] rows done, [1] diverged
+  double* seg_rel = a.take<double>(In);
+  double* seg_d0 = a.take<double>(In);
+  IterState* state = a.take<IterState>(1);
+  if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
+
+  hipStream_t s = h->stream;
+  st = launch_setup(h, &po, go, To, S, true);
+  if (st != KR_OK) return st;
+  ModeTables T{};
+  for (int k = 1; k < g.N; ++k) {
+    T.A[k] = To.A[k - 1]; T.V[k] = To.V[k - 1]; T.evals[k] = To.evals[k - 1]; T.Ginv[k] = To.Ginv[k - 1];
+    T.lev[k] = To.lev[k - 1]; T.Q[k] = To.Q[k - 1]; T.C[k] = To.C[k - 1];
+  }
+  KL(h, k_tucker_setup, dim3(1), dim3(256), 0, s, T, g, tg, (const double*)d_core, lambda, eps, Gn, GtP, Vw, wbuf,
+     S.flags);
+  KL(h, k_tucker_ainvu, dim3(Rn), dim3(256), 2 * 8 * (size_t)Rr, s, T, g, tg, (const double*)GtP,
+     (const double*)wbuf, AinvU);
+  KL(h, k_tucker_cinv, dim3(1), dim3(256), 0, s, tg, (const double*)Vw, (const double*)AinvU, Cinv, S.flags);
+  KL(h, k_sample_rows, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, T, g, tg, o.seed, o.stream, keys);
+  launch_sort_tree(h, g, keys, keys_alt, hist, tiletot, nblocks, tr);
+  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
+  KL(h, k_rows_tucker, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tg, tr, p->b, p->b_dtype, Omega, bD,
+     counts, S.flags);
+  KL(h, k_fill, dim3(grid_for((int64_t)In * Rr, 256, 1024)), dim3(256), 0, s, Z, (int64_t)In * Rr, 0.0);
+  KL(h, k_zero_bytes, dim3(grid_for(In, 256, 64)), dim3(256), 0, s, (uint32_t*)seg_done, (int64_t)In);
+  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)counters, (int64_t)64);
+  KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)state, (int64_t)(sizeof(IterState) / 4));
+  HIPCHK(h, hipGetLastError());
+  int enq = 0;
+  bool checked = false;
+  while (enq < max_iter) {
+    const int chunk = std::min(check_every, max_iter - enq);
+    for (int it = 0; it < chunk; ++it) {
+      launch_level_products(h, T, g, tr, P, Q, Omega, bD, nullptr, (const IterState*)state);
+      KL(h, k_tucker_update, dim3(In), dim3(256), 3 * 8 * (size_t)Rr, s, T, g, tg, (const double*)Q[1], Z,
+         (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv, (const double*)wbuf, eta,
+         tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, counters, counters + 1, state);
+      KL(h, k_tucker_tick, dim3(1), dim3(64), 0, s, In, max_iter, (const int32_t*)counters,
+         (const int32_t*)(counters + 1), state);
+    }
+    enq += chunk;
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(h->h_state, state, sizeof(IterState), hipMemcpyDeviceToHost, s));
+    if (!checked) HIPCHK(h, hipMemcpyAsync(h->h_small, S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (!checked) {
+      checked = true;
+      const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
+      if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in the factors or X");
+      if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
+      if (fl & KR_FLAG_CORE) KR_FAIL(h, KR_ESINGULAR, "G_(n) G_(n)^T or the Woodbury matrix is singular");
+    }
+    if (h->h_state->all_done) break;
+  }
+  KL(h, k_tucker_rows_out, dim3(grid_for((int64_t)In * Rn, 256, 1024)), dim3(256), 0, s, tg, (const double*)Z,
+     (const double*)GtP, In, (double*)d_A_out);
+  HIPCHK(h, hipGetLastError());
+  // per-row status
+  std::vector<int32_t> done(In), its(In);
+  std::vector<double> rel(In);
+  int32_t cnt_h[2];
+  HIPCHK(h, hipMemcpyAsync(done.data(), seg_done, In * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(its.data(), seg_iters, In * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(rel.data(), seg_rel, In * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(cnt_h, counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  kr_status result = KR_OK;
+  bool all = true;
+  double relmax = 0.0;
+  int itmax = 0;
+  for (int i = 0; i < In; ++i) {
+    all = all && done[i];
+    relmax = std::max(relmax, rel[i]);
+    itmax = std::max(itmax, done[i] ? its[i] : h->h_state->iters);
+  }
+  if (cnt_h[1]) {
+    result = KR_EDIVERGED;
+    h->err = "Richardson iteration diverged for at least one row";
+  } else if (!all) {
+    result = KR_WMAXITER;
+    h->err = "iteration limit reached before every row met the stopping rule";
+  }
+  if (info) {
+    info->iters = itmax;
+    info->status = result;
+    info->m = m;
+    info->distinct_rows = h->h_small[8 + g.N];
+    info->rel_update = relmax;
+  }
+  h->has_sketch = true;
+  h->g = g;
+  h->T = T;
+  h->tr = tr;
+  h->Omega = Omega;
+  h->counts = counts;
+  return result;
 }
 
 }  // extern "C"

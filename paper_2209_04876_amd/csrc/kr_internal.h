@@ -32,6 +32,8 @@ struct Geom {
   int64_t Rtot;
   int64_t Itot;
   int64_t m;
+  int seg_root;         // 1: mode 0 indexes independent segments (no factor); the
+                        //    level-1 node of segment i reads its own iterate row i
 };
 
 // Per-mode results of the setup kernel.
@@ -84,6 +86,7 @@ enum : int32_t {
   KR_FLAG_NONFINITE = 1,
   KR_FLAG_SINGULAR = 2,
   KR_FLAG_QUANT = 4,
+  KR_FLAG_CORE = 8,     // the core unfolding G_(n) G_(n)^T (or the Woodbury C) is singular
 };
 
 // ---------------------------------------------------------------------------

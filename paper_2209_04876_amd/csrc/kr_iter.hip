@@ -47,6 +47,12 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables T, Geom g, Tree tr
   const unsigned step = gridDim.x * blockDim.x;
   const unsigned e0 = blockIdx.x * blockDim.x + threadIdx.x;
   GDiv di(e0, W, step);
+  if (k == 1 && g.seg_root) {
+    // segment roots: copy the segment's own iterate (Pprev is segments x W)
+    for (unsigned e = e0; e < total; e += step, di.next())
+      Pout[e] = Pprev[(size_t)tr.idx[1][di.q] * W + di.r];
+    return;
+  }
   for (unsigned e = e0; e < total; e += step, di.next()) {
     const unsigned s = di.q, cq = di.r;
     const unsigned p = k == 1 ? 0u : (unsigned)tr.parent[k][s];

@@ -1,0 +1,120 @@
+"""GPU parity of Algorithm 3 (tucker_factor_update) against the oracle.
+
+Per row: the sketch (Philox counter word 2 = row) must match the oracle's draw bit
+for bit; the updated factor row must match the oracle's direct solution of the
+penalised sketched row problem.  At the 400^3 tensor workload a sample of rows is
+checked the same way, and every row's objective against the exact row optimum."""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.kron import kron_explicit, tucker_reconstruct, unfold
+from oracle.regression import kron_rows
+from oracle.tucker import FactorUpdateSetup, exact_factor_update
+from parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _tensor_case(I, R, seed, noise=0.05):
+    rng = np.random.default_rng(seed)
+    As = [rng.standard_normal((i, r)) for i, r in zip(I, R)]
+    G = rng.standard_normal(R)
+    X = tucker_reconstruct(G, As) + noise * rng.standard_normal(I)
+    return X, As, G
+
+
+def _gpu(X, As, G, dtype=None):
+    import torch
+    dt = dtype or torch.float64
+    return (torch.tensor(X, dtype=dt, device="cuda").contiguous(),
+            [torch.tensor(A, device="cuda") for A in As],
+            torch.tensor(G, device="cuda").contiguous())
+
+
+def _check_rows(kr, X, As, G, n, lam, m, seed, stream, A_gpu, rows, xtol):
+    S = FactorUpdateSetup(As, G, n, lam, 0.1)
+    B = unfold(X, n)
+    I = list(X.shape)
+    sizes = [I[n]] + [I[k] for k in range(len(I)) if k != n]
+    sk = kr.export_sketch(sizes)
+    for k in range(1, len(sizes)):
+        np.testing.assert_array_equal(sk["Q"][k], S.Q[k - 1])
+    grows = sk["rows"]
+    worst = 0.0
+    for i in rows:
+        osk = S.row_sketch(m, seed, stream, i)
+        sel = grows[:, 0] == i
+        np.testing.assert_array_equal(grows[sel, 1:], osk["ridx"])
+        np.testing.assert_array_equal(sk["counts"][sel], osk["counts"])
+        np.testing.assert_allclose(sk["Omega"][sel], osk["Omega"], rtol=2e-16, atol=0)
+        KD = kron_rows(S.As_other, osk["ridx"])
+        z = S.row_direct(KD, osk["Omega"], B[i, osk["rows"]])
+        worst = max(worst, rel_l2(A_gpu[i], S.GtP @ z))
+    assert worst < xtol, worst
+    return worst
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_factor_update_small(gpu_lib, n):
+    print("case tucker small mode", n, flush=True)
+    X, As, G = _tensor_case((20, 18, 16), (3, 3, 2), seed=11 + n)
+    tX, tA, tG = _gpu(X, As, G)
+    lam, m = 0.05, 300
+    A_new, info = gpu_lib.tucker_factor_update(tX, tA, tG, n, lam, eps=0.1, m=m, seed=0, stream=5, tol=1e-13)
+    assert info["status"] == "OK", info
+    worst = _check_rows(gpu_lib, X, As, G, n, lam, m, 0, 5, A_new.cpu().numpy(), range(X.shape[n]), 1e-10)
+    print("worst row rel-L2 %.2e, iterations %d" % (worst, info["iters"]), flush=True)
+
+
+def test_factor_update_four_modes_f32(gpu_lib):
+    import torch
+    print("case tucker N=4 float32 tensor", flush=True)
+    X, As, G = _tensor_case((9, 8, 7, 6), (2, 3, 2, 2), seed=21)
+    X = X.astype(np.float32).astype(np.float64)
+    tX, tA, tG = _gpu(X, As, G, torch.float32)
+    tA = [torch.tensor(A, device="cuda") for A in As]
+    A_new, info = gpu_lib.tucker_factor_update(tX, tA, tG, 2, 0.1, m=250, seed=3, stream=1, tol=1e-13)
+    assert info["status"] == "OK", info
+    _check_rows(gpu_lib, X, As, G, 2, 0.1, 250, 3, 1, A_new.cpu().numpy(), range(7), 1e-10)
+
+
+def test_factor_update_singular_core(gpu_lib):
+    print("case tucker singular core", flush=True)
+    X, As, G = _tensor_case((10, 9, 8), (3, 2, 2), seed=31)
+    G[1] = G[0]                   # two equal mode-0 slices: G_(0) G_(0)^T is singular
+    tX, tA, tG = _gpu(X, As, G)
+    with pytest.raises(gpu_lib.KronRegressError) as e:
+        gpu_lib.tucker_factor_update(tX, tA, tG, 0, 0.1, m=100)
+    assert e.value.status == -4
+
+
+def test_factor_update_tucker_tensor_workload(gpu_lib):
+    """The 400^3 FP32 tensor, rank (16,16,16), lam = 1e-3, m = 14,196 per row."""
+    import torch
+    w = workloads.tucker_tensor()
+    print("case", w["name"], "m_factor", w["m_factor"], flush=True)
+    X = w["X"]
+    As = [A.copy() for A in w["A_init"]]
+    G = w["G_init"]
+    tX = torch.from_numpy(X).cuda()
+    tA = [torch.tensor(A, device="cuda") for A in As]
+    tG = torch.tensor(G, device="cuda")
+    n = 0
+    A_new, info = gpu_lib.tucker_factor_update(tX, tA, tG, n, w["lam"], eps=w["eps"], m=w["m_factor"],
+                                               seed=w["seed"], stream=7, tol=1e-12)
+    assert info["status"] == "OK", info
+    Xd = X.astype(np.float64)
+    An = A_new.cpu().numpy()
+    _check_rows(gpu_lib, Xd, As, G, n, w["lam"], w["m_factor"], w["seed"], 7, An, [0, 1, 199, 398, 399], 1e-9)
+    # every row within (1 + eps) of its exact optimum
+    exact = exact_factor_update(Xd, As, G, n, w["lam"])
+    K = None
+    S = FactorUpdateSetup(As, G, n, w["lam"], w["eps"])
+    D = np.kron(S.As_other[0], S.As_other[1]) @ S.Gn.T if K is None else K
+    B = unfold(Xd, n)
+    f = lambda y, i: np.sum((D @ y - B[i]) ** 2) + w["lam"] * y @ y
+    ratios = np.array([f(An[i], i) / f(exact[i], i) for i in range(X.shape[0])])
+    print("row objective ratio: max %.4f median %.5f" % (ratios.max(), np.median(ratios)), flush=True)
+    assert ratios.max() <= 1 + w["eps"]
