@@ -11,6 +11,7 @@ Functions mirror the C entry points:
   kron_loss(As, b, x, lam)                 ||K x - b||^2 + lam ||x||^2 (float64)
   kron_exact(As, b, lam)                   exact KronMatMul optimum
   tucker_factor_update(X, As, G, mode, lam) Algorithm 3 (Tucker ALS factor update)
+  tucker_als(X, G, As, lam, sweeps)        Algorithm 1 sequenced over the calls above
   export_sketch(handle)                    last solve's sketch (tests)
 """
 
@@ -262,6 +263,37 @@ def tucker_factor_update(X, As, G, mode, lam, eps=0.1, delta=0.01, m=0, seed=0, 
     return out, info.as_dict()
 
 
+def als_stream(sweep, step):
+    """Philox stream of ALS step `step` (mode n, or N for the core) of a sweep."""
+    return (int(sweep) << 8) | int(step)
+
+
+def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, handle=None, tol=1e-12):
+    """Algorithm 1 (TuckerALS) driven through the C ABI: for every sweep, the
+    factor updates of Algorithm 3 in mode order, then the core update by
+    Algorithm 2 (kron_ridge with b = vec(X)), and the relative reconstruction
+    error ||X^ - X||^2 / ||X||^2 from kron_loss.  X, G and the factors are CUDA
+    tensors (G and the factors float64); returns (G, As, [rre per sweep])."""
+    torch = _torch()
+    h = handle or default_handle()
+    As = [A.clone() for A in As]
+    G = G.clone()
+    N = len(As)
+    Xv = X.reshape(-1)
+    zero = torch.zeros(G.numel(), dtype=torch.float64, device=G.device)
+    xx = kron_loss(As, Xv, zero, 0.0, handle=h)[0]
+    trace = []
+    for s in range(sweeps):
+        for n in range(N):
+            As[n], _ = tucker_factor_update(X, As, G, n, lam, eps=eps, m=m_factor, seed=seed,
+                                            stream=als_stream(s, n), handle=h, tol=tol)
+        g, _ = kron_ridge(As, Xv, lam, eps=eps, m=m_core, seed=seed, stream=als_stream(s, N), handle=h,
+                          tol=tol)
+        G = g.reshape(G.shape)
+        trace.append(kron_loss(As, Xv, g, 0.0, handle=h)[0] / xx)
+    return G, As, trace
+
+
 def profile_enable(enable=True, kernel_filter="", handle=None):
     """Bracket kernel launches whose name contains kernel_filter ("" = all) with HIP
     events on the handle's stream (clears old records)."""
@@ -310,6 +342,6 @@ def export_sketch(sizes, handle=None, cap=None):
 
 
 __all__ = ["Handle", "KronRegressError", "kron_regress", "kron_ridge", "kron_loss", "kron_exact",
-           "tucker_factor_update",
+           "tucker_factor_update", "tucker_als", "als_stream",
            "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query",
            "profile_names", "profile_breakdown"]

@@ -110,11 +110,72 @@ def test_factor_update_tucker_tensor_workload(gpu_lib):
     _check_rows(gpu_lib, Xd, As, G, n, w["lam"], w["m_factor"], w["seed"], 7, An, [0, 1, 199, 398, 399], 1e-9)
     # every row within (1 + eps) of its exact optimum
     exact = exact_factor_update(Xd, As, G, n, w["lam"])
-    K = None
     S = FactorUpdateSetup(As, G, n, w["lam"], w["eps"])
-    D = np.kron(S.As_other[0], S.As_other[1]) @ S.Gn.T if K is None else K
+    D = np.kron(S.As_other[0], S.As_other[1]) @ S.Gn.T
     B = unfold(Xd, n)
     f = lambda y, i: np.sum((D @ y - B[i]) ** 2) + w["lam"] * y @ y
     ratios = np.array([f(An[i], i) / f(exact[i], i) for i in range(X.shape[0])])
     print("row objective ratio: max %.4f median %.5f" % (ratios.max(), np.median(ratios)), flush=True)
     assert ratios.max() <= 1 + w["eps"]
+
+
+def test_core_update_tucker_workload(gpu_lib):
+    """Core update of ALS (Algorithm 2 with b = vec(X), FP32 X, lam = 1e-3) on the
+    400^3 tensor: bit-exact sketch, sketched normal equations satisfied, loss gate."""
+    import torch
+    from oracle.regression import exact_solution, loss
+    from parity import check_quantised_tables, check_sketch
+    w = workloads.tucker_tensor()
+    print("case core update", w["name"], "m", w["m_core"], flush=True)
+    As = w["A_init"]
+    X = w["X"]
+    tX = torch.from_numpy(X).cuda().reshape(-1)
+    tA = [torch.tensor(A, device="cuda") for A in As]
+    g, info = gpu_lib.kron_ridge(tA, tX, w["lam"], eps=w["eps"], m=w["m_core"], seed=w["seed"], stream=3,
+                                 tol=1e-12)
+    assert info["status"] == "OK", info
+    sk = gpu_lib.export_sketch([400, 400, 400])
+    check_quantised_tables(As, sk["Q"])
+    rows, ridx, counts, Omega = check_sketch(As, sk, w["m_core"], seed=w["seed"], stream=3)
+    gv = g.cpu().numpy()
+    bD = X.reshape(-1)[rows].astype(np.float64)
+    # sketched normal equations K_D^T Omega (K_D g - b_D) + lam g = 0, in row chunks
+    res = w["lam"] * gv
+    ref = np.zeros_like(gv)
+    for c0 in range(0, len(rows), 20000):
+        KD = kron_rows(As, ridx[c0:c0 + 20000])
+        r = KD @ gv - bD[c0:c0 + 20000]
+        res += KD.T @ (Omega[c0:c0 + 20000] * r)
+        ref += KD.T @ (Omega[c0:c0 + 20000] * bD[c0:c0 + 20000])
+    rel = np.linalg.norm(res) / np.linalg.norm(ref)
+    print("normal-equation residual %.2e, distinct rows %d" % (rel, len(rows)), flush=True)
+    assert rel < 1e-10
+    Xd = X.astype(np.float64).reshape(-1)
+    f = loss(As, Xd, gv, w["lam"])
+    opt = loss(As, Xd, exact_solution(As, Xd, w["lam"]), w["lam"])
+    print("loss / opt = %.5f" % (f / opt), flush=True)
+    assert f <= (1 + w["eps"]) * opt
+
+
+def test_als_matches_oracle_small(gpu_lib):
+    """Two sketched ALS sweeps through the C ABI against the oracle's sketched ALS
+    (same Philox streams; the oracle solves each sketched problem directly)."""
+    import torch
+    from oracle.tucker import tucker_als
+    print("case ALS small", flush=True)
+    rng = np.random.default_rng(41)
+    I, R = (24, 20, 18), (3, 3, 2)
+    Qs = [np.linalg.qr(rng.standard_normal((i, r)))[0] for i, r in zip(I, R)]
+    X = tucker_reconstruct(rng.standard_normal(R), Qs) + 0.01 * rng.standard_normal(I)
+    G0 = rng.standard_normal(R)
+    A0 = [rng.standard_normal((i, r)) for i, r in zip(I, R)]
+    lam, eps, mc, mf = 1e-3, 0.1, 3000, 400
+    Go, Ao, to = tucker_als(X, G0, A0, lam, 2, sketched=True, eps=eps, m_factor=mf, m_core=mc, seed=0)
+    Gg, Ag, tg = gpu_lib.tucker_als(torch.tensor(X, device="cuda"), torch.tensor(G0, device="cuda"),
+                                    [torch.tensor(A, device="cuda") for A in A0], lam, 2, eps=eps,
+                                    m_core=mc, m_factor=mf, seed=0)
+    print("rre oracle", to, "gpu", tg, flush=True)
+    np.testing.assert_allclose(tg, to, rtol=1e-7)
+    assert rel_l2(Gg.cpu().numpy(), Go) < 1e-7
+    for a, b in zip(Ag, Ao):
+        assert rel_l2(a.cpu().numpy(), b) < 1e-7
