@@ -77,12 +77,26 @@ typedef struct {
   int32_t max_iter;   /* Richardson iteration limit (default 200 when <= 0)           */
   int32_t check_every;/* iterations between convergence checks (default 8 when <= 0) */
   double tol;         /* stop when (1-sqrt(eps)) ||d|| <= tol ||x||, per RHS
-                         (default 1e-12 when <= 0)                                    */
+                         (default when <= 0: 1e-12 for KR_PREC_F64, 1e-9 for the
+                         refined precisions)                                          */
   uint64_t seed;      /* Philox key word 0                                            */
   uint64_t stream;    /* Philox key word 1                                            */
   int32_t flags;      /* KR_OPT_* bits                                                */
   int32_t workgroups; /* workgroups of the cooperative iteration (0 = automatic)      */
+  int32_t precision;  /* kr_precision of the Richardson iteration (0 = KR_PREC_F64)   */
+  int32_t reserved;   /* must be 0                                                    */
 } kr_opts;
+
+/* kr_opts.precision.  The fixed point of the Richardson iteration of Algorithm 2
+ * is set by the gradient alone; the preconditioner only sets the rate.  The
+ * refined precisions therefore keep the residual K~x - b~, the update of x and
+ * the norms of the stopping rule in float64, accumulate the adjoint
+ * K~^T Omega u in float32 and apply the preconditioner's mode products in
+ * KR_PREC_F32: float32; KR_PREC_BF16: bf16 MFMA; KR_PREC_FP8: e4m3 MFMA with
+ * per-operand scaling; all with float32 accumulation.  The result is still
+ * float64.  Refined precisions are not available with KR_OPT_COOPERATIVE or in
+ * tucker_factor_update (KR_EUNSUPPORTED). */
+typedef enum { KR_PREC_F64 = 0, KR_PREC_F32 = 1, KR_PREC_BF16 = 2, KR_PREC_FP8 = 3 } kr_precision;
 
 /* kr_opts.flags: run the whole iteration as one cooperative launch with grid
  * barriers (N >= 2 and the iterate small enough to fit in LDS; otherwise the

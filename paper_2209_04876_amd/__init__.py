@@ -43,10 +43,22 @@ class Problem(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint64),
-                ("flags", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 OPT_COOPERATIVE = 1
+
+# kr_precision: the arithmetic of the Richardson iteration (float64 plain, or
+# refined: float64 residual and update, float32 adjoint, preconditioner in the
+# named precision with float32 accumulation).
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+
+
+def _precision(name):
+    if name not in PRECISIONS:
+        raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
+    return PRECISIONS[name]
 
 
 class Info(ctypes.Structure):
@@ -177,17 +189,22 @@ def _x_like(As, nrhs, one_dim):
     return torch.empty(shape, dtype=torch.float64, device=As[0].device)
 
 
-def _opts(m, max_iter, tol, seed, stream, check_every, flags=0, workgroups=0):
+def _opts(m, max_iter, tol, seed, stream, check_every, flags=0, workgroups=0, precision="f64"):
     o = Opts()
-    o.m, o.max_iter, o.tol, o.seed, o.stream, o.check_every = m, max_iter, tol, seed, stream, check_every
+    o.m, o.max_iter, o.seed, o.stream, o.check_every = m, max_iter, seed, stream, check_every
+    o.tol = 0.0 if tol is None else tol
     o.flags, o.workgroups = flags, workgroups
+    o.precision = _precision(precision)
     return o
 
 
-def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=1e-12,
+def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
                check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
-               workgroups=0):
-    """Algorithm 2 with regularisation lam.  Returns (x float64, info dict)."""
+               workgroups=0, precision="f64"):
+    """Algorithm 2 with regularisation lam.  Returns (x float64, info dict).
+
+    tol=None takes the library default (1e-12 for "f64", 1e-9 for the refined
+    precisions "f32", "bf16", "fp8")."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
@@ -195,7 +212,7 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
     info = Info()
     st = h.lib.kron_ridge(h.ptr, ctypes.byref(p), lam, eps, delta,
                           ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                             OPT_COOPERATIVE if cooperative else 0, workgroups)),
+                                             OPT_COOPERATIVE if cooperative else 0, workgroups, precision)),
                           ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:
@@ -203,10 +220,11 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
     return x, info.as_dict()
 
 
-def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=1e-12,
+def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
                  check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
-                 workgroups=0):
-    """Algorithm 2 (lambda = 0).  Returns (x float64, info dict)."""
+                 workgroups=0, precision="f64"):
+    """Algorithm 2 (lambda = 0).  Returns (x float64, info dict); see kron_ridge
+    for tol and precision."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
@@ -214,7 +232,7 @@ def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200
     info = Info()
     st = h.lib.kron_regress(h.ptr, ctypes.byref(p), eps, delta,
                             ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                               OPT_COOPERATIVE if cooperative else 0, workgroups)),
+                                               OPT_COOPERATIVE if cooperative else 0, workgroups, precision)),
                             ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:

@@ -19,6 +19,7 @@
 #include "kr_stream.hip"
 #include "kr_persist.hip"
 #include "kr_tucker.hip"
+#include "kr_mixed.hip"
 
 using namespace kr;
 
@@ -110,6 +111,13 @@ void prof_clear(kr_handle h) {
 #define KL(h, kern, ...)                      \
   do {                                        \
     ProfScope _ps((h), #kern, (h)->stream);   \
+    hipLaunchKernelGGL(kern, __VA_ARGS__);    \
+  } while (0)
+
+// Launch with an explicit profiling name (for kernels instantiated per type).
+#define KLN(h, name, kern, ...)               \
+  do {                                        \
+    ProfScope _ps((h), (name), (h)->stream);  \
     hipLaunchKernelGGL(kern, __VA_ARGS__);    \
   } while (0)
 
@@ -367,6 +375,7 @@ static size_t solve_bytes(const Geom& g, int ntiles, int nblocks) {
   b += 3 * 8 * (size_t)g.Rtot * g.nrhs + sizeof(IterState) + 8 * (KR_MAXN + 1) + 512;
   b += 8 * (size_t)D * g.nrhs + 8 * (size_t)(level_cap(g, 1) + 2) + 512;
   b += 8 * (size_t)((level_cap(g, 1) + 31) / 32) * g.Rtot * g.nrhs + 512;
+  for (int k = 1; k < g.N; ++k) b += 4 * (size_t)level_cap(g, k) * g.R[k - 1] + 256;
   return b + 64 * 256 + 4096;
 }
 
@@ -392,43 +401,130 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
 }
 
 // One pass of the sampled products K~^T Omega (K~ x - b~) down and up the sample
-// tree: forward levels 1..N-1, the rows with the last adjoint level, adjoint
-// levels N-1..2, and (without segment roots) the root adjoint into Q[0].
-// P[0] is the iterate; Q[k] receives level-k results.
-static void launch_level_products(kr_handle h, const ModeTables& T, const Geom& g, const Tree& tr, double* const* P,
-                                  double* const* Q, const double* Omega, const double* bD, double* part,
+// tree: forward levels 1..N-1 (float64), the rows with the last adjoint level,
+// adjoint levels N-1..2, and (without segment roots) the root adjoint into Q[0].
+// P[0] is the iterate; Q[k] receives level-k results in the adjoint type T
+// (float64, or float32 in the refined precisions; part and Q are then float
+// buffers).
+template <typename T>
+static void launch_level_products(kr_handle h, const ModeTables& TT, const Geom& g, const Tree& tr, double* const* P,
+                                  void* const* Qv, const double* Omega, const double* bD, void* partv,
                                   const IterState* state) {
   hipStream_t s = h->stream;
+  T* Q[KR_MAXN + 1];
+  for (int k = 0; k <= KR_MAXN; ++k) Q[k] = (T*)Qv[k];
+  T* part = (T*)partv;
   for (int k = 1; k < g.N; ++k) {
     const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
-    KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k, (const double*)P[k - 1], P[k],
+    KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, TT, g, tr, k, (const double*)P[k - 1], P[k],
        state);
   }
   const int Rl = g.R[g.N - 1];
   const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
   const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
-  double* qlast = Q[g.N - 1];
+  T* qlast = Q[g.N - 1];
   const double* plast = P[g.N - 1];
   const dim3 rg(grid_for(rows_threads, 256));
+  const bool f32 = sizeof(T) == 4;
   switch (G) {
-    case 8: KL(h, k_rows_adj<8>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
-    case 16: KL(h, k_rows_adj<16>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
-    case 32: KL(h, k_rows_adj<32>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
-    default: KL(h, k_rows_adj<64>, rg, dim3(256), 0, s, T, g, tr, plast, Omega, bD, qlast, state); break;
+    case 8:
+      KLN(h, f32 ? "k_rows_adj<8,f32>" : "k_rows_adj<8>", (k_rows_adj<8, T>), rg, dim3(256), 0, s, TT, g, tr, plast,
+          Omega, bD, qlast, state);
+      break;
+    case 16:
+      KLN(h, f32 ? "k_rows_adj<16,f32>" : "k_rows_adj<16>", (k_rows_adj<16, T>), rg, dim3(256), 0, s, TT, g, tr,
+          plast, Omega, bD, qlast, state);
+      break;
+    case 32:
+      KLN(h, f32 ? "k_rows_adj<32,f32>" : "k_rows_adj<32>", (k_rows_adj<32, T>), rg, dim3(256), 0, s, TT, g, tr,
+          plast, Omega, bD, qlast, state);
+      break;
+    default:
+      KLN(h, f32 ? "k_rows_adj<64,f32>" : "k_rows_adj<64>", (k_rows_adj<64, T>), rg, dim3(256), 0, s, TT, g, tr,
+          plast, Omega, bD, qlast, state);
+      break;
   }
   for (int k = g.N - 1; k >= 2; --k) {
     const int64_t work = level_cap(g, k - 1) * g.rsuf[k - 1] * g.nrhs;
-    KL(h, k_adj_level, dim3(grid_for(work, 256)), dim3(256), 0, s, T, g, tr, k, (const double*)Q[k], Q[k - 1], state);
+    KLN(h, f32 ? "k_adj_level<f32>" : "k_adj_level", k_adj_level<T>, dim3(grid_for(work, 256)), dim3(256), 0, s, TT,
+        g, tr, k, (const T*)Q[k], Q[k - 1], state);
   }
   if (g.N >= 2 && !g.seg_root) {
     const int64_t CEr = g.R[0] >= 256 ? 1 : 256 / g.R[0];
     const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
     const int64_t nnb = (level_cap(g, 1) + RA_NODES - 1) / RA_NODES;
-    KL(h, k_adj_root_partial, dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr, (const double*)Q[1], part,
-       state);
-    KL(h, k_adj_root_sum, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr, (const double*)part, Q[0],
-       state);
+    KLN(h, f32 ? "k_adj_root_partial<f32>" : "k_adj_root_partial", k_adj_root_partial<T>,
+        dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr, (const T*)Q[1], part, state);
+    KLN(h, f32 ? "k_adj_root_sum<f32>" : "k_adj_root_sum", k_adj_root_sum<T>,
+        dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr, (const T*)part, Q[0], state);
   }
+}
+
+// The float64 preconditioner step, instantiated per fibre width (bucket of max R_n).
+static void launch_precond_update(kr_handle h, const ModeTables& T, const Geom& g, const double* grad, double* x,
+                                  double* t0, double* t1, double lambda, double eta, double tol, int max_iter,
+                                  IterState* st) {
+  hipStream_t s = h->stream;
+  int maxR = 1;
+  for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
+  const int ginv = lambda == 0.0 ? 1 : 0;
+  if (maxR <= 8)
+    KLN(h, "k_precond_update<8>", k_precond_update<8>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda, eta,
+        tol, max_iter, ginv, st);
+  else if (maxR <= 16)
+    KLN(h, "k_precond_update<16>", k_precond_update<16>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda,
+        eta, tol, max_iter, ginv, st);
+  else if (maxR <= 32)
+    KLN(h, "k_precond_update<32>", k_precond_update<32>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda,
+        eta, tol, max_iter, ginv, st);
+  else
+    KLN(h, "k_precond_update<64>", k_precond_update<64>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda,
+        eta, tol, max_iter, ginv, st);
+}
+
+// The refined-precision preconditioner step, instantiated per precision and per
+// number of 16-blocks along the widest mode.
+template <int MODE>
+static void launch_precond_mp_nb(kr_handle h, int nb, size_t lds, const ModeTables& T, const Geom& g,
+                                 const float* gr, double* x, float* t0, float* t1, double lambda, double eta,
+                                 double tol, int max_iter, int use_ginv, IterState* st) {
+  hipStream_t s = h->stream;
+  const int L = lds > 0;
+  static const char* names[4][4] = {
+      {"", "", "", ""},
+      {"k_precond_mp<f32,1>", "k_precond_mp<f32,2>", "k_precond_mp<f32,3>", "k_precond_mp<f32,4>"},
+      {"k_precond_mp<bf16,1>", "k_precond_mp<bf16,2>", "k_precond_mp<bf16,3>", "k_precond_mp<bf16,4>"},
+      {"k_precond_mp<fp8,1>", "k_precond_mp<fp8,2>", "k_precond_mp<fp8,3>", "k_precond_mp<fp8,4>"}};
+  const char* nm = names[MODE][std::min(std::max(nb, 1), 4) - 1];
+  switch (nb) {
+    case 1:
+      KLN(h, nm, (k_precond_mp<MODE, 1>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
+          max_iter, use_ginv, st);
+      break;
+    case 2:
+      KLN(h, nm, (k_precond_mp<MODE, 2>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
+          max_iter, use_ginv, st);
+      break;
+    case 3:
+      KLN(h, nm, (k_precond_mp<MODE, 3>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
+          max_iter, use_ginv, st);
+      break;
+    default:
+      KLN(h, nm, (k_precond_mp<MODE, 4>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
+          max_iter, use_ginv, st);
+      break;
+  }
+}
+
+static void launch_precond_mp(kr_handle h, int prec, int nb, size_t lds, const ModeTables& T, const Geom& g,
+                              const float* gr, double* x, float* t0, float* t1, double lambda, double eta, double tol,
+                              int max_iter, int use_ginv, IterState* st) {
+  if (prec == KR_PREC_F32)
+    launch_precond_mp_nb<KR_PREC_F32>(h, nb, lds, T, g, gr, x, t0, t1, lambda, eta, tol, max_iter, use_ginv, st);
+  else if (prec == KR_PREC_BF16)
+    launch_precond_mp_nb<KR_PREC_BF16>(h, nb, lds, T, g, gr, x, t0, t1, lambda, eta, tol, max_iter, use_ginv, st);
+  else
+    launch_precond_mp_nb<KR_PREC_FP8>(h, nb, lds, T, g, gr, x, t0, t1, lambda, eta, tol, max_iter, use_ginv, st);
 }
 
 static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
@@ -455,9 +551,14 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   for (int k = 0; k <= g.N; ++k)
     if ((double)level_cap(g, k) * (double)g.rsuf[k] * g.nrhs >= 2147483647.0)
       KR_FAIL(h, KR_EUNSUPPORTED, "level %d of the sample tree needs more than 2^31 entries", k);
+  const int prec = o.precision;
+  if (prec < KR_PREC_F64 || prec > KR_PREC_FP8 || o.reserved != 0)
+    KR_FAIL(h, KR_EINVAL, "opts.precision=%d invalid (or opts.reserved != 0)", prec);
+  if (prec != KR_PREC_F64 && (o.flags & KR_OPT_COOPERATIVE))
+    KR_FAIL(h, KR_EUNSUPPORTED, "the cooperative iteration runs in float64 only");
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
   const int check_every = o.check_every > 0 ? o.check_every : 8;
-  const double tol = o.tol > 0.0 ? o.tol : 1e-12;
+  const double tol = o.tol > 0.0 ? o.tol : (prec == KR_PREC_F64 ? 1e-12 : 1e-9);
   const double eta = 1.0 - std::sqrt(eps);
 
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
@@ -501,6 +602,8 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   B.rs1 = a.take<int64_t>(level_cap(g, 1) + 2);
   B.state = a.take<IterState>(1);
   unsigned* bar = a.take<unsigned>(64);
+  if (prec != KR_PREC_F64)
+    for (int k = 1; k < g.N; ++k) tr.arow32[k] = a.take<float>((size_t)level_cap(g, k) * g.R[k - 1]);
   if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
 
   hipStream_t s = h->stream;
@@ -518,6 +621,11 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
   KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype,
                      B.Omega, B.bD, B.counts, B.s.flags);
+  if (prec != KR_PREC_F64 && g.N >= 2) {
+    int64_t rows32 = 0;
+    for (int k = 1; k < g.N; ++k) rows32 = std::max<int64_t>(rows32, level_cap(g, k) * g.R[k - 1]);
+    KL(h, k_rows_to_f32, dim3(grid_for(rows32, 256, 1024)), dim3(256), 0, s, g, tr);
+  }
   // -- Richardson
   KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, (double*)d_x,
                      g.Rtot * g.nrhs, 0.0);
@@ -587,14 +695,30 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
       KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
     if (h->h_state->diverged == 2) KR_FAIL(h, KR_EHIP, "grid barrier timed out in the persistent iteration");
   } else {
+    // refined precisions: both float tensor buffers of the preconditioner in LDS
+    // when they fit beside its 16 KB matrix stage
+    const size_t mp_lds = 2 * 4 * (size_t)RT <= 48 * 1024 ? 2 * 4 * (size_t)RT : 0;
+    int maxR = 1;
+    for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
+    const int mp_nb = (maxR + 15) / 16;
     int iters_enqueued = 0;
     bool flags_checked = false;
     while (iters_enqueued < max_iter) {
       const int chunk = std::min(check_every, max_iter - iters_enqueued);
       for (int it = 0; it < chunk; ++it) {
-        launch_level_products(h, T, g, tr, B.P, B.Q, B.Omega, B.bD, B.part, (const IterState*)B.state);
-        KL(h, k_precond_update, dim3(1), dim3(1024), 0, s, T, g, (const double*)B.Q[0], (double*)d_x,
-                           B.t0, B.t1, lambda, eta, tol, max_iter, lambda == 0.0 ? 1 : 0, B.state);
+        if (prec == KR_PREC_F64) {
+          launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
+                                        (const IterState*)B.state);
+          launch_precond_update(h, T, g, (const double*)B.Q[0], (double*)d_x, B.t0, B.t1, lambda, eta, tol,
+                                max_iter, B.state);
+        } else {
+          launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
+                                       (const IterState*)B.state);
+          const int use_ginv = lambda == 0.0 ? 1 : 0;
+          const float* gr = (const float*)B.Q[0];
+          launch_precond_mp(h, prec, mp_nb, mp_lds, T, g, gr, (double*)d_x, (float*)B.t0, (float*)B.t1, lambda,
+                            eta, tol, max_iter, use_ginv, B.state);
+        }
       }
       iters_enqueued += chunk;
       HIPCHK(h, hipGetLastError());
@@ -884,6 +1008,8 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   g.seg_root = 1;
   kr_opts o{};
   if (opts) o = *opts;
+  if (o.precision != KR_PREC_F64)
+    KR_FAIL(h, KR_EUNSUPPORTED, "tucker_factor_update runs in float64 only (opts.precision=%d)", o.precision);
   int64_t mrow = o.m;
   if (mrow <= 0) {
     if (!(delta > 0.0 && delta < 1.0)) KR_FAIL(h, KR_EINVAL, "delta=%g outside (0, 1)", delta);
@@ -990,7 +1116,7 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   while (enq < max_iter) {
     const int chunk = std::min(check_every, max_iter - enq);
     for (int it = 0; it < chunk; ++it) {
-      launch_level_products(h, T, g, tr, P, Q, Omega, bD, nullptr, (const IterState*)state);
+      launch_level_products<double>(h, T, g, tr, P, (void* const*)Q, Omega, bD, nullptr, (const IterState*)state);
       KL(h, k_tucker_update, dim3(In), dim3(256), 3 * 8 * (size_t)Rr, s, T, g, tg, (const double*)Q[1], Z,
          (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv, (const double*)wbuf, eta,
          tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, counters, counters + 1, state);

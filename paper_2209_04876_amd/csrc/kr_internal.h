@@ -60,6 +60,7 @@ struct ModeTables {
 struct Tree {
   int32_t* idx[KR_MAXN + 1];
   double* arow[KR_MAXN + 1];    // arow[k][s][r] = A_{k-1}[idx[k][s]][r], contiguous per node
+  float* arow32[KR_MAXN + 1];   // float copies of arow[1..N-1] for the float32 adjoint (refined modes)
   int32_t* parent[KR_MAXN + 1];
   int32_t* fchild[KR_MAXN + 1];
   int32_t* rstart;

@@ -33,7 +33,14 @@ struct GDiv {
   }
 };
 
-__global__ void __launch_bounds__(256) k_fwd_level(ModeTables T, Geom g, Tree tr, int k,
+// Gathered factor rows of level k in the arithmetic type of the products.
+template <typename T> __device__ __forceinline__ const T* node_rows(const Tree& tr, int k);
+template <> __device__ __forceinline__ const double* node_rows<double>(const Tree& tr, int k) { return tr.arow[k]; }
+template <> __device__ __forceinline__ const float* node_rows<float>(const Tree& tr, int k) { return tr.arow32[k]; }
+
+// Forward level k (always float64: the residual K~x - b~ cancels, so it is formed
+// in float64 in every precision mode).
+__global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree tr, int k,
                                                   const double* __restrict__ Pprev,
                                                   double* __restrict__ Pout,
                                                   const IterState* __restrict__ st) {
@@ -67,13 +74,16 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables T, Geom g, Tree tr
 
 // Rows and the last adjoint level, fused.  A group of G lanes (power of two
 // >= R_{N-1}) owns one (level-(N-1) node p, rhs q); lane r keeps P[p][r][q] and
-// accumulates Q[p][r][q] over the children rows of p, four rows per step.
-template <int G>
-__global__ void __launch_bounds__(256) k_rows_adj(ModeTables T, Geom g, Tree tr,
+// accumulates Q[p][r][q] over the children rows of p, four rows per step.  The
+// row dot product and the residual u_j = <a, P> - b_j are float64; the weighted
+// residual Omega_j u_j is then accumulated in T (float64, or float32 in the
+// refined modes).
+template <int G, typename T>
+__global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr,
                                                  const double* __restrict__ Pprev,
                                                  const double* __restrict__ Omega,
                                                  const double* __restrict__ bD,
-                                                 double* __restrict__ Qout,
+                                                 T* __restrict__ Qout,
                                                  const IterState* __restrict__ st) {
   if (st->all_done) return;
   const int N = g.N, nrhs = g.nrhs;
@@ -90,7 +100,7 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables T, Geom g, Tree tr,
     const int q = active ? (int)(grp - p * nrhs) : 0;
     const bool ln = active && lane < R;
     const double pv = ln ? Pprev[(p * R + lane) * nrhs + q] : 0.0;
-    double acc = 0.0;
+    T acc = 0;
     const int j0 = active ? tr.fchild[N - 1][p] : 0;
     const int j1 = active ? tr.fchild[N - 1][p + 1] : 0;
     int j = j0;
@@ -110,30 +120,31 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables T, Geom g, Tree tr,
         for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, G);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = fma(om[u] * (y[u] - bb[u]), av[u], acc);
+      for (int u = 0; u < 4; ++u) acc = fma((T)(om[u] * (y[u] - bb[u])), (T)av[u], acc);
     }
     for (; j < j1; ++j) {
       const double a = ln ? AL[(int64_t)j * R + lane] : 0.0;
       double y = a * pv;
 #pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, G);
-      acc = fma(Omega[j] * (y - bD[(int64_t)j * nrhs + q]), a, acc);
+      acc = fma((T)(Omega[j] * (y - bD[(int64_t)j * nrhs + q])), (T)a, acc);
     }
     if (ln) Qout[(p * R + lane) * nrhs + q] = acc;
   }
 }
 
 // Adjoint level k (k = N-1 .. 2): Q_{k-1}[p][r][c][q] = sum_s a_{k-1}[i(s)][r] Q_k[s][c][q].
-__global__ void __launch_bounds__(256) k_adj_level(ModeTables T, Geom g, Tree tr, int k,
-                                                  const double* __restrict__ Qk,
-                                                  double* __restrict__ Qout,
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_level(ModeTables TT, Geom g, Tree tr, int k,
+                                                  const T* __restrict__ Qk,
+                                                  T* __restrict__ Qout,
                                                   const IterState* __restrict__ st) {
   if (st->all_done) return;
   const unsigned Sp = (unsigned)tr.cnt[k - 1];
   const unsigned W = (unsigned)(g.rsuf[k] * g.nrhs);
   const unsigned Wp = (unsigned)(g.rsuf[k - 1] * g.nrhs);
   const int Rk = g.R[k - 1];
-  const double* __restrict__ arow = tr.arow[k];
+  const T* __restrict__ arow = node_rows<T>(tr, k);
   const unsigned total = Sp * Wp;
   const unsigned step = gridDim.x * blockDim.x;
   const unsigned e0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,10 +153,10 @@ __global__ void __launch_bounds__(256) k_adj_level(ModeTables T, Geom g, Tree tr
     const unsigned p = di.q, rem = di.r;
     const unsigned r = rem / W, cq = rem - r * W;
     const int s0 = tr.fchild[k - 1][p], s1 = tr.fchild[k - 1][p + 1];
-    double acc = 0.0;
+    T acc = 0;
     int s = s0;
     for (; s + 4 <= s1; s += 4) {
-      double av[4], qv[4];
+      T av[4], qv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         av[u] = arow[(size_t)(s + u) * Rk + r];
@@ -163,12 +174,14 @@ __global__ void __launch_bounds__(256) k_adj_level(ModeTables T, Geom g, Tree tr
 // sum_{s in block b} a_0[i(s)][r0] Q_1[s][c].  Workgroup (column block, node block)
 // stages its node block's factor rows and Q_1 columns in LDS.
 #define RA_NODES 32
-__global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const double* __restrict__ Q1,
-                                                         double* __restrict__ partial,
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const T* __restrict__ Q1,
+                                                         T* __restrict__ partial,
                                                          const IterState* __restrict__ st) {
   if (st->all_done) return;
-  __shared__ double as[RA_NODES * 64];
-  __shared__ double qs[RA_NODES * 256];
+  __shared__ T as[RA_NODES * 64];
+  __shared__ T qs[RA_NODES * 256];
+  const T* __restrict__ arow1 = node_rows<T>(tr, 1);
   const unsigned S1 = (unsigned)tr.cnt[1];
   const int R0 = g.R[0];
   const unsigned W1 = (unsigned)(g.rsuf[1] * g.nrhs);
@@ -179,15 +192,15 @@ __global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const
     const unsigned cb = task % ncb, nbk = task / ncb;
     const unsigned e0 = cb * CE, s0 = nbk * RA_NODES;
     const unsigned ns = (S1 - s0) < RA_NODES ? (S1 - s0) : RA_NODES;
-    for (unsigned i = threadIdx.x; i < ns * (unsigned)R0; i += blockDim.x) as[i] = tr.arow[1][(size_t)s0 * R0 + i];
+    for (unsigned i = threadIdx.x; i < ns * (unsigned)R0; i += blockDim.x) as[i] = arow1[(size_t)s0 * R0 + i];
     for (unsigned i = threadIdx.x; i < ns * CE; i += blockDim.x) {
       const unsigned sn = i / CE, c = i - sn * CE;
-      qs[i] = e0 + c < W1 ? Q1[(size_t)(s0 + sn) * W1 + e0 + c] : 0.0;
+      qs[i] = e0 + c < W1 ? Q1[(size_t)(s0 + sn) * W1 + e0 + c] : T(0);
     }
     __syncthreads();
     const unsigned r0 = threadIdx.x / CE, c = threadIdx.x - r0 * CE;
     if (r0 < (unsigned)R0 && e0 + c < W1) {
-      double acc = 0.0;
+      T acc = 0;
       for (unsigned sn = 0; sn < ns; ++sn) acc = fma(as[sn * R0 + r0], qs[sn * CE + c], acc);
       partial[(size_t)nbk * g.Rtot * g.nrhs + (size_t)r0 * W1 + e0 + c] = acc;
     }
@@ -196,14 +209,15 @@ __global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const
 }
 
 // g = sum over node blocks of the partials, in block order (deterministic).
-__global__ void __launch_bounds__(256) k_adj_root_sum(Geom g, Tree tr, const double* __restrict__ partial,
-                                                     double* __restrict__ grad, const IterState* __restrict__ st) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_root_sum(Geom g, Tree tr, const T* __restrict__ partial,
+                                                     T* __restrict__ grad, const IterState* __restrict__ st) {
   if (st->all_done) return;
   const unsigned S1 = (unsigned)tr.cnt[1];
   const unsigned nnb = (S1 + RA_NODES - 1) / RA_NODES;
   const size_t RT = (size_t)g.Rtot * g.nrhs;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < RT; e += (size_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
+    T acc = 0;
     for (unsigned b = 0; b < nnb; ++b) acc += partial[(size_t)b * RT + e];
     grad[e] = acc;
   }
@@ -235,20 +249,13 @@ __device__ void wg_mode_fibre(const Geom& g, int n, const double* __restrict__ M
   }
 }
 
-__device__ void wg_mode_product(const Geom& g, int n, const double* __restrict__ M, int trans,
-                                const double* in, double* out) {
-  const int Rn = g.R[n];
-  if (Rn <= 8) wg_mode_fibre<8>(g, n, M, trans, in, out);
-  else if (Rn <= 16) wg_mode_fibre<16>(g, n, M, trans, in, out);
-  else if (Rn <= 32) wg_mode_fibre<32>(g, n, M, trans, in, out);
-  else wg_mode_fibre<64>(g, n, M, trans, in, out);
-}
-
 // d = M^+ (g + lambda x); x <- x - eta d for right-hand sides not yet converged;
 // per-RHS norms, stopping rule eta ||d|| <= tol ||x||, divergence test.
-// One workgroup of 1024 threads.  t0/t1 are Rtot x nrhs scratch buffers; each
-// factor matrix is staged in LDS before its mode product.
-__global__ void __launch_bounds__(1024) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
+// One workgroup of 256 threads.  t0/t1 are Rtot x nrhs scratch buffers; each
+// factor matrix is staged in LDS before its mode product.  RM (8, 16, 32 or 64)
+// bounds every R_n: one fibre width per kernel keeps the fibre in registers.
+template <int RM>
+__global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
                                                         double* __restrict__ x, double* __restrict__ t0,
                                                         double* __restrict__ t1, double lambda, double eta,
                                                         double tol, int max_iter, int use_ginv,
@@ -268,13 +275,13 @@ __global__ void __launch_bounds__(1024) k_precond_update(ModeTables T, Geom g, c
   if (use_ginv) {
     for (int n = 0; n < g.N; ++n) {
       stage(T.Ginv[n], n);
-      wg_mode_product(g, n, ms, 0, cur, nxt);
+      wg_mode_fibre<RM>(g, n, ms, 0, cur, nxt);
       double* tmp = cur; cur = nxt; nxt = tmp;
     }
   } else {
     for (int n = 0; n < g.N; ++n) {
       stage(T.V[n], n);
-      wg_mode_product(g, n, ms, 1, cur, nxt);
+      wg_mode_fibre<RM>(g, n, ms, 1, cur, nxt);
       double* tmp = cur; cur = nxt; nxt = tmp;
     }
     __syncthreads();
@@ -291,7 +298,7 @@ __global__ void __launch_bounds__(1024) k_precond_update(ModeTables T, Geom g, c
     }
     for (int n = 0; n < g.N; ++n) {
       stage(T.V[n], n);
-      wg_mode_product(g, n, ms, 0, cur, nxt);
+      wg_mode_fibre<RM>(g, n, ms, 0, cur, nxt);
       double* tmp = cur; cur = nxt; nxt = tmp;
     }
   }
@@ -339,14 +346,5 @@ __global__ void k_zero_bytes(uint32_t* __restrict__ p, int64_t nwords) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
 }
-
-template __global__ void k_rows_adj<8>(ModeTables, Geom, Tree, const double*, const double*, const double*,
-                                       double*, const IterState*);
-template __global__ void k_rows_adj<16>(ModeTables, Geom, Tree, const double*, const double*, const double*,
-                                        double*, const IterState*);
-template __global__ void k_rows_adj<32>(ModeTables, Geom, Tree, const double*, const double*, const double*,
-                                        double*, const IterState*);
-template __global__ void k_rows_adj<64>(ModeTables, Geom, Tree, const double*, const double*, const double*,
-                                        double*, const IterState*);
 
 }  // namespace kr

@@ -36,3 +36,28 @@ def test_binding_names_match_the_abi():
     import paper_2209_04876_amd as kr
     for n in ("kron_regress", "kron_ridge", "kron_loss", "kron_exact"):
         assert callable(getattr(kr, n))
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of kr_problem / kr_opts / kr_info have the C layout (gcc)."""
+    import subprocess
+    import paper_2209_04876_amd as kr
+    structs = {"kr_problem": kr.Problem, "kr_opts": kr.Opts, "kr_info": kr.Info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kron_regress.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
