@@ -19,6 +19,7 @@
 #include "kr_stream.hip"
 #include "kr_persist.hip"
 #include "kr_tucker.hip"
+#include "kr_precond.hip"
 #include "kr_mixed.hip"
 
 using namespace kr;
@@ -319,8 +320,11 @@ static size_t setup_bytes(const Geom& g) {
   return b + 8 * (size_t)g.N * 4096 + 1024;
 }
 
+// Factor setup: float64 copies, Grams, then the eigen-decomposition (eig) or, when
+// only G^{-1} is needed (lambda = 0 solves), the Cholesky route; then the
+// leverage tables.
 static kr_status launch_setup(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T,
-                              const SetupBufs& s, bool leverage) {
+                              const SetupBufs& s, bool leverage, bool eig = true) {
   KL(h, k_zero_bytes, dim3(1), dim3(64), 0, h->stream, (uint32_t*)s.flags, (int64_t)64);
   for (int n = 0; n < g.N; ++n) {
     const int64_t cnt = (int64_t)g.I[n] * g.R[n];
@@ -328,8 +332,25 @@ static kr_status launch_setup(kr_handle h, const kr_problem* p, const Geom& g, c
                        s.A64[n], cnt, s.flags);
   }
   KL(h, k_gram, dim3(g.N), dim3(256), 0, h->stream, T, g, s.gram);
-  KL(h, k_eig, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
-  if (leverage) KL(h, k_leverage, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
+  int maxR = 1;
+  for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
+  if (eig) {
+    KL(h, k_eig, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+  } else if (maxR <= 8) {
+    KLN(h, "k_chol<8>", k_chol<8>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+  } else if (maxR <= 16) {
+    KLN(h, "k_chol<16>", k_chol<16>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+  } else if (maxR <= 32) {
+    KLN(h, "k_chol<32>", k_chol<32>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+  } else {
+    KLN(h, "k_chol<64>", k_chol<64>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+  }
+  if (leverage) {
+    if (maxR <= 8) KLN(h, "k_leverage<8>", k_leverage<8>, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
+    else if (maxR <= 16) KLN(h, "k_leverage<16>", k_leverage<16>, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
+    else if (maxR <= 32) KLN(h, "k_leverage<32>", k_leverage<32>, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
+    else KLN(h, "k_leverage<64>", k_leverage<64>, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
+  }
   HIPCHK(h, hipGetLastError());
   return KR_OK;
 }
@@ -350,6 +371,7 @@ struct SolveBufs {
   double* Q[KR_MAXN + 1];
   double* t0;
   double* t1;
+  double* dinv;
   double* wrow;
   double* part;
   int64_t* rs1;
@@ -372,7 +394,7 @@ static size_t solve_bytes(const Geom& g, int ntiles, int nblocks) {
   for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
   b += 4 * (size_t)(D + 2) + 8 * (size_t)D;
   for (int k = 1; k < g.N; ++k) b += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs;
-  b += 3 * 8 * (size_t)g.Rtot * g.nrhs + sizeof(IterState) + 8 * (KR_MAXN + 1) + 512;
+  b += 3 * 8 * (size_t)g.Rtot * g.nrhs + 8 * (size_t)g.Rtot + sizeof(IterState) + 8 * (KR_MAXN + 1) + 768;
   b += 8 * (size_t)D * g.nrhs + 8 * (size_t)(level_cap(g, 1) + 2) + 512;
   b += 8 * (size_t)((level_cap(g, 1) + 31) / 32) * g.Rtot * g.nrhs + 512;
   for (int k = 1; k < g.N; ++k) b += 4 * (size_t)level_cap(g, k) * g.R[k - 1] + 256;
@@ -400,131 +422,163 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
   KL(h, k_tree_emit, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot, tr);
 }
 
+// Nodes per root-adjoint partial block: a multiple of RA_NODES with at most 64
+// blocks, so that the preconditioner kernel sums the partials itself.
+static int root_npb(const Geom& g) {
+  const int64_t per = (level_cap(g, 1) + 63) / 64;
+  return (int)(RA_NODES * ((per + RA_NODES - 1) / RA_NODES));
+}
+
 // One pass of the sampled products K~^T Omega (K~ x - b~) down and up the sample
-// tree: forward levels 1..N-1 (float64), the rows with the last adjoint level,
-// adjoint levels N-1..2, and (without segment roots) the root adjoint into Q[0].
-// P[0] is the iterate; Q[k] receives level-k results in the adjoint type T
-// (float64, or float32 in the refined precisions; part and Q are then float
-// buffers).
+// tree: forward levels 1..N-1, the rows with the last adjoint level, adjoint
+// levels N-1..2 and, without segment roots, the root adjoint (partial blocks of
+// npb level-1 nodes, then their sum into Q[0]; for N = 1 the rows write Q[0]).
+// P[0] is the iterate; Q[k] and part hold the adjoint type T (float64, or
+// float32 in the refined precisions).
 template <typename T>
 static void launch_level_products(kr_handle h, const ModeTables& TT, const Geom& g, const Tree& tr, double* const* P,
-                                  void* const* Qv, const double* Omega, const double* bD, void* partv,
-                                  const IterState* state) {
+                                 void* const* Qv, const double* Omega, const double* bD, void* partv,
+                                 const IterState* state) {
   hipStream_t s = h->stream;
   T* Q[KR_MAXN + 1];
   for (int k = 0; k <= KR_MAXN; ++k) Q[k] = (T*)Qv[k];
   T* part = (T*)partv;
-  for (int k = 1; k < g.N; ++k) {
-    const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
-    KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, TT, g, tr, k, (const double*)P[k - 1], P[k],
-       state);
-  }
+  const bool f32 = sizeof(T) == 4;
   const int Rl = g.R[g.N - 1];
   const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
-  const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
-  T* qlast = Q[g.N - 1];
-  const double* plast = P[g.N - 1];
-  const dim3 rg(grid_for(rows_threads, 256));
-  const bool f32 = sizeof(T) == 4;
-  switch (G) {
-    case 8:
-      KLN(h, f32 ? "k_rows_adj<8,f32>" : "k_rows_adj<8>", (k_rows_adj<8, T>), rg, dim3(256), 0, s, TT, g, tr, plast,
-          Omega, bD, qlast, state);
-      break;
-    case 16:
-      KLN(h, f32 ? "k_rows_adj<16,f32>" : "k_rows_adj<16>", (k_rows_adj<16, T>), rg, dim3(256), 0, s, TT, g, tr,
-          plast, Omega, bD, qlast, state);
-      break;
-    case 32:
-      KLN(h, f32 ? "k_rows_adj<32,f32>" : "k_rows_adj<32>", (k_rows_adj<32, T>), rg, dim3(256), 0, s, TT, g, tr,
-          plast, Omega, bD, qlast, state);
-      break;
-    default:
-      KLN(h, f32 ? "k_rows_adj<64,f32>" : "k_rows_adj<64>", (k_rows_adj<64, T>), rg, dim3(256), 0, s, TT, g, tr,
-          plast, Omega, bD, qlast, state);
-      break;
-  }
-  for (int k = g.N - 1; k >= 2; --k) {
-    const int64_t work = level_cap(g, k - 1) * g.rsuf[k - 1] * g.nrhs;
-    KLN(h, f32 ? "k_adj_level<f32>" : "k_adj_level", k_adj_level<T>, dim3(grid_for(work, 256)), dim3(256), 0, s, TT,
-        g, tr, k, (const T*)Q[k], Q[k - 1], state);
+  {
+    for (int k = 1; k < g.N; ++k) {
+      const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
+      KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, TT, g, tr, k, (const double*)P[k - 1], P[k],
+         state);
+    }
+    const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
+    T* qlast = Q[g.N - 1];
+    const double* plast = P[g.N - 1];
+    const dim3 rg(grid_for(rows_threads, 256));
+    switch (G) {
+      case 8:
+        KLN(h, f32 ? "k_rows_adj<8,f32>" : "k_rows_adj<8>", (k_rows_adj<8, T>), rg, dim3(256), 0, s, TT, g, tr, plast,
+            Omega, bD, qlast, state);
+        break;
+      case 16:
+        KLN(h, f32 ? "k_rows_adj<16,f32>" : "k_rows_adj<16>", (k_rows_adj<16, T>), rg, dim3(256), 0, s, TT, g, tr,
+            plast, Omega, bD, qlast, state);
+        break;
+      case 32:
+        KLN(h, f32 ? "k_rows_adj<32,f32>" : "k_rows_adj<32>", (k_rows_adj<32, T>), rg, dim3(256), 0, s, TT, g, tr,
+            plast, Omega, bD, qlast, state);
+        break;
+      default:
+        KLN(h, f32 ? "k_rows_adj<64,f32>" : "k_rows_adj<64>", (k_rows_adj<64, T>), rg, dim3(256), 0, s, TT, g, tr,
+            plast, Omega, bD, qlast, state);
+        break;
+    }
+    for (int k = g.N - 1; k >= 2; --k) {
+      const int64_t CE = adj_cols((int)g.R[k - 1]);
+      const int64_t tasks = level_cap(g, k - 1) * ((g.rsuf[k] * g.nrhs + CE - 1) / CE);
+      KLN(h, f32 ? "k_adj_level<f32>" : "k_adj_level", k_adj_level<T>, dim3(grid_for(tasks, 1, 8192)), dim3(256), 0,
+          s, TT, g, tr, k, (const T*)Q[k], Q[k - 1], state);
+    }
   }
   if (g.N >= 2 && !g.seg_root) {
-    const int64_t CEr = g.R[0] >= 256 ? 1 : 256 / g.R[0];
+    const int npb = root_npb(g);
+    const int64_t CEr = adj_cols((int)g.R[0]);
     const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
-    const int64_t nnb = (level_cap(g, 1) + RA_NODES - 1) / RA_NODES;
+    const int64_t nnb = (level_cap(g, 1) + npb - 1) / npb;
     KLN(h, f32 ? "k_adj_root_partial<f32>" : "k_adj_root_partial", k_adj_root_partial<T>,
-        dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr, (const T*)Q[1], part, state);
+        dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr, (const T*)Q[1], part, npb, state);
     KLN(h, f32 ? "k_adj_root_sum<f32>" : "k_adj_root_sum", k_adj_root_sum<T>,
-        dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr, (const T*)part, Q[0], state);
+        dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr, (const T*)part, npb, Q[0], state);
   }
 }
 
-// The float64 preconditioner step, instantiated per fibre width (bucket of max R_n).
-static void launch_precond_update(kr_handle h, const ModeTables& T, const Geom& g, const double* grad, double* x,
-                                  double* t0, double* t1, double lambda, double eta, double tol, int max_iter,
-                                  IterState* st) {
-  hipStream_t s = h->stream;
-  int maxR = 1;
-  for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
-  const int ginv = lambda == 0.0 ? 1 : 0;
-  if (maxR <= 8)
-    KLN(h, "k_precond_update<8>", k_precond_update<8>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda, eta,
-        tol, max_iter, ginv, st);
-  else if (maxR <= 16)
-    KLN(h, "k_precond_update<16>", k_precond_update<16>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda,
-        eta, tol, max_iter, ginv, st);
-  else if (maxR <= 32)
-    KLN(h, "k_precond_update<32>", k_precond_update<32>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda,
-        eta, tol, max_iter, ginv, st);
-  else
-    KLN(h, "k_precond_update<64>", k_precond_update<64>, dim3(1), dim3(256), 0, s, T, g, grad, x, t0, t1, lambda,
-        eta, tol, max_iter, ginv, st);
+// Dynamic LDS for the two tensor buffers of a preconditioner kernel, or 0 (then
+// the kernel works in t0/t1): at most 64 KB beside its static matrix stage.
+static size_t precond_lds(const Geom& g, size_t elem) {
+  const size_t b = 2 * elem * (size_t)(g.Rtot * g.nrhs);
+  return b <= 64 * 1024 ? b : 0;
 }
 
-// The refined-precision preconditioner step, instantiated per precision and per
-// number of 16-blocks along the widest mode.
-template <int MODE>
-static void launch_precond_mp_nb(kr_handle h, int nb, size_t lds, const ModeTables& T, const Geom& g,
-                                 const float* gr, double* x, float* t0, float* t1, double lambda, double eta,
-                                 double tol, int max_iter, int use_ginv, IterState* st) {
-  hipStream_t s = h->stream;
-  const int L = lds > 0;
+// Allow `bytes` of dynamic LDS for kernel fn (beyond the default limit); false
+// when the device refuses, and the caller then works without it.
+static bool allow_dynamic_lds(const void* fn, size_t bytes) {
+  if (bytes == 0) return true;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
+// Number of 16-blocks along the widest mode (1..4).
+static int mode_blocks(const Geom& g) {
+  int maxR = 1;
+  for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
+  return std::min(4, (maxR + 15) / 16);
+}
+
+struct PrecondArgs {
+  const void* grad;     // float64 or float32 gradient (Rtot x nrhs)
+  const double* dinv;   // diagonal of the eigenvector form (Rtot)
+  double* x;
+  void* t0;
+  void* t1;
+  double lambda, eta, tol;
+  int max_iter, use_ginv;
+  IterState* st;
+};
+
+template <int NB>
+static void launch_precond_f64_nb(kr_handle h, const ModeTables& T, const Geom& g, const PrecondArgs& a) {
+  static const char* names[] = {"k_precond_update<1>", "k_precond_update<2>", "k_precond_update<3>",
+                                "k_precond_update<4>"};
+  size_t lds = precond_lds(g, 8);
+  if (!allow_dynamic_lds((const void*)k_precond_update<NB>, lds)) {
+    (void)hipGetLastError();
+    lds = 0;
+  }
+  KLN(h, names[NB - 1], k_precond_update<NB>, dim3(1), dim3(256), lds, h->stream, T, g, (const double*)a.grad,
+      a.dinv, a.x, (double*)a.t0, (double*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol, a.max_iter, a.use_ginv,
+      a.st);
+}
+
+template <int MODE, int NB>
+static void launch_precond_mp_nb(kr_handle h, const ModeTables& T, const Geom& g, const PrecondArgs& a) {
   static const char* names[4][4] = {
       {"", "", "", ""},
       {"k_precond_mp<f32,1>", "k_precond_mp<f32,2>", "k_precond_mp<f32,3>", "k_precond_mp<f32,4>"},
       {"k_precond_mp<bf16,1>", "k_precond_mp<bf16,2>", "k_precond_mp<bf16,3>", "k_precond_mp<bf16,4>"},
       {"k_precond_mp<fp8,1>", "k_precond_mp<fp8,2>", "k_precond_mp<fp8,3>", "k_precond_mp<fp8,4>"}};
-  const char* nm = names[MODE][std::min(std::max(nb, 1), 4) - 1];
-  switch (nb) {
-    case 1:
-      KLN(h, nm, (k_precond_mp<MODE, 1>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
-          max_iter, use_ginv, st);
-      break;
-    case 2:
-      KLN(h, nm, (k_precond_mp<MODE, 2>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
-          max_iter, use_ginv, st);
-      break;
-    case 3:
-      KLN(h, nm, (k_precond_mp<MODE, 3>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
-          max_iter, use_ginv, st);
-      break;
-    default:
-      KLN(h, nm, (k_precond_mp<MODE, 4>), dim3(1), dim3(256), lds, s, T, g, gr, x, t0, t1, L, lambda, eta, tol,
-          max_iter, use_ginv, st);
-      break;
+  size_t lds = precond_lds(g, 4);
+  if (!allow_dynamic_lds((const void*)k_precond_mp<MODE, NB>, lds)) {
+    (void)hipGetLastError();
+    lds = 0;
+  }
+  KLN(h, names[MODE][NB - 1], (k_precond_mp<MODE, NB>), dim3(1), dim3(256), lds, h->stream, T, g,
+      (const float*)a.grad, a.dinv, a.x, (float*)a.t0, (float*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol,
+      a.max_iter, a.use_ginv, a.st);
+}
+
+template <int MODE>
+static void launch_precond_mode(kr_handle h, int nb, const ModeTables& T, const Geom& g, const PrecondArgs& a) {
+  if (MODE == KR_PREC_F64) {
+    if (nb == 1) launch_precond_f64_nb<1>(h, T, g, a);
+    else if (nb == 2) launch_precond_f64_nb<2>(h, T, g, a);
+    else if (nb == 3) launch_precond_f64_nb<3>(h, T, g, a);
+    else launch_precond_f64_nb<4>(h, T, g, a);
+  } else {
+    constexpr int M = MODE == KR_PREC_F64 ? KR_PREC_F32 : MODE;
+    if (nb == 1) launch_precond_mp_nb<M, 1>(h, T, g, a);
+    else if (nb == 2) launch_precond_mp_nb<M, 2>(h, T, g, a);
+    else if (nb == 3) launch_precond_mp_nb<M, 3>(h, T, g, a);
+    else launch_precond_mp_nb<M, 4>(h, T, g, a);
   }
 }
 
-static void launch_precond_mp(kr_handle h, int prec, int nb, size_t lds, const ModeTables& T, const Geom& g,
-                              const float* gr, double* x, float* t0, float* t1, double lambda, double eta, double tol,
-                              int max_iter, int use_ginv, IterState* st) {
-  if (prec == KR_PREC_F32)
-    launch_precond_mp_nb<KR_PREC_F32>(h, nb, lds, T, g, gr, x, t0, t1, lambda, eta, tol, max_iter, use_ginv, st);
-  else if (prec == KR_PREC_BF16)
-    launch_precond_mp_nb<KR_PREC_BF16>(h, nb, lds, T, g, gr, x, t0, t1, lambda, eta, tol, max_iter, use_ginv, st);
-  else
-    launch_precond_mp_nb<KR_PREC_FP8>(h, nb, lds, T, g, gr, x, t0, t1, lambda, eta, tol, max_iter, use_ginv, st);
+// One preconditioner step in precision prec.
+static void launch_precond(kr_handle h, int prec, const ModeTables& T, const Geom& g, const PrecondArgs& a) {
+  const int nb = mode_blocks(g);
+  if (prec == KR_PREC_F64) launch_precond_mode<KR_PREC_F64>(h, nb, T, g, a);
+  else if (prec == KR_PREC_F32) launch_precond_mode<KR_PREC_F32>(h, nb, T, g, a);
+  else if (prec == KR_PREC_BF16) launch_precond_mode<KR_PREC_BF16>(h, nb, T, g, a);
+  else launch_precond_mode<KR_PREC_FP8>(h, nb, T, g, a);
 }
 
 static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
@@ -597,6 +651,7 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   B.Q[0] = a.take<double>((size_t)g.Rtot * g.nrhs);
   B.t0 = a.take<double>((size_t)g.Rtot * g.nrhs);
   B.t1 = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B.dinv = a.take<double>((size_t)g.Rtot);
   B.wrow = a.take<double>((size_t)Dcap * g.nrhs);
   B.part = a.take<double>((size_t)((level_cap(g, 1) + RA_NODES - 1) / RA_NODES) * g.Rtot * g.nrhs);
   B.rs1 = a.take<int64_t>(level_cap(g, 1) + 2);
@@ -608,7 +663,10 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
 
   hipStream_t s = h->stream;
   // -- setup: leverage, quantised weights, CDFs
-  st = launch_setup(h, p, g, T, B.s, true);
+  // the eigenvectors are needed for lambda > 0 (the (kron Lambda + lambda)^+ form),
+  // fp8 (eigenvector form) and the cooperative iteration; otherwise G^{-1} suffices
+  const bool need_eig = lambda > 0.0 || prec == KR_PREC_FP8 || (o.flags & KR_OPT_COOPERATIVE);
+  st = launch_setup(h, p, g, T, B.s, true, need_eig);
   if (st != KR_OK) return st;
   // -- sampling
   int64_t sumI = 0;
@@ -627,6 +685,8 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     KL(h, k_rows_to_f32, dim3(grid_for(rows32, 256, 1024)), dim3(256), 0, s, g, tr);
   }
   // -- Richardson
+  if (lambda > 0.0 || prec == KR_PREC_FP8)
+    KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, s, T, g, lambda, B.dinv);
   KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, (double*)d_x,
                      g.Rtot * g.nrhs, 0.0);
   KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state,
@@ -695,30 +755,30 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
       KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
     if (h->h_state->diverged == 2) KR_FAIL(h, KR_EHIP, "grid barrier timed out in the persistent iteration");
   } else {
-    // refined precisions: both float tensor buffers of the preconditioner in LDS
-    // when they fit beside its 16 KB matrix stage
-    const size_t mp_lds = 2 * 4 * (size_t)RT <= 48 * 1024 ? 2 * 4 * (size_t)RT : 0;
-    int maxR = 1;
-    for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
-    const int mp_nb = (maxR + 15) / 16;
+    PrecondArgs pa{};
+    pa.grad = B.Q[0];
+    pa.dinv = B.dinv;
+    pa.x = (double*)d_x;
+    pa.t0 = B.t0;
+    pa.t1 = B.t1;
+    pa.lambda = lambda;
+    pa.eta = eta;
+    pa.tol = tol;
+    pa.max_iter = max_iter;
+    pa.use_ginv = lambda == 0.0 ? 1 : 0;
+    pa.st = B.state;
     int iters_enqueued = 0;
     bool flags_checked = false;
     while (iters_enqueued < max_iter) {
       const int chunk = std::min(check_every, max_iter - iters_enqueued);
       for (int it = 0; it < chunk; ++it) {
-        if (prec == KR_PREC_F64) {
+        if (prec == KR_PREC_F64)
           launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
                                         (const IterState*)B.state);
-          launch_precond_update(h, T, g, (const double*)B.Q[0], (double*)d_x, B.t0, B.t1, lambda, eta, tol,
-                                max_iter, B.state);
-        } else {
+        else
           launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
                                        (const IterState*)B.state);
-          const int use_ginv = lambda == 0.0 ? 1 : 0;
-          const float* gr = (const float*)B.Q[0];
-          launch_precond_mp(h, prec, mp_nb, mp_lds, T, g, gr, (double*)d_x, (float*)B.t0, (float*)B.t1, lambda,
-                            eta, tol, max_iter, use_ginv, B.state);
-        }
+        launch_precond(h, prec, T, g, pa);
       }
       iters_enqueued += chunk;
       HIPCHK(h, hipGetLastError());
@@ -822,6 +882,26 @@ kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* 
 // ---------------------------------------------------------------------------
 static int rm_bucket(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64; }
 
+// out[pre][o][post] = sum_r M(o, r) in[pre][r][post]: the fibre kernel for R_in <= 64,
+// the general one otherwise.
+static void launch_mode_product(kr_handle h, const double* in, double* out, int64_t pre, int Rin, int Rout,
+                                int64_t post, const double* M, int trans) {
+  hipStream_t s = h->stream;
+  if (Rin > 64) {
+    KL(h, k_mode_product, dim3(grid_for(pre * Rout * post, 256)), dim3(256), 0, s, in, out, pre, Rin, Rout, post, M,
+       trans);
+    return;
+  }
+  const dim3 grid((unsigned)((post + 255) / 256), (unsigned)((Rout + MP_OUT - 1) / MP_OUT),
+                  (unsigned)std::min<int64_t>(pre, 65535));
+  switch (rm_bucket(Rin)) {
+    case 8: KLN(h, "k_mode_product_fibre<8>", k_mode_product_fibre<8>, grid, dim3(256), 0, s, in, out, pre, Rin, Rout, post, M, trans); break;
+    case 16: KLN(h, "k_mode_product_fibre<16>", k_mode_product_fibre<16>, grid, dim3(256), 0, s, in, out, pre, Rin, Rout, post, M, trans); break;
+    case 32: KLN(h, "k_mode_product_fibre<32>", k_mode_product_fibre<32>, grid, dim3(256), 0, s, in, out, pre, Rin, Rout, post, M, trans); break;
+    default: KLN(h, "k_mode_product_fibre<64>", k_mode_product_fibre<64>, grid, dim3(256), 0, s, in, out, pre, Rin, Rout, post, M, trans); break;
+  }
+}
+
 kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void* d_x, double* h_loss) {
   if (!h) return KR_EINVAL;
   Geom g;
@@ -840,7 +920,9 @@ kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void*
     maxsz = std::max(maxsz, sz);
   }
   const int64_t C = (g.Itot / g.I[0]) * g.nrhs;
-  size_t need = setup_bytes(g) + 2 * 8 * (size_t)maxsz + 8 * (size_t)C + 8 * 64 + 4096;
+  // block sums of the stream: one per workgroup of 16 * SL_WAVES columns and RHS
+  const size_t nparts_max = (size_t)((C + 16 * SL_WAVES - 1) / (16 * SL_WAVES)) * g.nrhs;
+  size_t need = setup_bytes(g) + 2 * 8 * (size_t)maxsz + 8 * nparts_max + 8 * 64 + 4096;
   st = ensure(h, &h->aux, &h->aux_bytes, need);
   if (st != KR_OK) return st;
   Arena a{(char*)h->aux, h->aux_bytes, 0};
@@ -849,7 +931,7 @@ kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void*
   carve_setup(a, g, &T, &S);
   double* buf0 = a.take<double>(maxsz);
   double* buf1 = a.take<double>(maxsz);
-  double* partial = a.take<double>(C);
+  double* partial = a.take<double>(nparts_max);
   double* out = a.take<double>(64);
   hipStream_t s = h->stream;
   KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)S.flags, (int64_t)64);
@@ -865,20 +947,22 @@ kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void*
     int64_t pre = 1, post = g.nrhs;
     for (int k = 0; k < n; ++k) pre *= dims[k];
     for (int k = n + 1; k < g.N; ++k) post *= dims[k];
-    KL(h, k_mode_product, dim3(grid_for(pre * g.I[n] * post, 256)), dim3(256), 0, s, cur, dst, pre,
-                       g.R[n], g.I[n], post, (const double*)S.A64[n], 0);
+    launch_mode_product(h, cur, dst, pre, (int)g.R[n], (int)g.I[n], post, (const double*)S.A64[n], 0);
     dims[n] = g.I[n];
     cur = dst;
     dst = dst == buf0 ? buf1 : buf0;
   }
-  const dim3 sg(grid_for(C, 256, int64_t(1) << 30));
+  // one workgroup of SL_WAVES waves per 16 * SL_WAVES columns
+  const int64_t nbx = (C + 16 * SL_WAVES - 1) / (16 * SL_WAVES);
+  const dim3 sg((unsigned)nbx);
+  const dim3 sb(64 * SL_WAVES);
   switch (rm_bucket(g.R[0])) {
-    case 8: KL(h, k_stream_loss<8>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
-    case 16: KL(h, k_stream_loss<16>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
-    case 32: KL(h, k_stream_loss<32>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
-    default: KL(h, k_stream_loss<64>, sg, dim3(256), 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, partial); break;
+    case 8: KLN(h, "k_stream_loss<8>", k_stream_loss<2>, sg, sb, 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, g.nrhs, partial); break;
+    case 16: KLN(h, "k_stream_loss<16>", k_stream_loss<4>, sg, sb, 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, g.nrhs, partial); break;
+    case 32: KLN(h, "k_stream_loss<32>", k_stream_loss<8>, sg, sb, 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, g.nrhs, partial); break;
+    default: KLN(h, "k_stream_loss<64>", k_stream_loss<16>, sg, sb, 0, s, (const double*)S.A64[0], g.I[0], g.R[0], cur, p->b, p->b_dtype, C, g.nrhs, partial); break;
   }
-  KL(h, k_finish_loss, dim3(g.nrhs), dim3(1024), 0, s, (const double*)partial, C, (const double*)d_x,
+  KL(h, k_finish_loss, dim3(g.nrhs), dim3(1024), 0, s, (const double*)partial, nbx, (const double*)d_x,
                      g.Rtot, g.nrhs, lambda, out);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h_loss, out, g.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -943,8 +1027,7 @@ kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x)
     for (int k = 0; k < n; ++k) pre *= g.R[k];
     for (int k = n + 1; k < g.N; ++k) post *= g.R[k];
     double* o = (n == g.N - 1) ? (double*)d_x : dst;
-    KL(h, k_mode_product, dim3(grid_for(pre * g.R[n] * post, 256)), dim3(256), 0, s,
-                       (const double*)cur, o, pre, g.R[n], g.R[n], post, (const double*)T.V[n], 0);
+    launch_mode_product(h, (const double*)cur, o, pre, (int)g.R[n], (int)g.R[n], post, (const double*)T.V[n], 0);
     if (n != g.N - 1) std::swap(cur, dst);
   }
   HIPCHK(h, hipGetLastError());

@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree t
 
 // Rows and the last adjoint level, fused.  A group of G lanes (power of two
 // >= R_{N-1}) owns one (level-(N-1) node p, rhs q); lane r keeps P[p][r][q] and
-// accumulates Q[p][r][q] over the children rows of p, four rows per step.  The
+// accumulates Q[p][r][q] over the children rows of p, eight rows per step (their
+// loads issued together).  The
 // row dot product and the residual u_j = <a, P> - b_j are float64; the weighted
 // residual Omega_j u_j is then accumulated in T (float64, or float32 in the
 // refined modes).
@@ -104,23 +105,23 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
     const int j0 = active ? tr.fchild[N - 1][p] : 0;
     const int j1 = active ? tr.fchild[N - 1][p + 1] : 0;
     int j = j0;
-    for (; j + 4 <= j1; j += 4) {
-      double av[4], y[4], om[4], bb[4];
+    for (; j + 8 <= j1; j += 8) {
+      double av[8], y[8], om[8], bb[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         av[u] = ln ? AL[(int64_t)(j + u) * R + lane] : 0.0;
         om[u] = Omega[j + u];
         bb[u] = bD[(int64_t)(j + u) * nrhs + q];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) y[u] = av[u] * pv;
+      for (int u = 0; u < 8; ++u) y[u] = av[u] * pv;
 #pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, G);
+        for (int u = 0; u < 8; ++u) y[u] += __shfl_xor(y[u], o, G);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = fma((T)(om[u] * (y[u] - bb[u])), (T)av[u], acc);
+      for (int u = 0; u < 8; ++u) acc = fma((T)(om[u] * (y[u] - bb[u])), (T)av[u], acc);
     }
     for (; j < j1; ++j) {
       const double a = ln ? AL[(int64_t)j * R + lane] : 0.0;
@@ -133,207 +134,109 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
   }
 }
 
-// Adjoint level k (k = N-1 .. 2): Q_{k-1}[p][r][c][q] = sum_s a_{k-1}[i(s)][r] Q_k[s][c][q].
+// Adjoint of one block of nodes: out[r][e0 + c] = sum_{s in [s0, s1)} a[s][r] q[s][e0 + c]
+// for r < Rk and the column block c < CE of the W columns.  Thread (r, c) keeps one
+// sum; up to RA_NODES nodes' factor rows and q columns (at most ADJ_QS entries)
+// are staged in LDS at a time and added in increasing node order.  Used for the
+// adjoint levels (the children of one parent) and the root adjoint (a block of
+// level-1 nodes).
+#define RA_NODES 32
+#define ADJ_QS 2048
+template <typename T>
+__device__ void adj_block(const T* __restrict__ arow, int Rk, const T* __restrict__ q, unsigned W, unsigned s0,
+                          unsigned s1, unsigned e0, unsigned CE, T* __restrict__ out, T* as, T* qs) {
+  const unsigned r0 = threadIdx.x / CE, c = threadIdx.x - r0 * CE;
+  const bool mine = r0 < (unsigned)Rk && e0 + c < W;
+  const unsigned chunk = min((unsigned)RA_NODES, (unsigned)ADJ_QS / CE);
+  T acc = 0;
+  for (unsigned b0 = s0; b0 < s1; b0 += chunk) {
+    const unsigned ns = min(chunk, s1 - b0);
+    __syncthreads();
+    for (unsigned i = threadIdx.x; i < ns * (unsigned)Rk; i += blockDim.x) as[i] = arow[(size_t)b0 * Rk + i];
+    for (unsigned i = threadIdx.x; i < ns * CE; i += blockDim.x) {
+      const unsigned sn = i / CE, cc = i - sn * CE;
+      qs[i] = e0 + cc < W ? q[(size_t)(b0 + sn) * W + e0 + cc] : T(0);
+    }
+    __syncthreads();
+    if (mine)
+      for (unsigned sn = 0; sn < ns; ++sn) acc = fma(as[sn * Rk + r0], qs[sn * CE + c], acc);
+  }
+  if (mine) out[(size_t)r0 * W + e0 + c] = acc;
+}
+
+__host__ __device__ __forceinline__ unsigned adj_cols(int Rk) { return Rk >= 256 ? 1u : 256u / (unsigned)Rk; }
+
+// Adjoint level k (k = N-1 .. 2): Q_{k-1}[p][r][c] = sum_{s child of p} a_{k-1}[i(s)][r]
+// Q_k[s][c] (c < rsuf[k] nrhs).  One task per (parent, column block).
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_level(ModeTables TT, Geom g, Tree tr, int k,
                                                   const T* __restrict__ Qk,
                                                   T* __restrict__ Qout,
                                                   const IterState* __restrict__ st) {
   if (st->all_done) return;
+  __shared__ T as[RA_NODES * 64];
+  __shared__ T qs[ADJ_QS];
   const unsigned Sp = (unsigned)tr.cnt[k - 1];
-  const unsigned W = (unsigned)(g.rsuf[k] * g.nrhs);
-  const unsigned Wp = (unsigned)(g.rsuf[k - 1] * g.nrhs);
   const int Rk = g.R[k - 1];
+  const unsigned W = (unsigned)(g.rsuf[k] * g.nrhs);
+  const unsigned CE = adj_cols(Rk);
+  const unsigned ncb = (W + CE - 1) / CE;
   const T* __restrict__ arow = node_rows<T>(tr, k);
-  const unsigned total = Sp * Wp;
-  const unsigned step = gridDim.x * blockDim.x;
-  const unsigned e0 = blockIdx.x * blockDim.x + threadIdx.x;
-  GDiv di(e0, Wp, step);
-  for (unsigned e = e0; e < total; e += step, di.next()) {
-    const unsigned p = di.q, rem = di.r;
-    const unsigned r = rem / W, cq = rem - r * W;
-    const int s0 = tr.fchild[k - 1][p], s1 = tr.fchild[k - 1][p + 1];
-    T acc = 0;
-    int s = s0;
-    for (; s + 4 <= s1; s += 4) {
-      T av[4], qv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        av[u] = arow[(size_t)(s + u) * Rk + r];
-        qv[u] = Qk[(size_t)(s + u) * W + cq];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = fma(av[u], qv[u], acc);
-    }
-    for (; s < s1; ++s) acc = fma(arow[(size_t)s * Rk + r], Qk[(size_t)s * W + cq], acc);
-    Qout[e] = acc;
+  for (unsigned task = blockIdx.x; task < Sp * ncb; task += gridDim.x) {
+    const unsigned p = task / ncb, cb = task - p * ncb;
+    adj_block(arow, Rk, Qk, W, (unsigned)tr.fchild[k - 1][p], (unsigned)tr.fchild[k - 1][p + 1], cb * CE, CE,
+              Qout + (size_t)p * Rk * W, as, qs);
   }
 }
 
-// Root adjoint, split over blocks of level-1 nodes: partial[b][r0][c] =
-// sum_{s in block b} a_0[i(s)][r0] Q_1[s][c].  Workgroup (column block, node block)
-// stages its node block's factor rows and Q_1 columns in LDS.
-#define RA_NODES 32
+// Root adjoint, split over blocks of npb level-1 nodes (npb a multiple of
+// RA_NODES): partial[b][r0][c] = sum_{s in block b} a_0[i(s)][r0] Q_1[s][c].
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const T* __restrict__ Q1,
-                                                         T* __restrict__ partial,
+                                                         T* __restrict__ partial, int npb,
                                                          const IterState* __restrict__ st) {
   if (st->all_done) return;
   __shared__ T as[RA_NODES * 64];
-  __shared__ T qs[RA_NODES * 256];
-  const T* __restrict__ arow1 = node_rows<T>(tr, 1);
+  __shared__ T qs[ADJ_QS];
   const unsigned S1 = (unsigned)tr.cnt[1];
   const int R0 = g.R[0];
   const unsigned W1 = (unsigned)(g.rsuf[1] * g.nrhs);
-  const unsigned CE = R0 >= 256 ? 1u : 256u / (unsigned)R0;
+  const unsigned CE = adj_cols(R0);
   const unsigned ncb = (W1 + CE - 1) / CE;
-  const unsigned nnb = (S1 + RA_NODES - 1) / RA_NODES;
+  const unsigned nnb = (S1 + npb - 1) / npb;
   for (unsigned task = blockIdx.x; task < ncb * nnb; task += gridDim.x) {
     const unsigned cb = task % ncb, nbk = task / ncb;
-    const unsigned e0 = cb * CE, s0 = nbk * RA_NODES;
-    const unsigned ns = (S1 - s0) < RA_NODES ? (S1 - s0) : RA_NODES;
-    for (unsigned i = threadIdx.x; i < ns * (unsigned)R0; i += blockDim.x) as[i] = arow1[(size_t)s0 * R0 + i];
-    for (unsigned i = threadIdx.x; i < ns * CE; i += blockDim.x) {
-      const unsigned sn = i / CE, c = i - sn * CE;
-      qs[i] = e0 + c < W1 ? Q1[(size_t)(s0 + sn) * W1 + e0 + c] : T(0);
-    }
-    __syncthreads();
-    const unsigned r0 = threadIdx.x / CE, c = threadIdx.x - r0 * CE;
-    if (r0 < (unsigned)R0 && e0 + c < W1) {
-      T acc = 0;
-      for (unsigned sn = 0; sn < ns; ++sn) acc = fma(as[sn * R0 + r0], qs[sn * CE + c], acc);
-      partial[(size_t)nbk * g.Rtot * g.nrhs + (size_t)r0 * W1 + e0 + c] = acc;
-    }
-    __syncthreads();
+    const unsigned b0 = nbk * (unsigned)npb;
+    adj_block(node_rows<T>(tr, 1), R0, Q1, W1, b0, min(S1, b0 + (unsigned)npb), cb * CE, CE,
+              partial + (size_t)nbk * g.Rtot * g.nrhs, as, qs);
   }
 }
 
-// g = sum over node blocks of the partials, in block order (deterministic).
+// Partial blocks of the root adjoint: ceil(S_1 / npb); npb = 0 means the
+// gradient was written directly (one block).
+__device__ __forceinline__ unsigned root_blocks(const int64_t* __restrict__ cnt, int npb) {
+  return npb > 0 ? (unsigned)((cnt[1] + npb - 1) / npb) : 1u;
+}
+
+// g = sum over the partial blocks in block order (deterministic).  Each thread
+// issues the loads of up to 16 blocks at once before adding them in order.
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_root_sum(Geom g, Tree tr, const T* __restrict__ partial,
+__global__ void __launch_bounds__(256) k_adj_root_sum(Geom g, Tree tr, const T* __restrict__ partial, int npb,
                                                      T* __restrict__ grad, const IterState* __restrict__ st) {
   if (st->all_done) return;
-  const unsigned S1 = (unsigned)tr.cnt[1];
-  const unsigned nnb = (S1 + RA_NODES - 1) / RA_NODES;
+  const unsigned nnb = root_blocks(tr.cnt, npb);
   const size_t RT = (size_t)g.Rtot * g.nrhs;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < RT; e += (size_t)gridDim.x * blockDim.x) {
     T acc = 0;
-    for (unsigned b = 0; b < nnb; ++b) acc += partial[(size_t)b * RT + e];
+    for (unsigned b0 = 0; b0 < nnb; b0 += 16) {
+      T v[16];
+#pragma unroll
+      for (unsigned u = 0; u < 16; ++u) v[u] = b0 + u < nnb ? partial[(size_t)(b0 + u) * RT + e] : T(0);
+#pragma unroll
+      for (unsigned u = 0; u < 16; ++u)
+        if (b0 + u < nnb) acc += v[u];
+    }
     grad[e] = acc;
-  }
-}
-
-// Mode product inside one workgroup: out = in x_n M, M is R_n x R_n (M[a][b]),
-// transposed when trans != 0.  Tensor layout [R_0..R_{N-1}][nrhs].  Each thread
-// owns whole mode-n fibres: it reads the fibre once into registers and forms all
-// R_n outputs.
-template <int RM>
-__device__ void wg_mode_fibre(const Geom& g, int n, const double* __restrict__ M, int trans,
-                              const double* in, double* out) {
-  const int Rn = g.R[n];
-  const unsigned post = (unsigned)(g.rsuf[n + 1] * g.nrhs);
-  const unsigned nfib = (unsigned)(g.Rtot * g.nrhs) / (unsigned)Rn;
-  GDiv di(threadIdx.x, post, blockDim.x);
-  for (unsigned f = threadIdx.x; f < nfib; f += blockDim.x, di.next()) {
-    const size_t base = (size_t)di.q * Rn * post + di.r;
-    double v[RM];
-#pragma unroll
-    for (int b = 0; b < RM; ++b) v[b] = b < Rn ? in[base + (size_t)b * post] : 0.0;
-    for (int a = 0; a < Rn; ++a) {
-      double acc = 0.0;
-#pragma unroll
-      for (int b = 0; b < RM; ++b)
-        if (b < Rn) acc = fma(trans ? M[b * Rn + a] : M[a * Rn + b], v[b], acc);
-      out[base + (size_t)a * post] = acc;
-    }
-  }
-}
-
-// d = M^+ (g + lambda x); x <- x - eta d for right-hand sides not yet converged;
-// per-RHS norms, stopping rule eta ||d|| <= tol ||x||, divergence test.
-// One workgroup of 256 threads.  t0/t1 are Rtot x nrhs scratch buffers; each
-// factor matrix is staged in LDS before its mode product.  RM (8, 16, 32 or 64)
-// bounds every R_n: one fibre width per kernel keeps the fibre in registers.
-template <int RM>
-__global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
-                                                        double* __restrict__ x, double* __restrict__ t0,
-                                                        double* __restrict__ t1, double lambda, double eta,
-                                                        double tol, int max_iter, int use_ginv,
-                                                        IterState* __restrict__ st) {
-  __shared__ double red[16];
-  __shared__ double ms[64 * 64];
-  if (st->all_done) return;
-  const int64_t total = g.Rtot * g.nrhs;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) t0[e] = grad[e] + lambda * x[e];
-  double* cur = t0;
-  double* nxt = t1;
-  auto stage = [&](const double* M, int n) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < g.R[n] * g.R[n]; e += blockDim.x) ms[e] = M[e];
-    __syncthreads();
-  };
-  if (use_ginv) {
-    for (int n = 0; n < g.N; ++n) {
-      stage(T.Ginv[n], n);
-      wg_mode_fibre<RM>(g, n, ms, 0, cur, nxt);
-      double* tmp = cur; cur = nxt; nxt = tmp;
-    }
-  } else {
-    for (int n = 0; n < g.N; ++n) {
-      stage(T.V[n], n);
-      wg_mode_fibre<RM>(g, n, ms, 1, cur, nxt);
-      double* tmp = cur; cur = nxt; nxt = tmp;
-    }
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-      int64_t r = e / g.nrhs;
-      double prod = 1.0;
-      for (int n = g.N - 1; n >= 0; --n) {
-        const int rn = (int)(r % g.R[n]);
-        r /= g.R[n];
-        prod *= T.evals[n][rn];
-      }
-      const double den = prod + lambda;
-      cur[e] = den > 0.0 ? cur[e] / den : 0.0;
-    }
-    for (int n = 0; n < g.N; ++n) {
-      stage(T.V[n], n);
-      wg_mode_fibre<RM>(g, n, ms, 0, cur, nxt);
-      double* tmp = cur; cur = nxt; nxt = tmp;
-    }
-  }
-  __syncthreads();
-  // cur = d.  Update and norms per right-hand side.
-  const int it = st->iters;
-  int all = 1, div = 0;
-  for (int q = 0; q < g.nrhs; ++q) {
-    const int done = st->done[q];
-    double dd = 0.0, xx = 0.0;
-    for (int64_t r = threadIdx.x; r < g.Rtot; r += blockDim.x) {
-      const int64_t e = r * g.nrhs + q;
-      const double d = cur[e];
-      double xv = x[e];
-      if (!done) { xv = fma(-eta, d, xv); x[e] = xv; }
-      dd = fma(d, d, dd);
-      xx = fma(xv, xv, xx);
-    }
-    dd = block_sum(dd, red);
-    xx = block_sum(xx, red);
-    if (threadIdx.x == 0 && !done) {
-      const double dn = sqrt(dd), xn = sqrt(xx);
-      const double rel = xn > 0.0 ? eta * dn / xn : (dn > 0.0 ? INFINITY : 0.0);
-      st->rel[q] = rel;
-      if (it == 0) st->dnorm0[q] = dn;
-      const bool bad = !isfinite(dn) || !isfinite(xn) || (it > 0 && dn > 1e6 * st->dnorm0[q] && dn > 0.0);
-      if (bad) { div = 1; }
-      if (rel <= tol || bad) { st->done[q] = 1; st->it_rhs[q] = it + 1; }
-    }
-    if (threadIdx.x == 0) all &= st->done[q];
-  }
-  if (threadIdx.x == 0) {
-    st->iters = it + 1;
-    if (div) st->diverged = 1;
-    if (all || div || it + 1 >= max_iter) st->all_done = 1;
   }
 }
 

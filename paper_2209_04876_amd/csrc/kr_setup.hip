@@ -58,10 +58,13 @@ __global__ void __launch_bounds__(256) k_gram(ModeTables T, Geom g, double* __re
 }
 
 // One wave per mode.  Two-sided Jacobi with the round-robin (tournament)
-// ordering: each round applies floor(R/2) disjoint rotations at once (columns
-// A <- A J and V <- V J, then rows A <- J^T A); R-1 rounds make a sweep.  A
-// rotation is skipped when |a_pq| is below rounding relative to
-// sqrt(|a_pp a_qq|); sweeps stop when a sweep performs no rotation.
+// ordering: each round applies floor(R/2) disjoint rotations at once, A <- J^T A J
+// and V <- V J; R-1 rounds (R even; R rounds with a dummy player when R is odd)
+// make a sweep.  The rotations of a round act on disjoint index pairs, so the
+// update splits into independent 2x2 blocks (rows of pair k, columns of pair l),
+// each transformed by one lane.  A rotation is skipped when |a_pq| <=
+// 1e-16 sqrt(|a_pp a_qq|) (the rounding level); sweeps stop when a sweep performs
+// no rotation.
 __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* __restrict__ gram,
                                             int32_t* __restrict__ flags) {
   __shared__ double a[KR_RMAX * KR_RMAX];
@@ -79,6 +82,7 @@ __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* 
   }
   const int mpl = (R & 1) ? R + 1 : R;   // players in the round-robin (dummy = R when odd)
   const int npair = mpl / 2;
+  const int nblk = npair * npair;
   __syncthreads();
   for (int sweep = 0; sweep < 60 && R > 1; ++sweep) {
     if (lane == 0) rotated = 0;
@@ -87,15 +91,15 @@ __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* 
       if (lane < npair) {
         int p, q;
         if (lane == 0) { p = mpl - 1; q = round; }
-        else { p = (round + lane) % (mpl - 1); q = (round - lane + (mpl - 1)) % (mpl - 1); }
+        else {
+          p = round + lane; if (p >= mpl - 1) p -= mpl - 1;
+          q = round - lane; if (q < 0) q += mpl - 1;
+        }
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, sn = 0.0;
-        bool act = q < R;
-        if (act) {
+        if (q < R) {
           const double apq = a[p * R + q], app = a[p * R + p], aqq = a[q * R + q];
-          if (apq == 0.0 || fabs(apq) <= 1e-17 * sqrt(fabs(app * aqq))) {
-            act = false;
-          } else {
+          if (!(apq == 0.0 || fabs(apq) <= 1e-16 * sqrt(fabs(app * aqq)))) {
             const double theta = (aqq - app) / (2.0 * apq);
             const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -104,34 +108,39 @@ __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* 
           }
         }
         cs_c[lane] = c; cs_s[lane] = sn;
-        cs_p[lane] = act ? p : -1; cs_q[lane] = q;
+        cs_p[lane] = p; cs_q[lane] = q;   // q == R marks the dummy
       }
       __syncthreads();
-      // columns of A and V: for row i and pair k
-      for (int e = lane; e < R * npair; e += 64) {
-        const int k = e % npair, i = e / npair;
-        const int p = cs_p[k];
-        if (p < 0) continue;
-        const int q = cs_q[k];
-        const double c = cs_c[k], sn = cs_s[k];
-        const double aip = a[i * R + p], aiq = a[i * R + q];
-        a[i * R + p] = c * aip - sn * aiq;
-        a[i * R + q] = sn * aip + c * aiq;
-        const double vip = v[i * R + p], viq = v[i * R + q];
-        v[i * R + p] = c * vip - sn * viq;
-        v[i * R + q] = sn * vip + c * viq;
+      // A <- J^T A J by 2x2 blocks: rows {p_k, q_k} x columns {p_l, q_l}
+      for (int b = lane; b < nblk; b += 64) {
+        const int k = b / npair, l = b - k * npair;
+        const int pk = cs_p[k], qk = cs_q[k], pl = cs_p[l], ql = cs_q[l];
+        const double ck = cs_c[k], sk = cs_s[k], cl = cs_c[l], sl = cs_s[l];
+        const bool qkv = qk < R, qlv = ql < R;
+        const double b00 = a[pk * R + pl];
+        const double b01 = qlv ? a[pk * R + ql] : 0.0;
+        const double b10 = qkv ? a[qk * R + pl] : 0.0;
+        const double b11 = (qkv && qlv) ? a[qk * R + ql] : 0.0;
+        // columns: [x0 x1] <- [c x0 - s x1, s x0 + c x1] with pair l
+        const double c00 = cl * b00 - sl * b01, c01 = sl * b00 + cl * b01;
+        const double c10 = cl * b10 - sl * b11, c11 = sl * b10 + cl * b11;
+        // rows with pair k; the element a rotation annihilates is set to exactly
+        // zero (left to rounding it would keep re-triggering rotations)
+        const bool annihilated = k == l && sk != 0.0;
+        a[pk * R + pl] = ck * c00 - sk * c10;
+        if (qlv) a[pk * R + ql] = annihilated ? 0.0 : ck * c01 - sk * c11;
+        if (qkv) a[qk * R + pl] = annihilated ? 0.0 : sk * c00 + ck * c10;
+        if (qkv && qlv) a[qk * R + ql] = sk * c01 + ck * c11;
       }
-      __syncthreads();
-      // rows of A: for column j and pair k
+      // V <- V J: row i, pair l
       for (int e = lane; e < R * npair; e += 64) {
-        const int k = e % npair, j = e / npair;
-        const int p = cs_p[k];
-        if (p < 0) continue;
-        const int q = cs_q[k];
-        const double c = cs_c[k], sn = cs_s[k];
-        const double apj = a[p * R + j], aqj = a[q * R + j];
-        a[p * R + j] = c * apj - sn * aqj;
-        a[q * R + j] = sn * apj + c * aqj;
+        const int i = e / npair, l = e - i * npair;
+        const int pl = cs_p[l], ql = cs_q[l];
+        if (ql >= R) continue;
+        const double cl = cs_c[l], sl = cs_s[l];
+        const double vip = v[i * R + pl], viq = v[i * R + ql];
+        v[i * R + pl] = cl * vip - sl * viq;
+        v[i * R + ql] = sl * vip + cl * viq;
       }
       __syncthreads();
     }
@@ -164,7 +173,80 @@ __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* 
   }
 }
 
+// lambda = 0 without the eigenvectors: one wave per mode factors G = L L^T
+// (right-looking Cholesky; a pivot at or below max(I,R) eps max_i G_ii -- the
+// resolution of G itself -- flags the factor singular and is clamped there),
+// forms L^{-1} column by column (lane c
+// owns column c, in registers) and writes G^{-1} = L^{-T} L^{-1}, V := L^{-T} and
+// unit "eigenvalues".  k_leverage then computes sum_k (a_i . V[:,k])^2 = ||L^{-1}
+// a_i||^2 = a_i^T G^{-1} a_i, the leverage score of row i.
+template <int RM>
+__global__ void __launch_bounds__(64) k_chol(ModeTables T, Geom g, const double* __restrict__ gram,
+                                             int32_t* __restrict__ flags) {
+  __shared__ double a[KR_RMAX * KR_RMAX];
+  __shared__ double li[KR_RMAX * KR_RMAX];
+  __shared__ double dinv[KR_RMAX];
+  __shared__ int sing;
+  const int n = blockIdx.x;
+  const int R = g.R[n], I = g.I[n];
+  const int lane = threadIdx.x;
+  const double* G = gram + (size_t)n * KR_RMAX * KR_RMAX;
+  for (int e = lane; e < R * R; e += 64) a[e] = G[e];
+  if (lane == 0) sing = 0;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int k = 0; k < R; ++k) dmax = fmax(dmax, a[k * R + k]);
+  const double thr = (double)max(I, R) * 2.220446049250313e-16 * dmax;
+  for (int j = 0; j < R; ++j) {
+    if (lane == 0) {
+      double d = a[j * R + j];
+      if (!(d > thr)) { sing = 1; d = thr > 0.0 ? thr : 1.0; }
+      const double l = sqrt(d);
+      a[j * R + j] = l;
+      dinv[j] = 1.0 / l;
+    }
+    __syncthreads();
+    for (int i = j + 1 + lane; i < R; i += 64) a[i * R + j] *= dinv[j];
+    __syncthreads();
+    const int m = R - j - 1;
+    for (int e = lane; e < m * m; e += 64) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) a[i * R + k] -= a[i * R + j] * a[k * R + j];
+    }
+    __syncthreads();
+  }
+  // column c of L^{-1}: x_i = 0 (i < c), x_c = 1 / L_cc, x_i = -(sum_{k<i} L_ik x_k) / L_ii
+  if (lane < R) {
+    const int c = lane;
+    double x[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc = fma(i < R ? a[i * R + k] : 0.0, x[k], acc);
+      x[i] = i < c ? 0.0 : (i == c ? dinv[i] : (i < R ? -acc * dinv[i] : 0.0));
+    }
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+      if (i < R) li[i * R + c] = x[i];
+  }
+  __syncthreads();
+  double* V = T.V[n];
+  double* ev = T.evals[n];
+  double* Gi = T.Ginv[n];
+  for (int e = lane; e < R * R; e += 64) {
+    const int p = e / R, q = e % R;
+    V[e] = li[q * R + p];
+    double acc = 0.0;
+    for (int k = max(p, q); k < R; ++k) acc = fma(li[k * R + p], li[k * R + q], acc);
+    Gi[e] = acc;
+  }
+  for (int k = lane; k < R; k += 64) ev[k] = 1.0;
+  if (lane == 0 && sing) atomicOr(flags, KR_FLAG_SINGULAR);
+}
+
 // One workgroup (256 threads) per mode.
+template <int RM>
 __global__ void __launch_bounds__(256) k_leverage(ModeTables T, Geom g, int32_t* __restrict__ flags) {
   __shared__ double vs[KR_RMAX * KR_RMAX];
   __shared__ double inv[KR_RMAX];
@@ -188,19 +270,24 @@ __global__ void __launch_bounds__(256) k_leverage(ModeTables T, Geom g, int32_t*
     inv[threadIdx.x] = lk > eps_r * eps_r * lmax ? 1.0 / lk : 0.0;
   }
   __syncthreads();
-  // leverage per row; thread-local partial sums in increasing row order
+  // leverage per row (the row held in registers); thread-local partial sums in
+  // increasing row order
   double part = 0.0;
   for (int i = threadIdx.x; i < I; i += blockDim.x) {
     const double* ai = A + (size_t)i * R;
-    double l = 0.0;
+    double x[RM];
     bool zero = true;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+      x[r] = r < R ? ai[r] : 0.0;
+      zero &= (x[r] == 0.0);
+    }
+    double l = 0.0;
     for (int k = 0; k < R; ++k) {
       double dot = 0.0;
-      for (int r = 0; r < R; ++r) {
-        const double x = ai[r];
-        zero &= (x == 0.0);
-        dot = fma(x, vs[r * R + k], dot);
-      }
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+        if (r < R) dot = fma(x[r], vs[r * R + k], dot);
       l = fma(dot * dot, inv[k], l);
     }
     if (zero) l = 0.0;

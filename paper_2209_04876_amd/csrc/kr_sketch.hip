@@ -83,25 +83,50 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __r
 // Exclusive scan of n uint32 values in place, one workgroup of 1024 threads:
 // each thread scans a contiguous chunk, chunk totals are scanned in LDS.
 __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int64_t n) {
+  // exclusive scan in tiles of 1024 x SCAN_K entries: coalesced loads into LDS,
+  // each thread scans SCAN_K consecutive entries, a block scan of the thread
+  // totals, coalesced stores; a running carry links the tiles.
+  constexpr int SCAN_K = 8;
+  __shared__ uint32_t tile[1024 * SCAN_K + 1024 * SCAN_K / 32];
   __shared__ uint32_t s[1024];
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t b = (int64_t)threadIdx.x * chunk;
-  const int64_t e = b + chunk < n ? b + chunk : n;
-  uint32_t tot = 0;
-  for (int64_t i = b; i < e; ++i) tot += v[i];
-  s[threadIdx.x] = tot;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+  __shared__ uint32_t carry;
+  auto ix = [](int i) { return i + (i >> 5); };   // one pad word per 32: conflict-free column reads
+  if (threadIdx.x == 0) carry = 0u;
+  for (int64_t t0 = 0; t0 < n; t0 += 1024 * SCAN_K) {
+    uint32_t ld[SCAN_K];
+#pragma unroll
+    for (int j = 0; j < SCAN_K; ++j) {
+      const int64_t i = t0 + (int64_t)j * 1024 + threadIdx.x;
+      ld[j] = i < n ? v[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < SCAN_K; ++j) tile[ix(j * 1024 + threadIdx.x)] = ld[j];
     __syncthreads();
-    s[threadIdx.x] += add;
+    uint32_t loc[SCAN_K], tot = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_K; ++j) {
+      loc[j] = tot;
+      tot += tile[ix(threadIdx.x * SCAN_K + j)];
+    }
+    s[threadIdx.x] = tot;
     __syncthreads();
-  }
-  uint32_t run = s[threadIdx.x] - tot;
-  for (int64_t i = b; i < e; ++i) {
-    const uint32_t x = v[i];
-    v[i] = run;
-    run += x;
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    const uint32_t base = carry + s[threadIdx.x] - tot;
+#pragma unroll
+    for (int j = 0; j < SCAN_K; ++j) tile[ix(threadIdx.x * SCAN_K + j)] = base + loc[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SCAN_K; ++j) {
+      const int64_t i = t0 + (int64_t)j * 1024 + threadIdx.x;
+      if (i < n) v[i] = tile[ix(j * 1024 + threadIdx.x)];
+    }
+    if (threadIdx.x == 1023) carry += s[1023];
+    __syncthreads();
   }
 }
 

@@ -37,53 +37,125 @@ __global__ void __launch_bounds__(256) k_mode_product(const double* __restrict__
   }
 }
 
-#define STREAM_ROWS 64
-
-// partial[c] = sum_{i0} ((sum_r A0[i0][r] Y[r][c]) - b[i0][c])^2, b of dtype bdt.
-template <int RM>
-__global__ void __launch_bounds__(256) k_stream_loss(const double* __restrict__ A0, int I0, int R0,
-                                                    const double* __restrict__ Y, const void* __restrict__ b,
-                                                    int bdt, int64_t C, double* __restrict__ partial) {
-  __shared__ double a_s[STREAM_ROWS * RM];
+// The same product for R_in <= RIN: workgroup (c block, block of MP_OUT outputs
+// o, pre index) -- o is uniform over the workgroup, so M is read through the
+// scalar cache; each thread loads its input fibre in[pre][.][c] once and forms
+// MP_OUT outputs from it.
+#define MP_OUT 16
+template <int RIN>
+__global__ void __launch_bounds__(256) k_mode_product_fibre(const double* __restrict__ in, double* __restrict__ out,
+                                                           int64_t pre, int Rin, int Rout, int64_t post,
+                                                           const double* __restrict__ M, int trans) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool act = c < C;
-  double y[RM];
+  if (c >= post) return;
+  const int o0 = blockIdx.y * MP_OUT;
+  for (int64_t b = blockIdx.z; b < pre; b += gridDim.z) {
+    const double* src = in + b * Rin * post + c;
+    double v[RIN];
 #pragma unroll
-  for (int r = 0; r < RM; ++r) y[r] = (act && r < R0) ? Y[(int64_t)r * C + c] : 0.0;
-  double acc = 0.0;
-  for (int base = 0; base < I0; base += STREAM_ROWS) {
-    const int rows = min(STREAM_ROWS, I0 - base);
-    __syncthreads();
-    for (int e = threadIdx.x; e < rows * RM; e += blockDim.x) {
-      const int i = e / RM, r = e % RM;
-      a_s[e] = r < R0 ? A0[(int64_t)(base + i) * R0 + r] : 0.0;
-    }
-    __syncthreads();
-    if (act) {
-      if (bdt == KR_F32) {
-        const float* bb = (const float*)b + (int64_t)base * C + c;
+    for (int r = 0; r < RIN; ++r) v[r] = r < Rin ? src[(int64_t)r * post] : 0.0;
 #pragma unroll 4
-        for (int i = 0; i < rows; ++i) {
-          double v = 0.0;
+    for (int oo = 0; oo < MP_OUT; ++oo) {
+      const int o = o0 + oo;
+      if (o >= Rout) break;
+      double acc = 0.0;
 #pragma unroll
-          for (int r = 0; r < RM; ++r) v = fma(a_s[i * RM + r], y[r], v);
-          const double d = v - (double)bb[(int64_t)i * C];
-          acc = fma(d, d, acc);
-        }
-      } else {
-        const double* bb = (const double*)b + (int64_t)base * C + c;
-#pragma unroll 4
-        for (int i = 0; i < rows; ++i) {
-          double v = 0.0;
-#pragma unroll
-          for (int r = 0; r < RM; ++r) v = fma(a_s[i * RM + r], y[r], v);
-          const double d = v - bb[(int64_t)i * C];
-          acc = fma(d, d, acc);
-        }
-      }
+      for (int r = 0; r < RIN; ++r)
+        if (r < Rin) acc = fma(trans ? M[(int64_t)r * Rout + o] : M[(int64_t)o * Rin + r], v[r], acc);
+      out[(b * Rout + o) * post + c] = acc;
     }
   }
-  if (act) partial[c] = acc;
+}
+
+#define STREAM_ROWS 64
+
+typedef double ks_f64x4 __attribute__((ext_vector_type(4)));
+
+// Squared residual, streaming b once: acc[c] = sum_{i0} ((A0 Y)[i0][c] - b[i0][c])^2 for
+// the [I_0][C] view of b (b of dtype bdt).  (A0 Y) is formed on the matrix cores:
+// each wave owns 16 columns and walks the rows in blocks of 16 with
+// v_mfma_f64_16x16x4 (A = A0 block, lane l: row l%16, k l/16; B = Y block, lane
+// l: k l/16, column l%16; D lane l item v: row l/16 + 4v, column l%16), KS
+// k-steps of 4.  A0 is staged in LDS per workgroup (rows padded against bank
+// conflicts), in chunks when large.  Two row blocks' loads of b are in flight.
+// The workgroup writes its per-RHS sums partial[blockIdx.x * nrhs + q] (columns
+// c = col * nrhs + q).
+#define SL_WAVES 16
+#define SL_LDS 8192
+template <int KS>
+__global__ void __launch_bounds__(64 * SL_WAVES) k_stream_loss(const double* __restrict__ A0, int I0, int R0,
+                                                              const double* __restrict__ Y, const void* __restrict__ b,
+                                                              int bdt, int64_t C, int nrhs,
+                                                              double* __restrict__ partial) {
+  __shared__ double a_s[SL_LDS];
+  __shared__ double red[SL_WAVES];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int stride = 4 * KS + 1;   // padded row of A0 in LDS
+  const int64_t c0 = ((int64_t)blockIdx.x * SL_WAVES + wave) * 16;
+  const int64_t c = c0 + col;
+  const bool act = c < C;
+  const int64_t cc = act ? c : C - 1;   // inactive lanes read a valid column, discarded
+  double yb[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int r = 4 * ks + kq;
+    yb[ks] = r < R0 ? Y[(int64_t)r * C + cc] : 0.0;
+  }
+  const int chunk = (SL_LDS / stride) & ~15;   // rows per LDS chunk, a multiple of 16
+  double acc = 0.0;
+  for (int ic = 0; ic < I0; ic += chunk) {
+    const int rows = min(chunk, I0 - ic);
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * 4 * KS; e += blockDim.x) {
+      const int i = e / (4 * KS), r = e - i * (4 * KS);
+      a_s[i * stride + r] = r < R0 ? A0[(int64_t)(ic + i) * R0 + r] : 0.0;
+    }
+    __syncthreads();
+    auto block = [&](int i0, const double* bv) {
+      ks_f64x4 d = {0.0, 0.0, 0.0, 0.0};
+      const int ia = i0 + col;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const double av = ia < rows ? a_s[ia * stride + 4 * ks + kq] : 0.0;
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, yb[ks], d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + kq + 4 * v;
+        if (i < rows) {
+          const double e = d[v] - bv[v];
+          acc = fma(e, e, acc);
+        }
+      }
+    };
+    auto load_b = [&](int i0, double* bv) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + kq + 4 * v;
+        const int64_t off = (int64_t)(ic + min(i, rows - 1)) * C + cc;
+        bv[v] = bdt == KR_F32 ? (double)((const float*)b)[off] : ((const double*)b)[off];
+      }
+    };
+    int i0 = 0;
+    for (; i0 + 32 <= rows; i0 += 32) {
+      double b0[4], b1[4];
+      load_b(i0, b0);
+      load_b(i0 + 16, b1);
+      block(i0, b0);
+      block(i0 + 16, b1);
+    }
+    for (; i0 < rows; i0 += 16) {
+      double b0[4];
+      load_b(i0, b0);
+      block(i0, b0);
+    }
+  }
+  if (!act) acc = 0.0;
+  for (int q = 0; q < nrhs; ++q) {
+    const double t = block_sum((act && (int)(c % nrhs) == q) ? acc : 0.0, red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nrhs + q] = t;
+  }
 }
 
 // Z[r][c] = sum_{i0} U0[i0][r] b[i0][c]
@@ -122,15 +194,24 @@ __global__ void __launch_bounds__(256) k_stream_contract0(const double* __restri
   }
 }
 
-// out[q] = sum over c = q (mod nrhs) of partial[c] + lambda * sum_r x[r][q]^2.
-// One workgroup per right-hand side; fixed summation order.
-__global__ void __launch_bounds__(1024) k_finish_loss(const double* __restrict__ partial, int64_t C,
+// out[q] = sum over the nparts block sums of partial[p * nrhs + q] + lambda * sum_r
+// x[r][q]^2.  One workgroup per right-hand side; fixed summation order.
+__global__ void __launch_bounds__(1024) k_finish_loss(const double* __restrict__ partial, int64_t nparts,
                                                      const double* __restrict__ x, int64_t Rtot, int nrhs,
                                                      double lambda, double* __restrict__ out) {
   __shared__ double red[16];
   const int q = blockIdx.x;
   double s = 0.0;
-  for (int64_t c = (int64_t)threadIdx.x * nrhs + q; c < C; c += (int64_t)blockDim.x * nrhs) s += partial[c];
+  for (int64_t p0 = threadIdx.x; p0 < nparts; p0 += 8 * (int64_t)blockDim.x) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t p = p0 + u * (int64_t)blockDim.x;
+      v[u] = p < nparts ? partial[p * nrhs + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
   double xx = 0.0;
   for (int64_t r = threadIdx.x; r < Rtot; r += blockDim.x) {
     const double v = x[r * nrhs + q];
@@ -183,10 +264,6 @@ __global__ void __launch_bounds__(256) k_exact_scale(ModeTables T, Geom g, doubl
   }
 }
 
-template __global__ void k_stream_loss<8>(const double*, int, int, const double*, const void*, int, int64_t, double*);
-template __global__ void k_stream_loss<16>(const double*, int, int, const double*, const void*, int, int64_t, double*);
-template __global__ void k_stream_loss<32>(const double*, int, int, const double*, const void*, int, int64_t, double*);
-template __global__ void k_stream_loss<64>(const double*, int, int, const double*, const void*, int, int64_t, double*);
 template __global__ void k_stream_contract0<8>(const double*, int, int, const void*, int, int64_t, double*);
 template __global__ void k_stream_contract0<16>(const double*, int, int, const void*, int, int64_t, double*);
 template __global__ void k_stream_contract0<32>(const double*, int, int, const void*, int, int64_t, double*);
