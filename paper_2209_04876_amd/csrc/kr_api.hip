@@ -422,21 +422,24 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
   KL(h, k_tree_emit, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot, tr);
 }
 
-// Nodes per root-adjoint partial block: a multiple of RA_NODES with at most 64
-// blocks, so that the preconditioner kernel sums the partials itself.
-static int root_npb(const Geom& g) {
-  const int64_t per = (level_cap(g, 1) + 63) / 64;
+// Nodes per root-adjoint block (a multiple of RA_NODES): all level-1 nodes in one
+// block up to 2048 of them (the root adjoint then writes g itself), else at most
+// 64 blocks, which the preconditioner kernel sums.  Needs tr.ncnt.
+static int root_npb(const Tree& tr) {
+  const int64_t S1 = std::max<int64_t>(1, tr.ncnt[1]);
+  const int64_t per = S1 <= 2048 ? S1 : (S1 + 63) / 64;
   return (int)(RA_NODES * ((per + RA_NODES - 1) / RA_NODES));
 }
 
 // One pass of the sampled products K~^T Omega (K~ x - b~) down and up the sample
-// tree: forward levels 1..N-1, the rows with the last adjoint level, adjoint
+// tree: forward levels 1..N-2, the last forward level with the rows and the last
+// adjoint level, adjoint
 // levels N-1..2 and, without segment roots, the root adjoint (partial blocks of
 // npb level-1 nodes, then their sum into Q[0]; for N = 1 the rows write Q[0]).
 // P[0] is the iterate; Q[k] and part hold the adjoint type T (float64, or
 // float32 in the refined precisions).
 template <typename T>
-static void launch_level_products(kr_handle h, const ModeTables& TT, const Geom& g, const Tree& tr, double* const* P,
+static int launch_level_products(kr_handle h, const ModeTables& TT, const Geom& g, const Tree& tr, double* const* P,
                                  void* const* Qv, const double* Omega, const double* bD, void* partv,
                                  const IterState* state) {
   hipStream_t s = h->stream;
@@ -447,15 +450,16 @@ static void launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
   const int Rl = g.R[g.N - 1];
   const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
   {
-    for (int k = 1; k < g.N; ++k) {
-      const int64_t work = level_cap(g, k) * g.rsuf[k] * g.nrhs;
-      KL(h, k_fwd_level, dim3(grid_for(work, 256)), dim3(256), 0, s, TT, g, tr, k, (const double*)P[k - 1], P[k],
-         state);
+    // forward levels 1..N-2; the rows kernel forms level N-1 itself
+    for (int k = 1; k < g.N - 1; ++k) {
+      const int64_t work = tr.ncnt[k] * g.rsuf[k] * g.nrhs;
+      KL(h, k_fwd_level, dim3(grid_for(work, 256, 2048)), dim3(256), 0, s, TT, g, tr, k, (const double*)P[k - 1],
+         P[k], state);
     }
-    const int64_t rows_threads = level_cap(g, g.N - 1) * g.nrhs * G;
     T* qlast = Q[g.N - 1];
-    const double* plast = P[g.N - 1];
-    const dim3 rg(grid_for(rows_threads, 256));
+    const double* plast = P[g.N >= 2 ? g.N - 2 : 0];
+    // one wave per (node, rhs), grid-stride, at most a few workgroups per CU
+    const dim3 rg(grid_for(tr.ncnt[g.N - 1] * g.nrhs, 4, 1024));
     switch (G) {
       case 8:
         KLN(h, f32 ? "k_rows_adj<8,f32>" : "k_rows_adj<8>", (k_rows_adj<8, T>), rg, dim3(256), 0, s, TT, g, tr, plast,
@@ -476,21 +480,21 @@ static void launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
     }
     for (int k = g.N - 1; k >= 2; --k) {
       const int64_t CE = adj_cols((int)g.R[k - 1]);
-      const int64_t tasks = level_cap(g, k - 1) * ((g.rsuf[k] * g.nrhs + CE - 1) / CE);
-      KLN(h, f32 ? "k_adj_level<f32>" : "k_adj_level", k_adj_level<T>, dim3(grid_for(tasks, 1, 8192)), dim3(256), 0,
+      const int64_t tasks = tr.ncnt[k - 1] * ((g.rsuf[k] * g.nrhs + CE - 1) / CE);
+      KLN(h, f32 ? "k_adj_level<f32>" : "k_adj_level", k_adj_level<T>, dim3(grid_for(tasks, 1, 2048)), dim3(ADJ_THREADS), 0,
           s, TT, g, tr, k, (const T*)Q[k], Q[k - 1], state);
     }
   }
   if (g.N >= 2 && !g.seg_root) {
-    const int npb = root_npb(g);
+    const int npb = root_npb(tr);
     const int64_t CEr = adj_cols((int)g.R[0]);
     const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
-    const int64_t nnb = (level_cap(g, 1) + npb - 1) / npb;
+    const int64_t nnb = (tr.ncnt[1] + npb - 1) / npb;
     KLN(h, f32 ? "k_adj_root_partial<f32>" : "k_adj_root_partial", k_adj_root_partial<T>,
-        dim3(grid_for(ncb * nnb, 1, 4096)), dim3(256), 0, s, g, tr, (const T*)Q[1], part, npb, state);
-    KLN(h, f32 ? "k_adj_root_sum<f32>" : "k_adj_root_sum", k_adj_root_sum<T>,
-        dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g, tr, (const T*)part, npb, Q[0], state);
+        dim3(grid_for(ncb * nnb, 1, 4096)), dim3(ADJ_THREADS), 0, s, g, tr, (const T*)Q[1], part, npb, state);
+    return npb;
   }
+  return 0;
 }
 
 // Dynamic LDS for the two tensor buffers of a preconditioner kernel, or 0 (then
@@ -515,7 +519,8 @@ static int mode_blocks(const Geom& g) {
 }
 
 struct PrecondArgs {
-  const void* grad;     // float64 or float32 gradient (Rtot x nrhs)
+  const void* grad;     // float64 or float32 gradient (Rtot x nrhs), as nnb partial blocks
+  unsigned nnb;
   const double* dinv;   // diagonal of the eigenvector form (Rtot)
   double* x;
   void* t0;
@@ -535,7 +540,7 @@ static void launch_precond_f64_nb(kr_handle h, const ModeTables& T, const Geom& 
     lds = 0;
   }
   KLN(h, names[NB - 1], k_precond_update<NB>, dim3(1), dim3(256), lds, h->stream, T, g, (const double*)a.grad,
-      a.dinv, a.x, (double*)a.t0, (double*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol, a.max_iter, a.use_ginv,
+      a.nnb, a.dinv, a.x, (double*)a.t0, (double*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol, a.max_iter, a.use_ginv,
       a.st);
 }
 
@@ -552,7 +557,7 @@ static void launch_precond_mp_nb(kr_handle h, const ModeTables& T, const Geom& g
     lds = 0;
   }
   KLN(h, names[MODE][NB - 1], (k_precond_mp<MODE, NB>), dim3(1), dim3(256), lds, h->stream, T, g,
-      (const float*)a.grad, a.dinv, a.x, (float*)a.t0, (float*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol,
+      (const float*)a.grad, a.nnb, a.dinv, a.x, (float*)a.t0, (float*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol,
       a.max_iter, a.use_ginv, a.st);
 }
 
@@ -679,6 +684,20 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
   KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype,
                      B.Omega, B.bD, B.counts, B.s.flags);
+  // one host round trip: the setup flags and the level counts of the sample tree,
+  // which the iteration kernels take by value
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  {
+    const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
+    if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A or b");
+    if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
+    if ((fl & KR_FLAG_SINGULAR) && lambda == 0.0)
+      KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
+    for (int k = 0; k <= KR_MAXN; ++k) tr.ncnt[k] = (int64_t)h->h_small[8 + k];
+  }
   if (prec != KR_PREC_F64 && g.N >= 2) {
     int64_t rows32 = 0;
     for (int k = 1; k < g.N; ++k) rows32 = std::max<int64_t>(rows32, level_cap(g, k) * g.R[k - 1]);
@@ -757,6 +776,7 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   } else {
     PrecondArgs pa{};
     pa.grad = B.Q[0];
+    pa.nnb = 1;
     pa.dinv = B.dinv;
     pa.x = (double*)d_x;
     pa.t0 = B.t0;
@@ -767,17 +787,24 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     pa.max_iter = max_iter;
     pa.use_ginv = lambda == 0.0 ? 1 : 0;
     pa.st = B.state;
+    // Host checks: after the first check_every iterations, the next chunk is the
+    // number of iterations the observed per-RHS contraction rate predicts to
+    // reach tol (plus one), so a solve usually needs two checks and launches few
+    // iterations that find the state already converged.
     int iters_enqueued = 0;
     bool flags_checked = false;
+    int chunk = std::min(check_every, max_iter);
     while (iters_enqueued < max_iter) {
-      const int chunk = std::min(check_every, max_iter - iters_enqueued);
+      chunk = std::max(1, std::min(chunk, max_iter - iters_enqueued));
       for (int it = 0; it < chunk; ++it) {
-        if (prec == KR_PREC_F64)
-          launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
-                                        (const IterState*)B.state);
-        else
-          launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
-                                       (const IterState*)B.state);
+        const int npb =
+            prec == KR_PREC_F64
+                ? launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
+                                                (const IterState*)B.state)
+                : launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
+                                               (const IterState*)B.state);
+        pa.grad = npb > 0 ? (const void*)B.part : (const void*)B.Q[0];
+        pa.nnb = npb > 0 ? (unsigned)((tr.ncnt[1] + npb - 1) / npb) : 1u;
         launch_precond(h, prec, T, g, pa);
       }
       iters_enqueued += chunk;
@@ -796,8 +823,22 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
           KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
       }
       if (h->h_state->all_done) break;
+      const IterState& S0 = *h->h_state;
+      int predict = 0;
+      for (int q = 0; q < g.nrhs; ++q) {
+        if (S0.done[q]) continue;
+        const double r1 = S0.rel_first[q], rk = S0.rel[q];
+        const int k = S0.iters;
+        int need = check_every;
+        if (k > 1 && r1 > 0.0 && rk > 0.0 && rk < r1 && std::isfinite(r1) && std::isfinite(rk)) {
+          const double rho = std::pow(rk / r1, 1.0 / (k - 1));
+          if (rho > 0.0 && rho < 0.999)
+            need = (int)std::ceil(std::log(tol / rk) / std::log(rho)) + 1;
+        }
+        predict = std::max(predict, std::max(1, need));
+      }
+      chunk = predict;
     }
-
   }
   HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
@@ -882,12 +923,12 @@ kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* 
 // ---------------------------------------------------------------------------
 static int rm_bucket(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64; }
 
-// out[pre][o][post] = sum_r M(o, r) in[pre][r][post]: the fibre kernel for R_in <= 64,
-// the general one otherwise.
+// out[pre][o][post] = sum_r M(o, r) in[pre][r][post]: the fibre kernel for R_in <= 64
+// and post >= 64, the general one otherwise.
 static void launch_mode_product(kr_handle h, const double* in, double* out, int64_t pre, int Rin, int Rout,
                                 int64_t post, const double* M, int trans) {
   hipStream_t s = h->stream;
-  if (Rin > 64) {
+  if (Rin > 64 || post < 64) {   // the fibre kernel needs fibres long enough to fill its lanes
     KL(h, k_mode_product, dim3(grid_for(pre * Rout * post, 256)), dim3(256), 0, s, in, out, pre, Rin, Rout, post, M,
        trans);
     return;
@@ -1189,6 +1230,11 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
   KL(h, k_rows_tucker, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tg, tr, p->b, p->b_dtype, Omega, bD,
      counts, S.flags);
+  // level counts of the sample tree for the iteration kernels (one host round trip)
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  for (int k = 0; k <= KR_MAXN; ++k) tr.ncnt[k] = (int64_t)h->h_small[8 + k];
   KL(h, k_fill, dim3(grid_for((int64_t)In * Rr, 256, 1024)), dim3(256), 0, s, Z, (int64_t)In * Rr, 0.0);
   KL(h, k_zero_bytes, dim3(grid_for(In, 256, 64)), dim3(256), 0, s, (uint32_t*)seg_done, (int64_t)In);
   KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)counters, (int64_t)64);

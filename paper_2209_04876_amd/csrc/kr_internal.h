@@ -65,7 +65,9 @@ struct Tree {
   int32_t* fchild[KR_MAXN + 1];
   int32_t* rstart;
   uint64_t* rkey;
-  int64_t* cnt;                 // KR_MAXN + 1 entries
+  int64_t* cnt;                 // KR_MAXN + 1 entries (device)
+  int64_t ncnt[KR_MAXN + 1];    // the same counts, copied to the host once the tree is
+                                // built and passed by value to the iteration kernels
 };
 
 // Solver state shared between the iteration kernels (device memory).
@@ -78,6 +80,7 @@ struct IterState {
   int32_t it_rhs[64];   // iterations at which each RHS stopped
   double dnorm0[64];    // ||d|| of the first iteration, per RHS
   double rel[64];       // eta ||d|| / ||x|| of the last iteration, per RHS
+  double rel_first[64]; // the same after the first iteration (rate estimate for polling)
 };
 
 #define KR_MAX_RHS 64

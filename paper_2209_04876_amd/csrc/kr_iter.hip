@@ -38,14 +38,37 @@ template <typename T> __device__ __forceinline__ const T* node_rows(const Tree& 
 template <> __device__ __forceinline__ const double* node_rows<double>(const Tree& tr, int k) { return tr.arow[k]; }
 template <> __device__ __forceinline__ const float* node_rows<float>(const Tree& tr, int k) { return tr.arow32[k]; }
 
+// sum_{r < n} a[r] src[r * step] in increasing r, with the loads of 16 terms issued
+// together (a serial load-FMA chain is latency-bound).
+__device__ __forceinline__ double dot_batched(const double* __restrict__ a, const double* __restrict__ src,
+                                              int64_t step, int n) {
+  double acc = 0.0;
+  for (int r0 = 0; r0 < n; r0 += 16) {
+    double av[16], sv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      av[u] = r0 + u < n ? a[r0 + u] : 0.0;
+      sv[u] = r0 + u < n ? src[(int64_t)(r0 + u) * step] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (r0 + u < n) acc = fma(av[u], sv[u], acc);
+  }
+  return acc;
+}
+
+// The level kernels do not test for convergence: the host stops launching them,
+// and the few passes launched after the last iteration only rewrite scratch
+// levels (the preconditioner kernel leaves x unchanged then).  Level counts come
+// from tr.ncnt (host copies), so no dependent load precedes the work.
+//
 // Forward level k (always float64: the residual K~x - b~ cancels, so it is formed
 // in float64 in every precision mode).
 __global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree tr, int k,
                                                   const double* __restrict__ Pprev,
                                                   double* __restrict__ Pout,
                                                   const IterState* __restrict__ st) {
-  if (st->all_done) return;
-  const unsigned S = (unsigned)tr.cnt[k];
+  const unsigned S = (unsigned)tr.ncnt[k];
   const unsigned W = (unsigned)(g.rsuf[k] * g.nrhs);         // entries per level-k node
   const unsigned Wp = (unsigned)(g.rsuf[k - 1] * g.nrhs);    // entries per parent
   const int Rk = g.R[k - 1];
@@ -63,22 +86,18 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree t
   for (unsigned e = e0; e < total; e += step, di.next()) {
     const unsigned s = di.q, cq = di.r;
     const unsigned p = k == 1 ? 0u : (unsigned)tr.parent[k][s];
-    const double* a = arow + (size_t)s * Rk;
-    const double* src = Pprev + (size_t)p * Wp + cq;
-    double acc = 0.0;
-#pragma unroll 4
-    for (int r = 0; r < Rk; ++r) acc = fma(a[r], src[r * W], acc);
-    Pout[e] = acc;
+    Pout[e] = dot_batched(arow + (size_t)s * Rk, Pprev + (size_t)p * Wp + cq, W, Rk);
   }
 }
 
-// Rows and the last adjoint level, fused.  A group of G lanes (power of two
-// >= R_{N-1}) owns one (level-(N-1) node p, rhs q); lane r keeps P[p][r][q] and
-// accumulates Q[p][r][q] over the children rows of p, eight rows per step (their
-// loads issued together).  The
-// row dot product and the residual u_j = <a, P> - b_j are float64; the weighted
-// residual Omega_j u_j is then accumulated in T (float64, or float32 in the
-// refined modes).
+// The last forward level, the rows and the last adjoint level, fused.  One wave
+// owns one (level-(N-1) node p, rhs q).  Its NGR = 64/G lane groups (G a power of
+// two >= R_{N-1}) first form P_{N-1}[p][r][q] in lane r: from P_{N-2}[parent(p)]
+// and the gathered factor row a_{N-2}[i(p)] (P_0 = x with the root as parent;
+// for N = 1 it is x itself; for a segment root it is the segment's own iterate).
+// Group gi then takes rows j0 + gi, j0 + gi + NGR, ... of p, four per step:
+// u_j = <a_{N-1}[i(j)], P_{N-1}[p]> - b_j in float64 and Q[p][r][q] +=
+// (Omega_j u_j) a_{N-1}[i(j)][r] in T; the groups' sums are added in a fixed order.
 template <int G, typename T>
 __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr,
                                                  const double* __restrict__ Pprev,
@@ -86,82 +105,152 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
                                                  const double* __restrict__ bD,
                                                  T* __restrict__ Qout,
                                                  const IterState* __restrict__ st) {
-  if (st->all_done) return;
+  constexpr int NGR = 64 / G;
   const int N = g.N, nrhs = g.nrhs;
   const int R = g.R[N - 1];
   const double* __restrict__ AL = tr.arow[N];
-  const int64_t Sp = tr.cnt[N - 1];
+  const int64_t ntask = tr.ncnt[N - 1] * nrhs;
   const int lane = threadIdx.x & (G - 1);
-  const int64_t ngroups_total = Sp * nrhs;
-  const int64_t gpb = blockDim.x / G;
-  for (int64_t grp = blockIdx.x * gpb + threadIdx.x / G; grp - (threadIdx.x / G) < ngroups_total;
-       grp += (int64_t)gridDim.x * gpb) {
-    const bool active = grp < ngroups_total;
-    const int64_t p = active ? grp / nrhs : 0;
-    const int q = active ? (int)(grp - p * nrhs) : 0;
-    const bool ln = active && lane < R;
-    const double pv = ln ? Pprev[(p * R + lane) * nrhs + q] : 0.0;
+  const int gi = (threadIdx.x & 63) / G;
+  const bool ln = lane < R;
+  const int64_t wpb = blockDim.x >> 6;
+  for (int64_t task = blockIdx.x * wpb + (threadIdx.x >> 6); task < ntask; task += (int64_t)gridDim.x * wpb) {
+    const int64_t p = task / nrhs;
+    const int q = (int)(task - p * nrhs);
+    // P_{N-1}[p][lane][q]
+    double pv = 0.0;
+    if (ln) {
+      if (N == 1) {
+        pv = Pprev[(int64_t)lane * nrhs + q];
+      } else if (N == 2 && g.seg_root) {
+        pv = Pprev[((int64_t)tr.idx[1][p] * R + lane) * nrhs + q];
+      } else {
+        const int Rp = g.R[N - 2];
+        const int64_t par = N >= 3 ? tr.parent[N - 1][p] : 0;
+        const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
+        const double* __restrict__ src = Pprev + par * (int64_t)Rp * R * nrhs + (int64_t)lane * nrhs + q;
+        const int64_t step = (int64_t)R * nrhs;
+        pv = dot_batched(a, src, step, Rp);
+      }
+    }
     T acc = 0;
-    const int j0 = active ? tr.fchild[N - 1][p] : 0;
-    const int j1 = active ? tr.fchild[N - 1][p + 1] : 0;
-    int j = j0;
-    for (; j + 8 <= j1; j += 8) {
-      double av[8], y[8], om[8], bb[8];
+    const int j0 = tr.fchild[N - 1][p], j1 = tr.fchild[N - 1][p + 1];
+    int j = j0 + gi;
+    for (; j + 3 * NGR < j1; j += 4 * NGR) {
+      double av[4], y[4], om[4], bb[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        av[u] = ln ? AL[(int64_t)(j + u) * R + lane] : 0.0;
-        om[u] = Omega[j + u];
-        bb[u] = bD[(int64_t)(j + u) * nrhs + q];
+      for (int u = 0; u < 4; ++u) {
+        const int jj = j + u * NGR;
+        av[u] = ln ? AL[(int64_t)jj * R + lane] : 0.0;
+        om[u] = Omega[jj];
+        bb[u] = bD[(int64_t)jj * nrhs + q];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) y[u] = av[u] * pv;
+      for (int u = 0; u < 4; ++u) y[u] = av[u] * pv;
 #pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) y[u] += __shfl_xor(y[u], o, G);
+        for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, G);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc = fma((T)(om[u] * (y[u] - bb[u])), (T)av[u], acc);
+      for (int u = 0; u < 4; ++u) acc = fma((T)(om[u] * (y[u] - bb[u])), (T)av[u], acc);
     }
-    for (; j < j1; ++j) {
+    for (; j < j1; j += NGR) {
       const double a = ln ? AL[(int64_t)j * R + lane] : 0.0;
       double y = a * pv;
 #pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, G);
       acc = fma((T)(Omega[j] * (y - bD[(int64_t)j * nrhs + q])), (T)a, acc);
     }
-    if (ln) Qout[(p * R + lane) * nrhs + q] = acc;
+    // sum over the groups of the wave (fixed pairing order)
+#pragma unroll
+    for (int o = G; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if (gi == 0 && ln) Qout[(p * R + lane) * nrhs + q] = acc;
   }
 }
 
 // Adjoint of one block of nodes: out[r][e0 + c] = sum_{s in [s0, s1)} a[s][r] q[s][e0 + c]
-// for r < Rk and the column block c < CE of the W columns.  Thread (r, c) keeps one
-// sum; up to RA_NODES nodes' factor rows and q columns (at most ADJ_QS entries)
-// are staged in LDS at a time and added in increasing node order.  Used for the
+// for r < Rk and the column block c < CE of the W columns.  Output (r, c) belongs to
+// threads (r, c) + 256 k of a workgroup of 256 k threads; up to ADJ_CHUNK nodes' factor rows and q columns (at most ADJ_QS entries
+// each) are staged in LDS at a time and added in increasing node order.  Used for the
 // adjoint levels (the children of one parent) and the root adjoint (a block of
 // level-1 nodes).
 #define RA_NODES 32
+#define ADJ_CHUNK 128
 #define ADJ_QS 2048
+#define ADJ_THREADS 1024
 template <typename T>
 __device__ void adj_block(const T* __restrict__ arow, int Rk, const T* __restrict__ q, unsigned W, unsigned s0,
-                          unsigned s1, unsigned e0, unsigned CE, T* __restrict__ out, T* as, T* qs) {
-  const unsigned r0 = threadIdx.x / CE, c = threadIdx.x - r0 * CE;
+                          unsigned s1, unsigned e0, unsigned CE, T* __restrict__ out, T* as, T* qs, T* red) {
+  constexpr int NPF = ADJ_QS / ADJ_THREADS;   // staged entries per thread
+  const unsigned r0 = (threadIdx.x & 255) / CE, c = (threadIdx.x & 255) - r0 * CE;
   const bool mine = r0 < (unsigned)Rk && e0 + c < W;
-  const unsigned chunk = min((unsigned)RA_NODES, (unsigned)ADJ_QS / CE);
+  const unsigned chunk = min((unsigned)ADJ_CHUNK, min((unsigned)ADJ_QS / CE, (unsigned)ADJ_QS / (unsigned)Rk));
+  // a chunk's staged entries fit in NPF per thread; the next chunk's loads are
+  // issued before the current chunk is summed
+  T va[NPF], vq[NPF];
+  auto load = [&](unsigned b0) {
+    const unsigned ns = min(chunk, s1 - b0);
+    const unsigned na = ns * (unsigned)Rk, nq = ns * CE;
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const unsigned i = threadIdx.x + u * ADJ_THREADS;
+      va[u] = i < na ? arow[(size_t)b0 * Rk + i] : T(0);
+      const unsigned sn = i / CE, cc = i - sn * CE;
+      vq[u] = (i < nq && e0 + cc < W) ? q[(size_t)(b0 + sn) * W + e0 + cc] : T(0);
+    }
+  };
+  auto store = [&](unsigned b0) {
+    const unsigned ns = min(chunk, s1 - b0);
+    const unsigned na = ns * (unsigned)Rk, nq = ns * CE;
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const unsigned i = threadIdx.x + u * ADJ_THREADS;
+      if (i < na) as[i] = va[u];
+      if (i < nq) qs[i] = vq[u];
+    }
+  };
+  // ADJ_THREADS / 256 threads share an output: part p sums nodes p, p + nparts,
+  // ... of every chunk, four at a time, and the parts are added in order at the end
+  const unsigned nparts = ADJ_THREADS >> 8, part = threadIdx.x >> 8;
   T acc = 0;
+  __syncthreads();
+  if (s0 < s1) {
+    load(s0);
+    store(s0);
+  }
+  __syncthreads();
   for (unsigned b0 = s0; b0 < s1; b0 += chunk) {
     const unsigned ns = min(chunk, s1 - b0);
-    __syncthreads();
-    for (unsigned i = threadIdx.x; i < ns * (unsigned)Rk; i += blockDim.x) as[i] = arow[(size_t)b0 * Rk + i];
-    for (unsigned i = threadIdx.x; i < ns * CE; i += blockDim.x) {
-      const unsigned sn = i / CE, cc = i - sn * CE;
-      qs[i] = e0 + cc < W ? q[(size_t)(b0 + sn) * W + e0 + cc] : T(0);
+    const bool more = b0 + chunk < s1;
+    if (more) load(b0 + chunk);
+    if (mine) {
+      unsigned sn = part;
+      for (; sn + 3 * nparts < ns; sn += 4 * nparts) {
+        T av[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = as[(sn + u * nparts) * Rk + r0];
+          qv[u] = qs[(sn + u * nparts) * CE + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = fma(av[u], qv[u], acc);
+      }
+      for (; sn < ns; sn += nparts) acc = fma(as[sn * Rk + r0], qs[sn * CE + c], acc);
     }
     __syncthreads();
-    if (mine)
-      for (unsigned sn = 0; sn < ns; ++sn) acc = fma(as[sn * Rk + r0], qs[sn * CE + c], acc);
+    if (more) store(b0 + chunk);
+    __syncthreads();
   }
-  if (mine) out[(size_t)r0 * W + e0 + c] = acc;
+  if (nparts > 1) {
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (part == 0) {
+      for (unsigned k = 1; k < nparts; ++k) acc += red[threadIdx.x + 256 * k];
+    }
+    __syncthreads();
+  }
+  if (mine && part == 0) out[(size_t)r0 * W + e0 + c] = acc;
 }
 
 __host__ __device__ __forceinline__ unsigned adj_cols(int Rk) { return Rk >= 256 ? 1u : 256u / (unsigned)Rk; }
@@ -169,14 +258,14 @@ __host__ __device__ __forceinline__ unsigned adj_cols(int Rk) { return Rk >= 256
 // Adjoint level k (k = N-1 .. 2): Q_{k-1}[p][r][c] = sum_{s child of p} a_{k-1}[i(s)][r]
 // Q_k[s][c] (c < rsuf[k] nrhs).  One task per (parent, column block).
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_level(ModeTables TT, Geom g, Tree tr, int k,
+__global__ void __launch_bounds__(ADJ_THREADS) k_adj_level(ModeTables TT, Geom g, Tree tr, int k,
                                                   const T* __restrict__ Qk,
                                                   T* __restrict__ Qout,
                                                   const IterState* __restrict__ st) {
-  if (st->all_done) return;
-  __shared__ T as[RA_NODES * 64];
+  __shared__ T as[ADJ_QS];
   __shared__ T qs[ADJ_QS];
-  const unsigned Sp = (unsigned)tr.cnt[k - 1];
+  __shared__ T red[ADJ_THREADS];
+  const unsigned Sp = (unsigned)tr.ncnt[k - 1];
   const int Rk = g.R[k - 1];
   const unsigned W = (unsigned)(g.rsuf[k] * g.nrhs);
   const unsigned CE = adj_cols(Rk);
@@ -185,20 +274,20 @@ __global__ void __launch_bounds__(256) k_adj_level(ModeTables TT, Geom g, Tree t
   for (unsigned task = blockIdx.x; task < Sp * ncb; task += gridDim.x) {
     const unsigned p = task / ncb, cb = task - p * ncb;
     adj_block(arow, Rk, Qk, W, (unsigned)tr.fchild[k - 1][p], (unsigned)tr.fchild[k - 1][p + 1], cb * CE, CE,
-              Qout + (size_t)p * Rk * W, as, qs);
+              Qout + (size_t)p * Rk * W, as, qs, red);
   }
 }
 
 // Root adjoint, split over blocks of npb level-1 nodes (npb a multiple of
 // RA_NODES): partial[b][r0][c] = sum_{s in block b} a_0[i(s)][r0] Q_1[s][c].
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const T* __restrict__ Q1,
+__global__ void __launch_bounds__(ADJ_THREADS) k_adj_root_partial(Geom g, Tree tr, const T* __restrict__ Q1,
                                                          T* __restrict__ partial, int npb,
                                                          const IterState* __restrict__ st) {
-  if (st->all_done) return;
-  __shared__ T as[RA_NODES * 64];
+  __shared__ T as[ADJ_QS];
   __shared__ T qs[ADJ_QS];
-  const unsigned S1 = (unsigned)tr.cnt[1];
+  __shared__ T red[ADJ_THREADS];
+  const unsigned S1 = (unsigned)tr.ncnt[1];
   const int R0 = g.R[0];
   const unsigned W1 = (unsigned)(g.rsuf[1] * g.nrhs);
   const unsigned CE = adj_cols(R0);
@@ -208,37 +297,10 @@ __global__ void __launch_bounds__(256) k_adj_root_partial(Geom g, Tree tr, const
     const unsigned cb = task % ncb, nbk = task / ncb;
     const unsigned b0 = nbk * (unsigned)npb;
     adj_block(node_rows<T>(tr, 1), R0, Q1, W1, b0, min(S1, b0 + (unsigned)npb), cb * CE, CE,
-              partial + (size_t)nbk * g.Rtot * g.nrhs, as, qs);
+              partial + (size_t)nbk * g.Rtot * g.nrhs, as, qs, red);
   }
 }
 
-// Partial blocks of the root adjoint: ceil(S_1 / npb); npb = 0 means the
-// gradient was written directly (one block).
-__device__ __forceinline__ unsigned root_blocks(const int64_t* __restrict__ cnt, int npb) {
-  return npb > 0 ? (unsigned)((cnt[1] + npb - 1) / npb) : 1u;
-}
-
-// g = sum over the partial blocks in block order (deterministic).  Each thread
-// issues the loads of up to 16 blocks at once before adding them in order.
-template <typename T>
-__global__ void __launch_bounds__(256) k_adj_root_sum(Geom g, Tree tr, const T* __restrict__ partial, int npb,
-                                                     T* __restrict__ grad, const IterState* __restrict__ st) {
-  if (st->all_done) return;
-  const unsigned nnb = root_blocks(tr.cnt, npb);
-  const size_t RT = (size_t)g.Rtot * g.nrhs;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < RT; e += (size_t)gridDim.x * blockDim.x) {
-    T acc = 0;
-    for (unsigned b0 = 0; b0 < nnb; b0 += 16) {
-      T v[16];
-#pragma unroll
-      for (unsigned u = 0; u < 16; ++u) v[u] = b0 + u < nnb ? partial[(size_t)(b0 + u) * RT + e] : T(0);
-#pragma unroll
-      for (unsigned u = 0; u < 16; ++u)
-        if (b0 + u < nnb) acc += v[u];
-    }
-    grad[e] = acc;
-  }
-}
 
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

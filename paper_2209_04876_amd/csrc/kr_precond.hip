@@ -32,36 +32,69 @@ __device__ __forceinline__ int pc_mat_off(const Geom& g, int n) {
 
 __device__ __forceinline__ bool pc_mats_fit(const Geom& g) { return pc_mat_off(g, g.N) <= PC_MATS; }
 
-// Stage mode n's matrix (or all modes when they fit) into ms; caller syncs.
+// Stage mode n's matrix (or all modes when they fit) into ms; caller syncs.  The
+// loads of all staged entries of a thread are issued before the LDS stores.
 template <typename TM>
 __device__ void pc_stage(const Geom& g, const double* const* Ms, int n, bool all, TM* ms) {
   const int n0 = all ? 0 : n, n1 = all ? g.N : n + 1;
   int off = 0;
   for (int m = n0; m < n1; ++m) {
     const int RR = (int)(g.R[m] * g.R[m]);
-    for (int e = threadIdx.x; e < RR; e += blockDim.x) ms[off + e] = (TM)Ms[m][e];
+    const double* __restrict__ M = Ms[m];
+    for (int e0 = threadIdx.x; e0 < RR; e0 += PC_BATCH * blockDim.x) {
+      double v[PC_BATCH];
+#pragma unroll
+      for (int u = 0; u < PC_BATCH; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        v[u] = e < RR ? M[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PC_BATCH; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        if (e < RR) ms[off + e] = (TM)v[u];
+      }
+    }
     off += RR;
   }
 }
 
-// h = g + lambda x into cur, PC_BATCH elements per thread per step.
+// h = g + lambda x into cur, where g is the sum, in block order, of nnb partial
+// blocks of total entries each (the root adjoint's split; one block unless the
+// tree has very many level-1 nodes).  Loads of PC_HB elements x 4 blocks are
+// issued together.
+#define PC_HB 4
 template <typename TG, typename TT>
-__device__ void pc_load_h(const TG* __restrict__ grad, const double* __restrict__ x, double lambda, TT* cur,
-                          int64_t total) {
+__device__ void pc_load_h(const TG* __restrict__ part, unsigned nnb, const double* __restrict__ x, double lambda,
+                          TT* cur, int64_t total) {
   const int64_t bd = blockDim.x;
-  for (int64_t e0 = threadIdx.x; e0 < total; e0 += PC_BATCH * bd) {
-    TG gv[PC_BATCH];
-    double xv[PC_BATCH];
+  for (int64_t e0 = threadIdx.x; e0 < total; e0 += PC_HB * bd) {
+    TG gs[PC_HB];
+    double xv[PC_HB];
 #pragma unroll
-    for (int u = 0; u < PC_BATCH; ++u) {
+    for (int u = 0; u < PC_HB; ++u) {
       const int64_t e = e0 + u * bd;
-      gv[u] = e < total ? grad[e] : TG(0);
+      gs[u] = TG(0);
       xv[u] = (e < total && lambda != 0.0) ? x[e] : 0.0;
     }
+    for (unsigned b0 = 0; b0 < nnb; b0 += 4) {
+      TG v[PC_HB][4];
 #pragma unroll
-    for (int u = 0; u < PC_BATCH; ++u) {
+      for (int u = 0; u < PC_HB; ++u)
+#pragma unroll
+        for (unsigned k = 0; k < 4; ++k) {
+          const int64_t e = e0 + u * bd;
+          v[u][k] = (e < total && b0 + k < nnb) ? part[(size_t)(b0 + k) * total + e] : TG(0);
+        }
+#pragma unroll
+      for (int u = 0; u < PC_HB; ++u)
+#pragma unroll
+        for (unsigned k = 0; k < 4; ++k)
+          if (b0 + k < nnb) gs[u] += v[u][k];
+    }
+#pragma unroll
+    for (int u = 0; u < PC_HB; ++u) {
       const int64_t e = e0 + u * bd;
-      if (e < total) cur[e] = (TT)((double)gv[u] + lambda * xv[u]);
+      if (e < total) cur[e] = (TT)((double)gs[u] + lambda * xv[u]);
     }
   }
 }
@@ -87,14 +120,14 @@ __device__ void pc_scale(const Geom& g, const double* __restrict__ dinv, TT* cur
 
 // x <- x - eta d for right-hand sides not yet converged; float64 norms, the
 // stopping rule and the divergence test; the iteration counter.
+// it and done_lane (lane q of every wave holds done[q]) are read at kernel start.
 template <typename TT>
 __device__ void pc_update(const Geom& g, const TT* d_t, double* __restrict__ x, double eta, double tol, int max_iter,
-                          IterState* __restrict__ st, double* red) {
-  const int it = st->iters;
+                          IterState* __restrict__ st, double* red, int it, int done_lane) {
   int all = 1, div = 0;
   const int64_t bd = blockDim.x;
   for (int q = 0; q < g.nrhs; ++q) {
-    const int done = st->done[q];
+    const int done = __shfl(done_lane, q, 64);
     double dd = 0.0, xx = 0.0;
     for (int64_t r0 = threadIdx.x; r0 < g.Rtot; r0 += PC_BATCH * bd) {
       double xv[PC_BATCH], dv[PC_BATCH];
@@ -121,12 +154,12 @@ __device__ void pc_update(const Geom& g, const TT* d_t, double* __restrict__ x, 
       const double dn = sqrt(dd), xn = sqrt(xx);
       const double rel = xn > 0.0 ? eta * dn / xn : (dn > 0.0 ? INFINITY : 0.0);
       st->rel[q] = rel;
-      if (it == 0) st->dnorm0[q] = dn;
+      if (it == 0) { st->dnorm0[q] = dn; st->rel_first[q] = rel; }
       const bool bad = !isfinite(dn) || !isfinite(xn) || (it > 0 && dn > 1e6 * st->dnorm0[q] && dn > 0.0);
       if (bad) div = 1;
       if (rel <= tol || bad) { st->done[q] = 1; st->it_rhs[q] = it + 1; }
     }
-    if (threadIdx.x == 0) all &= st->done[q];
+    if (threadIdx.x == 0) all &= (done || st->done[q]);
   }
   if (threadIdx.x == 0) {
     st->iters = it + 1;
@@ -371,10 +404,11 @@ __device__ void pc_mode_lp(const Geom& g, int n, const float* M, int trans, floa
   }
 }
 
-// Float64 step.  dinv (Rtot) holds 1 / (kron Lambda + lambda) (0 where the sum
+// Float64 step.  grad holds the gradient as nnb partial blocks (summed here); dinv (Rtot) holds 1 / (kron Lambda + lambda) (0 where the sum
 // vanishes) for the eigenvector form.
 template <int NB>
 __global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
+                                                       unsigned nnb,
                                                        const double* __restrict__ dinv, double* __restrict__ x,
                                                        double* __restrict__ t0, double* __restrict__ t1, int lds,
                                                        double lambda, double eta, double tol, int max_iter,
@@ -382,15 +416,19 @@ __global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, co
   extern __shared__ double pd_dyn[];
   __shared__ double red[16];
   __shared__ double ms[PC_MATS];
-  if (st->all_done) return;
+  // state loads issued together with the staging and h loads below
+  const int all_done = st->all_done;
+  const int it0 = st->iters;
+  const int done_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->done[threadIdx.x & 63] : 1;
   const int64_t total = g.Rtot * g.nrhs;
   double* cur = lds ? pd_dyn : t0;
   double* nxt = lds ? pd_dyn + total : t1;
   const bool all = pc_mats_fit(g);
   const double* const* Ms = use_ginv ? T.Ginv : T.V;
   if (all) pc_stage(g, Ms, 0, true, ms);
-  pc_load_h(grad, x, lambda, cur, total);
+  pc_load_h(grad, nnb, x, lambda, cur, total);
   __syncthreads();
+  if (all_done) return;
   auto product = [&](int n, int trans) {
     if (!all) {
       pc_stage(g, Ms, n, false, ms);
@@ -408,7 +446,7 @@ __global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, co
     __syncthreads();
     for (int n = 0; n < g.N; ++n) product(n, 0);
   }
-  pc_update(g, cur, x, eta, tol, max_iter, st, red);
+  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane);
 }
 
 // Refined-precision step: float32 gradient and tensor, mode products in MODE.
@@ -416,6 +454,7 @@ __global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, co
 // round far better in e4m3 than the inverse Grams (fewer iterations, measured).
 template <int MODE, int NB>
 __global__ void __launch_bounds__(256) k_precond_mp(ModeTables T, Geom g, const float* __restrict__ grad,
+                                                   unsigned nnb,
                                                    const double* __restrict__ dinv, double* __restrict__ x,
                                                    float* __restrict__ t0, float* __restrict__ t1, int lds,
                                                    double lambda, double eta, double tol, int max_iter, int use_ginv,
@@ -425,7 +464,10 @@ __global__ void __launch_bounds__(256) k_precond_mp(ModeTables T, Geom g, const 
   __shared__ float redf[16];
   __shared__ float ms[PC_MATS];
   __shared__ float mscale[KR_MAXN];
-  if (st->all_done) return;
+  // state loads issued together with the staging and h loads below
+  const int all_done = st->all_done;
+  const int it0 = st->iters;
+  const int done_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->done[threadIdx.x & 63] : 1;
   const int64_t total = g.Rtot * g.nrhs;
   float* cur = lds ? mp_dyn : t0;
   float* nxt = lds ? mp_dyn + total : t1;
@@ -433,8 +475,9 @@ __global__ void __launch_bounds__(256) k_precond_mp(ModeTables T, Geom g, const 
   const bool all = pc_mats_fit(g);
   const double* const* Ms = ginv ? T.Ginv : T.V;
   if (all) pc_stage(g, Ms, 0, true, ms);
-  pc_load_h(grad, x, lambda, cur, total);
+  pc_load_h(grad, nnb, x, lambda, cur, total);
   __syncthreads();
+  if (all_done) return;
   auto scale_of = [&](int n, const float* M) {
     if (MODE == KR_PREC_FP8) {
       float mx = 0.0f;
@@ -465,7 +508,7 @@ __global__ void __launch_bounds__(256) k_precond_mp(ModeTables T, Geom g, const 
     __syncthreads();
     for (int n = 0; n < g.N; ++n) product(n, 0);
   }
-  pc_update(g, cur, x, eta, tol, max_iter, st, red);
+  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane);
 }
 
 // dinv[r] = 1 / (prod_n lambda_n[r_n] + lambda), 0 where that sum is not positive.
