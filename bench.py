@@ -38,6 +38,57 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def algorithmic_bytes(I, R, S):
+    """Bytes each iteration / loss kernel must move per launch for an N = 3 problem
+    with one right-hand side: its inputs read once and outputs written once.
+    S = [1, S1, S2, D]: nodes per level of the sample tree (D = distinct rows)."""
+    R0, R1, R2 = R
+    Rtot = R0 * R1 * R2
+    Itot = I[0] * I[1] * I[2]
+    C = Itot // I[0]
+    S1, S2, D = S[1], S[2], S[3]
+    mats = 8 * (R0 * R0 + R1 * R1 + R2 * R2)
+    out = {
+        # b once, Y = x x_2 A_2 x_3 A_3 (R_0 x C) once, A_0 once
+        "k_stream_loss<16>": Itot * 8 + R0 * C * 8 + I[0] * R0 * 8,
+        # gradient (float32), x read and written (float64), factor matrices
+        "k_precond_mp<bf16,1>": Rtot * 4 + 2 * Rtot * 8 + mats,
+        "k_precond_mp<fp8,1>": Rtot * 4 + 2 * Rtot * 8 + mats,
+        "k_precond_mp<f32,1>": Rtot * 4 + 2 * Rtot * 8 + mats,
+        "k_precond_update<1>": Rtot * 8 + 2 * Rtot * 8 + mats,
+        # x, level-1 rows of A_0, P_1 (S1 x R1 R2) written
+        "k_fwd_level": Rtot * 8 + S1 * R0 * 8 + S1 * R1 * R2 * 8,
+        # P_1 of the parents, level-2 rows of A_1, rows of A_2, Omega and b at the
+        # distinct rows, tree links; Q_2 (S2 x R2, float32) written
+        "k_rows_adj<16,f32>": S1 * R1 * R2 * 8 + S2 * R1 * 8 + D * R2 * 8 + 2 * D * 8 + 3 * S2 * 4 + S2 * R2 * 4,
+        # float32 level-2 rows of A_1 and Q_2, links; Q_1 (S1 x R1 R2, float32) written
+        "k_adj_level<f32>": S2 * R1 * 4 + S2 * R2 * 4 + 2 * S1 * 4 + S1 * R1 * R2 * 4,
+        # float32 level-1 rows of A_0 and Q_1; the gradient (Rtot, float32) written
+        "k_adj_root_partial<f32>": S1 * R0 * 4 + S1 * R1 * R2 * 4 + Rtot * 4,
+    }
+    return out
+
+
+def recorded_traffic():
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy), as recorded in profiles/skewed_regression_hbm_counters.md;
+    an entry counts only while its kernel source still hashes as recorded."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "skewed_regression_hbm_counters.md")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        m = re.match(r"- traffic (\S+) bytes=(\d+) source=(\S+) sha256_16=([0-9a-f]+)", line.strip())
+        if not m:
+            continue
+        src = os.path.join(ROOT, "paper_2209_04876_amd", "csrc", m.group(3))
+        if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == m.group(4):
+            out[m.group(1)] = int(m.group(2))
+    return out
+
+
 def cpu_baseline(w, seconds=12.0):
     """The oracle (as it stands) on the host cores: full solves of the same workload
     (leverage, quantised tables, Philox samples, merge, gather, explicit sampled rows,
@@ -71,6 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)"
@@ -79,6 +132,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        # a plain copy of known size: reads and writes exactly 2^30 bytes each, so
+        # FETCH_SIZE / WRITE_SIZE of this dispatch give the counters' byte scale
+        src = torch.ones(2**27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 2**30}), flush=True)
+        return
 
     import paper_2209_04876_amd as kr
     import workloads
@@ -103,9 +167,11 @@ def main():
         f = kr.kron_loss(tA, tb, x)[0]
         return f, info
 
-    def timed(prec, roof_kernel=None):
-        if roof_kernel:
-            kr.profile_enable(True, roof_kernel)
+    def timed(prec, roof_filter=None):
+        """K steps; with roof_filter, the matching kernels are bracketed by events
+        (left enabled for the caller to query)."""
+        if roof_filter:
+            kr.profile_enable(True, roof_filter)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ratios, iters, D = [], [], []
@@ -116,9 +182,7 @@ def main():
             D.append(info["distinct_rows"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        prof = kr.profile_query(roof_kernel) if roof_kernel else None
-        kr.profile_enable(False)
-        return dt, ratios, iters, D, prof
+        return dt, ratios, iters, D
 
     breakdowns = {}
     for prec in ("bf16", "f64"):
@@ -133,22 +197,35 @@ def main():
     breakdown = breakdowns["bf16"]
     dominant = max(breakdown, key=lambda k: breakdown[k]["ms"])
 
-    # timed region of `value`: K bf16-refined steps; only the dominant streaming
-    # kernel is bracketed by events
-    roof_kernel = "k_stream_loss<16>"
-    dt, ratios, iters, D, (nl, lms) = timed("bf16", roof_kernel)
+    # sample-tree level counts of this workload's sketch (same for every step)
+    sk = kr.export_sketch(I)
+    S = [1, len(np.unique(sk["rows"][:, 0])), len(np.unique(sk["rows"][:, :2], axis=0)), len(sk["rows"])]
+    alg = algorithmic_bytes(I, R, S)
+    stream_kernel = "k_stream_loss<16>"
+
+    # timed region of `value`: K bf16-refined steps; the step's dominant kernel and
+    # the loss stream are bracketed by HIP events on the library's stream
+    dt, ratios, iters, D = timed("bf16", dominant + "|" + stream_kernel)
+    nl, lms = kr.profile_query(dominant)
+    ns_, sms = kr.profile_query(stream_kernel)
+    kr.profile_enable(False)
     ms_per_step = 1000.0 * dt / args.steps
     value = args.steps / dt
     # the same K steps in float64 plain, for the comparison
-    dt64, ratios64, iters64, _, _ = timed("f64")
+    dt64, ratios64, iters64, _ = timed("f64")
     value64 = args.steps / dt64
 
-    # algorithmic bytes of one loss-stream launch: b (float64) once, Y = x x_2 A2 x_3 A3
-    # (R_1 x I_2 I_3 float64) once, one float64 partial per column
-    C = Itot // I[0]
-    bytes_per_launch = Itot * 8 + R[0] * C * 8 + C * 8
-    avg_ms = lms / max(nl, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = recorded_traffic()
+
+    def roofline(kernel, n, ms):
+        avg_ms = ms / max(n, 1)
+        b = alg.get(kernel)
+        ach = b / (avg_ms * 1e-3) / 1e9 if b and avg_ms > 0 else None
+        return {"kernel": kernel, "bound": "hbm", "achieved": None if ach is None else round(ach, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 5),
+                "traffic": traffic.get(kernel), "avg_launch_ms": round(avg_ms, 5), "launches": n,
+                "algorithmic_bytes_per_launch": b}
+
     gate_ok = max(ratios) <= 1.1 and max(ratios64) <= 1.1
     out = {
         "metric": METRIC,
@@ -179,10 +256,9 @@ def main():
         "dominant_kernel_one_step": dominant,
         "kernel_breakdown_ms": {k: v["ms"] for k, v in breakdown.items()},
         "kernel_breakdown_ms_fp64": {k: v["ms"] for k, v in breakdowns["f64"].items()},
-        "roofline": {"kernel": roof_kernel, "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_ms": round(avg_ms, 5),
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline": roofline(dominant, nl, lms),
+        "hbm_stream": roofline(stream_kernel, ns_, sms),
+        "sample_tree_levels": S,
     }
     if not args.no_cpu_baseline:
         del tA, tb

@@ -170,7 +170,8 @@ kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* 
                            int32_t* h_counts, int64_t cap, int64_t* h_D);
 
 /* Measurement support: when enabled, every kernel launch of the handle whose
- * name contains `filter` (NULL or "" = every kernel) is bracketed by a pair of
+ * name contains `filter`, or one of its '|'-separated alternatives (NULL or "" =
+ * every kernel), is bracketed by a pair of
  * HIP events on the handle's stream (adds a little launch overhead per bracketed
  * launch).  kr_profile_enable clears earlier records.
  * kr_profile_query synchronises on the recorded events and returns the number

@@ -78,13 +78,27 @@ hipEvent_t pool_event(kr_handle h) {
 }
 
 // Records an event pair around one launch when profiling is enabled.
+// Does kernel name n contain one of the '|'-separated alternatives of filter (an
+// empty filter matches every kernel)?
+static bool prof_match(const std::string& filter, const char* n) {
+  if (filter.empty()) return true;
+  size_t b = 0;
+  while (b <= filter.size()) {
+    size_t e = filter.find('|', b);
+    if (e == std::string::npos) e = filter.size();
+    if (e > b && std::strstr(n, filter.substr(b, e - b).c_str())) return true;
+    b = e + 1;
+  }
+  return false;
+}
+
 struct ProfScope {
   kr_handle h;
   const char* name;
   hipStream_t s;
   hipEvent_t a = nullptr;
   ProfScope(kr_handle h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) {
-    if (h->prof_on && (h->prof_filter.empty() || std::strstr(n, h->prof_filter.c_str()))) {
+    if (h->prof_on && prof_match(h->prof_filter, n)) {
       a = pool_event(h);
       hipEventRecord(a, s);
     }
