@@ -103,6 +103,9 @@ typedef enum { KR_PREC_F64 = 0, KR_PREC_F32 = 1, KR_PREC_BF16 = 2, KR_PREC_FP8 =
  * flag is ignored) instead of one kernel launch per phase with host
  * convergence checks every check_every iterations. */
 #define KR_OPT_COOPERATIVE 1
+/* kr_opts.flags: with opts.m == 0, take m = ceil(R ln R / eps) samples (R = prod R_n,
+ * natural log) instead of Algorithm 2's theory count. */
+#define KR_OPT_M_RLNR 2
 
 typedef struct {
   int32_t iters;          /* Richardson iterations performed (max over RHS)          */
@@ -137,6 +140,22 @@ kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps
  * float64 prod(R) x nrhs; h_loss receives nrhs values. */
 kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void* d_x,
                     double* h_loss);
+
+/* Many independent ridge problems (Algorithm 2 each; uneven N, I_n, R_n and
+ * right-hand sides) in one call: count problems probs[i] with regularisation
+ * lambda[i] (host array) and outputs d_x[i] (host array of device pointers, each
+ * prod(R) x nrhs float64).  Each problem's setup and sketch is enqueued with the
+ * single-problem kernels; the Richardson iterations of all problems then run in
+ * one persistent launch whose workgroups take problems from a device queue,
+ * largest first, and iterate each to its own stopping rule with workgroup
+ * barriers only.  opts applies to every problem (seed and stream shared; problem
+ * i draws with Philox stream opts->stream + i); float64 only; every R_n <= 16.
+ * h_info (host array of count entries, may be NULL) receives each problem's
+ * result; the return value is KR_OK when every problem converged, else the first
+ * failing problem's status (its message in kr_last_error). */
+kr_status kron_ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda,
+                             double eps, double delta, const kr_opts* opts, void* const* d_x,
+                             kr_info* h_info);
 
 /* The exact minimiser via the factor thin SVDs and KronMatMul (the paper's
  * exact baseline): x* = (kron V) diag(kron s / (kron s^2 + lambda)) (kron U)^T b.

@@ -48,6 +48,7 @@ class Opts(ctypes.Structure):
 
 
 OPT_COOPERATIVE = 1
+OPT_M_RLNR = 2
 
 # kr_precision: the arithmetic of the Richardson iteration (float64 plain, or
 # refined: float64 residual and update, float32 adjoint, preconditioner in the
@@ -91,6 +92,8 @@ def load_library(path=LIB_PATH):
     P, O, IN = ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.POINTER(Info)
     lib.kron_regress.argtypes = [c_p, P, c_d, c_d, O, c_p, IN]
     lib.kron_ridge.argtypes = [c_p, P, c_d, c_d, c_d, O, c_p, IN]
+    lib.kron_ridge_batched.argtypes = [c_p, ctypes.c_int32, P, ctypes.POINTER(c_d), c_d, c_d, O,
+                                       ctypes.POINTER(c_p), IN]
     lib.kron_loss.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d)]
     lib.kron_exact.argtypes = [c_p, P, c_d, c_p]
     lib.tucker_factor_update.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_d, c_d, O, c_p, IN]
@@ -238,6 +241,41 @@ def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200
     if st == KR_WMAXITER and not allow_maxiter:
         raise KronRegressError(st, "iteration limit reached")
     return x, info.as_dict()
+
+
+def kron_ridge_batched(problems, lams, eps=0.1, delta=0.01, m=0, m_rule=None, seed=0, stream=0, max_iter=200,
+                       tol=None, handle=None, raise_on_error=True):
+    """Many independent ridge problems in one call (one persistent launch for all
+    Richardson iterations).  problems: list of (As, b) with As a list of CUDA factor
+    tensors (every R_n <= 16) and b a CUDA tensor; lams: one lambda per problem.
+    m_rule="rlnr" takes m = ceil(R ln R / eps) per problem (with m=0).  Problem i
+    draws with Philox stream `stream + i`.  Returns (xs, infos) and, with
+    raise_on_error=False, also the call's status (per-problem statuses are in infos)."""
+    h = handle or default_handle()
+    n = len(problems)
+    if len(lams) != n:
+        raise ValueError("one lambda per problem")
+    probs = (Problem * n)()
+    keep, xs = [], []
+    for i, (As, b) in enumerate(problems):
+        p, k = _problem(As, b)
+        probs[i] = p
+        keep.append(k)
+        keep.append(b)
+        xs.append(_x_like(As, p.nrhs, b.dim() == 1))
+    lam_arr = (ctypes.c_double * n)(*[float(v) for v in lams])
+    xptr = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    infos = (Info * n)()
+    flags = OPT_M_RLNR if m_rule == "rlnr" else 0
+    if m_rule not in (None, "rlnr"):
+        raise ValueError("m_rule must be None or 'rlnr'")
+    st = h.lib.kron_ridge_batched(h.ptr, n, probs, lam_arr, eps, delta,
+                                  ctypes.byref(_opts(m, max_iter, tol, seed, stream, 8, flags)), xptr, infos)
+    out = [infos[i].as_dict() for i in range(n)]
+    if raise_on_error:
+        h._check(st)   # raises for a negative status (the first failing problem)
+        return xs, out
+    return xs, out, st
 
 
 def kron_loss(As, b, x, lam=0.0, handle=None):

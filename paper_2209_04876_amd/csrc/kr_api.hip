@@ -20,6 +20,7 @@
 #include "kr_persist.hip"
 #include "kr_tucker.hip"
 #include "kr_precond.hip"
+#include "kr_batched.hip"
 #include "kr_mixed.hip"
 
 using namespace kr;
@@ -50,6 +51,8 @@ struct kr_handle_s {
   size_t aux_bytes = 0;
   IterState* h_state = nullptr;   // pinned
   int64_t* h_small = nullptr;     // pinned scratch (flags, counts)
+  void* h_batch = nullptr;         // pinned staging of batched descriptors and results
+  size_t h_batch_bytes = 0;
   // last sketch, for kr_export_sketch
   bool has_sketch = false;
   Geom g{};
@@ -247,6 +250,7 @@ kr_status kr_destroy(kr_handle h) {
   if (h->aux) hipFree(h->aux);
   if (h->h_state) hipHostFree(h->h_state);
   if (h->h_small) hipHostFree(h->h_small);
+  if (h->h_batch) hipHostFree(h->h_batch);
   delete h;
   return KR_OK;
 }
@@ -600,30 +604,111 @@ static void launch_precond(kr_handle h, int prec, const ModeTables& T, const Geo
   else launch_precond_mode<KR_PREC_FP8>(h, nb, T, g, a);
 }
 
-static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
-                       const kr_opts* opts, void* d_x, kr_info* info) {
-  if (!h) return KR_EINVAL;
-  Geom g;
+// Validation, the sample count and the geometry of one Algorithm 2 problem.
+static kr_status prepare_problem(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
+                                 const kr_opts& o, Geom* gout) {
+  Geom& g = *gout;
   kr_status st = make_geom(h, p, &g);
   if (st != KR_OK) return st;
-  if (!p->b || !d_x) KR_FAIL(h, KR_EINVAL, "b or x is NULL");
+  if (!p->b) KR_FAIL(h, KR_EINVAL, "b is NULL");
   if (!(eps > 0.0 && eps < 1.0)) KR_FAIL(h, KR_EINVAL, "eps=%g outside (0, 1)", eps);
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda=%g invalid", lambda);
-  kr_opts o{};
-  if (opts) o = *opts;
   int64_t m = o.m;
-  if (m <= 0) {
+  if (m <= 0 && (o.flags & KR_OPT_M_RLNR)) {
+    const double R = (double)g.Rtot;
+    m = std::max<int64_t>(1, (int64_t)std::ceil(R * std::log(R) / eps));
+  } else if (m <= 0) {
     if (!(delta > 0.0 && delta < 1.0)) KR_FAIL(h, KR_EINVAL, "delta=%g outside (0, 1)", delta);
     const double R = (double)g.Rtot;
-    const double s = std::ceil(1680.0 * R * std::log(40.0 * R) * std::log(1.0 / delta) / eps);
-    if (s > 2.0e9) KR_FAIL(h, KR_EUNSUPPORTED, "theory sample count %.3g too large; pass opts.m", s);
-    m = (int64_t)s;
+    const double sc = std::ceil(1680.0 * R * std::log(40.0 * R) * std::log(1.0 / delta) / eps);
+    if (sc > 2.0e9) KR_FAIL(h, KR_EUNSUPPORTED, "theory sample count %.3g too large; pass opts.m", sc);
+    m = (int64_t)sc;
   }
   if (m > (int64_t(1) << 31) - 2) KR_FAIL(h, KR_EUNSUPPORTED, "m=%lld too large", (long long)m);
   g.m = m;
   for (int k = 0; k <= g.N; ++k)
     if ((double)level_cap(g, k) * (double)g.rsuf[k] * g.nrhs >= 2147483647.0)
       KR_FAIL(h, KR_EUNSUPPORTED, "level %d of the sample tree needs more than 2^31 entries", k);
+  return KR_OK;
+}
+
+// Workspace of one problem's solve, carved from a.  P[0] is the caller's x.
+static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTables* T, SolveBufs* B, Tree* tr,
+                        unsigned** bar) {
+  const int64_t m = g.m;
+  const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
+  carve_setup(a, g, T, &B->s);
+  B->keys = a.take<uint64_t>(m);
+  B->keys_alt = a.take<uint64_t>(m);
+  B->hist = a.take<uint32_t>((size_t)256 * nblocks);
+  B->tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
+  for (int k = 1; k <= g.N; ++k) {
+    const int64_t c = level_cap(g, k);
+    tr->idx[k] = a.take<int32_t>(c + 2);
+    tr->parent[k] = a.take<int32_t>(c + 2);
+    tr->fchild[k] = a.take<int32_t>(c + 2);
+    tr->arow[k] = a.take<double>((size_t)c * g.R[k - 1]);
+  }
+  tr->fchild[0] = a.take<int32_t>(4);
+  const int64_t Dcap = level_cap(g, g.N);
+  tr->rstart = a.take<int32_t>(Dcap + 2);
+  tr->rkey = a.take<uint64_t>(Dcap + 1);
+  tr->cnt = a.take<int64_t>(KR_MAXN + 1);
+  B->Omega = a.take<double>(Dcap);
+  B->counts = a.take<int32_t>(Dcap);
+  B->bD = a.take<double>((size_t)Dcap * g.nrhs);
+  B->P[0] = (double*)d_x;
+  for (int k = 1; k < g.N; ++k) {
+    B->P[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
+    B->Q[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
+  }
+  B->Q[0] = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B->t0 = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B->t1 = a.take<double>((size_t)g.Rtot * g.nrhs);
+  B->dinv = a.take<double>((size_t)g.Rtot);
+  B->wrow = a.take<double>((size_t)Dcap * g.nrhs);
+  B->part = a.take<double>((size_t)((level_cap(g, 1) + RA_NODES - 1) / RA_NODES) * g.Rtot * g.nrhs);
+  B->rs1 = a.take<int64_t>(level_cap(g, 1) + 2);
+  B->state = a.take<IterState>(1);
+  *bar = a.take<unsigned>(64);
+  if (f32rows)
+    for (int k = 1; k < g.N; ++k) tr->arow32[k] = a.take<float>((size_t)level_cap(g, k) * g.R[k - 1]);
+}
+
+// Setup (Gram, eigen or Cholesky route, leverage tables), sampling, the stable
+// radix sort, the sample tree and the gathered rows of one problem, enqueued on
+// the handle's stream without host synchronisation.
+static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T, SolveBufs& B,
+                               Tree& tr, const kr_opts& o, bool need_eig) {
+  hipStream_t s = h->stream;
+  const int64_t m = g.m;
+  const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
+  kr_status st = launch_setup(h, p, g, T, B.s, true, need_eig);
+  if (st != KR_OK) return st;
+  int64_t sumI = 0;
+  for (int n = 0; n < g.N; ++n) sumI += g.I[n];
+  const int in_lds = sumI * 8 <= 48 * 1024;
+  KL(h, k_sample, dim3(grid_for(m, 256, 2048)), dim3(256), in_lds ? sumI * 8 : 0, s, T, g, o.seed, o.stream,
+     (uint64_t)0, in_lds, B.keys);
+  launch_sort_tree(h, g, B.keys, B.keys_alt, B.hist, B.tiletot, nblocks, tr);
+  const int64_t Dcap = level_cap(g, g.N);
+  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
+  KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype, B.Omega, B.bD,
+     B.counts, B.s.flags);
+  HIPCHK(h, hipGetLastError());
+  return KR_OK;
+}
+
+static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
+                       const kr_opts* opts, void* d_x, kr_info* info) {
+  if (!h) return KR_EINVAL;
+  kr_opts o{};
+  if (opts) o = *opts;
+  Geom g;
+  kr_status st = prepare_problem(h, p, lambda, eps, delta, o, &g);
+  if (st != KR_OK) return st;
+  if (!d_x) KR_FAIL(h, KR_EINVAL, "x is NULL");
+  const int64_t m = g.m;
   const int prec = o.precision;
   if (prec < KR_PREC_F64 || prec > KR_PREC_FP8 || o.reserved != 0)
     KR_FAIL(h, KR_EINVAL, "opts.precision=%d invalid (or opts.reserved != 0)", prec);
@@ -635,72 +720,24 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   const double eta = 1.0 - std::sqrt(eps);
 
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
-  const int ntiles = nblocks;
-  st = ensure(h, &h->ws, &h->ws_bytes, solve_bytes(g, ntiles, nblocks));
+  st = ensure(h, &h->ws, &h->ws_bytes, solve_bytes(g, nblocks, nblocks));
   if (st != KR_OK) return st;
   Arena a{(char*)h->ws, h->ws_bytes, 0};
   ModeTables T{};
   SolveBufs B{};
-  carve_setup(a, g, &T, &B.s);
-  B.keys = a.take<uint64_t>(m);
-  B.keys_alt = a.take<uint64_t>(m);
-  B.hist = a.take<uint32_t>((size_t)256 * nblocks);
-  B.tiletot = a.take<int64_t>((size_t)ntiles * (KR_MAXN + 1));
   Tree tr{};
-  for (int k = 1; k <= g.N; ++k) {
-    const int64_t c = level_cap(g, k);
-    tr.idx[k] = a.take<int32_t>(c + 2);
-    tr.parent[k] = a.take<int32_t>(c + 2);
-    tr.fchild[k] = a.take<int32_t>(c + 2);
-    tr.arow[k] = a.take<double>((size_t)c * g.R[k - 1]);
-  }
-  tr.fchild[0] = a.take<int32_t>(4);
-  const int64_t Dcap = level_cap(g, g.N);
-  tr.rstart = a.take<int32_t>(Dcap + 2);
-  tr.rkey = a.take<uint64_t>(Dcap + 1);
-  tr.cnt = a.take<int64_t>(KR_MAXN + 1);
-  B.Omega = a.take<double>(Dcap);
-  B.counts = a.take<int32_t>(Dcap);
-  B.bD = a.take<double>((size_t)Dcap * g.nrhs);
-  B.P[0] = (double*)d_x;
-  for (int k = 1; k < g.N; ++k) {
-    B.P[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
-    B.Q[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
-  }
-  B.Q[0] = a.take<double>((size_t)g.Rtot * g.nrhs);
-  B.t0 = a.take<double>((size_t)g.Rtot * g.nrhs);
-  B.t1 = a.take<double>((size_t)g.Rtot * g.nrhs);
-  B.dinv = a.take<double>((size_t)g.Rtot);
-  B.wrow = a.take<double>((size_t)Dcap * g.nrhs);
-  B.part = a.take<double>((size_t)((level_cap(g, 1) + RA_NODES - 1) / RA_NODES) * g.Rtot * g.nrhs);
-  B.rs1 = a.take<int64_t>(level_cap(g, 1) + 2);
-  B.state = a.take<IterState>(1);
-  unsigned* bar = a.take<unsigned>(64);
-  if (prec != KR_PREC_F64)
-    for (int k = 1; k < g.N; ++k) tr.arow32[k] = a.take<float>((size_t)level_cap(g, k) * g.R[k - 1]);
+  unsigned* bar = nullptr;
+  carve_solve(a, g, prec != KR_PREC_F64, d_x, &T, &B, &tr, &bar);
   if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
 
   hipStream_t s = h->stream;
-  // -- setup: leverage, quantised weights, CDFs
   // the eigenvectors are needed for lambda > 0 (the (kron Lambda + lambda)^+ form),
   // fp8 (eigenvector form) and the cooperative iteration; otherwise G^{-1} suffices
   const bool need_eig = lambda > 0.0 || prec == KR_PREC_FP8 || (o.flags & KR_OPT_COOPERATIVE);
-  st = launch_setup(h, p, g, T, B.s, true, need_eig);
+  st = launch_sketch(h, p, g, T, B, tr, o, need_eig);
   if (st != KR_OK) return st;
-  // -- sampling
-  int64_t sumI = 0;
-  for (int n = 0; n < g.N; ++n) sumI += g.I[n];
-  const int in_lds = sumI * 8 <= 48 * 1024;
-  KL(h, k_sample, dim3(grid_for(m, 256, 2048)), dim3(256), in_lds ? sumI * 8 : 0, s, T, g, o.seed,
-                     o.stream, (uint64_t)0, in_lds, B.keys);
-  // -- stable radix sort and the sample tree (distinct prefixes per level)
-  launch_sort_tree(h, g, B.keys, B.keys_alt, B.hist, B.tiletot, nblocks, tr);
-  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
-  KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype,
-                     B.Omega, B.bD, B.counts, B.s.flags);
   // one host round trip: the setup flags and the level counts of the sample tree,
   // which the iteration kernels take by value
-  HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
@@ -886,6 +923,204 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   return result;
 }
 
+// Per-problem result of a batched solve, gathered on the device.
+struct BatchResult {
+  int32_t iters, all_done, diverged, flags;
+  int64_t distinct_rows;
+  double rel;
+};
+
+__global__ void k_batch_collect(const BatchDesc* __restrict__ descs, int count, BatchResult* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const BatchDesc& d = descs[i];
+    const IterState* st = d.st;
+    BatchResult r;
+    r.iters = st->iters;
+    int all = 1;
+    double rel = 0.0;
+    for (int q = 0; q < d.g.nrhs; ++q) {
+      all &= st->done[q];
+      rel = fmax(rel, st->rel[q]);
+    }
+    r.all_done = all;
+    r.diverged = st->diverged;
+    r.flags = *d.flags;
+    r.distinct_rows = d.tr.cnt[d.g.N];
+    r.rel = rel;
+    out[i] = r;
+  }
+}
+
+static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
+                               double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {
+  if (!h) return KR_EINVAL;
+  if (count < 0) KR_FAIL(h, KR_EINVAL, "count=%d", count);
+  if (count == 0) return KR_OK;
+  if (!probs || !lambda || !d_x) KR_FAIL(h, KR_EINVAL, "probs, lambda or x is NULL");
+  kr_opts o{};
+  if (opts) o = *opts;
+  if (o.precision != KR_PREC_F64 || o.reserved != 0)
+    KR_FAIL(h, KR_EUNSUPPORTED, "batched solves run in float64 only (opts.precision=%d)", o.precision);
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  const double tol = o.tol > 0.0 ? o.tol : 1e-12;
+  const double eta = 1.0 - std::sqrt(eps);
+  // pass 1: geometry, limits, and which problems are large.  A workgroup walks a
+  // problem's rows 32 (node, rhs) pairs at a time, so a problem with many
+  // distinct rows would keep one workgroup busy for long; those (more than
+  // BATCH_BIG_ROWS sampled rows x right-hand sides) take the multi-kernel path
+  // instead, one after the other, before the persistent launch.
+  constexpr double BATCH_BIG_ROWS = 131072.0;
+  std::vector<Geom> G(count);
+  std::vector<double> cost(count);
+  std::vector<char> big(count, 0);
+  for (int i = 0; i < count; ++i) {
+    kr_opts oi = o;
+    oi.stream = o.stream + (uint64_t)i;
+    kr_status st = prepare_problem(h, &probs[i], lambda[i], eps, delta, oi, &G[i]);
+    if (st != KR_OK) return st;
+    if (!d_x[i]) KR_FAIL(h, KR_EINVAL, "x of problem %d is NULL", i);
+    for (int n = 0; n < G[i].N; ++n)
+      if (G[i].R[n] > 16) KR_FAIL(h, KR_EUNSUPPORTED, "batched solves need R_n <= 16 (problem %d)", i);
+    const Geom& g = G[i];
+    double sumR = 0.0;
+    for (int n = 0; n < g.N; ++n) sumR += (double)g.R[n];
+    cost[i] = (double)level_cap(g, g.N) * g.R[g.N - 1] * g.nrhs + (double)level_cap(g, 1) * g.Rtot * g.nrhs +
+              (double)g.Rtot * g.nrhs * sumR;
+    big[i] = (double)level_cap(g, g.N) * g.nrhs > BATCH_BIG_ROWS;
+  }
+  kr_status first = KR_OK;
+  std::string first_msg;
+  auto note = [&](int i, kr_status si, const std::string& msg) {
+    if (si != KR_OK && first == KR_OK) {
+      first = si;
+      first_msg = "problem " + std::to_string(i) + ": " + msg;
+    }
+  };
+  for (int i = 0; i < count; ++i) {
+    if (!big[i]) continue;
+    kr_opts oi = o;
+    oi.stream = o.stream + (uint64_t)i;
+    kr_info inf{};
+    const kr_status si = solve(h, &probs[i], lambda[i], eps, delta, &oi, d_x[i], &inf);
+    if (si == KR_EHIP || si == KR_ENOMEM) return si;
+    if (info) info[i] = inf;
+    note(i, si, si == KR_OK ? std::string() : h->err);
+  }
+  size_t total = 0;
+  int nsmall = 0;
+  for (int i = 0; i < count; ++i) {
+    if (big[i]) continue;
+    const int nb = (int)((G[i].m + SORT_TILE - 1) / SORT_TILE);
+    total += solve_bytes(G[i], nb, nb) + 1024;
+    ++nsmall;
+  }
+  if (nsmall == 0) {
+    h->has_sketch = false;
+    if (first != KR_OK) h->err = first_msg;
+    return first;
+  }
+  total += (size_t)count * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 4096;
+  kr_status st = ensure(h, &h->ws, &h->ws_bytes, total);
+  if (st != KR_OK) return st;
+  const size_t host_bytes = (size_t)count * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 256;
+  if (host_bytes > h->h_batch_bytes) {
+    if (h->h_batch) HIPCHK(h, hipHostFree(h->h_batch));
+    h->h_batch = nullptr;
+    h->h_batch_bytes = 0;
+    HIPCHK(h, hipHostMalloc(&h->h_batch, host_bytes, hipHostMallocDefault));
+    h->h_batch_bytes = host_bytes;
+  }
+  BatchDesc* hd = (BatchDesc*)h->h_batch;
+  int32_t* horder = (int32_t*)(hd + count);
+  BatchResult* hres = (BatchResult*)(((uintptr_t)(horder + count) + 15) & ~(uintptr_t)15);
+  Arena a{(char*)h->ws, h->ws_bytes, 0};
+  BatchDesc* d_descs = a.take<BatchDesc>(count);
+  int32_t* d_order = a.take<int32_t>(count);
+  int32_t* d_queue = a.take<int32_t>(64);
+  BatchResult* d_res = a.take<BatchResult>(count);
+  hipStream_t s = h->stream;
+  // pass 2: carve, and enqueue every remaining problem's setup and sketch
+  std::vector<int32_t> slot(count, -1), idx;
+  for (int i = 0; i < count; ++i)
+    if (!big[i]) { slot[i] = (int32_t)idx.size(); idx.push_back(i); }
+  for (int i : idx) {
+    const Geom& g = G[i];
+    ModeTables T{};
+    SolveBufs B{};
+    Tree tr{};
+    unsigned* bar = nullptr;
+    carve_solve(a, g, false, d_x[i], &T, &B, &tr, &bar);
+    if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
+    kr_opts oi = o;
+    oi.stream = o.stream + (uint64_t)i;
+    st = launch_sketch(h, &probs[i], g, T, B, tr, oi, lambda[i] > 0.0);
+    if (st != KR_OK) return st;
+    if (lambda[i] > 0.0)
+      KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, s, T, g, lambda[i], B.dinv);
+    KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, (double*)d_x[i], g.Rtot * g.nrhs,
+       0.0);
+    KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
+    BatchDesc& d = hd[slot[i]];
+    std::memset(&d, 0, sizeof(BatchDesc));
+    d.g = g;
+    d.T = T;
+    d.tr = tr;
+    for (int k = 0; k <= KR_MAXN; ++k) { d.P[k] = B.P[k]; d.Q[k] = B.Q[k]; }
+    d.Omega = B.Omega;
+    d.bD = B.bD;
+    d.t0 = B.t0;
+    d.t1 = B.t1;
+    d.dinv = B.dinv;
+    d.st = B.state;
+    d.flags = B.s.flags;
+    d.lambda = lambda[i];
+    d.use_ginv = lambda[i] == 0.0 ? 1 : 0;
+  }
+  // problems largest first (indices into the descriptor array)
+  const int nb_ = nsmall;
+  std::vector<int32_t> ord(nb_);
+  for (int k = 0; k < nb_; ++k) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[idx[x]] > cost[idx[y]]; });
+  std::memcpy(horder, ord.data(), nb_ * sizeof(int32_t));
+  HIPCHK(h, hipMemcpyAsync(d_descs, hd, nb_ * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(d_order, horder, nb_ * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)d_queue, (int64_t)64);
+  int dev = 0, ncu = 0, per_cu = 0;
+  HIPCHK(h, hipGetDevice(&dev));
+  HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_richardson<1>, BT_THREADS,
+                                                         0));
+  const int nwg = std::max(1, std::min(nb_, std::max(1, per_cu) * ncu));
+  KLN(h, "k_batched_richardson", k_batched_richardson<1>, dim3(nwg), dim3(BT_THREADS), 0, s,
+      (const BatchDesc*)d_descs, (const int32_t*)d_order, nb_, d_queue, eta, tol, max_iter);
+  KL(h, k_batch_collect, dim3(grid_for(nb_, 256, 64)), dim3(256), 0, s, (const BatchDesc*)d_descs, nb_, d_res);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(hres, d_res, nb_ * sizeof(BatchResult), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) {
+    if (big[i]) continue;
+    const BatchResult& r = hres[slot[i]];
+    kr_status si = KR_OK;
+    const char* msg = "";
+    if (r.flags & KR_FLAG_NONFINITE) { si = KR_EINVAL; msg = "non-finite entries in A or b"; }
+    else if (r.flags & KR_FLAG_QUANT) { si = KR_EINVAL; msg = "a factor has no non-zero leverage to sample from"; }
+    else if ((r.flags & KR_FLAG_SINGULAR) && lambda[i] == 0.0) { si = KR_ESINGULAR; msg = "a factor Gram matrix is singular and lambda = 0"; }
+    else if (r.diverged) { si = KR_EDIVERGED; msg = "Richardson iteration diverged"; }
+    else if (!r.all_done) { si = KR_WMAXITER; msg = "iteration limit reached before the stopping rule was met"; }
+    if (info) {
+      info[i].iters = r.iters;
+      info[i].status = si;
+      info[i].m = G[i].m;
+      info[i].distinct_rows = r.distinct_rows;
+      info[i].rel_update = r.rel;
+    }
+    note(i, si, msg);
+  }
+  h->has_sketch = false;
+  if (first != KR_OK) h->err = first_msg;
+  return first;
+}
+
 extern "C" {
 
 kr_status kron_regress(kr_handle h, const kr_problem* p, double eps, double delta, const kr_opts* opts,
@@ -896,6 +1131,11 @@ kr_status kron_regress(kr_handle h, const kr_problem* p, double eps, double delt
 kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
                      const kr_opts* opts, void* d_x, kr_info* info) {
   return solve(h, p, lambda, eps, delta, opts, d_x, info);
+}
+
+kr_status kron_ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
+                             double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {
+  return solve_batched(h, count, probs, lambda, eps, delta, opts, d_x, info);
 }
 
 kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega, int32_t* h_counts,

@@ -404,25 +404,22 @@ __device__ void pc_mode_lp(const Geom& g, int n, const float* M, int trans, floa
   }
 }
 
-// Float64 step.  grad holds the gradient as nnb partial blocks (summed here); dinv (Rtot) holds 1 / (kron Lambda + lambda) (0 where the sum
-// vanishes) for the eigenvector form.
+// Float64 step of one workgroup (any multiple of 64 threads).  grad holds the
+// gradient as nnb partial blocks (summed here); dinv (Rtot) holds
+// 1 / (kron Lambda + lambda) (0 where the sum vanishes) for the eigenvector form.
+// cur/nxt are the two tensor buffers (LDS or global); ms stages factor matrices
+// (PC_MATS entries), red holds 16 doubles.  Returns without touching x when the
+// state is already converged.
 template <int NB>
-__global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
-                                                       unsigned nnb,
-                                                       const double* __restrict__ dinv, double* __restrict__ x,
-                                                       double* __restrict__ t0, double* __restrict__ t1, int lds,
-                                                       double lambda, double eta, double tol, int max_iter,
-                                                       int use_ginv, IterState* __restrict__ st) {
-  extern __shared__ double pd_dyn[];
-  __shared__ double red[16];
-  __shared__ double ms[PC_MATS];
+__device__ void pc_step_f64(const ModeTables& T, const Geom& g, const double* __restrict__ grad, unsigned nnb,
+                            const double* __restrict__ dinv, double* __restrict__ x, double* cur, double* nxt,
+                            double lambda, double eta, double tol, int max_iter, int use_ginv,
+                            IterState* __restrict__ st, double* red, double* ms) {
   // state loads issued together with the staging and h loads below
   const int all_done = st->all_done;
   const int it0 = st->iters;
   const int done_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->done[threadIdx.x & 63] : 1;
   const int64_t total = g.Rtot * g.nrhs;
-  double* cur = lds ? pd_dyn : t0;
-  double* nxt = lds ? pd_dyn + total : t1;
   const bool all = pc_mats_fit(g);
   const double* const* Ms = use_ginv ? T.Ginv : T.V;
   if (all) pc_stage(g, Ms, 0, true, ms);
@@ -447,6 +444,23 @@ __global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, co
     for (int n = 0; n < g.N; ++n) product(n, 0);
   }
   pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane);
+}
+
+// Float64 step as its own launch (one workgroup of 256 threads); the tensor
+// buffers are in dynamic LDS when lds != 0, else t0/t1.
+template <int NB>
+__global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
+                                                       unsigned nnb,
+                                                       const double* __restrict__ dinv, double* __restrict__ x,
+                                                       double* __restrict__ t0, double* __restrict__ t1, int lds,
+                                                       double lambda, double eta, double tol, int max_iter,
+                                                       int use_ginv, IterState* __restrict__ st) {
+  extern __shared__ double pd_dyn[];
+  __shared__ double red[16];
+  __shared__ double ms[PC_MATS];
+  const int64_t total = g.Rtot * g.nrhs;
+  pc_step_f64<NB>(T, g, grad, nnb, dinv, x, lds ? pd_dyn : t0, lds ? pd_dyn + total : t1, lambda, eta, tol, max_iter,
+                  use_ginv, st, red, ms);
 }
 
 // Refined-precision step: float32 gradient and tensor, mode products in MODE.
