@@ -58,8 +58,28 @@ typedef enum { KR_F64 = 0, KR_F32 = 1 } kr_dtype;
 
 typedef struct kr_handle_s* kr_handle;
 
+/* An implicit response b = K X_true + sigma E, for problems whose dense b would
+ * not fit in memory (prod(I) x nrhs entries).  Only the sampled rows of b are
+ * ever formed: K X_true at a sampled row by the sample tree's Kronecker-row
+ * products (the same contraction as K~x in the iteration), plus sigma E[i][q].
+ * E[i][q] is a standard normal drawn by the Box-Muller transform from the first
+ * two words (w0, w1) of Philox4x64-10 with key (seed, stream) and counter
+ * (i, q, 0, 0), where i is K's row index:
+ *   u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1],  u2 = (w1 >> 11) 2^-53 in [0, 1),
+ *   E  = sqrt(-2 ln u1) cos(2 pi u2).
+ * X_true is a device pointer to prod(R) x nrhs float64 (row-major); the struct
+ * itself is read during the call only.  kron_loss and tucker_factor_update need
+ * a dense b and reject problems that carry a generator. */
+typedef struct {
+  const double* X_true;
+  double sigma;
+  uint64_t seed;
+  uint64_t stream;
+} kr_response_gen;
+
 /* One Kronecker regression problem.  A[n] points to an I[n] x R[n] row-major
- * matrix of dtype a_dtype; b to prod(I) x nrhs entries of dtype b_dtype. */
+ * matrix of dtype a_dtype; b to prod(I) x nrhs entries of dtype b_dtype, or b is
+ * NULL and gen describes an implicit response. */
 typedef struct {
   int32_t N;                       /* number of factors, 1..KR_MAX_MODES            */
   int32_t nrhs;                    /* right-hand sides sharing the sketch (>= 1)    */
@@ -68,7 +88,8 @@ typedef struct {
   const void* A[KR_MAX_MODES];     /* device pointers                                */
   int32_t a_dtype;                 /* kr_dtype                                       */
   int32_t b_dtype;                 /* kr_dtype                                       */
-  const void* b;                   /* device pointer                                 */
+  const void* b;                   /* device pointer, or NULL with gen               */
+  const kr_response_gen* gen;      /* host pointer or NULL                           */
 } kr_problem;
 
 typedef struct {

@@ -19,6 +19,8 @@ Modules
   regression  Algorithm 2 (FastKroneckerRegression): the sketched problem, its
               direct minimiser, the preconditioned Richardson replay, the exact
               optimum (KronMatMul baseline) and the loss.
+  response    implicit responses b = K X_true + sigma E (Philox Box-Muller
+              noise indexed by row), for workloads whose dense b is too large.
   tucker      Algorithm 3 (FastFactorMatrixUpdate), the Woodbury form of its
               preconditioner, exact factor-row solutions and exact Tucker ALS
               (Algorithm 1).
@@ -27,4 +29,4 @@ Parity status of every function is stated in its docstring ("pinned by ..."
 names the test that ties it to something other than itself).
 """
 
-from . import philox, kron, leverage, sampling, regression, tucker  # noqa: F401
+from . import philox, kron, leverage, sampling, regression, tucker, response  # noqa: F401

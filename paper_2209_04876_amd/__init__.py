@@ -33,11 +33,29 @@ class KronRegressError(RuntimeError):
         self.status = status
 
 
+class ResponseGenC(ctypes.Structure):
+    _fields_ = [("X_true", ctypes.c_void_p), ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_uint64)]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("nrhs", ctypes.c_int32),
                 ("I", ctypes.c_int64 * MAX_MODES), ("R", ctypes.c_int64 * MAX_MODES),
                 ("A", ctypes.c_void_p * MAX_MODES), ("a_dtype", ctypes.c_int32),
-                ("b_dtype", ctypes.c_int32), ("b", ctypes.c_void_p)]
+                ("b_dtype", ctypes.c_int32), ("b", ctypes.c_void_p), ("gen", ctypes.POINTER(ResponseGenC))]
+
+
+class ResponseGen:
+    """An implicit response b = K X_true + sigma E, passed in place of b: only the
+    sampled rows of b are formed (on the GPU).  E[i][q] is the Box-Muller normal of
+    Philox4x64-10 words 0 and 1 at counter (i, q, 0, 0), key (seed, stream), with i
+    K's row index.  X_true: contiguous float64 CUDA tensor, prod(R) or prod(R) x nrhs."""
+
+    def __init__(self, X_true, sigma, seed=0, stream=0):
+        self.X_true, self.sigma, self.seed, self.stream = X_true, float(sigma), int(seed), int(stream)
+
+    def dim(self):
+        return self.X_true.dim()
 
 
 class Opts(ctypes.Structure):
@@ -172,7 +190,15 @@ def _problem(As, b):
         p.A[n] = A.data_ptr()
         keep.append(A)
     p.a_dtype = {torch.float64: KR_F64, torch.float32: KR_F32}[adt]
-    if b is not None:
+    if isinstance(b, ResponseGen):
+        X = b.X_true
+        if not (X.is_cuda and X.is_contiguous() and X.dim() in (1, 2) and X.dtype == torch.float64):
+            raise ValueError("X_true must be a contiguous 1-D or 2-D float64 CUDA tensor")
+        p.nrhs = 1 if X.dim() == 1 else X.shape[1]
+        g = ResponseGenC(X.data_ptr(), b.sigma, b.seed & 0xFFFFFFFFFFFFFFFF, b.stream & 0xFFFFFFFFFFFFFFFF)
+        p.gen = ctypes.pointer(g)
+        keep += [g, X]
+    elif b is not None:
         if not (b.is_cuda and b.is_contiguous() and b.dim() in (1, 2)):
             raise ValueError("b must be a contiguous 1-D or 2-D CUDA tensor")
         p.nrhs = 1 if b.dim() == 1 else b.shape[1]
@@ -397,7 +423,7 @@ def export_sketch(sizes, handle=None, cap=None):
             "Omega": Omega, "counts": counts.astype(np.int64)}
 
 
-__all__ = ["Handle", "KronRegressError", "kron_regress", "kron_ridge", "kron_loss", "kron_exact",
+__all__ = ["Handle", "KronRegressError", "ResponseGen", "kron_regress", "kron_ridge", "kron_loss", "kron_exact",
            "tucker_factor_update", "tucker_als", "als_stream",
            "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query",
            "profile_names", "profile_breakdown"]

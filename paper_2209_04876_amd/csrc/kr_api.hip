@@ -610,7 +610,12 @@ static kr_status prepare_problem(kr_handle h, const kr_problem* p, double lambda
   Geom& g = *gout;
   kr_status st = make_geom(h, p, &g);
   if (st != KR_OK) return st;
-  if (!p->b) KR_FAIL(h, KR_EINVAL, "b is NULL");
+  if (!p->b && !p->gen) KR_FAIL(h, KR_EINVAL, "b is NULL and no response generator is given");
+  if (p->gen) {
+    if (p->b) KR_FAIL(h, KR_EINVAL, "give either b or a response generator, not both");
+    if (!p->gen->X_true) KR_FAIL(h, KR_EINVAL, "response generator without X_true");
+    if (!std::isfinite(p->gen->sigma)) KR_FAIL(h, KR_EINVAL, "response generator sigma is not finite");
+  }
   if (!(eps > 0.0 && eps < 1.0)) KR_FAIL(h, KR_EINVAL, "eps=%g outside (0, 1)", eps);
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda=%g invalid", lambda);
   int64_t m = o.m;
@@ -695,6 +700,15 @@ static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, 
   KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
   KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype, B.Omega, B.bD,
      B.counts, B.s.flags);
+  if (p->gen) {
+    // implicit response: forward levels 1..N-2 of X_true, then the rows
+    const double* X = p->gen->X_true;
+    for (int k = 1; k <= g.N - 2; ++k)
+      KL(h, k_gen_level, dim3(grid_for(level_cap(g, k) * g.rsuf[k] * g.nrhs, 256, 4096)), dim3(256), 0, s, g, tr, k,
+         k == 1 ? X : (const double*)B.P[k - 1], B.P[k]);
+    KL(h, k_gen_rows, dim3(grid_for(Dcap, 256, 4096)), dim3(256), 0, s, g, tr,
+       g.N >= 3 ? (const double*)B.P[g.N - 2] : X, p->gen->sigma, p->gen->seed, p->gen->stream, B.bD, B.s.flags);
+  }
   HIPCHK(h, hipGetLastError());
   return KR_OK;
 }
@@ -1345,6 +1359,7 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   if (p->N < 2) KR_FAIL(h, KR_EINVAL, "a factor update needs N >= 2");
   if (mode < 0 || mode >= p->N) KR_FAIL(h, KR_EINVAL, "mode %d outside 0..%d", mode, p->N - 1);
   if (p->nrhs != 1) KR_FAIL(h, KR_EINVAL, "the tensor is a single right-hand side");
+  if (p->gen) KR_FAIL(h, KR_EINVAL, "a factor update needs the dense tensor X, not a response generator");
   if (!p->b || !d_core || !d_A_out) KR_FAIL(h, KR_EINVAL, "X, core or output is NULL");
   if (!(eps > 0.0 && eps < 1.0)) KR_FAIL(h, KR_EINVAL, "eps=%g outside (0, 1)", eps);
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda=%g invalid", lambda);

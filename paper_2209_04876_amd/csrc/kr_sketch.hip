@@ -338,10 +338,88 @@ __global__ void __launch_bounds__(256) k_rows(ModeTables T, Geom g, Tree tr, con
     const double om = 1.0 / den;
     Omega[j] = (double)c * om;
     counts[j] = c;
+    if (!b) continue;   // implicit response: k_gen_rows fills bD
     for (int q = 0; q < g.nrhs; ++q) {
       const int64_t e = lin * g.nrhs + q;
       const double v = b_dtype == KR_F32 ? (double)((const float*)b)[e] : ((const double*)b)[e];
       bD[j * g.nrhs + q] = v;
+      bad |= !isfinite(v);
+    }
+  }
+  if (bad) atomicOr(flags, KR_FLAG_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// Implicit response b = K X_true + sigma E, formed at the distinct rows only.
+// K X_true at a sampled row is the same Kronecker-row product as K~x in the
+// iteration, taken down the sample tree with X_true in place of x.
+// ---------------------------------------------------------------------------
+
+// Forward level k applied to X_true:
+// P_k[s][cq] = sum_r A_{k-1}[i_k(s)][r] P_{k-1}[parent(s)][r][cq], P_0 = X_true.
+__global__ void __launch_bounds__(256) k_gen_level(Geom g, Tree tr, int k, const double* __restrict__ Pp,
+                                                   double* __restrict__ Po) {
+  const int64_t S = tr.cnt[k];
+  const int64_t W = g.rsuf[k] * g.nrhs, Wp = g.rsuf[k - 1] * g.nrhs;
+  const int Rk = g.R[k - 1];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < S * W;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / W, cq = e - s * W;
+    const int64_t p = k == 1 ? 0 : tr.parent[k][s];
+    const double* __restrict__ a = tr.arow[k] + s * Rk;
+    const double* __restrict__ src = Pp + p * Wp + cq;
+    double acc = 0.0;
+    for (int r = 0; r < Rk; ++r) acc = fma(a[r], src[(int64_t)r * W], acc);
+    Po[e] = acc;
+  }
+}
+
+// Standard normal E[i][q]: Box-Muller on the first two words of Philox4x64-10
+// with counter (i, q, 0, 0) and key (seed, stream).
+__device__ __forceinline__ double gen_normal(uint64_t i, uint64_t q, uint64_t seed, uint64_t stream) {
+  const u64x4 w = philox4x64_10(i, q, 0ull, 0ull, seed, stream);
+  const double u1 = (double)((w.v[0] >> 11) + 1ull) * 0x1p-53;
+  const double u2 = (double)(w.v[1] >> 11) * 0x1p-53;
+  const double two_pi = 6.283185307179586;
+  return sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+}
+
+// b~_j[q] = (K X_true)[i_j][q] + sigma E[i_j][q] for every distinct row j: the
+// last two tree levels contracted from P_{N-2} (X_true itself when N <= 2).
+__global__ void __launch_bounds__(256) k_gen_rows(Geom g, Tree tr, const double* __restrict__ Pn2, double sigma,
+                                                  uint64_t seed, uint64_t stream, double* __restrict__ bD,
+                                                  int32_t* __restrict__ flags) {
+  const int64_t D = tr.cnt[g.N];
+  const int N = g.N, nrhs = g.nrhs;
+  const int RL = g.R[N - 1];
+  const int RP = N >= 2 ? g.R[N - 2] : 1;
+  int bad = 0;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < D;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = tr.rkey[j];
+    int64_t lin = 0;
+    for (int n = 0; n < N; ++n) lin = lin * g.I[n] + (int64_t)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+    const double* __restrict__ aL = tr.arow[N] + j * RL;
+    const double* __restrict__ aP = nullptr;
+    int64_t base = 0;
+    if (N >= 2) {
+      const int64_t s = tr.parent[N][j];
+      aP = tr.arow[N - 1] + s * RP;
+      base = (N >= 3 ? (int64_t)tr.parent[N - 1][s] : 0) * g.rsuf[N - 2] * nrhs;
+    }
+    for (int q = 0; q < nrhs; ++q) {
+      double y = 0.0;
+      if (N == 1) {
+        for (int r = 0; r < RL; ++r) y = fma(aL[r], Pn2[(int64_t)r * nrhs + q], y);
+      } else {
+        for (int r1 = 0; r1 < RP; ++r1) {
+          double t = 0.0;
+          for (int r2 = 0; r2 < RL; ++r2) t = fma(aL[r2], Pn2[base + ((int64_t)r1 * RL + r2) * nrhs + q], t);
+          y = fma(aP[r1], t, y);
+        }
+      }
+      const double v = y + sigma * gen_normal((uint64_t)lin, (uint64_t)q, seed, stream);
+      bD[j * nrhs + q] = v;
       bad |= !isfinite(v);
     }
   }

@@ -42,7 +42,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     """ctypes mirrors of kr_problem / kr_opts / kr_info have the C layout (gcc)."""
     import subprocess
     import paper_2209_04876_amd as kr
-    structs = {"kr_problem": kr.Problem, "kr_opts": kr.Opts, "kr_info": kr.Info}
+    structs = {"kr_problem": kr.Problem, "kr_opts": kr.Opts, "kr_info": kr.Info,
+               "kr_response_gen": kr.ResponseGenC}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kron_regress.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
