@@ -404,15 +404,20 @@ static int64_t level_cap(const Geom& g, int k) {
   return (int64_t)std::min<double>((double)g.m, prod);
 }
 
-static size_t solve_bytes(const Geom& g, int ntiles, int nblocks) {
+// Workspace of one solve.  lean: the batched team's layout, which never forms
+// the level-(N-1) products (N >= 3) nor the single-problem iteration's row and
+// partial-sum buffers.
+static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = false) {
   size_t b = setup_bytes(g);
   b += 2 * 8 * (size_t)g.m + 4 * 256 * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
   const int64_t D = level_cap(g, g.N);
   b += (size_t)D * (8 + 8 * g.nrhs + 4);
   for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
   b += 4 * (size_t)(D + 2) + 8 * (size_t)D;
-  for (int k = 1; k < g.N; ++k) b += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs;
+  for (int k = 1; k < g.N; ++k)
+    if (!(lean && g.N >= 3 && k == g.N - 1)) b += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs + 512;
   b += 3 * 8 * (size_t)g.Rtot * g.nrhs + 8 * (size_t)g.Rtot + sizeof(IterState) + 8 * (KR_MAXN + 1) + 768;
+  if (lean) return b + 8 * (size_t)(level_cap(g, 1) + 2) + 64 * 256 + 8192;
   b += 8 * (size_t)D * g.nrhs + 8 * (size_t)(level_cap(g, 1) + 2) + 512;
   b += 8 * (size_t)((level_cap(g, 1) + 31) / 32) * g.Rtot * g.nrhs + 512;
   for (int k = 1; k < g.N; ++k) b += 4 * (size_t)level_cap(g, k) * g.R[k - 1] + 256;
@@ -639,7 +644,7 @@ static kr_status prepare_problem(kr_handle h, const kr_problem* p, double lambda
 
 // Workspace of one problem's solve, carved from a.  P[0] is the caller's x.
 static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTables* T, SolveBufs* B, Tree* tr,
-                        unsigned** bar) {
+                        unsigned** bar, bool lean = false) {
   const int64_t m = g.m;
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
   carve_setup(a, g, T, &B->s);
@@ -664,6 +669,10 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   B->bD = a.take<double>((size_t)Dcap * g.nrhs);
   B->P[0] = (double*)d_x;
   for (int k = 1; k < g.N; ++k) {
+    if (lean && g.N >= 3 && k == g.N - 1) {
+      B->P[k] = B->Q[k] = nullptr;
+      continue;
+    }
     B->P[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
     B->Q[k] = a.take<double>((size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs);
   }
@@ -671,8 +680,8 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   B->t0 = a.take<double>((size_t)g.Rtot * g.nrhs);
   B->t1 = a.take<double>((size_t)g.Rtot * g.nrhs);
   B->dinv = a.take<double>((size_t)g.Rtot);
-  B->wrow = a.take<double>((size_t)Dcap * g.nrhs);
-  B->part = a.take<double>((size_t)((level_cap(g, 1) + RA_NODES - 1) / RA_NODES) * g.Rtot * g.nrhs);
+  B->wrow = lean ? nullptr : a.take<double>((size_t)Dcap * g.nrhs);
+  B->part = lean ? nullptr : a.take<double>((size_t)((level_cap(g, 1) + RA_NODES - 1) / RA_NODES) * g.Rtot * g.nrhs);
   B->rs1 = a.take<int64_t>(level_cap(g, 1) + 2);
   B->state = a.take<IterState>(1);
   *bar = a.take<unsigned>(64);
@@ -965,6 +974,44 @@ __global__ void k_batch_collect(const BatchDesc* __restrict__ descs, int count, 
   }
 }
 
+// Stage list of one team problem's iteration (see kr_batched.hip).
+static void team_stages(const Geom& g, const ModeTables& T, bool use_ginv, LExtra* L) {
+  int n = 0;
+  auto add = [&](int kind, int k, int trans, int io, const double* M) {
+    L->st[n].kind = kind;
+    L->st[n].k = k;
+    L->st[n].trans = trans;
+    L->st[n].io = io;
+    L->st[n].M = M;
+    ++n;
+  };
+  const int N = g.N;
+  if (N <= 2) {
+    add(LS_ROWS, 0, 0, 0, nullptr);
+  } else {
+    for (int k = 1; k <= N - 2; ++k) add(LS_FWD, k, 0, 0, nullptr);
+    add(LS_ROWS2, 0, 0, 0, nullptr);
+    for (int k = N - 2; k >= 2; --k) add(LS_ADJ, k, 0, 0, nullptr);
+  }
+  if (N >= 2) add(LS_ROOT, 0, 0, 0, nullptr);
+  int j = 0;   // mode products alternate t0, t1; the first reads h = g + lambda x
+  auto mode = [&](int k, int trans, bool scale, const double* M) {
+    int io = (j == 0 ? 1 : 0) | (scale ? 2 : 0) | ((j & 1) ? 4 : 0) | (j > 0 && ((j - 1) & 1) ? 8 : 0);
+    add(LS_MODE, k, trans, io, M);
+    ++j;
+  };
+  if (use_ginv) {
+    for (int k = 0; k < N; ++k) mode(k, 0, false, T.Ginv[k]);
+  } else {
+    for (int k = 0; k < N; ++k) mode(k, 1, k == N - 1, T.V[k]);
+    for (int k = 0; k < N; ++k) mode(k, 0, false, T.V[k]);
+  }
+  L->dfin = (j - 1) & 1;
+  add(LS_UPD, 0, 0, 0, nullptr);
+  L->nst = n;
+  L->nchunk = (int32_t)((g.Rtot + BT_THREADS - 1) / BT_THREADS);
+}
+
 static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
                                double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {
   if (!h) return KR_EINVAL;
@@ -978,15 +1025,17 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
   const double tol = o.tol > 0.0 ? o.tol : 1e-12;
   const double eta = 1.0 - std::sqrt(eps);
-  // pass 1: geometry, limits, and which problems are large.  A workgroup walks a
-  // problem's rows 32 (node, rhs) pairs at a time, so a problem with many
-  // distinct rows would keep one workgroup busy for long; those (more than
-  // BATCH_BIG_ROWS sampled rows x right-hand sides) take the multi-kernel path
-  // instead, one after the other, before the persistent launch.
+  // pass 1: geometry, limits and routes.  A queue workgroup walks a problem's
+  // rows 32 (node, rhs) pairs at a time, so problems with more than
+  // BATCH_BIG_ROWS sampled rows x right-hand sides go to the team instead (up to
+  // LS_MAXP of them); a large single-factor problem has no tree level to split
+  // over and takes the multi-kernel path.
   constexpr double BATCH_BIG_ROWS = 131072.0;
+  enum Route : char { QUEUE = 0, TEAM = 1, SOLO = 2 };
   std::vector<Geom> G(count);
   std::vector<double> cost(count);
-  std::vector<char> big(count, 0);
+  std::vector<char> route(count, QUEUE);
+  int nteam_p = 0;
   for (int i = 0; i < count; ++i) {
     kr_opts oi = o;
     oi.stream = o.stream + (uint64_t)i;
@@ -996,11 +1045,16 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     for (int n = 0; n < G[i].N; ++n)
       if (G[i].R[n] > 16) KR_FAIL(h, KR_EUNSUPPORTED, "batched solves need R_n <= 16 (problem %d)", i);
     const Geom& g = G[i];
+    if ((double)g.Rtot * g.nrhs > 2147483647.0)
+      KR_FAIL(h, KR_EUNSUPPORTED, "batched solves need prod(R) x nrhs < 2^31 (problem %d)", i);
     double sumR = 0.0;
     for (int n = 0; n < g.N; ++n) sumR += (double)g.R[n];
     cost[i] = (double)level_cap(g, g.N) * g.R[g.N - 1] * g.nrhs + (double)level_cap(g, 1) * g.Rtot * g.nrhs +
               (double)g.Rtot * g.nrhs * sumR;
-    big[i] = (double)level_cap(g, g.N) * g.nrhs > BATCH_BIG_ROWS;
+    if ((double)level_cap(g, g.N) * g.nrhs > BATCH_BIG_ROWS) {
+      if (g.N == 1) route[i] = SOLO;
+      else if (nteam_p < LS_MAXP) { route[i] = TEAM; ++nteam_p; }
+    }
   }
   kr_status first = KR_OK;
   std::string first_msg;
@@ -1011,7 +1065,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     }
   };
   for (int i = 0; i < count; ++i) {
-    if (!big[i]) continue;
+    if (route[i] != SOLO) continue;
     kr_opts oi = o;
     oi.stream = o.stream + (uint64_t)i;
     kr_info inf{};
@@ -1020,23 +1074,31 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     if (info) info[i] = inf;
     note(i, si, si == KR_OK ? std::string() : h->err);
   }
-  size_t total = 0;
-  int nsmall = 0;
-  for (int i = 0; i < count; ++i) {
-    if (big[i]) continue;
-    const int nb = (int)((G[i].m + SORT_TILE - 1) / SORT_TILE);
-    total += solve_bytes(G[i], nb, nb) + 1024;
-    ++nsmall;
-  }
-  if (nsmall == 0) {
+  // descriptor slots: queue problems first, then the team's
+  std::vector<int32_t> slot(count, -1), idx;
+  for (int i = 0; i < count; ++i)
+    if (route[i] == QUEUE) { slot[i] = (int32_t)idx.size(); idx.push_back(i); }
+  const int nq = (int)idx.size();
+  for (int i = 0; i < count; ++i)
+    if (route[i] == TEAM) { slot[i] = (int32_t)idx.size(); idx.push_back(i); }
+  const int nall = (int)idx.size();
+  if (nall == 0) {
     h->has_sketch = false;
     if (first != KR_OK) h->err = first_msg;
     return first;
   }
-  total += (size_t)count * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 4096;
+  size_t total = 0, nparts = 0;
+  for (int i : idx) {
+    const int nb = (int)((G[i].m + SORT_TILE - 1) / SORT_TILE);
+    total += solve_bytes(G[i], nb, nb, route[i] == TEAM) + 1024;
+    if (route[i] == TEAM) nparts += (size_t)((G[i].Rtot + BT_THREADS - 1) / BT_THREADS) * G[i].nrhs * 2;
+  }
+  total += (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 4096;
+  total += (size_t)nteam_p * (sizeof(LExtra) + 8 + 4) + nparts * 8 + 8192;
   kr_status st = ensure(h, &h->ws, &h->ws_bytes, total);
   if (st != KR_OK) return st;
-  const size_t host_bytes = (size_t)count * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 256;
+  const size_t host_bytes = (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) +
+                            (size_t)nteam_p * sizeof(LExtra) + 1024;
   if (host_bytes > h->h_batch_bytes) {
     if (h->h_batch) HIPCHK(h, hipHostFree(h->h_batch));
     h->h_batch = nullptr;
@@ -1044,26 +1106,38 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     HIPCHK(h, hipHostMalloc(&h->h_batch, host_bytes, hipHostMallocDefault));
     h->h_batch_bytes = host_bytes;
   }
-  BatchDesc* hd = (BatchDesc*)h->h_batch;
-  int32_t* horder = (int32_t*)(hd + count);
-  BatchResult* hres = (BatchResult*)(((uintptr_t)(horder + count) + 15) & ~(uintptr_t)15);
+  char* hb = (char*)h->h_batch;
+  BatchDesc* hd = (BatchDesc*)hb;
+  LExtra* hl = (LExtra*)(((uintptr_t)(hd + nall) + 15) & ~(uintptr_t)15);
+  int32_t* horder = (int32_t*)(hl + nteam_p);
+  BatchResult* hres = (BatchResult*)(((uintptr_t)(horder + nall) + 15) & ~(uintptr_t)15);
+  int32_t* habort = (int32_t*)(hres + nall);
   Arena a{(char*)h->ws, h->ws_bytes, 0};
-  BatchDesc* d_descs = a.take<BatchDesc>(count);
-  int32_t* d_order = a.take<int32_t>(count);
-  int32_t* d_queue = a.take<int32_t>(64);
-  BatchResult* d_res = a.take<BatchResult>(count);
+  BatchDesc* d_descs = a.take<BatchDesc>(nall);
+  LExtra* d_l = a.take<LExtra>(std::max(1, nteam_p));
+  int32_t* d_order = a.take<int32_t>(nall);
+  BatchResult* d_res = a.take<BatchResult>(nall);
+  // launch-wide counters, cleared together: queue counter, team barrier, abort
+  // flag, then per team problem a ticket and a done step
+  const size_t cnt_words = 64 + (size_t)nteam_p * 3;
+  uint32_t* d_cnt = a.take<uint32_t>(cnt_words);
+  int32_t* d_queue = (int32_t*)d_cnt;
+  unsigned* d_bar = d_cnt + 16;
+  int32_t* d_abort = (int32_t*)(d_cnt + 32);
+  int32_t* d_ticket = (int32_t*)(d_cnt + 64);
+  int64_t* d_done = a.take<int64_t>(std::max(1, nteam_p));
+  double* d_part = a.take<double>(std::max<size_t>(1, nparts));
   hipStream_t s = h->stream;
-  // pass 2: carve, and enqueue every remaining problem's setup and sketch
-  std::vector<int32_t> slot(count, -1), idx;
-  for (int i = 0; i < count; ++i)
-    if (!big[i]) { slot[i] = (int32_t)idx.size(); idx.push_back(i); }
+  // pass 2: carve, and enqueue every problem's setup and sketch
+  size_t part_off = 0;
   for (int i : idx) {
     const Geom& g = G[i];
+    const bool team = route[i] == TEAM;
     ModeTables T{};
     SolveBufs B{};
     Tree tr{};
     unsigned* bar = nullptr;
-    carve_solve(a, g, false, d_x[i], &T, &B, &tr, &bar);
+    carve_solve(a, g, false, d_x[i], &T, &B, &tr, &bar, team);
     if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
     kr_opts oi = o;
     oi.stream = o.stream + (uint64_t)i;
@@ -1089,30 +1163,84 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     d.flags = B.s.flags;
     d.lambda = lambda[i];
     d.use_ginv = lambda[i] == 0.0 ? 1 : 0;
+    if (team) {
+      const int ti = slot[i] - nq;
+      LExtra& L = hl[ti];
+      std::memset(&L, 0, sizeof(LExtra));
+      team_stages(g, T, d.use_ginv != 0, &L);
+      L.part = d_part + part_off;
+      part_off += (size_t)L.nchunk * g.nrhs * 2;
+      L.ticket = d_ticket + ti;
+    }
   }
-  // problems largest first (indices into the descriptor array)
-  const int nb_ = nsmall;
-  std::vector<int32_t> ord(nb_);
-  for (int k = 0; k < nb_; ++k) ord[k] = k;
+  // queue problems largest first
+  std::vector<int32_t> ord(nq);
+  for (int k = 0; k < nq; ++k) ord[k] = k;
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[idx[x]] > cost[idx[y]]; });
-  std::memcpy(horder, ord.data(), nb_ * sizeof(int32_t));
-  HIPCHK(h, hipMemcpyAsync(d_descs, hd, nb_ * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
-  HIPCHK(h, hipMemcpyAsync(d_order, horder, nb_ * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)d_queue, (int64_t)64);
-  int dev = 0, ncu = 0, per_cu = 0;
+  std::memcpy(horder, ord.data(), nq * sizeof(int32_t));
+  HIPCHK(h, hipMemcpyAsync(d_descs, hd, nall * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+  if (nteam_p) HIPCHK(h, hipMemcpyAsync(d_l, hl, nteam_p * sizeof(LExtra), hipMemcpyHostToDevice, s));
+  if (nq) HIPCHK(h, hipMemcpyAsync(d_order, horder, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, d_cnt, (int64_t)cnt_words);
+  KL(h, k_zero_bytes, dim3(grid_for(std::max(1, nteam_p) * 2, 256, 64)), dim3(256), 0, s, (uint32_t*)d_done,
+     (int64_t)std::max(1, nteam_p) * 2);
+  // launch shape: every workgroup resident; the queue's share by estimated cost
+  int dev = 0, ncu = 0, per_cu = 0, wclk = 0;
   HIPCHK(h, hipGetDevice(&dev));
   HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_richardson<1>, BT_THREADS,
-                                                         0));
-  const int nwg = std::max(1, std::min(nb_, std::max(1, per_cu) * ncu));
-  KLN(h, "k_batched_richardson", k_batched_richardson<1>, dim3(nwg), dim3(BT_THREADS), 0, s,
-      (const BatchDesc*)d_descs, (const int32_t*)d_order, nb_, d_queue, eta, tol, max_iter);
-  KL(h, k_batch_collect, dim3(grid_for(nb_, 256, 64)), dim3(256), 0, s, (const BatchDesc*)d_descs, nb_, d_res);
+  HIPCHK(h, hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, dev));   // kHz
+  HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_richardson, BT_THREADS, 0));
+  const int slots = std::max(1, per_cu) * ncu;
+  double cq = 0.0, ct = 0.0;
+  for (int i : idx) (route[i] == TEAM ? ct : cq) += cost[i];
+  int nqwg = 0, grid = 0;
+  if (nteam_p == 0) {
+    nqwg = grid = std::min(nq, slots);
+  } else if (nq == 0) {
+    grid = slots;
+  } else {
+    grid = slots;
+    nqwg = (int)std::lround((double)slots * cq / (cq + ct));
+    nqwg = std::max(1, std::min(std::min(nqwg, nq), slots - 1));
+  }
+  BatchArgs ba{};
+  ba.descs = d_descs;
+  ba.order = d_order;
+  ba.nqueue = nq;
+  ba.nteam_prob = nteam_p;
+  ba.L = d_l;
+  ba.done_step = d_done;
+  ba.queue = d_queue;
+  ba.bar = d_bar;
+  ba.abortf = d_abort;
+  ba.nqueue_wg = nqwg;
+  ba.max_iter = max_iter;
+  ba.eta = eta;
+  ba.tol = tol;
+  ba.limit = (uint64_t)std::max(1, wclk) * 1000ull * 30ull;   // 30 s of waiting at one barrier
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(h, hipStreamIsCapturing(s, &cap));
+  if (nteam_p > 0 && cap == hipStreamCaptureStatusNone) {
+    // the team's barrier needs every workgroup resident: a cooperative launch
+    // guarantees it (or fails)
+    void* args[] = {&ba};
+    hipError_t e;
+    {
+      ProfScope ps(h, "k_batched_richardson", s);
+      e = hipLaunchCooperativeKernel((const void*)k_batched_richardson, dim3(grid), dim3(BT_THREADS), args, 0, s);
+    }
+    HIPCHK(h, e);
+  } else {
+    KLN(h, "k_batched_richardson", k_batched_richardson, dim3(grid), dim3(BT_THREADS), 0, s, ba);
+  }
+  KL(h, k_batch_collect, dim3(grid_for(nall, 256, 64)), dim3(256), 0, s, (const BatchDesc*)d_descs, nall, d_res);
   HIPCHK(h, hipGetLastError());
-  HIPCHK(h, hipMemcpyAsync(hres, d_res, nb_ * sizeof(BatchResult), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(hres, d_res, nall * sizeof(BatchResult), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(habort, d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  if (*habort) KR_FAIL(h, KR_EHIP, "the batched team's barrier timed out (workgroups not resident?)");
   for (int i = 0; i < count; ++i) {
-    if (big[i]) continue;
+    if (route[i] == SOLO) continue;
     const BatchResult& r = hres[slot[i]];
     kr_status si = KR_OK;
     const char* msg = "";
