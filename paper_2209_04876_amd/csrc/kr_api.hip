@@ -1009,7 +1009,7 @@ static void team_stages(const Geom& g, const ModeTables& T, bool use_ginv, LExtr
   L->dfin = (j - 1) & 1;
   add(LS_UPD, 0, 0, 0, nullptr);
   L->nst = n;
-  L->nchunk = (int32_t)((g.Rtot + BT_THREADS - 1) / BT_THREADS);
+  L->nchunk = (int32_t)((g.Rtot + TM_THREADS - 1) / TM_THREADS);
 }
 
 static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
@@ -1030,7 +1030,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   // BATCH_BIG_ROWS sampled rows x right-hand sides go to the team instead (up to
   // LS_MAXP of them); a large single-factor problem has no tree level to split
   // over and takes the multi-kernel path.
-  constexpr double BATCH_BIG_ROWS = 131072.0;
+  constexpr double BATCH_BIG_ROWS = 8192.0;
   enum Route : char { QUEUE = 0, TEAM = 1, SOLO = 2 };
   std::vector<Geom> G(count);
   std::vector<double> cost(count);
@@ -1091,7 +1091,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   for (int i : idx) {
     const int nb = (int)((G[i].m + SORT_TILE - 1) / SORT_TILE);
     total += solve_bytes(G[i], nb, nb, route[i] == TEAM) + 1024;
-    if (route[i] == TEAM) nparts += (size_t)((G[i].Rtot + BT_THREADS - 1) / BT_THREADS) * G[i].nrhs * 2;
+    if (route[i] == TEAM) nparts += (size_t)((G[i].Rtot + TM_THREADS - 1) / TM_THREADS) * G[i].nrhs * 2;
   }
   total += (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 4096;
   total += (size_t)nteam_p * (sizeof(LExtra) + 8 + 4) + nparts * 8 + 8192;
@@ -1184,25 +1184,12 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, d_cnt, (int64_t)cnt_words);
   KL(h, k_zero_bytes, dim3(grid_for(std::max(1, nteam_p) * 2, 256, 64)), dim3(256), 0, s, (uint32_t*)d_done,
      (int64_t)std::max(1, nteam_p) * 2);
-  // launch shape: every workgroup resident; the queue's share by estimated cost
-  int dev = 0, ncu = 0, per_cu = 0, wclk = 0;
+  // launch shapes: the queue kernel, then the team kernel with every workgroup
+  // resident
+  int dev = 0, ncu = 0, wclk = 0;
   HIPCHK(h, hipGetDevice(&dev));
   HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   HIPCHK(h, hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, dev));   // kHz
-  HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_richardson, BT_THREADS, 0));
-  const int slots = std::max(1, per_cu) * ncu;
-  double cq = 0.0, ct = 0.0;
-  for (int i : idx) (route[i] == TEAM ? ct : cq) += cost[i];
-  int nqwg = 0, grid = 0;
-  if (nteam_p == 0) {
-    nqwg = grid = std::min(nq, slots);
-  } else if (nq == 0) {
-    grid = slots;
-  } else {
-    grid = slots;
-    nqwg = (int)std::lround((double)slots * cq / (cq + ct));
-    nqwg = std::max(1, std::min(std::min(nqwg, nq), slots - 1));
-  }
   BatchArgs ba{};
   ba.descs = d_descs;
   ba.order = d_order;
@@ -1213,25 +1200,35 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   ba.queue = d_queue;
   ba.bar = d_bar;
   ba.abortf = d_abort;
-  ba.nqueue_wg = nqwg;
   ba.max_iter = max_iter;
   ba.eta = eta;
   ba.tol = tol;
   ba.limit = (uint64_t)std::max(1, wclk) * 1000ull * 30ull;   // 30 s of waiting at one barrier
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  HIPCHK(h, hipStreamIsCapturing(s, &cap));
-  if (nteam_p > 0 && cap == hipStreamCaptureStatusNone) {
-    // the team's barrier needs every workgroup resident: a cooperative launch
-    // guarantees it (or fails)
-    void* args[] = {&ba};
-    hipError_t e;
-    {
-      ProfScope ps(h, "k_batched_richardson", s);
-      e = hipLaunchCooperativeKernel((const void*)k_batched_richardson, dim3(grid), dim3(BT_THREADS), args, 0, s);
+  if (nq > 0) {
+    int per_cu = 0;
+    HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_queue, BT_THREADS, 0));
+    const int grid = std::max(1, std::min(nq, std::max(1, per_cu) * ncu));
+    KLN(h, "k_batched_queue", k_batched_queue, dim3(grid), dim3(BT_THREADS), 0, s, ba);
+  }
+  if (nteam_p > 0) {
+    int per_cu = 0;
+    HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_team, TM_THREADS, 0));
+    const int grid = std::max(1, per_cu) * ncu;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(h, hipStreamIsCapturing(s, &cap));
+    if (cap == hipStreamCaptureStatusNone) {
+      // the team's barrier needs every workgroup resident: a cooperative launch
+      // guarantees it (or fails)
+      void* args[] = {&ba};
+      hipError_t e;
+      {
+        ProfScope ps(h, "k_batched_team", s);
+        e = hipLaunchCooperativeKernel((const void*)k_batched_team, dim3(grid), dim3(TM_THREADS), args, 0, s);
+      }
+      HIPCHK(h, e);
+    } else {
+      KLN(h, "k_batched_team", k_batched_team, dim3(grid), dim3(TM_THREADS), 0, s, ba);
     }
-    HIPCHK(h, e);
-  } else {
-    KLN(h, "k_batched_richardson", k_batched_richardson, dim3(grid), dim3(BT_THREADS), 0, s, ba);
   }
   KL(h, k_batch_collect, dim3(grid_for(nall, 256, 64)), dim3(256), 0, s, (const BatchDesc*)d_descs, nall, d_res);
   HIPCHK(h, hipGetLastError());

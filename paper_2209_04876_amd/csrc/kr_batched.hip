@@ -3,14 +3,13 @@
 //
 // Each problem's setup and sketch (Gram, leverage, sampling, sort, sample tree,
 // gathered rows) is enqueued with the single-problem kernels.  The Richardson
-// iterations of all problems then run in one launch of k_batched_richardson,
-// whose workgroups split into two groups:
+// iterations then run in two persistent launches:
 //
-//   queue  workgroups that take the next small problem from a device queue
+//   queue  k_batched_queue: workgroups take the next small problem from a queue
 //          (largest first) and run its whole iteration -- forward levels, rows,
 //          adjoint levels, root adjoint, preconditioner and update -- with
 //          workgroup barriers only, until the stopping rule holds or max_iter;
-//   team   the other workgroups, which iterate all large problems together.
+//   team   k_batched_team: all workgroups iterate all large problems together.
 //          Each problem's iteration is a list of stages (forward levels, fused
 //          rows, adjoint levels, root, one stage per preconditioner mode product,
 //          update); at every step each active problem runs its next stage, and
@@ -26,7 +25,8 @@
 
 namespace kr {
 
-#define BT_THREADS 512   // threads per workgroup of the batched launch
+#define BT_THREADS 512   // threads per workgroup of the queue kernel
+#define TM_THREADS 256   // threads per workgroup of the team kernel
 
 // Everything one problem's iteration needs (device array, one entry per problem).
 struct BatchDesc {
@@ -200,91 +200,129 @@ struct LStage {
 struct LExtra {
   LStage st[LS_MAXST];
   int32_t nst;
-  int32_t nchunk;       // update chunks of BT_THREADS rows
+  int32_t nchunk;       // update chunks of TM_THREADS rows
   int32_t dfin;         // buffer holding M^+ h after the last mode product: 0 = t0, 1 = t1
   int32_t pad;
   double* part;         // update partial norms: nchunk x nrhs x 2
   int32_t* ticket;      // update arrivals
 };
 
-// Work items (threads, a multiple of BT_THREADS) of stage st of problem d.
+// Work items (threads, a multiple of TM_THREADS) of stage st of problem d.
 __device__ int64_t ls_threads(const BatchDesc& d, const LExtra& L, const LStage& st) {
   const Geom& g = d.g;
   int64_t n = 0;
   switch (st.kind) {
-    case LS_FWD: n = d.tr.cnt[st.k] * g.rsuf[st.k] * g.nrhs; break;
+    case LS_FWD: n = (d.tr.cnt[st.k] + 15) / 16 * ((g.rsuf[st.k] * g.nrhs + 15) / 16) * 64; break;
     case LS_ROWS: n = (g.N >= 2 ? d.tr.cnt[g.N - 1] : 1) * g.nrhs * 16; break;
-    case LS_ROWS2: n = d.tr.cnt[g.N - 2] * g.nrhs * 16; break;
-    case LS_ADJ: n = d.tr.cnt[st.k - 1] * g.rsuf[st.k - 1] * g.nrhs; break;
-    case LS_ROOT: n = g.Rtot * g.nrhs; break;
+    case LS_ROWS2: n = d.tr.cnt[g.N - 2] * 64; break;
+    case LS_ADJ: n = d.tr.cnt[st.k - 1] * ((g.rsuf[st.k] * g.nrhs + 15) / 16) * 64; break;
+    case LS_ROOT: n = ((g.rsuf[1] * g.nrhs + 15) / 16) * 64; break;
     case LS_MODE: n = ((g.Rtot * g.nrhs / g.R[st.k] + 15) / 16) * 64; break;
     case LS_UPD: n = (int64_t)L.nchunk * BT_THREADS; break;
   }
-  return (n + BT_THREADS - 1) / BT_THREADS * BT_THREADS;
+  return (n + TM_THREADS - 1) / TM_THREADS * TM_THREADS;
 }
 
-// Forward level k, output element e.
-__device__ __forceinline__ void ls_forward(const BatchDesc& d, int k, int64_t e) {
+// Forward level k on v_mfma_f64_16x16x4, one wave per tile of 16 consecutive
+// level-k nodes x 16 columns cq: P_k[s][cq] = sum_r a_k[s][r] P_{k-1}[parent(s)][r][cq]
+// is, per parent, a (children x R_k) (R_k x W) product.  A tile whose 16 nodes
+// have one parent (nodes are grouped by parent) uses the matrix cores; a tile
+// that spans parents falls back to per-lane dot products.
+__device__ __forceinline__ void ls_forward(const BatchDesc& d, int k, int64_t v) {
   const Geom& g = d.g;
   const int64_t W = g.rsuf[k] * g.nrhs, Wp = g.rsuf[k - 1] * g.nrhs;
-  if (e >= d.tr.cnt[k] * W) return;
+  const int64_t S = d.tr.cnt[k];
+  const int64_t nct = (W + 15) / 16;
+  const int64_t tile = v >> 6;
+  const int lane = (int)(v & 63);
+  if (tile >= ((S + 15) / 16) * nct) return;   // uniform over the wave
+  const int64_t st = tile / nct;
+  const int64_t s0 = st * 16, c0 = (tile - st * nct) * 16;
   const int Rk = g.R[k - 1];
-  const int64_t s = e / W, cq = e - s * W;
-  const int64_t p = k == 1 ? 0 : d.tr.parent[k][s];
-  d.P[k][e] = dot_batched(d.tr.arow[k] + s * Rk, d.P[k - 1] + p * Wp + cq, W, Rk);
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t slast = s0 + 15 < S ? s0 + 15 : S - 1;
+  const int64_t p0 = k == 1 ? 0 : d.tr.parent[k][s0];
+  const int64_t p1 = k == 1 ? 0 : d.tr.parent[k][slast];
+  const double* __restrict__ arow = d.tr.arow[k];
+  const double* __restrict__ Pp = d.P[k - 1];
+  double* __restrict__ Po = d.P[k];
+  const int64_t cq = c0 + col;
+  if (p0 == p1) {
+    double A[4], B[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = 4 * ks + kq;
+      const int64_t s = s0 + col;
+      A[ks] = (s < S && kk < Rk) ? arow[s * Rk + kk] : 0.0;
+      B[ks] = (kk < Rk && cq < W) ? Pp[p0 * Wp + (int64_t)kk * W + cq] : 0.0;
+    }
+    pc_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks], B[ks], acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t s = s0 + kq + 4 * u;
+      if (s < S && cq < W) Po[s * W + cq] = acc[u];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t s = s0 + kq + 4 * u;
+      if (s < S && cq < W) {
+        const int64_t p = d.tr.parent[k][s];
+        Po[s * W + cq] = dot_batched(arow + s * Rk, Pp + p * Wp + cq, W, Rk);
+      }
+    }
+  }
 }
 
-// Adjoint level k, output element e of Q_{k-1}.
-__device__ __forceinline__ void ls_adjoint(const BatchDesc& d, int k, int64_t e) {
+// Adjoint level k (and the root, k = 1) on v_mfma_f64_16x16x4, one wave per
+// (level-(k-1) node p, 16 columns cq): Q_{k-1}[p][r][cq] = sum over the children
+// s of p of a_k[s][r] Q_k[s][cq], an (R_k x children) (children x W) product
+// accumulated four children per step.  Rows r >= R_k and columns cq >= W are
+// zero padding.
+__device__ __forceinline__ void ls_adjoint(const BatchDesc& d, int k, int64_t v) {
   const Geom& g = d.g;
   const int64_t W = g.rsuf[k] * g.nrhs, Wp = g.rsuf[k - 1] * g.nrhs;
-  if (e >= d.tr.cnt[k - 1] * Wp) return;
+  const int64_t Sp = k == 1 ? 1 : d.tr.cnt[k - 1];
+  const int64_t nct = (W + 15) / 16;
+  const int64_t tile = v >> 6;
+  const int lane = (int)(v & 63);
+  if (tile >= Sp * nct) return;   // uniform over the wave
+  const int64_t p = tile / nct;
+  const int64_t c0 = (tile - p * nct) * 16;
   const int Rk = g.R[k - 1];
-  const int64_t p = e / Wp, rem = e - p * Wp;
-  const int64_t r = rem / W, cq = rem - r * W;
-  const int s0 = d.tr.fchild[k - 1][p], s1 = d.tr.fchild[k - 1][p + 1];
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t s0 = k == 1 ? 0 : d.tr.fchild[k - 1][p];
+  const int64_t s1 = k == 1 ? d.tr.cnt[1] : d.tr.fchild[k - 1][p + 1];
   const double* __restrict__ arow = d.tr.arow[k];
   const double* __restrict__ Qk = d.Q[k];
-  double acc = 0.0;
-  int s = s0;
-  for (; s + 4 <= s1; s += 4) {
-    double av[4], qv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      av[u] = arow[(int64_t)(s + u) * Rk + r];
-      qv[u] = Qk[(int64_t)(s + u) * W + cq];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc = fma(av[u], qv[u], acc);
+  const int64_t cq = c0 + col;
+  const bool rok = col < Rk, cok = cq < W;
+  pc_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  // children sb + kq (lane group kq) per step; the trip counts are uniform
+  int64_t sb = s0;
+  for (; sb + 8 <= s1; sb += 8) {   // two steps per trip, loads issued together
+    const int64_t sa = sb + kq, sc = sb + 4 + kq;
+    const double a0 = rok ? arow[sa * Rk + col] : 0.0;
+    const double b0 = cok ? Qk[sa * W + cq] : 0.0;
+    const double a1 = rok ? arow[sc * Rk + col] : 0.0;
+    const double b1 = cok ? Qk[sc * W + cq] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
   }
-  for (; s < s1; ++s) acc = fma(arow[(int64_t)s * Rk + r], Qk[(int64_t)s * W + cq], acc);
-  d.Q[k - 1][e] = acc;
-}
-
-// Root adjoint, output element e of the gradient.
-__device__ __forceinline__ void ls_root(const BatchDesc& d, int64_t e) {
-  const Geom& g = d.g;
-  if (e >= g.Rtot * g.nrhs) return;
-  const int64_t W1 = g.rsuf[1] * g.nrhs;
-  const int R0 = g.R[0];
-  const int64_t S1 = d.tr.cnt[1];
-  const int64_t r0 = e / W1, c = e - r0 * W1;
-  const double* __restrict__ a0 = d.tr.arow[1];
-  const double* __restrict__ Q1 = d.Q[1];
-  double acc = 0.0;
-  int64_t s = 0;
-  for (; s + 4 <= S1; s += 4) {
-    double av[4], qv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      av[u] = a0[(s + u) * R0 + r0];
-      qv[u] = Q1[(s + u) * W1 + c];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc = fma(av[u], qv[u], acc);
+  for (; sb < s1; sb += 4) {
+    const int64_t sl = sb + kq;
+    const double a = (sl < s1 && rok) ? arow[sl * Rk + col] : 0.0;
+    const double b = (sl < s1 && cok) ? Qk[sl * W + cq] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  for (; s < S1; ++s) acc = fma(a0[s * R0 + r0], Q1[s * W1 + c], acc);
-  d.Q[0][e] = acc;
+  double* __restrict__ Qo = d.Q[k - 1];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = kq + 4 * u;
+    if (r < Rk && cok) Qo[p * Wp + (int64_t)r * W + cq] = acc[u];
+  }
 }
 
 // Residual sum of one level-(N-1) node's rows for a 16-lane group: returns
@@ -351,47 +389,133 @@ __device__ __forceinline__ void ls_rows(const BatchDesc& d, int64_t v) {
   if (ln) d.Q[N - 1][(p * R + lane) * nrhs + q] = acc;
 }
 
-// Fused last two levels for N >= 3: a 16-lane group per (level-(N-2) node p,
-// rhs q), lane = r_N.  For every child s of p: the forward value
-// P_{N-1}[s] = a_{N-1}[s] . P_{N-2}[p], the residuals of s's rows, their
-// adjoint Q_{N-1}[s], and its outer product with a_{N-1}[s] accumulated into
-// Q_{N-2}[p].  Neither P_{N-1} nor Q_{N-1} is written.
-__device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v) {
+#define LS_FACT 4096   // LDS entries per staged factor (I_n x R_n <= 4096)
+
+// Stage the factors of modes N-2 and N-1 of problem i into LDS unless they are
+// there already (the tag holds the problem whose factors are staged, -1 none).
+// Called by the whole workgroup; returns whether they are staged.
+__device__ bool ls_stage_factors(const BatchDesc& d, int i, double* fa, int* tag) {
+  const Geom& g = d.g;
+  const int N = g.N;
+  const int nP = g.I[N - 2] * g.R[N - 2], nL = g.I[N - 1] * g.R[N - 1];
+  if (nP > LS_FACT || nL > LS_FACT) return false;
+  if (*tag == i) return true;
+  __syncthreads();   // every thread is done with the previous factors
+  const double* __restrict__ AP = d.T.A[N - 2];
+  const double* __restrict__ AL = d.T.A[N - 1];
+  for (int e = threadIdx.x; e < nP; e += blockDim.x) fa[e] = AP[e];
+  for (int e = threadIdx.x; e < nL; e += blockDim.x) fa[LS_FACT + e] = AL[e];
+  if (threadIdx.x == 0) *tag = i;
+  __syncthreads();   // factors and tag visible to every thread
+  return true;
+}
+
+// Fused last two levels for N >= 3, one wave per level-(N-2) node p (all
+// right-hand sides in turn), on v_mfma_f64_16x16x4.  The rows j of p's subtree
+// are contiguous; per block of 16 rows, with AV the rows' mode-(N-2) factor rows
+// (16 x R_{N-1}), AN their last-mode factor rows (16 x R_N) and
+// P = P_{N-2}[p][:, :, q] (R_{N-1} x R_N):
+//   M = AV P                      (the rows' level-(N-1) values, one MFMA chain)
+//   y_j = sum_r AN[j][r] M[j][r]  (k_j x, a 16-lane reduction)
+//   u_j = Omega_j (y_j - b_j)
+//   Q += AV^T diag(u) AN          (the adjoint of both levels, one MFMA chain)
+// and Q is Q_{N-2}[p][:, :, q].  Neither level-(N-1) product is formed.  Lane
+// l = 16 g + c: c indexes the tile's columns, g its row quarter.  Row data
+// (keys, weights, responses) streams in chunks of 64 rows, one row per lane, and
+// reaches the tile layouts by shuffles; the next chunk is loaded while the
+// current one is processed.  The factor rows come from LDS (fa) when the
+// workgroup has staged them, else from global memory (fa = nullptr).
+__device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const double* fa) {
   const Geom& g = d.g;
   const int N = g.N, nrhs = g.nrhs;
   const int RL = g.R[N - 1], RP = g.R[N - 2];
-  const int64_t task = v >> 4;
-  const unsigned lane = (unsigned)v & 15u;
-  if (task >= d.tr.cnt[N - 2] * nrhs) return;   // uniform over the group
-  const int64_t p = task / nrhs;
-  const int q = (int)(task - p * nrhs);
-  const bool ln = (int)lane < RL;
-  const int64_t pbase = p * (int64_t)RP * RL * nrhs + (int64_t)lane * nrhs + q;
+  const int64_t p = v >> 6;
+  const int lane = (int)(v & 63);
+  if (p >= d.tr.cnt[N - 2]) return;   // uniform over the wave
+  const int c = lane & 15, gq = lane >> 4;
+  const int64_t pb = p * (int64_t)RP * RL * nrhs;
   const double* __restrict__ Pn2 = d.P[N - 2];
-  double pp[16], acc2[16];
+  const int c0 = d.tr.fchild[N - 2][p], c1 = d.tr.fchild[N - 2][p + 1];
+  const int j0 = d.tr.fchild[N - 1][c0], j1 = d.tr.fchild[N - 1][c1];
+  const double* __restrict__ AP = fa ? fa : d.T.A[N - 2];
+  const double* __restrict__ AL = fa ? fa + LS_FACT : d.T.A[N - 1];
+  const int shP = g.shift[N - 2], shL = g.shift[N - 1];
+  const uint64_t mP = (1ull << g.bits[N - 2]) - 1ull, mL = (1ull << g.bits[N - 1]) - 1ull;
+  const uint64_t* __restrict__ keys = d.tr.rkey;
+  double* __restrict__ Qo = d.Q[N - 2];
+  for (int q = 0; q < nrhs; ++q) {
+    double Bf[4];   // B operand of M = AV P: P[r' = 4 ks + gq][c]
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    pp[r] = (ln && r < RP) ? Pn2[pbase + (int64_t)r * RL * nrhs] : 0.0;
-    acc2[r] = 0.0;
-  }
-  const int s0 = d.tr.fchild[N - 2][p], s1 = d.tr.fchild[N - 2][p + 1];
-  const double* __restrict__ aP = d.tr.arow[N - 1];
-  for (int s = s0; s < s1; ++s) {
-    double av[16];
+    for (int ks = 0; ks < 4; ++ks) {
+      const int r1 = 4 * ks + gq;
+      Bf[ks] = (r1 < RP && c < RL) ? Pn2[pb + ((int64_t)r1 * RL + c) * nrhs + q] : 0.0;
+    }
+    auto load_chunk = [&](int jc, uint64_t& k, double& om, double& bq) {
+      const int j = jc + lane;
+      const bool ok = j < j1;
+      k = ok ? keys[j] : 0ull;
+      om = ok ? d.Omega[j] : 0.0;
+      bq = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
+    };
+    pc_f64x4 acc2 = {0.0, 0.0, 0.0, 0.0};   // Q[r' = gq + 4 v][c]
+    uint64_t kc = 0;
+    double oc = 0.0, bc = 0.0;
+    if (j0 < j1) load_chunk(j0, kc, oc, bc);
+    for (int jc = j0; jc < j1; jc += 64) {
+      uint64_t kn = 0;
+      double on = 0.0, bn = 0.0;
+      if (jc + 64 < j1) load_chunk(jc + 64, kn, on, bn);
+      const int nblk = (j1 - jc) >= 64 ? 4 : (j1 - jc + 15) / 16;
+      for (int ub = 0; ub < nblk; ++ub) {
+        const int jb = jc + 16 * ub;
+        // A layout: row jb + c
+        const uint64_t ka = __shfl(kc, 16 * ub + c, 64);
+        const bool va = jb + c < j1;
+        const int iPa = (int)((ka >> shP) & mP);
+        double Af[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) av[r] = r < RP ? aP[(int64_t)s * RP + r] : 0.0;
-    double pv = 0.0;
+        for (int ks = 0; ks < 4; ++ks) {
+          const int r1 = 4 * ks + gq;
+          Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
+        }
+        pc_f64x4 M = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < 16; ++r) pv = fma(av[r], pp[r], pv);
-    const double acc1 = ls_rows_of(d, d.tr.fchild[N - 1][s], d.tr.fchild[N - 1][s + 1], pv, q, lane, ln);
+        for (int ks = 0; ks < 4; ++ks) M = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], Bf[ks], M, 0, 0, 0);
+        // D layout: rows jb + gq + 4 u
+        double an[4], Aa[4], om[4], bq[4], W[4], y[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc2[r] = fma(av[r], acc1, acc2[r]);
-  }
-  if (ln) {
-    double* __restrict__ Qo = d.Q[N - 2];
+        for (int u = 0; u < 4; ++u) {
+          const int src = 16 * ub + gq + 4 * u;
+          const uint64_t kd = __shfl(kc, src, 64);
+          om[u] = __shfl(oc, src, 64);
+          bq[u] = __shfl(bc, src, 64);
+          const bool vd = jb + gq + 4 * u < j1;
+          const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
+          an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
+          Aa[u] = (vd && c < RP) ? AP[iPd * RP + c] : 0.0;
+          if (!vd) om[u] = 0.0;
+        }
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      if (r < RP) Qo[pbase + (int64_t)r * RL * nrhs] = acc2[r];
+        for (int u = 0; u < 4; ++u) y[u] = an[u] * M[u];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, 16);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) W[u] = an[u] * (om[u] * (y[u] - bq[u]));
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W[ks], acc2, 0, 0, 0);
+      }
+      kc = kn;
+      oc = on;
+      bc = bn;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r1 = gq + 4 * u;
+      if (r1 < RP && c < RL) Qo[pb + ((int64_t)r1 * RL + c) * nrhs + q] = acc2[u];
+    }
   }
 }
 
@@ -445,20 +569,20 @@ __device__ __forceinline__ void ls_mode(const BatchDesc& d, const LStage& st, in
   }
 }
 
-// Update stage, one workgroup per chunk of BT_THREADS rows r of x (all RHS):
+// Update stage, one workgroup per chunk of TM_THREADS rows r of x (all RHS):
 // x <- x - eta d for RHS not yet converged, chunk partial norms of d and x per
 // RHS.  The last chunk to arrive sums the partials in chunk order and applies the
 // stopping rule and the divergence test (as the single-problem update does).
 // Returns true in the workgroup that finished the iteration of a problem whose
 // solve is over.
 __device__ bool ls_update(const BatchDesc& d, const LExtra& L, int64_t chunk, double eta, double tol, int max_iter,
-                          double* red2 /* 16 x LS_MAXRHS x 2 */, int* flag_s) {
+                          double* red2 /* waves x LS_MAXRHS x 2 */, int* flag_s) {
   const Geom& g = d.g;
   const int nrhs = g.nrhs;
   IterState* __restrict__ st = d.st;
   const double* __restrict__ dt = L.dfin ? d.t1 : d.t0;
   double* __restrict__ x = d.P[0];
-  const int64_t r = chunk * BT_THREADS + threadIdx.x;
+  const int64_t r = chunk * TM_THREADS + threadIdx.x;
   const bool ok = r < g.Rtot;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int q = 0; q < nrhs; ++q) {
@@ -582,7 +706,6 @@ struct BatchArgs {
   int32_t* queue;           // queue counter (0 at launch)
   unsigned* bar;            // team barrier: [0] arrivals, [1] generation
   int32_t* abortf;
-  int nqueue_wg;            // workgroups 0 .. nqueue_wg-1 serve the queue, the rest form the team
   int max_iter;
   double eta, tol;
   uint64_t limit;           // barrier wait bound (wall-clock ticks)
@@ -594,10 +717,10 @@ __device__ void batched_queue(const BatchArgs& a, double* ms, double* red) {
   for (;;) {
     if (threadIdx.x == 0) cur_s = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int qi = cur_s;
+    const int qi = __builtin_amdgcn_readfirstlane(cur_s);
     __syncthreads();
     if (qi >= a.nqueue) break;
-    const BatchDesc& d = a.descs[a.order[qi]];
+    const BatchDesc& d = a.descs[__builtin_amdgcn_readfirstlane(a.order[qi])];
     const Geom& g = d.g;
     const int N = g.N;
     const int32_t fl = *d.flags;
@@ -635,12 +758,14 @@ __device__ void batched_queue(const BatchArgs& a, double* ms, double* red) {
 // The large-problem body: the team's lockstep over stage steps.  LDS (from the
 // queue body's matrix buffer): the offsets of every problem's work items in this
 // step, a scan buffer and the update's per-wave partial norms.
-#define LS_WAVES (BT_THREADS / 64)
+#define LS_WAVES (TM_THREADS / 64)
 __device__ void batched_team(const BatchArgs& a, unsigned rank, unsigned nteam, char* lds) {
   int64_t* off = (int64_t*)lds;                                  // LS_MAXP + 1
   int64_t* wtot = off + LS_MAXP + 1;                             // LS_WAVES
   double* red2 = (double*)(wtot + LS_WAVES);                     // LS_WAVES x LS_MAXRHS x 2
-  __shared__ int flag_s, any_s;
+  double* fact = red2 + LS_WAVES * LS_MAXRHS * 2;                // 2 x LS_FACT staged factors
+  __shared__ int flag_s, any_s, tag_s;
+  if (threadIdx.x == 0) tag_s = -1;
   const int np = a.nteam_prob;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int64_t t = 0;; ++t) {
@@ -649,7 +774,7 @@ __device__ void batched_team(const BatchArgs& a, unsigned rank, unsigned nteam, 
     if (threadIdx.x == 0) { any_s = 0; off[0] = 0; }
     __syncthreads();
     int64_t carry = 0;
-    for (int b0 = 0; b0 < np; b0 += BT_THREADS) {
+    for (int b0 = 0; b0 < np; b0 += TM_THREADS) {
       const int i = b0 + threadIdx.x;
       int64_t n = 0;
       if (i < np) {
@@ -679,29 +804,33 @@ __device__ void batched_team(const BatchArgs& a, unsigned rank, unsigned nteam, 
     }
     if (!any_s) break;   // every problem is done (the same memory state in every workgroup)
     const int64_t total = off[np];
-    for (int64_t base = (int64_t)rank * BT_THREADS; base < total; base += (int64_t)nteam * BT_THREADS) {
-      // the problem owning items base .. base + BT_THREADS - 1 (uniform)
+    for (int64_t base = (int64_t)rank * TM_THREADS; base < total; base += (int64_t)nteam * TM_THREADS) {
+      // the problem owning items base .. base + TM_THREADS - 1 (uniform)
       int lo = 0, hi = np;   // off[lo] <= base < off[hi]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (off[mid] <= base) lo = mid; else hi = mid;
       }
-      const int i = lo;
+      // uniform values in scalar registers: the descriptor fields then load
+      // through the scalar cache instead of occupying vector registers
+      const int i = __builtin_amdgcn_readfirstlane(lo);
       const BatchDesc& d = a.descs[a.nqueue + i];
       const LExtra& L = a.L[i];
       const LStage st = L.st[t % L.nst];
-      const int64_t v0 = base - off[i];
+      const int64_t oi = off[i];
+      const int64_t v0 = base - (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(oi >> 32)) << 32) |
+                                          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)oi));
       const int64_t v = v0 + threadIdx.x;
       switch (st.kind) {
         case LS_FWD: ls_forward(d, st.k, v); break;
         case LS_ROWS: ls_rows(d, v); break;
-        case LS_ROWS2: ls_rows2(d, v); break;
+        case LS_ROWS2: ls_rows2(d, v, ls_stage_factors(d, i, fact, &tag_s) ? fact : nullptr); break;
         case LS_ADJ: ls_adjoint(d, st.k, v); break;
-        case LS_ROOT: ls_root(d, v); break;
+        case LS_ROOT: ls_adjoint(d, 1, v); break;
         case LS_MODE: ls_mode(d, st, v); break;
         default:
-          if (v0 / BT_THREADS < L.nchunk &&
-              ls_update(d, L, v0 / BT_THREADS, a.eta, a.tol, a.max_iter, red2, &flag_s) && threadIdx.x == 0)
+          if (v0 / TM_THREADS < L.nchunk &&
+              ls_update(d, L, v0 / TM_THREADS, a.eta, a.tol, a.max_iter, red2, &flag_s) && threadIdx.x == 0)
             a.done_step[i] = t + 1;
           break;
       }
@@ -710,14 +839,19 @@ __device__ void batched_team(const BatchArgs& a, unsigned rank, unsigned nteam, 
   }
 }
 
-static_assert((LS_MAXP + 1 + LS_WAVES) * 8 + LS_WAVES * LS_MAXRHS * 2 * 8 <= PC_MATS * 8,
-              "the team's LDS must fit in the queue body's matrix buffer");
+#define TM_LDS_BYTES ((LS_MAXP + 1 + LS_WAVES) * 8 + LS_WAVES * LS_MAXRHS * 2 * 8 + 2 * LS_FACT * 8)
 
-__global__ void __launch_bounds__(BT_THREADS) k_batched_richardson(BatchArgs a) {
+// Small problems: one workgroup per problem from the queue.
+__global__ void __launch_bounds__(BT_THREADS) k_batched_queue(BatchArgs a) {
   __shared__ double ms[PC_MATS];
   __shared__ double red[16];
-  if ((int)blockIdx.x < a.nqueue_wg) batched_queue(a, ms, red);
-  else batched_team(a, blockIdx.x - a.nqueue_wg, gridDim.x - a.nqueue_wg, (char*)ms);
+  batched_queue(a, ms, red);
+}
+
+// Large problems: the team, every workgroup resident (cooperative launch).
+__global__ void __launch_bounds__(TM_THREADS) k_batched_team(BatchArgs a) {
+  __shared__ __attribute__((aligned(16))) char lds[TM_LDS_BYTES];
+  batched_team(a, blockIdx.x, gridDim.x, lds);
 }
 
 }  // namespace kr

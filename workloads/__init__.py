@@ -14,6 +14,9 @@ Workloads (sizes as named in the tests and the benchmark):
   paper_e1          the paper's synthetic Kronecker regression: two n x d factors
                     with entries N(1, 0.001^2), b = 1, lam = 1e-3
   random_problem    any shapes, for parity sweeps and edge cases
+  batched_ridge     256 ridge problems of uneven shape: N ~ U{2,3,4},
+                    I_n ~ U{32..256}, R_n ~ U{4..16}, 1-8 right-hand sides,
+                    lambda = 10^U(-4,0), FP32 factors, implicit responses
 """
 
 import math
@@ -116,3 +119,29 @@ def random_problem(I, R, seed=0, sigma=0.01, nrhs=1, heavy=0, scale=100.0):
         x_true, b = x_true[:, 0], b[:, 0]
     assert b.shape[0] == Itot
     return dict(name="random I=%s R=%s" % (list(I), list(R)), As=As, b=b, x_true=x_true)
+
+
+def batched_ridge_specs(seed=5, count=256, I_range=(32, 256), R_range=(4, 16), N_range=(2, 4), rhs_range=(1, 8)):
+    """Shapes and parameters of the batched ridge workload (no arrays): one dict per
+    problem with N, I, R, nrhs, lam, a factor seed, and the response's Philox key
+    (b = K X_true + 0.01 e with e drawn by row, since prod(I) x nrhs entries would
+    not fit in memory for N = 4).  m = ceil(R ln R / eps) per problem."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        N = int(rng.integers(N_range[0], N_range[1] + 1))
+        I = tuple(int(v) for v in rng.integers(I_range[0], I_range[1] + 1, size=N))
+        R = tuple(int(v) for v in rng.integers(R_range[0], R_range[1] + 1, size=N))
+        nrhs = int(rng.integers(rhs_range[0], rhs_range[1] + 1))
+        lam = float(10.0 ** rng.uniform(-4.0, 0.0))
+        out.append(dict(N=N, I=I, R=R, nrhs=nrhs, lam=lam, data_seed=int(seed) * 100000 + i, sigma=0.01,
+                        noise_key=(int(seed), i)))
+    return out
+
+
+def batched_ridge_arrays(spec):
+    """Factors (FP32, N(0,1)) and X_true (N(0,1)) of one batched_ridge problem."""
+    rng = np.random.default_rng(spec["data_seed"])
+    As = [rng.standard_normal((In, Rn)).astype(np.float32) for In, Rn in zip(spec["I"], spec["R"])]
+    X = rng.standard_normal((int(np.prod(spec["R"])), spec["nrhs"]))
+    return As, X
