@@ -127,6 +127,17 @@ typedef enum { KR_PREC_F64 = 0, KR_PREC_F32 = 1, KR_PREC_BF16 = 2, KR_PREC_FP8 =
 /* kr_opts.flags: with opts.m == 0, take m = ceil(R ln R / eps) samples (R = prod R_n,
  * natural log) instead of Algorithm 2's theory count. */
 #define KR_OPT_M_RLNR 2
+/* kron_ridge_batched only.  KR_OPT_GRAPH: the enqueued work of the call is
+ * captured into a HIP graph the first time and replayed by later calls whose
+ * problems, buffers, parameters and handle workspace are all unchanged (the
+ * handle keeps one graph; problems on the multi-kernel path run outside it).
+ * KR_OPT_AUTOTUNE: the first call for a batch shape (count, orders, sizes) times
+ * each candidate launch configuration -- the size above which a problem joins
+ * the team of workgroups rather than the one-workgroup queue, and the team's
+ * workgroups per compute unit -- by solving the batch with it, keeps the
+ * fastest for the handle, and returns the results of a final solve with it. */
+#define KR_OPT_GRAPH 4
+#define KR_OPT_AUTOTUNE 8
 
 typedef struct {
   int32_t iters;          /* Richardson iterations performed (max over RHS)          */
@@ -166,17 +177,27 @@ kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void*
  * right-hand sides) in one call: count problems probs[i] with regularisation
  * lambda[i] (host array) and outputs d_x[i] (host array of device pointers, each
  * prod(R) x nrhs float64).  Each problem's setup and sketch is enqueued with the
- * single-problem kernels; the Richardson iterations of all problems then run in
- * one persistent launch whose workgroups take problems from a device queue,
- * largest first, and iterate each to its own stopping rule with workgroup
- * barriers only.  opts applies to every problem (seed and stream shared; problem
- * i draws with Philox stream opts->stream + i); float64 only; every R_n <= 16.
+ * single-problem kernels; the Richardson iterations then run in two persistent
+ * launches: small problems on a queue (one workgroup per problem, largest
+ * first, workgroup barriers only), and the rest iterated together by a team of
+ * workgroups in lockstep stages separated by a bounded team barrier (at most
+ * 1024 such problems; a large single-factor problem takes the single-problem
+ * path).  opts applies to every problem (seed and stream shared; problem i
+ * draws with Philox stream opts->stream + i); flags KR_OPT_M_RLNR, KR_OPT_GRAPH
+ * and KR_OPT_AUTOTUNE apply; float64 only; every R_n <= 16 and prod(R) x nrhs
+ * below 2^31 (else KR_EUNSUPPORTED).  KR_EHIP if the team barrier times out.
  * h_info (host array of count entries, may be NULL) receives each problem's
  * result; the return value is KR_OK when every problem converged, else the first
  * failing problem's status (its message in kr_last_error). */
 kr_status kron_ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda,
                              double eps, double delta, const kr_opts* opts, void* const* d_x,
                              kr_info* h_info);
+
+/* The launch configuration the handle's autotuner chose last (or the default
+ * when it has tuned nothing): the team threshold in sampled rows x right-hand
+ * sides, and the team's workgroups per compute unit (0 = as many as fit).
+ * Host pointers; either may be NULL. */
+kr_status kr_batched_config(kr_handle h, double* big_rows, int32_t* team_per_cu);
 
 /* The exact minimiser via the factor thin SVDs and KronMatMul (the paper's
  * exact baseline): x* = (kron V) diag(kron s / (kron s^2 + lambda)) (kron U)^T b.

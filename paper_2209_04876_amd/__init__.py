@@ -67,6 +67,8 @@ class Opts(ctypes.Structure):
 
 OPT_COOPERATIVE = 1
 OPT_M_RLNR = 2
+OPT_GRAPH = 4
+OPT_AUTOTUNE = 8
 
 # kr_precision: the arithmetic of the Richardson iteration (float64 plain, or
 # refined: float64 residual and update, float32 adjoint, preconditioner in the
@@ -112,6 +114,7 @@ def load_library(path=LIB_PATH):
     lib.kron_ridge.argtypes = [c_p, P, c_d, c_d, c_d, O, c_p, IN]
     lib.kron_ridge_batched.argtypes = [c_p, ctypes.c_int32, P, ctypes.POINTER(c_d), c_d, c_d, O,
                                        ctypes.POINTER(c_p), IN]
+    lib.kr_batched_config.argtypes = [c_p, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_int32)]
     lib.kron_loss.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d)]
     lib.kron_exact.argtypes = [c_p, P, c_d, c_p]
     lib.tucker_factor_update.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_d, c_d, O, c_p, IN]
@@ -120,7 +123,7 @@ def load_library(path=LIB_PATH):
     lib.kr_profile_query.argtypes = [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(c_d)]
     lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
-    for name in ("kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_loss",
+    for name in ("kr_batched_config", "kron_ridge_batched", "kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_loss",
                  "kron_exact", "kr_export_sketch", "tucker_factor_update"):
         getattr(lib, name).restype = c_i
     _lib = lib
@@ -270,29 +273,34 @@ def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200
 
 
 def kron_ridge_batched(problems, lams, eps=0.1, delta=0.01, m=0, m_rule=None, seed=0, stream=0, max_iter=200,
-                       tol=None, handle=None, raise_on_error=True):
-    """Many independent ridge problems in one call (one persistent launch for all
+                       tol=None, handle=None, raise_on_error=True, graph=False, autotune=False, xs=None):
+    """Many independent ridge problems in one call (persistent launches for all
     Richardson iterations).  problems: list of (As, b) with As a list of CUDA factor
-    tensors (every R_n <= 16) and b a CUDA tensor; lams: one lambda per problem.
-    m_rule="rlnr" takes m = ceil(R ln R / eps) per problem (with m=0).  Problem i
-    draws with Philox stream `stream + i`.  Returns (xs, infos) and, with
-    raise_on_error=False, also the call's status (per-problem statuses are in infos)."""
+    tensors (every R_n <= 16) and b a CUDA tensor or a ResponseGen; lams: one
+    lambda per problem.  m_rule="rlnr" takes m = ceil(R ln R / eps) per problem
+    (with m=0).  Problem i draws with Philox stream `stream + i`.  graph=True
+    captures the call's work into a HIP graph and replays it on later calls with
+    the same problems and outputs (pass the previous xs to reuse the buffers);
+    autotune=True times the candidate launch configurations on the first call
+    for a batch shape.  Returns (xs, infos) and, with raise_on_error=False, also
+    the call's status (per-problem statuses are in infos)."""
     h = handle or default_handle()
     n = len(problems)
     if len(lams) != n:
         raise ValueError("one lambda per problem")
     probs = (Problem * n)()
-    keep, xs = [], []
+    keep, new_xs = [], []
     for i, (As, b) in enumerate(problems):
         p, k = _problem(As, b)
         probs[i] = p
         keep.append(k)
         keep.append(b)
-        xs.append(_x_like(As, p.nrhs, b.dim() == 1))
+        new_xs.append(xs[i] if xs is not None else _x_like(As, p.nrhs, b.dim() == 1))
+    xs = new_xs
     lam_arr = (ctypes.c_double * n)(*[float(v) for v in lams])
     xptr = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
     infos = (Info * n)()
-    flags = OPT_M_RLNR if m_rule == "rlnr" else 0
+    flags = (OPT_M_RLNR if m_rule == "rlnr" else 0) | (OPT_GRAPH if graph else 0) | (OPT_AUTOTUNE if autotune else 0)
     if m_rule not in (None, "rlnr"):
         raise ValueError("m_rule must be None or 'rlnr'")
     st = h.lib.kron_ridge_batched(h.ptr, n, probs, lam_arr, eps, delta,
@@ -302,6 +310,15 @@ def kron_ridge_batched(problems, lams, eps=0.1, delta=0.01, m=0, m_rule=None, se
         h._check(st)   # raises for a negative status (the first failing problem)
         return xs, out
     return xs, out, st
+
+
+def batched_config(handle=None):
+    """(team threshold in sampled rows x RHS, team workgroups per CU) last chosen
+    by the handle's autotuner (the defaults before any tuning)."""
+    h = handle or default_handle()
+    br, wg = ctypes.c_double(), ctypes.c_int32()
+    h._check(h.lib.kr_batched_config(h.ptr, ctypes.byref(br), ctypes.byref(wg)))
+    return br.value, wg.value
 
 
 def kron_loss(As, b, x, lam=0.0, handle=None):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -53,6 +54,12 @@ struct kr_handle_s {
   int64_t* h_small = nullptr;     // pinned scratch (flags, counts)
   void* h_batch = nullptr;         // pinned staging of batched descriptors and results
   size_t h_batch_bytes = 0;
+  // batched solves: the captured graph of the last KR_OPT_GRAPH call and its
+  // signature, and the autotuned launch configuration per batch shape
+  hipGraphExec_t bgraph = nullptr;
+  std::vector<uint64_t> bgraph_sig;
+  std::map<std::vector<int64_t>, std::pair<double, int>> tune;
+  bool capturing = false;
   // last sketch, for kr_export_sketch
   bool has_sketch = false;
   Geom g{};
@@ -101,7 +108,7 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t a = nullptr;
   ProfScope(kr_handle h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) {
-    if (h->prof_on && prof_match(h->prof_filter, n)) {
+    if (h->prof_on && !h->capturing && prof_match(h->prof_filter, n)) {
       a = pool_event(h);
       hipEventRecord(a, s);
     }
@@ -251,6 +258,7 @@ kr_status kr_destroy(kr_handle h) {
   if (h->h_state) hipHostFree(h->h_state);
   if (h->h_small) hipHostFree(h->h_small);
   if (h->h_batch) hipHostFree(h->h_batch);
+  if (h->bgraph) hipGraphExecDestroy(h->bgraph);
   delete h;
   return KR_OK;
 }
@@ -715,7 +723,7 @@ static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, 
     for (int k = 1; k <= g.N - 2; ++k)
       KL(h, k_gen_level, dim3(grid_for(level_cap(g, k) * g.rsuf[k] * g.nrhs, 256, 4096)), dim3(256), 0, s, g, tr, k,
          k == 1 ? X : (const double*)B.P[k - 1], B.P[k]);
-    KL(h, k_gen_rows, dim3(grid_for(Dcap, 256, 4096)), dim3(256), 0, s, g, tr,
+    KL(h, k_gen_rows, dim3(grid_for(Dcap * g.nrhs, 256, 8192)), dim3(256), 0, s, g, tr,
        g.N >= 3 ? (const double*)B.P[g.N - 2] : X, p->gen->sigma, p->gen->seed, p->gen->stream, B.bD, B.s.flags);
   }
   HIPCHK(h, hipGetLastError());
@@ -1012,8 +1020,17 @@ static void team_stages(const Geom& g, const ModeTables& T, bool use_ginv, LExtr
   L->nchunk = (int32_t)((g.Rtot + TM_THREADS - 1) / TM_THREADS);
 }
 
+// Launch configuration of a batched solve: problems with more sampled rows x
+// right-hand sides than big_rows go to the team; the team kernel runs
+// team_per_cu workgroups per compute unit (0 = as many as fit).
+struct BatchCfg {
+  double big_rows = 8192.0;
+  int team_per_cu = 0;
+};
+
 static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
-                               double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {
+                               double delta, const kr_opts* opts, void* const* d_x, kr_info* info,
+                               const BatchCfg& cfg, bool graph) {
   if (!h) return KR_EINVAL;
   if (count < 0) KR_FAIL(h, KR_EINVAL, "count=%d", count);
   if (count == 0) return KR_OK;
@@ -1026,11 +1043,11 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   const double tol = o.tol > 0.0 ? o.tol : 1e-12;
   const double eta = 1.0 - std::sqrt(eps);
   // pass 1: geometry, limits and routes.  A queue workgroup walks a problem's
-  // rows 32 (node, rhs) pairs at a time, so problems with more than
-  // BATCH_BIG_ROWS sampled rows x right-hand sides go to the team instead (up to
-  // LS_MAXP of them); a large single-factor problem has no tree level to split
-  // over and takes the multi-kernel path.
-  constexpr double BATCH_BIG_ROWS = 8192.0;
+  // rows 32 (node, rhs) pairs at a time, so problems with more than cfg.big_rows
+  // sampled rows x right-hand sides go to the team instead (up to LS_MAXP of
+  // them); a large single-factor problem has no tree level to split over and
+  // takes the multi-kernel path (outside any captured graph).
+  const double BATCH_BIG_ROWS = cfg.big_rows;
   enum Route : char { QUEUE = 0, TEAM = 1, SOLO = 2 };
   std::vector<Geom> G(count);
   std::vector<double> cost(count);
@@ -1128,6 +1145,54 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   int64_t* d_done = a.take<int64_t>(std::max(1, nteam_p));
   double* d_part = a.take<double>(std::max<size_t>(1, nparts));
   hipStream_t s = h->stream;
+  // graph mode: the work enqueued below (everything but the multi-kernel
+  // problems above) is captured once and replayed while the signature -- every
+  // pointer, shape and parameter it depends on -- is unchanged
+  bool replay = false;
+  std::vector<uint64_t> sig;
+  if (graph) {
+    auto put = [&](uint64_t v) { sig.push_back(v); };
+    auto putd = [&](double v) { uint64_t u; std::memcpy(&u, &v, 8); sig.push_back(u); };
+    put((uint64_t)count); putd(eps); putd(delta); put((uint64_t)o.m); put((uint64_t)max_iter); putd(tol);
+    put(o.seed); put(o.stream); put((uint64_t)o.flags); putd(cfg.big_rows); put((uint64_t)cfg.team_per_cu);
+    put((uint64_t)(uintptr_t)h->ws); put((uint64_t)h->ws_bytes); put((uint64_t)(uintptr_t)h->h_batch);
+    put((uint64_t)(uintptr_t)s);
+    for (int i = 0; i < count; ++i) {
+      const kr_problem& pr = probs[i];
+      put((uint64_t)pr.N); put((uint64_t)pr.nrhs); put((uint64_t)pr.a_dtype); put((uint64_t)pr.b_dtype);
+      for (int n = 0; n < pr.N; ++n) { put((uint64_t)pr.I[n]); put((uint64_t)pr.R[n]); put((uint64_t)(uintptr_t)pr.A[n]); }
+      put((uint64_t)(uintptr_t)pr.b);
+      if (pr.gen) { put((uint64_t)(uintptr_t)pr.gen->X_true); putd(pr.gen->sigma); put(pr.gen->seed); put(pr.gen->stream); }
+      else put(0);
+      putd(lambda[i]);
+      put((uint64_t)(uintptr_t)d_x[i]);
+    }
+    replay = h->bgraph && sig == h->bgraph_sig;
+  }
+  struct CaptureGuard {   // ends an unfinished capture on every early return
+    kr_handle h;
+    hipStream_t s;
+    bool active = false;
+    ~CaptureGuard() {
+      if (!active) return;
+      hipGraph_t gr = nullptr;
+      (void)hipStreamEndCapture(s, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      h->capturing = false;
+    }
+  } cap_guard{h, s};
+  if (graph && !replay) {
+    if (!s) KR_FAIL(h, KR_EUNSUPPORTED, "graph capture needs a stream other than the legacy default stream");
+    if (h->bgraph) {
+      (void)hipGraphExecDestroy(h->bgraph);
+      h->bgraph = nullptr;
+      h->bgraph_sig.clear();
+    }
+    HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    cap_guard.active = true;
+    h->capturing = true;
+  }
+  const bool enq = !replay;   // enqueue work (else only rebuild the host descriptors)
   // pass 2: carve, and enqueue every problem's setup and sketch
   size_t part_off = 0;
   for (int i : idx) {
@@ -1141,13 +1206,15 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
     kr_opts oi = o;
     oi.stream = o.stream + (uint64_t)i;
-    st = launch_sketch(h, &probs[i], g, T, B, tr, oi, lambda[i] > 0.0);
-    if (st != KR_OK) return st;
-    if (lambda[i] > 0.0)
-      KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, s, T, g, lambda[i], B.dinv);
-    KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, (double*)d_x[i], g.Rtot * g.nrhs,
-       0.0);
-    KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
+    if (enq) {
+      st = launch_sketch(h, &probs[i], g, T, B, tr, oi, lambda[i] > 0.0);
+      if (st != KR_OK) return st;
+      if (lambda[i] > 0.0)
+        KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, s, T, g, lambda[i], B.dinv);
+      KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, (double*)d_x[i], g.Rtot * g.nrhs,
+         0.0);
+      KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
+    }
     BatchDesc& d = hd[slot[i]];
     std::memset(&d, 0, sizeof(BatchDesc));
     d.g = g;
@@ -1178,62 +1245,79 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   for (int k = 0; k < nq; ++k) ord[k] = k;
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[idx[x]] > cost[idx[y]]; });
   std::memcpy(horder, ord.data(), nq * sizeof(int32_t));
-  HIPCHK(h, hipMemcpyAsync(d_descs, hd, nall * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
-  if (nteam_p) HIPCHK(h, hipMemcpyAsync(d_l, hl, nteam_p * sizeof(LExtra), hipMemcpyHostToDevice, s));
-  if (nq) HIPCHK(h, hipMemcpyAsync(d_order, horder, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, d_cnt, (int64_t)cnt_words);
-  KL(h, k_zero_bytes, dim3(grid_for(std::max(1, nteam_p) * 2, 256, 64)), dim3(256), 0, s, (uint32_t*)d_done,
-     (int64_t)std::max(1, nteam_p) * 2);
-  // launch shapes: the queue kernel, then the team kernel with every workgroup
-  // resident
-  int dev = 0, ncu = 0, wclk = 0;
-  HIPCHK(h, hipGetDevice(&dev));
-  HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(h, hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, dev));   // kHz
-  BatchArgs ba{};
-  ba.descs = d_descs;
-  ba.order = d_order;
-  ba.nqueue = nq;
-  ba.nteam_prob = nteam_p;
-  ba.L = d_l;
-  ba.done_step = d_done;
-  ba.queue = d_queue;
-  ba.bar = d_bar;
-  ba.abortf = d_abort;
-  ba.max_iter = max_iter;
-  ba.eta = eta;
-  ba.tol = tol;
-  ba.limit = (uint64_t)std::max(1, wclk) * 1000ull * 30ull;   // 30 s of waiting at one barrier
-  if (nq > 0) {
-    int per_cu = 0;
-    HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_queue, BT_THREADS, 0));
-    const int grid = std::max(1, std::min(nq, std::max(1, per_cu) * ncu));
-    KLN(h, "k_batched_queue", k_batched_queue, dim3(grid), dim3(BT_THREADS), 0, s, ba);
-  }
-  if (nteam_p > 0) {
-    int per_cu = 0;
-    HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_team, TM_THREADS, 0));
-    const int grid = std::max(1, per_cu) * ncu;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    HIPCHK(h, hipStreamIsCapturing(s, &cap));
-    if (cap == hipStreamCaptureStatusNone) {
-      // the team's barrier needs every workgroup resident: a cooperative launch
-      // guarantees it (or fails)
-      void* args[] = {&ba};
-      hipError_t e;
-      {
-        ProfScope ps(h, "k_batched_team", s);
-        e = hipLaunchCooperativeKernel((const void*)k_batched_team, dim3(grid), dim3(TM_THREADS), args, 0, s);
-      }
-      HIPCHK(h, e);
-    } else {
-      KLN(h, "k_batched_team", k_batched_team, dim3(grid), dim3(TM_THREADS), 0, s, ba);
+  if (enq) {
+    HIPCHK(h, hipMemcpyAsync(d_descs, hd, nall * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+    if (nteam_p) HIPCHK(h, hipMemcpyAsync(d_l, hl, nteam_p * sizeof(LExtra), hipMemcpyHostToDevice, s));
+    if (nq) HIPCHK(h, hipMemcpyAsync(d_order, horder, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, d_cnt, (int64_t)cnt_words);
+    KL(h, k_zero_bytes, dim3(grid_for(std::max(1, nteam_p) * 2, 256, 64)), dim3(256), 0, s, (uint32_t*)d_done,
+       (int64_t)std::max(1, nteam_p) * 2);
+    // launch shapes: the queue kernel, then the team kernel with every workgroup
+    // resident
+    int dev = 0, ncu = 0, wclk = 0;
+    HIPCHK(h, hipGetDevice(&dev));
+    HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(h, hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, dev));   // kHz
+    BatchArgs ba{};
+    ba.descs = d_descs;
+    ba.order = d_order;
+    ba.nqueue = nq;
+    ba.nteam_prob = nteam_p;
+    ba.L = d_l;
+    ba.done_step = d_done;
+    ba.queue = d_queue;
+    ba.bar = d_bar;
+    ba.abortf = d_abort;
+    ba.max_iter = max_iter;
+    ba.eta = eta;
+    ba.tol = tol;
+    ba.limit = (uint64_t)std::max(1, wclk) * 1000ull * 30ull;   // 30 s of waiting at one barrier
+    if (nq > 0) {
+      int per_cu = 0;
+      HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_queue, BT_THREADS, 0));
+      const int grid = std::max(1, std::min(nq, std::max(1, per_cu) * ncu));
+      KLN(h, "k_batched_queue", k_batched_queue, dim3(grid), dim3(BT_THREADS), 0, s, ba);
     }
+    if (nteam_p > 0) {
+      int per_cu = 0;
+      HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batched_team, TM_THREADS, 0));
+      per_cu = std::max(1, per_cu);
+      if (cfg.team_per_cu > 0) per_cu = std::min(per_cu, cfg.team_per_cu);
+      const int grid = per_cu * ncu;
+      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+      HIPCHK(h, hipStreamIsCapturing(s, &cap));
+      if (cap == hipStreamCaptureStatusNone) {
+        // the team's barrier needs every workgroup resident: a cooperative launch
+        // guarantees it (or fails)
+        void* args[] = {&ba};
+        hipError_t e;
+        {
+          ProfScope ps(h, "k_batched_team", s);
+          e = hipLaunchCooperativeKernel((const void*)k_batched_team, dim3(grid), dim3(TM_THREADS), args, 0, s);
+        }
+        HIPCHK(h, e);
+      } else {
+        KLN(h, "k_batched_team", k_batched_team, dim3(grid), dim3(TM_THREADS), 0, s, ba);
+      }
+    }
+    KL(h, k_batch_collect, dim3(grid_for(nall, 256, 64)), dim3(256), 0, s, (const BatchDesc*)d_descs, nall, d_res);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(hres, d_res, nall * sizeof(BatchResult), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(habort, d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   }
-  KL(h, k_batch_collect, dim3(grid_for(nall, 256, 64)), dim3(256), 0, s, (const BatchDesc*)d_descs, nall, d_res);
-  HIPCHK(h, hipGetLastError());
-  HIPCHK(h, hipMemcpyAsync(hres, d_res, nall * sizeof(BatchResult), hipMemcpyDeviceToHost, s));
-  HIPCHK(h, hipMemcpyAsync(habort, d_abort, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if (graph && !replay) {
+    hipGraph_t gr = nullptr;
+    cap_guard.active = false;
+    h->capturing = false;
+    HIPCHK(h, hipStreamEndCapture(s, &gr));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIPCHK(h, e);
+    h->bgraph = ex;
+    h->bgraph_sig = sig;
+  }
+  if (graph) HIPCHK(h, hipGraphLaunch(h->bgraph, s));
   HIPCHK(h, hipStreamSynchronize(s));
   if (*habort) KR_FAIL(h, KR_EHIP, "the batched team's barrier timed out (workgroups not resident?)");
   for (int i = 0; i < count; ++i) {
@@ -1274,7 +1358,64 @@ kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps
 
 kr_status kron_ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
                              double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {
-  return solve_batched(h, count, probs, lambda, eps, delta, opts, d_x, info);
+  if (!h) return KR_EINVAL;
+  kr_opts o{};
+  if (opts) o = *opts;
+  const bool graph = (o.flags & KR_OPT_GRAPH) != 0;
+  BatchCfg cfg;
+  if ((o.flags & KR_OPT_AUTOTUNE) && count > 0 && probs && lambda && d_x) {
+    // batch shape class: count, sum of N, and the binary magnitudes of the summed
+    // unknowns and of the summed design rows (capped by the sample count)
+    int64_t sumN = 0;
+    double sumR = 0.0, sumRows = 0.0;
+    for (int i = 0; i < count; ++i) {
+      double R = 1.0, I = 1.0;
+      for (int n = 0; n < probs[i].N && n < KR_MAX_MODES; ++n) { R *= (double)probs[i].R[n]; I *= (double)probs[i].I[n]; }
+      sumN += probs[i].N;
+      sumR += R * std::max(1, probs[i].nrhs);
+      sumRows += std::min(I, std::max(R, 1.0) * 100.0) * std::max(1, probs[i].nrhs);
+    }
+    const std::vector<int64_t> key = {count, sumN, (int64_t)std::floor(4.0 * std::log2(sumR + 1.0)),
+                                      (int64_t)std::floor(4.0 * std::log2(sumRows + 1.0)), o.m, o.flags & KR_OPT_M_RLNR};
+    auto it = h->tune.find(key);
+    if (it == h->tune.end()) {
+      // time every candidate on this batch (full solves; the last, chosen run
+      // below produces the returned results)
+      const double rows_c[] = {2048.0, 8192.0, 32768.0};
+      const int wg_c[] = {1, 0};
+      double best_ms = 1e300;
+      BatchCfg best;
+      for (double br : rows_c)
+        for (int wg : wg_c) {
+          BatchCfg c;
+          c.big_rows = br;
+          c.team_per_cu = wg;
+          const auto t0 = std::chrono::steady_clock::now();
+          const kr_status st = solve_batched(h, count, probs, lambda, eps, delta, opts, d_x, info, c, false);
+          const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          if (st == KR_EHIP || st == KR_ENOMEM || st == KR_EUNSUPPORTED) return st;
+          if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+      it = h->tune.emplace(key, std::make_pair(best.big_rows, best.team_per_cu)).first;
+    }
+    cfg.big_rows = it->second.first;
+    cfg.team_per_cu = it->second.second;
+  }
+  return solve_batched(h, count, probs, lambda, eps, delta, opts, d_x, info, cfg, graph);
+}
+
+kr_status kr_batched_config(kr_handle h, double* big_rows, int32_t* team_per_cu) {
+  if (!h) return KR_EINVAL;
+  if (h->tune.empty()) {
+    const BatchCfg c;
+    if (big_rows) *big_rows = c.big_rows;
+    if (team_per_cu) *team_per_cu = c.team_per_cu;
+    return KR_OK;
+  }
+  const auto& v = h->tune.rbegin()->second;
+  if (big_rows) *big_rows = v.first;
+  if (team_per_cu) *team_per_cu = v.second;
+  return KR_OK;
 }
 
 kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega, int32_t* h_counts,

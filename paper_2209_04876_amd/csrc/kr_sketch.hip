@@ -389,39 +389,36 @@ __device__ __forceinline__ double gen_normal(uint64_t i, uint64_t q, uint64_t se
 __global__ void __launch_bounds__(256) k_gen_rows(Geom g, Tree tr, const double* __restrict__ Pn2, double sigma,
                                                   uint64_t seed, uint64_t stream, double* __restrict__ bD,
                                                   int32_t* __restrict__ flags) {
-  const int64_t D = tr.cnt[g.N];
   const int N = g.N, nrhs = g.nrhs;
+  const int64_t total = tr.cnt[N] * nrhs;
   const int RL = g.R[N - 1];
   const int RP = N >= 2 ? g.R[N - 2] : 1;
   int bad = 0;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < D;
-       j += (int64_t)gridDim.x * blockDim.x) {
+  // one thread per (row j, rhs q)
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / nrhs;
+    const int q = (int)(e - j * nrhs);
     const uint64_t key = tr.rkey[j];
     int64_t lin = 0;
     for (int n = 0; n < N; ++n) lin = lin * g.I[n] + (int64_t)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
     const double* __restrict__ aL = tr.arow[N] + j * RL;
-    const double* __restrict__ aP = nullptr;
-    int64_t base = 0;
-    if (N >= 2) {
+    double y = 0.0;
+    if (N == 1) {
+      for (int r = 0; r < RL; ++r) y = fma(aL[r], Pn2[(int64_t)r * nrhs + q], y);
+    } else {
       const int64_t s = tr.parent[N][j];
-      aP = tr.arow[N - 1] + s * RP;
-      base = (N >= 3 ? (int64_t)tr.parent[N - 1][s] : 0) * g.rsuf[N - 2] * nrhs;
-    }
-    for (int q = 0; q < nrhs; ++q) {
-      double y = 0.0;
-      if (N == 1) {
-        for (int r = 0; r < RL; ++r) y = fma(aL[r], Pn2[(int64_t)r * nrhs + q], y);
-      } else {
-        for (int r1 = 0; r1 < RP; ++r1) {
-          double t = 0.0;
-          for (int r2 = 0; r2 < RL; ++r2) t = fma(aL[r2], Pn2[base + ((int64_t)r1 * RL + r2) * nrhs + q], t);
-          y = fma(aP[r1], t, y);
-        }
+      const double* __restrict__ aP = tr.arow[N - 1] + s * RP;
+      const int64_t base = (N >= 3 ? (int64_t)tr.parent[N - 1][s] : 0) * g.rsuf[N - 2] * nrhs + q;
+      for (int r1 = 0; r1 < RP; ++r1) {
+        double t = 0.0;
+        for (int r2 = 0; r2 < RL; ++r2) t = fma(aL[r2], Pn2[base + ((int64_t)r1 * RL + r2) * nrhs], t);
+        y = fma(aP[r1], t, y);
       }
-      const double v = y + sigma * gen_normal((uint64_t)lin, (uint64_t)q, seed, stream);
-      bD[j * nrhs + q] = v;
-      bad |= !isfinite(v);
     }
+    const double v = y + sigma * gen_normal((uint64_t)lin, (uint64_t)q, seed, stream);
+    bD[j * nrhs + q] = v;
+    bad |= !isfinite(v);
   }
   if (bad) atomicOr(flags, KR_FLAG_NONFINITE);
 }

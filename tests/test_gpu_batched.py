@@ -199,3 +199,66 @@ def test_batched_rejects_wide_modes_and_low_precision(gpu_lib):
         gpu_lib.kron_ridge_batched([(tA, tb)], [0.1], m=100)
     assert e.value.status == -6
     assert gpu_lib.kron_ridge_batched([], [], m=100) == ([], [])
+
+
+def _mixed_batch(gpu_lib, seed):
+    import torch
+    specs = [((60, 50, 40), (3, 4, 3), 2, 0.02), ((400, 300), (8, 6), 2, 0.1), ((9, 8), (3, 2), 1, 0.01),
+             ((20, 18, 16, 15), (2, 3, 3, 2), 2, 0.05), ((12, 10, 9), (3, 2, 3), 3, 0.2)]
+    probs, lams, dense = [], [], []
+    for i, (I, R, nrhs, lam) in enumerate(specs):
+        w = workloads.random_problem(I, R, seed=seed + i, nrhs=nrhs, sigma=0.05)
+        probs.append(([torch.tensor(A, device="cuda") for A in w["As"]], torch.tensor(w["b"], device="cuda")))
+        lams.append(lam)
+        dense.append(w)
+    return probs, lams, dense
+
+
+def test_batched_graph_replays_match_eager(gpu_lib):
+    """KR_OPT_GRAPH: the first call captures, later calls with the same buffers
+    replay; every replay (with eager work and synchronisations between them, and
+    new response values in the same buffers) equals the eager solve."""
+    import torch
+    probs, lams, _ = _mixed_batch(gpu_lib, 800)
+    stream = torch.cuda.Stream()
+    h = gpu_lib.Handle(stream=stream)
+    he = gpu_lib.Handle(stream=stream)
+    print("case batched graph", flush=True)
+    kw = dict(m=60000, seed=3, stream=5, tol=1e-12, max_iter=400)
+    with torch.cuda.stream(stream):
+        xs = None
+        for rep in range(4):
+            if rep == 2:   # new data in the same buffers: the replay must see it
+                for _, b in probs:
+                    b.mul_(1.5).add_(0.25)
+            xs, infos = gpu_lib.kron_ridge_batched(probs, lams, handle=h, graph=True, xs=xs, **kw)
+            stream.synchronize()
+            xe, _ = gpu_lib.kron_ridge_batched(probs, lams, handle=he, **kw)
+            stream.synchronize()
+            _ = torch.randn(1000, device="cuda").sum().item()   # unrelated eager work between replays
+            for i, (a, b) in enumerate(zip(xs, xe)):
+                assert infos[i]["status"] == "OK", (rep, i, infos[i])
+                assert torch.equal(a, b), (rep, i, rel_l2(a.cpu().numpy(), b.cpu().numpy()))
+    h.close()
+    he.close()
+
+
+def test_batched_autotune_keeps_results(gpu_lib):
+    """KR_OPT_AUTOTUNE times the candidate configurations and returns the
+    minimiser of every problem (checked against the oracle)."""
+    import torch
+    probs, lams, dense = _mixed_batch(gpu_lib, 900)
+    h = gpu_lib.Handle()
+    m = 60000
+    print("case batched autotune", flush=True)
+    xs, infos = gpu_lib.kron_ridge_batched(probs, lams, m=m, seed=4, stream=9, tol=1e-12, max_iter=400, handle=h,
+                                           autotune=True)
+    br, wg = gpu_lib.batched_config(handle=h)
+    print("chosen", br, wg, flush=True)
+    assert br in (2048.0, 8192.0, 32768.0) and wg in (0, 1)
+    for i, (w, x, info) in enumerate(zip(dense, xs, infos)):
+        assert info["status"] == "OK", (i, info)
+        sk = sketch(w["As"], m, 4, 9 + i)
+        x64 = sketched_solution(w["As"], w["b"], sk["rows"], sk["ridx"], sk["Omega"], lams[i])
+        assert rel_l2(x.cpu().numpy(), x64) < 1e-10, i
+    h.close()
