@@ -17,6 +17,9 @@ Workload (default): skewed_regression, N=3 factors 512x16 (26 rows per mode
 scaled x100), K is 1.34e8 x 4096, b = K x_true + 0.1 e in float64 (1.07 GB),
 eps = 0.1, m = ceil(R ln R / eps) = 340,696, Philox seed 0.
 
+Also times the batched ridge workload (256 uneven problems per call; the
+"batched" object of the line; --no-batched skips it).
+
 Prints one JSON line.  --gpus above 1 is refused (single-GPU build).
 """
 
@@ -115,6 +118,65 @@ def cpu_baseline(w, seconds=12.0):
                       "workload, %.1f s wall" % (n, dt)}
 
 
+def batched_leg(kr, torch, steps):
+    """The batched ridge workload: 256 uneven problems per kron_ridge_batched call
+    (sketch of every problem, then the queue and team persistent kernels).
+
+    Rate: problems solved per second over whole calls.  Roofline of the two
+    persistent kernels together: per Richardson iteration each distinct sampled
+    row streams its packed key (8 B), merged weight Omega_j (8 B) and response
+    (8 B per right-hand side); sum over problems of iterations x D x (16 + 8 nrhs)
+    bytes divided by the kernels' event-timed duration."""
+    import numpy as np
+    import workloads
+    specs = workloads.batched_ridge_specs()
+    probs, lams = [], []
+    t = time.perf_counter()
+    for sp in specs:
+        As, X = workloads.batched_ridge_arrays(sp)
+        tA = [torch.tensor(A, device="cuda") for A in As]
+        gen = kr.ResponseGen(torch.tensor(X, device="cuda"), sp["sigma"], seed=sp["noise_key"][0],
+                             stream=sp["noise_key"][1])
+        probs.append((tA, gen))
+        lams.append(sp["lam"])
+    log("batched workload generated in %.1f s (%d problems)" % (time.perf_counter() - t, len(probs)))
+
+    def call():
+        return kr.kron_ridge_batched(probs, lams, eps=0.1, m_rule="rlnr", seed=0, max_iter=400)
+
+    call()   # warmup (workspace allocation)
+    kr.profile_enable(True, "k_batched_team|k_batched_queue")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xs, infos = call()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    nt, tms = kr.profile_query("k_batched_team")
+    nq, qms = kr.profile_query("k_batched_queue")
+    kr.profile_enable(False)
+    iter_ms = (tms + qms) / steps
+    nrhs = [sp["nrhs"] for sp in specs]
+    bytes_iter = sum(inf["iters"] * inf["distinct_rows"] * (16 + 8 * q) for inf, q in zip(infos, nrhs))
+    ach = bytes_iter / (iter_ms * 1e-3) / 1e9 if iter_ms > 0 else None
+    it = [inf["iters"] for inf in infos]
+    return {
+        "workload": "batched ridge: %d problems, N~U{2,3,4}, I_n~U{32..256}, R_n~U{4..16}, 1-8 RHS, "
+                    "lambda=10^U(-4,0), FP32 factors, implicit b = K X_true + 0.01 e, "
+                    "m = ceil(R ln R / 0.1) per problem" % len(specs),
+        "value": round(len(specs) / dt, 3), "unit": "solves/s", "ms_per_batch": round(1000.0 * dt, 3),
+        "steps": steps, "dtype": "f64",
+        "sum_m": int(sum(inf["m"] for inf in infos)), "sum_distinct_rows": int(sum(inf["distinct_rows"] for inf in infos)),
+        "iters_max": int(max(it)), "iters_mean": round(float(np.mean(it)), 2),
+        "converged": int(sum(inf["status"] == "OK" for inf in infos)),
+        "iteration_kernels_ms": round(iter_ms, 3),
+        "roofline": {"kernel": "k_batched_team+k_batched_queue", "bound": "hbm",
+                     "achieved": None if ach is None else round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                     "algorithmic_bytes_per_launch": int(bytes_iter)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +184,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched ridge workload")
+    ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -260,6 +324,8 @@ def main():
         "hbm_stream": roofline(stream_kernel, ns_, sms),
         "sample_tree_levels": S,
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(kr, torch, args.batched_steps)
     if not args.no_cpu_baseline:
         del tA, tb
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
