@@ -72,13 +72,13 @@ def algorithmic_bytes(I, R, S):
     return out
 
 
-def recorded_traffic():
+def recorded_traffic(name="skewed_regression_hbm_counters.md"):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain copy), as recorded in profiles/skewed_regression_hbm_counters.md;
-    an entry counts only while its kernel source still hashes as recorded."""
+    scaled by a plain copy), as recorded in profiles/<name>; an entry counts only
+    while its kernel source still hashes as recorded."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "skewed_regression_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", name)
     out = {}
     if not os.path.exists(path):
         return out
@@ -172,7 +172,8 @@ def batched_leg(kr, torch, steps):
         "iteration_kernels_ms": round(iter_ms, 3),
         "roofline": {"kernel": "k_batched_team+k_batched_queue", "bound": "hbm",
                      "achieved": None if ach is None else round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 5),
+                     "traffic": recorded_traffic("batched_ridge_hbm_counters.md").get("k_batched_team+k_batched_queue"),
                      "algorithmic_bytes_per_launch": int(bytes_iter)},
     }
 
