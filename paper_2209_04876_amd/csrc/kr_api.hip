@@ -457,8 +457,11 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
 // block up to 2048 of them (the root adjoint then writes g itself), else at most
 // 64 blocks, which the preconditioner kernel sums.  Needs tr.ncnt.
 static int root_npb(const Tree& tr) {
+  // up to 2048 level-1 nodes: about four partial blocks of at least 128 nodes
+  // (their sum costs the preconditioner little, and the root adjoint spreads
+  // over more workgroups); beyond, 64 blocks
   const int64_t S1 = std::max<int64_t>(1, tr.ncnt[1]);
-  const int64_t per = S1 <= 2048 ? S1 : (S1 + 63) / 64;
+  const int64_t per = S1 <= 2048 ? std::max<int64_t>(std::min<int64_t>(S1, 128), (S1 + 3) / 4) : (S1 + 63) / 64;
   return (int)(RA_NODES * ((per + RA_NODES - 1) / RA_NODES));
 }
 
