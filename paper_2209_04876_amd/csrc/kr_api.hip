@@ -573,7 +573,7 @@ static void launch_precond_f64_nb(kr_handle h, const ModeTables& T, const Geom& 
     (void)hipGetLastError();
     lds = 0;
   }
-  KLN(h, names[NB - 1], k_precond_update<NB>, dim3(1), dim3(256), lds, h->stream, T, g, (const double*)a.grad,
+  KLN(h, names[NB - 1], k_precond_update<NB>, dim3(1), dim3(PC_THREADS), lds, h->stream, T, g, (const double*)a.grad,
       a.nnb, a.dinv, a.x, (double*)a.t0, (double*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol, a.max_iter, a.use_ginv,
       a.st);
 }
@@ -590,7 +590,7 @@ static void launch_precond_mp_nb(kr_handle h, const ModeTables& T, const Geom& g
     (void)hipGetLastError();
     lds = 0;
   }
-  KLN(h, names[MODE][NB - 1], (k_precond_mp<MODE, NB>), dim3(1), dim3(256), lds, h->stream, T, g,
+  KLN(h, names[MODE][NB - 1], (k_precond_mp<MODE, NB>), dim3(1), dim3(PC_THREADS), lds, h->stream, T, g,
       (const float*)a.grad, a.nnb, a.dinv, a.x, (float*)a.t0, (float*)a.t1, (int)(lds > 0), a.lambda, a.eta, a.tol,
       a.max_iter, a.use_ginv, a.st);
 }

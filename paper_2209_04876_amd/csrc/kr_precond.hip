@@ -21,6 +21,9 @@ typedef short pc_bf16x4 __attribute__((ext_vector_type(4)));
 typedef float pc_f32x4 __attribute__((ext_vector_type(4)));
 
 #define PC_MATS 4096   // LDS entries for the staged factor matrices
+#ifndef PC_THREADS
+#define PC_THREADS 512 // threads of the single-problem preconditioner kernels
+#endif
 #define PC_BATCH 8     // elements per thread whose loads are issued together
 
 // Offset of mode n's matrix in the staged table.
@@ -446,10 +449,10 @@ __device__ void pc_step_f64(const ModeTables& T, const Geom& g, const double* __
   pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane);
 }
 
-// Float64 step as its own launch (one workgroup of 256 threads); the tensor
+// Float64 step as its own launch (one workgroup of PC_THREADS threads); the tensor
 // buffers are in dynamic LDS when lds != 0, else t0/t1.
 template <int NB>
-__global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
+__global__ void __launch_bounds__(PC_THREADS) k_precond_update(ModeTables T, Geom g, const double* __restrict__ grad,
                                                        unsigned nnb,
                                                        const double* __restrict__ dinv, double* __restrict__ x,
                                                        double* __restrict__ t0, double* __restrict__ t1, int lds,
@@ -467,7 +470,7 @@ __global__ void __launch_bounds__(256) k_precond_update(ModeTables T, Geom g, co
 // fp8 takes the eigenvector form also for lambda = 0: its orthogonal factors
 // round far better in e4m3 than the inverse Grams (fewer iterations, measured).
 template <int MODE, int NB>
-__global__ void __launch_bounds__(256) k_precond_mp(ModeTables T, Geom g, const float* __restrict__ grad,
+__global__ void __launch_bounds__(PC_THREADS) k_precond_mp(ModeTables T, Geom g, const float* __restrict__ grad,
                                                    unsigned nnb,
                                                    const double* __restrict__ dinv, double* __restrict__ x,
                                                    float* __restrict__ t0, float* __restrict__ t1, int lds,
