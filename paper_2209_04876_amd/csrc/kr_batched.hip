@@ -218,7 +218,7 @@ __device__ int64_t ls_threads(const BatchDesc& d, const LExtra& L, const LStage&
     case LS_ADJ: n = d.tr.cnt[st.k - 1] * ((g.rsuf[st.k] * g.nrhs + 15) / 16) * 64; break;
     case LS_ROOT: n = ((g.rsuf[1] * g.nrhs + 15) / 16) * 64; break;
     case LS_MODE: n = ((g.Rtot * g.nrhs / g.R[st.k] + 15) / 16) * 64; break;
-    case LS_UPD: n = (int64_t)L.nchunk * BT_THREADS; break;
+    case LS_UPD: n = (int64_t)L.nchunk * TM_THREADS; break;
   }
   return (n + TM_THREADS - 1) / TM_THREADS * TM_THREADS;
 }
@@ -410,6 +410,81 @@ __device__ bool ls_stage_factors(const BatchDesc& d, int i, double* fa, int* tag
   return true;
 }
 
+// The rows j0..j1 of one level-(N-2) subtree for one rhs q, one wave (see
+// ls_rows2 for the contraction): Bf holds the B operand of M = AV P in tile
+// layout; the adjoint accumulates into acc2 (Q[r' = gq + 4 v][c]).  Row data
+// streams in 64-row chunks with the next chunk in flight; AP and AL are the
+// mode-(N-2) and last-mode factors (LDS or global).
+__device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int j1, int q, const double* Bf,
+                                                const double* __restrict__ AP, const double* __restrict__ AL,
+                                                int lane, pc_f64x4& acc2) {
+  const Geom& g = d.g;
+  const int N = g.N, nrhs = g.nrhs;
+  const int RL = g.R[N - 1], RP = g.R[N - 2];
+  const int c = lane & 15, gq = lane >> 4;
+  const int shP = g.shift[N - 2], shL = g.shift[N - 1];
+  const uint64_t mP = (1ull << g.bits[N - 2]) - 1ull, mL = (1ull << g.bits[N - 1]) - 1ull;
+  const uint64_t* __restrict__ keys = d.tr.rkey;
+  auto load_chunk = [&](int jc, uint64_t& k, double& om, double& bq) {
+    const int j = jc + lane;
+    const bool ok = j < j1;
+    k = ok ? keys[j] : 0ull;
+    om = ok ? d.Omega[j] : 0.0;
+    bq = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
+  };
+  uint64_t kc = 0;
+  double oc = 0.0, bc = 0.0;
+  if (j0 < j1) load_chunk(j0, kc, oc, bc);
+  for (int jc = j0; jc < j1; jc += 64) {
+    uint64_t kn = 0;
+    double on = 0.0, bn = 0.0;
+    if (jc + 64 < j1) load_chunk(jc + 64, kn, on, bn);
+    const int nblk = (j1 - jc) >= 64 ? 4 : (j1 - jc + 15) / 16;
+    for (int ub = 0; ub < nblk; ++ub) {
+      const int jb = jc + 16 * ub;
+      const uint64_t ka = __shfl(kc, 16 * ub + c, 64);
+      const bool va = jb + c < j1;
+      const int iPa = (int)((ka >> shP) & mP);
+      double Af[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int r1 = 4 * ks + gq;
+        Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
+      }
+      pc_f64x4 M = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) M = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], Bf[ks], M, 0, 0, 0);
+      double an[4], Aa[4], om[4], bq[4], W[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int src = 16 * ub + gq + 4 * u;
+        const uint64_t kd = __shfl(kc, src, 64);
+        om[u] = __shfl(oc, src, 64);
+        bq[u] = __shfl(bc, src, 64);
+        const bool vd = jb + gq + 4 * u < j1;
+        const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
+        an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
+        Aa[u] = (vd && c < RP) ? AP[iPd * RP + c] : 0.0;
+        if (!vd) om[u] = 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = an[u] * M[u];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, 16);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) W[u] = an[u] * (om[u] * (y[u] - bq[u]));
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W[ks], acc2, 0, 0, 0);
+    }
+    kc = kn;
+    oc = on;
+    bc = bn;
+  }
+}
+
 // Fused last two levels for N >= 3, one wave per level-(N-2) node p (all
 // right-hand sides in turn), on v_mfma_f64_16x16x4.  The rows j of p's subtree
 // are contiguous; per block of 16 rows, with AV the rows' mode-(N-2) factor rows
@@ -443,79 +518,94 @@ __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const do
   const uint64_t mP = (1ull << g.bits[N - 2]) - 1ull, mL = (1ull << g.bits[N - 1]) - 1ull;
   const uint64_t* __restrict__ keys = d.tr.rkey;
   double* __restrict__ Qo = d.Q[N - 2];
-  for (int q = 0; q < nrhs; ++q) {
-    double Bf[4];   // B operand of M = AV P: P[r' = 4 ks + gq][c]
+  // B operand of M = AV P for rhs q: P[r' = 4 ks + gq][c]
+  auto load_B = [&](int q, double* B) {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int r1 = 4 * ks + gq;
-      Bf[ks] = (r1 < RP && c < RL) ? Pn2[pb + ((int64_t)r1 * RL + c) * nrhs + q] : 0.0;
+      B[ks] = (r1 < RP && c < RL) ? Pn2[pb + ((int64_t)r1 * RL + c) * nrhs + q] : 0.0;
     }
-    auto load_chunk = [&](int jc, uint64_t& k, double& om, double& bq) {
-      const int j = jc + lane;
-      const bool ok = j < j1;
-      k = ok ? keys[j] : 0ull;
-      om = ok ? d.Omega[j] : 0.0;
-      bq = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
-    };
-    pc_f64x4 acc2 = {0.0, 0.0, 0.0, 0.0};   // Q[r' = gq + 4 v][c]
-    uint64_t kc = 0;
-    double oc = 0.0, bc = 0.0;
-    if (j0 < j1) load_chunk(j0, kc, oc, bc);
-    for (int jc = j0; jc < j1; jc += 64) {
-      uint64_t kn = 0;
-      double on = 0.0, bn = 0.0;
-      if (jc + 64 < j1) load_chunk(jc + 64, kn, on, bn);
-      const int nblk = (j1 - jc) >= 64 ? 4 : (j1 - jc + 15) / 16;
-      for (int ub = 0; ub < nblk; ++ub) {
-        const int jb = jc + 16 * ub;
-        // A layout: row jb + c
-        const uint64_t ka = __shfl(kc, 16 * ub + c, 64);
-        const bool va = jb + c < j1;
-        const int iPa = (int)((ka >> shP) & mP);
-        double Af[4];
+  };
+  // one block of 16 rows jb.. of the 64-row chunk held in (kc, oc, bc), slot ub
+  auto block = [&](int jb, int ub, uint64_t kc, double oc, double bc, const double* Bf, pc_f64x4& acc2) {
+    // A layout: row jb + c
+    const uint64_t ka = __shfl(kc, 16 * ub + c, 64);
+    const bool va = jb + c < j1;
+    const int iPa = (int)((ka >> shP) & mP);
+    double Af[4];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int r1 = 4 * ks + gq;
-          Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
-        }
-        pc_f64x4 M = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) M = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], Bf[ks], M, 0, 0, 0);
-        // D layout: rows jb + gq + 4 u
-        double an[4], Aa[4], om[4], bq[4], W[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int src = 16 * ub + gq + 4 * u;
-          const uint64_t kd = __shfl(kc, src, 64);
-          om[u] = __shfl(oc, src, 64);
-          bq[u] = __shfl(bc, src, 64);
-          const bool vd = jb + gq + 4 * u < j1;
-          const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
-          an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
-          Aa[u] = (vd && c < RP) ? AP[iPd * RP + c] : 0.0;
-          if (!vd) om[u] = 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] = an[u] * M[u];
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, 16);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) W[u] = an[u] * (om[u] * (y[u] - bq[u]));
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W[ks], acc2, 0, 0, 0);
-      }
-      kc = kn;
-      oc = on;
-      bc = bn;
+    for (int ks = 0; ks < 4; ++ks) {
+      const int r1 = 4 * ks + gq;
+      Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
     }
+    pc_f64x4 M = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) M = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], Bf[ks], M, 0, 0, 0);
+    // D layout: rows jb + gq + 4 u
+    double an[4], Aa[4], om[4], bq[4], W[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int src = 16 * ub + gq + 4 * u;
+      const uint64_t kd = __shfl(kc, src, 64);
+      om[u] = __shfl(oc, src, 64);
+      bq[u] = __shfl(bc, src, 64);
+      const bool vd = jb + gq + 4 * u < j1;
+      const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
+      an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
+      Aa[u] = (vd && c < RP) ? AP[iPd * RP + c] : 0.0;
+      if (!vd) om[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = an[u] * M[u];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, 16);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) W[u] = an[u] * (om[u] * (y[u] - bq[u]));
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W[ks], acc2, 0, 0, 0);
+  };
+  auto store = [&](int q, const pc_f64x4& acc2) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r1 = gq + 4 * u;
       if (r1 < RP && c < RL) Qo[pb + ((int64_t)r1 * RL + c) * nrhs + q] = acc2[u];
     }
+  };
+  if (j1 - j0 <= 64) {
+    // the whole subtree in one chunk: keys and weights once, the next rhs's P
+    // block and responses loaded while this rhs is processed
+    const int j = j0 + lane;
+    const bool ok = j < j1;
+    const uint64_t kc = ok ? keys[j] : 0ull;
+    const double oc = ok ? d.Omega[j] : 0.0;
+    double bc = ok ? d.bD[(int64_t)j * nrhs] : 0.0;
+    double Bf[4];
+    load_B(0, Bf);
+    const int nblk = (j1 - j0 + 15) / 16;
+    for (int q = 0; q < nrhs; ++q) {
+      double Bn[4] = {0.0, 0.0, 0.0, 0.0}, bn = 0.0;
+      if (q + 1 < nrhs) {
+        load_B(q + 1, Bn);
+        bn = ok ? d.bD[(int64_t)j * nrhs + q + 1] : 0.0;
+      }
+      pc_f64x4 acc2 = {0.0, 0.0, 0.0, 0.0};   // Q[r' = gq + 4 v][c]
+      for (int ub = 0; ub < nblk; ++ub) block(j0 + 16 * ub, ub, kc, oc, bc, Bf, acc2);
+      store(q, acc2);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) Bf[ks] = Bn[ks];
+      bc = bn;
+    }
+    return;
+  }
+  for (int q = 0; q < nrhs; ++q) {
+    double Bf[4];
+    load_B(q, Bf);
+    pc_f64x4 acc2 = {0.0, 0.0, 0.0, 0.0};
+    ls_subtree_rows(d, j0, j1, q, Bf, AP, AL, lane, acc2);
+    store(q, acc2);
   }
 }
 
