@@ -526,47 +526,6 @@ __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const do
       B[ks] = (r1 < RP && c < RL) ? Pn2[pb + ((int64_t)r1 * RL + c) * nrhs + q] : 0.0;
     }
   };
-  // one block of 16 rows jb.. of the 64-row chunk held in (kc, oc, bc), slot ub
-  auto block = [&](int jb, int ub, uint64_t kc, double oc, double bc, const double* Bf, pc_f64x4& acc2) {
-    // A layout: row jb + c
-    const uint64_t ka = __shfl(kc, 16 * ub + c, 64);
-    const bool va = jb + c < j1;
-    const int iPa = (int)((ka >> shP) & mP);
-    double Af[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int r1 = 4 * ks + gq;
-      Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
-    }
-    pc_f64x4 M = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) M = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], Bf[ks], M, 0, 0, 0);
-    // D layout: rows jb + gq + 4 u
-    double an[4], Aa[4], om[4], bq[4], W[4], y[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int src = 16 * ub + gq + 4 * u;
-      const uint64_t kd = __shfl(kc, src, 64);
-      om[u] = __shfl(oc, src, 64);
-      bq[u] = __shfl(bc, src, 64);
-      const bool vd = jb + gq + 4 * u < j1;
-      const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
-      an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
-      Aa[u] = (vd && c < RP) ? AP[iPd * RP + c] : 0.0;
-      if (!vd) om[u] = 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) y[u] = an[u] * M[u];
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, 16);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) W[u] = an[u] * (om[u] * (y[u] - bq[u]));
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W[ks], acc2, 0, 0, 0);
-  };
   auto store = [&](int q, const pc_f64x4& acc2) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -575,28 +534,79 @@ __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const do
     }
   };
   if (j1 - j0 <= 64) {
-    // the whole subtree in one chunk: keys and weights once, the next rhs's P
-    // block and responses loaded while this rhs is processed
+    // the whole subtree in one chunk: keys and weights are loaded once, and two
+    // right-hand sides share each block's factor-row gathers (two independent
+    // MFMA chains per wave)
     const int j = j0 + lane;
     const bool ok = j < j1;
     const uint64_t kc = ok ? keys[j] : 0ull;
     const double oc = ok ? d.Omega[j] : 0.0;
-    double bc = ok ? d.bD[(int64_t)j * nrhs] : 0.0;
-    double Bf[4];
-    load_B(0, Bf);
     const int nblk = (j1 - j0 + 15) / 16;
-    for (int q = 0; q < nrhs; ++q) {
-      double Bn[4] = {0.0, 0.0, 0.0, 0.0}, bn = 0.0;
-      if (q + 1 < nrhs) {
-        load_B(q + 1, Bn);
-        bn = ok ? d.bD[(int64_t)j * nrhs + q + 1] : 0.0;
-      }
-      pc_f64x4 acc2 = {0.0, 0.0, 0.0, 0.0};   // Q[r' = gq + 4 v][c]
-      for (int ub = 0; ub < nblk; ++ub) block(j0 + 16 * ub, ub, kc, oc, bc, Bf, acc2);
-      store(q, acc2);
+    for (int q = 0; q < nrhs; q += 2) {
+      const bool two = q + 1 < nrhs;
+      double B0[4], B1[4] = {0.0, 0.0, 0.0, 0.0};
+      load_B(q, B0);
+      if (two) load_B(q + 1, B1);
+      const double bc0 = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
+      const double bc1 = (ok && two) ? d.bD[(int64_t)j * nrhs + q + 1] : 0.0;
+      pc_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+      for (int ub = 0; ub < nblk; ++ub) {
+        const int jb = j0 + 16 * ub;
+        const uint64_t ka = __shfl(kc, 16 * ub + c, 64);
+        const bool va = jb + c < j1;
+        const int iPa = (int)((ka >> shP) & mP);
+        double Af[4];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) Bf[ks] = Bn[ks];
-      bc = bn;
+        for (int ks = 0; ks < 4; ++ks) {
+          const int r1 = 4 * ks + gq;
+          Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
+        }
+        pc_f64x4 M0 = {0.0, 0.0, 0.0, 0.0}, M1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          M0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], B0[ks], M0, 0, 0, 0);
+          M1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], B1[ks], M1, 0, 0, 0);
+        }
+        double an[4], Aa[4], om[4], y0[4], y1[4], W0[4], W1[4], b0[4], b1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int src = 16 * ub + gq + 4 * u;
+          const uint64_t kd = __shfl(kc, src, 64);
+          om[u] = __shfl(oc, src, 64);
+          b0[u] = __shfl(bc0, src, 64);
+          b1[u] = __shfl(bc1, src, 64);
+          const bool vd = jb + gq + 4 * u < j1;
+          const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
+          an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
+          Aa[u] = (vd && c < RP) ? AP[iPd * RP + c] : 0.0;
+          if (!vd) om[u] = 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          y0[u] = an[u] * M0[u];
+          y1[u] = an[u] * M1[u];
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            y0[u] += __shfl_xor(y0[u], o, 16);
+            y1[u] += __shfl_xor(y1[u], o, 16);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          W0[u] = an[u] * (om[u] * (y0[u] - b0[u]));
+          W1[u] = an[u] * (om[u] * (y1[u] - b1[u]));
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W0[ks], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W1[ks], acc1, 0, 0, 0);
+        }
+      }
+      store(q, acc0);
+      if (two) store(q + 1, acc1);
     }
     return;
   }
