@@ -99,6 +99,13 @@ def paper_e1(n, d, seed=0):
     return dict(name="paper_e1 n=%d d=%d" % (n, d), As=As, b=np.ones(n * n), lam=1e-3, eps=0.1)
 
 
+def paper_e1_samples(d, alpha=1e-5, eps=0.1, delta=0.01):
+    """The paper's sample count for its synthetic runs: its theory count for
+    R = d^2 scaled by alpha, ceil(alpha 1680 R ln(40 R) ln(1/delta) / eps)."""
+    R = d * d
+    return int(math.ceil(alpha * 1680 * R * math.log(40 * R) * math.log(1.0 / delta) / eps))
+
+
 def random_problem(I, R, seed=0, sigma=0.01, nrhs=1, heavy=0, scale=100.0):
     """Factors A(n) I_n x R_n i.i.d. N(0,1) (optionally `heavy` rows per mode scaled),
     x_true ~ N(0,1), b = K x_true + sigma e.  With nrhs > 1, b and x_true have
