@@ -95,7 +95,8 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree t
 // two >= R_{N-1}) first form P_{N-1}[p][r][q] in lane r: from P_{N-2}[parent(p)]
 // and the gathered factor row a_{N-2}[i(p)] (P_0 = x with the root as parent;
 // for N = 1 it is x itself; for a segment root it is the segment's own iterate).
-// Group gi then takes rows j0 + gi, j0 + gi + NGR, ... of p, four per step:
+// Group gi then takes rows j0 + gi, j0 + gi + NGR, ... of p, four per step (the
+// first four requested before the node's forward value, later ones one step ahead):
 // u_j = <a_{N-1}[i(j)], P_{N-1}[p]> - b_j in float64 and Q[p][r][q] +=
 // (Omega_j u_j) a_{N-1}[i(j)][r] in T; the groups' sums are added in a fixed order.
 template <int G, typename T>
@@ -117,6 +118,21 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
   for (int64_t task = blockIdx.x * wpb + (threadIdx.x >> 6); task < ntask; task += (int64_t)gridDim.x * wpb) {
     const int64_t p = task / nrhs;
     const int q = (int)(task - p * nrhs);
+    // the first four rows of this group are requested before the forward value
+    // of the node, so that both memory round trips overlap
+    const int j0 = tr.fchild[N - 1][p], j1 = tr.fchild[N - 1][p + 1];
+    double av[4], om[4], bb[4];
+    auto load4 = [&](int jb) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = jb + u * NGR;
+        const bool ok = jj < j1;
+        av[u] = (ok && ln) ? AL[(int64_t)jj * R + lane] : 0.0;
+        om[u] = ok ? Omega[jj] : 0.0;
+        bb[u] = ok ? bD[(int64_t)jj * nrhs + q] : 0.0;
+      }
+    };
+    load4(j0 + gi);
     // P_{N-1}[p][lane][q]
     double pv = 0.0;
     if (ln) {
@@ -134,17 +150,9 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
       }
     }
     T acc = 0;
-    const int j0 = tr.fchild[N - 1][p], j1 = tr.fchild[N - 1][p + 1];
-    int j = j0 + gi;
-    for (; j + 3 * NGR < j1; j += 4 * NGR) {
-      double av[4], y[4], om[4], bb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int jj = j + u * NGR;
-        av[u] = ln ? AL[(int64_t)jj * R + lane] : 0.0;
-        om[u] = Omega[jj];
-        bb[u] = bD[(int64_t)jj * nrhs + q];
-      }
+    // rows j0 + gi + NGR k, four per step; absent rows carry zero weight
+    for (int j = j0 + gi; j < j1; j += 4 * NGR) {
+      double y[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) y[u] = av[u] * pv;
 #pragma unroll
@@ -152,15 +160,15 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
 #pragma unroll
         for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, G);
       }
+      double t[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = fma((T)(om[u] * (y[u] - bb[u])), (T)av[u], acc);
-    }
-    for (; j < j1; j += NGR) {
-      const double a = ln ? AL[(int64_t)j * R + lane] : 0.0;
-      double y = a * pv;
-#pragma unroll
-      for (int o = G / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, G);
-      acc = fma((T)(Omega[j] * (y - bD[(int64_t)j * nrhs + q])), (T)a, acc);
+      for (int u = 0; u < 4; ++u) t[u] = om[u] * (y[u] - bb[u]);
+      const double a0 = av[0], a1 = av[1], a2 = av[2], a3 = av[3];
+      if (j + 4 * NGR < j1) load4(j + 4 * NGR);
+      acc = fma((T)t[0], (T)a0, acc);
+      acc = fma((T)t[1], (T)a1, acc);
+      acc = fma((T)t[2], (T)a2, acc);
+      acc = fma((T)t[3], (T)a3, acc);
     }
     // sum over the groups of the wave (fixed pairing order)
 #pragma unroll

@@ -262,3 +262,43 @@ def test_batched_autotune_keeps_results(gpu_lib):
         x64 = sketched_solution(w["As"], w["b"], sk["rows"], sk["ridx"], sk["Omega"], lams[i])
         assert rel_l2(x.cpu().numpy(), x64) < 1e-10, i
     h.close()
+
+
+def test_batched_edge_routes_and_statuses(gpu_lib):
+    """A large single-factor problem (single-problem path), a singular lambda = 0
+    problem large enough for the team (ESINGULAR, isolated), and the iteration
+    limit (WMAXITER for every problem, positive return status)."""
+    import torch
+    rng = np.random.default_rng(77)
+    A1 = rng.standard_normal((200000, 8))
+    b1 = A1 @ rng.standard_normal(8) + 0.01 * rng.standard_normal(200000)
+    w2 = workloads.random_problem((60, 50, 40), (3, 4, 3), seed=78, nrhs=2, sigma=0.05)
+    As3 = [A.copy() for A in w2["As"]]
+    As3[1][:, 1] = As3[1][:, 0]   # rank-deficient factor
+    w4 = workloads.random_problem((30, 20), (4, 3), seed=79, sigma=0.05)
+    probs = [([torch.tensor(A1, device="cuda")], torch.tensor(b1, device="cuda")),
+             ([torch.tensor(A, device="cuda") for A in w2["As"]], torch.tensor(w2["b"], device="cuda")),
+             ([torch.tensor(A, device="cuda") for A in As3], torch.tensor(w2["b"], device="cuda")),
+             ([torch.tensor(A, device="cuda") for A in w4["As"]], torch.tensor(w4["b"], device="cuda"))]
+    lams = [0.01, 0.02, 0.0, 0.1]
+    m = 150000
+    print("case batched edge routes", flush=True)
+    xs, infos, st = gpu_lib.kron_ridge_batched(probs, lams, m=m, seed=3, stream=30, tol=1e-12, max_iter=400,
+                                               raise_on_error=False)
+    assert st == -4, (st, infos)
+    assert infos[2]["status"] == "ESINGULAR"
+    dense = [([A1], b1), (w2["As"], w2["b"]), None, (w4["As"], w4["b"])]
+    for i in (0, 1, 3):
+        assert infos[i]["status"] == "OK", (i, infos[i])
+        As, b = dense[i]
+        sk = sketch(As, m, 3, 30 + i)
+        assert infos[i]["distinct_rows"] == len(sk["rows"])
+        x64 = sketched_solution(As, b, sk["rows"], sk["ridx"], sk["Omega"], lams[i])
+        assert rel_l2(xs[i].cpu().numpy(), x64) < 1e-10, i
+    # the iteration limit: every problem stops after two iterations
+    keep = [probs[1], probs[3]]
+    xs2, infos2, st2 = gpu_lib.kron_ridge_batched(keep, [0.02, 0.1], m=m, seed=3, stream=30, tol=1e-14, max_iter=2,
+                                                  raise_on_error=False)
+    assert st2 == 1, st2
+    assert [inf["status"] for inf in infos2] == ["WMAXITER", "WMAXITER"]
+    assert [inf["iters"] for inf in infos2] == [2, 2]
