@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -228,6 +229,7 @@ static kr_status make_geom(kr_handle h, const kr_problem* p, Geom* g) {
   for (int n = p->N - 2; n >= 0; --n) g->shift[n] = g->shift[n + 1] + g->bits[n + 1];
   for (int k = 1; k <= p->N; ++k) g->lshift[k] = g->shift[k - 1];
   g->lshift[0] = kb;
+  for (int n = 0; n < p->N; ++n) g->orig[n] = g->inv[n] = n;
   return KR_OK;
 }
 
@@ -1056,12 +1058,63 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   std::vector<double> cost(count);
   std::vector<char> route(count, QUEUE);
   int nteam_p = 0;
+  // Reordered modes (N >= 3): the tree's level-(N-2) products hold
+  // S_{N-2} x R_{N-2} R_{N-1} entries per right-hand side, S_{N-2} <= min(m,
+  // prod of the first N-2 sizes); the two modes that minimise that product go
+  // last (the others keep their order).  The sample is the same (the sampler
+  // draws by the caller's mode), and x and X_true are transposed in and out.
+  std::vector<kr_problem> pp(probs, probs + count);
+  std::vector<kr_response_gen> pgen(count);
+  std::vector<char> permuted(count, 0);
+  std::vector<std::array<int, KR_MAXN>> perm(count);
   for (int i = 0; i < count; ++i) {
     kr_opts oi = o;
     oi.stream = o.stream + (uint64_t)i;
     kr_status st = prepare_problem(h, &probs[i], lambda[i], eps, delta, oi, &G[i]);
     if (st != KR_OK) return st;
     if (!d_x[i]) KR_FAIL(h, KR_EINVAL, "x of problem %d is NULL", i);
+    const int N = probs[i].N;
+    for (int n = 0; n < KR_MAXN; ++n) perm[i][n] = n;
+    if (N >= 3) {
+      auto level_size = [&](int a, int b) {
+        double Ip = 1.0;
+        for (int n = 0; n < N; ++n)
+          if (n != a && n != b) Ip *= (double)probs[i].I[n];
+        return std::min(Ip, (double)G[i].m) * (double)probs[i].R[a] * (double)probs[i].R[b];
+      };
+      const double base = level_size(N - 2, N - 1);
+      double best = base;
+      int ba = N - 2, bb = N - 1;
+      for (int a = 0; a < N; ++a)
+        for (int b = a + 1; b < N; ++b) {
+          const double c = level_size(a, b);
+          if (c < best) { best = c; ba = a; bb = b; }
+        }
+      if (best * 1.25 < base) {
+        int k = 0;
+        for (int n = 0; n < N; ++n)
+          if (n != ba && n != bb) perm[i][k++] = n;
+        perm[i][k++] = ba;
+        perm[i][k++] = bb;
+        kr_problem& q = pp[i];
+        for (int n = 0; n < N; ++n) {
+          q.A[n] = probs[i].A[perm[i][n]];
+          q.I[n] = probs[i].I[perm[i][n]];
+          q.R[n] = probs[i].R[perm[i][n]];
+        }
+        if (probs[i].gen) {
+          pgen[i] = *probs[i].gen;
+          q.gen = &pgen[i];   // X_true is replaced by its transposed copy in pass 2
+        }
+        st = prepare_problem(h, &q, lambda[i], eps, delta, oi, &G[i]);
+        if (st != KR_OK) return st;
+        for (int n = 0; n < N; ++n) {
+          G[i].orig[n] = perm[i][n];
+          G[i].inv[perm[i][n]] = n;
+        }
+        permuted[i] = 1;
+      }
+    }
     for (int n = 0; n < G[i].N; ++n)
       if (G[i].R[n] > 16) KR_FAIL(h, KR_EUNSUPPORTED, "batched solves need R_n <= 16 (problem %d)", i);
     const Geom& g = G[i];
@@ -1111,6 +1164,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   for (int i : idx) {
     const int nb = (int)((G[i].m + SORT_TILE - 1) / SORT_TILE);
     total += solve_bytes(G[i], nb, nb, route[i] == TEAM) + 1024;
+    if (permuted[i]) total += 2 * 8 * (size_t)G[i].Rtot * G[i].nrhs + 1024;   // x and X_true in tree order
     if (route[i] == TEAM) nparts += (size_t)((G[i].Rtot + TM_THREADS - 1) / TM_THREADS) * G[i].nrhs * 2;
   }
   total += (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 4096;
@@ -1198,6 +1252,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   const bool enq = !replay;   // enqueue work (else only rebuild the host descriptors)
   // pass 2: carve, and enqueue every problem's setup and sketch
   size_t part_off = 0;
+  std::vector<double*> xtree(count, nullptr);   // tree-order iterate of a reordered problem
   for (int i : idx) {
     const Geom& g = G[i];
     const bool team = route[i] == TEAM;
@@ -1205,17 +1260,27 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     SolveBufs B{};
     Tree tr{};
     unsigned* bar = nullptr;
-    carve_solve(a, g, false, d_x[i], &T, &B, &tr, &bar, team);
+    double* xi = (double*)d_x[i];
+    double* Xt = nullptr;
+    if (permuted[i]) {
+      xi = a.take<double>((size_t)g.Rtot * g.nrhs);
+      Xt = a.take<double>((size_t)g.Rtot * g.nrhs);
+      xtree[i] = xi;
+      if (pp[i].gen) pgen[i].X_true = Xt;
+    }
+    carve_solve(a, g, false, xi, &T, &B, &tr, &bar, team);
     if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
     kr_opts oi = o;
     oi.stream = o.stream + (uint64_t)i;
     if (enq) {
-      st = launch_sketch(h, &probs[i], g, T, B, tr, oi, lambda[i] > 0.0);
+      if (permuted[i] && pp[i].gen)
+        KL(h, k_permute_modes, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g,
+           probs[i].gen->X_true, Xt, 1);
+      st = launch_sketch(h, &pp[i], g, T, B, tr, oi, lambda[i] > 0.0);
       if (st != KR_OK) return st;
       if (lambda[i] > 0.0)
         KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, s, T, g, lambda[i], B.dinv);
-      KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, (double*)d_x[i], g.Rtot * g.nrhs,
-         0.0);
+      KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, xi, g.Rtot * g.nrhs, 0.0);
       KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
     }
     BatchDesc& d = hd[slot[i]];
@@ -1303,6 +1368,10 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
         KLN(h, "k_batched_team", k_batched_team, dim3(grid), dim3(TM_THREADS), 0, s, ba);
       }
     }
+    for (int i : idx)   // reordered problems: x back to the caller's mode order
+      if (permuted[i])
+        KL(h, k_permute_modes, dim3(grid_for(G[i].Rtot * G[i].nrhs, 256, 1024)), dim3(256), 0, s, G[i],
+           (const double*)xtree[i], (double*)d_x[i], 0);
     KL(h, k_batch_collect, dim3(grid_for(nall, 256, 64)), dim3(256), 0, s, (const BatchDesc*)d_descs, nall, d_res);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(hres, d_res, nall * sizeof(BatchResult), hipMemcpyDeviceToHost, s));

@@ -34,6 +34,8 @@ struct Geom {
   int64_t m;
   int seg_root;         // 1: mode 0 indexes independent segments (no factor); the
                         //    level-1 node of segment i reads its own iterate row i
+  int orig[KR_MAXN];    // the caller's mode of tree mode n (identity unless the
+  int inv[KR_MAXN];     //    modes were reordered); inv is its inverse
 };
 
 // Per-mode results of the setup kernel.

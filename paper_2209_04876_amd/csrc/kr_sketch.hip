@@ -43,10 +43,12 @@ __global__ void __launch_bounds__(256) k_sample(ModeTables T, Geom g, uint64_t s
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.m;
        t += (int64_t)gridDim.x * blockDim.x) {
     uint64_t key = 0;
+    // the caller's mode o draws from word o % 4 of block (t, o / 4, row, 0); it is
+    // tree mode n = inv[o] (the same mode unless the modes were reordered)
     for (int grp = 0; grp * 4 < g.N; ++grp) {
       const u64x4 w = philox4x64_10((uint64_t)t, (uint64_t)grp, row, 0ull, seed, stream);
       for (int k = 0; k < 4 && grp * 4 + k < g.N; ++k) {
-        const int n = grp * 4 + k;
+        const int n = g.inv[grp * 4 + k];
         const uint64_t u = w.v[k] >> 32;
         // number of CDF entries <= u  (index i with C_{i-1} <= u < C_i)
         int lo = 0, hi = g.I[n];
@@ -330,7 +332,8 @@ __global__ void __launch_bounds__(256) k_rows(ModeTables T, Geom g, Tree tr, con
     const uint64_t key = tr.rkey[j];
     double den = (double)g.m;
     int64_t lin = 0;
-    for (int n = 0; n < g.N; ++n) {
+    for (int o = 0; o < g.N; ++o) {   // in the caller's mode order
+      const int n = g.inv[o];
       const int i = (int)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
       den = den * ((double)T.Q[n][i] * 0x1p-32);
       lin = lin * g.I[n] + i;
@@ -347,6 +350,32 @@ __global__ void __launch_bounds__(256) k_rows(ModeTables T, Geom g, Tree tr, con
     }
   }
   if (bad) atomicOr(flags, KR_FLAG_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// Reordered modes: a prod(R) x nrhs tensor between the caller's mode order and
+// the tree's.  to_tree: dst[r'][q] = src[r][q]; else dst[r][q] = src[r'][q], where
+// r' is the tree-order multi-index (r'_n = r_{orig[n]}).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_permute_modes(Geom g, const double* __restrict__ src,
+                                                       double* __restrict__ dst, int to_tree) {
+  const int N = g.N, nrhs = g.nrhs;
+  const int64_t total = g.Rtot * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rt = e / nrhs;
+    const int q = (int)(e - rt * nrhs);
+    int r[KR_MAXN];
+    int64_t rem = rt;
+    for (int n = N - 1; n >= 0; --n) {
+      r[n] = (int)(rem % g.R[n]);
+      rem /= g.R[n];
+    }
+    int64_t lin = 0;
+    for (int o = 0; o < N; ++o) lin = lin * g.R[g.inv[o]] + r[g.inv[o]];
+    if (to_tree) dst[e] = src[lin * nrhs + q];
+    else dst[lin * nrhs + q] = src[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -400,8 +429,11 @@ __global__ void __launch_bounds__(256) k_gen_rows(Geom g, Tree tr, const double*
     const int64_t j = e / nrhs;
     const int q = (int)(e - j * nrhs);
     const uint64_t key = tr.rkey[j];
-    int64_t lin = 0;
-    for (int n = 0; n < N; ++n) lin = lin * g.I[n] + (int64_t)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+    int64_t lin = 0;   // K's row index in the caller's mode order
+    for (int o = 0; o < N; ++o) {
+      const int n = g.inv[o];
+      lin = lin * g.I[n] + (int64_t)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+    }
     const double* __restrict__ aL = tr.arow[N] + j * RL;
     double y = 0.0;
     if (N == 1) {
