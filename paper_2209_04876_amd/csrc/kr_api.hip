@@ -61,6 +61,11 @@ struct kr_handle_s {
   std::vector<uint64_t> bgraph_sig;
   std::map<std::vector<int64_t>, std::pair<double, int>> tune;
   bool capturing = false;
+  // side streams (default priority) over which a batched call spreads the
+  // problems' setup and sketch, forked from and joined to the handle's stream
+  hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // last sketch, for kr_export_sketch
   bool has_sketch = false;
   Geom g{};
@@ -261,6 +266,11 @@ kr_status kr_destroy(kr_handle h) {
   if (h->h_small) hipHostFree(h->h_small);
   if (h->h_batch) hipHostFree(h->h_batch);
   if (h->bgraph) hipGraphExecDestroy(h->bgraph);
+  for (int k = 0; k < 4; ++k) {
+    if (h->side[k]) hipStreamDestroy(h->side[k]);
+    if (h->join_ev[k]) hipEventDestroy(h->join_ev[k]);
+  }
+  if (h->fork_ev) hipEventDestroy(h->fork_ev);
   delete h;
   return KR_OK;
 }
@@ -1226,6 +1236,13 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     }
     replay = h->bgraph && sig == h->bgraph_sig;
   }
+  if (!h->fork_ev) {
+    HIPCHK(h, hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    for (int k = 0; k < 4; ++k) {
+      HIPCHK(h, hipStreamCreateWithFlags(&h->side[k], hipStreamNonBlocking));
+      HIPCHK(h, hipEventCreateWithFlags(&h->join_ev[k], hipEventDisableTiming));
+    }
+  }
   struct CaptureGuard {   // ends an unfinished capture on every early return
     kr_handle h;
     hipStream_t s;
@@ -1250,10 +1267,22 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     h->capturing = true;
   }
   const bool enq = !replay;   // enqueue work (else only rebuild the host descriptors)
-  // pass 2: carve, and enqueue every problem's setup and sketch
+  // pass 2: carve, and enqueue every problem's setup and sketch, spread over the
+  // side streams (fork here, join before the persistent kernels)
   size_t part_off = 0;
   std::vector<double*> xtree(count, nullptr);   // tree-order iterate of a reordered problem
+  struct StreamRestore {   // the handle's stream back on every return
+    kr_handle h;
+    hipStream_t s;
+    ~StreamRestore() { h->stream = s; }
+  } stream_restore{h, s};
+  if (enq) {
+    HIPCHK(h, hipEventRecord(h->fork_ev, s));
+    for (int k = 0; k < 4; ++k) HIPCHK(h, hipStreamWaitEvent(h->side[k], h->fork_ev, 0));
+  }
+  int pidx = 0;
   for (int i : idx) {
+    h->stream = h->side[pidx++ & 3];
     const Geom& g = G[i];
     const bool team = route[i] == TEAM;
     ModeTables T{};
@@ -1274,14 +1303,14 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     oi.stream = o.stream + (uint64_t)i;
     if (enq) {
       if (permuted[i] && pp[i].gen)
-        KL(h, k_permute_modes, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, g,
+        KL(h, k_permute_modes, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, h->stream, g,
            probs[i].gen->X_true, Xt, 1);
       st = launch_sketch(h, &pp[i], g, T, B, tr, oi, lambda[i] > 0.0);
       if (st != KR_OK) return st;
       if (lambda[i] > 0.0)
-        KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, s, T, g, lambda[i], B.dinv);
-      KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, s, xi, g.Rtot * g.nrhs, 0.0);
-      KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
+        KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, h->stream, T, g, lambda[i], B.dinv);
+      KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, h->stream, xi, g.Rtot * g.nrhs, 0.0);
+      KL(h, k_zero_bytes, dim3(1), dim3(256), 0, h->stream, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
     }
     BatchDesc& d = hd[slot[i]];
     std::memset(&d, 0, sizeof(BatchDesc));
@@ -1308,6 +1337,12 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
       L.ticket = d_ticket + ti;
     }
   }
+  h->stream = s;
+  if (enq)
+    for (int k = 0; k < 4; ++k) {
+      HIPCHK(h, hipEventRecord(h->join_ev[k], h->side[k]));
+      HIPCHK(h, hipStreamWaitEvent(s, h->join_ev[k], 0));
+    }
   // queue problems largest first
   std::vector<int32_t> ord(nq);
   for (int k = 0; k < nq; ++k) ord[k] = k;
