@@ -410,14 +410,17 @@ __device__ bool ls_stage_factors(const BatchDesc& d, int i, double* fa, int* tag
   return true;
 }
 
-// The rows j0..j1 of one level-(N-2) subtree for one rhs q, one wave (see
-// ls_rows2 for the contraction): Bf holds the B operand of M = AV P in tile
-// layout; the adjoint accumulates into acc2 (Q[r' = gq + 4 v][c]).  Row data
-// streams in 64-row chunks with the next chunk in flight; AP and AL are the
-// mode-(N-2) and last-mode factors (LDS or global).
-__device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int j1, int q, const double* Bf,
+// The rows j0..j1 of one level-(N-2) subtree for right-hand sides q and, when
+// two, q + 1, one wave (see ls_rows2 for the contraction).  B0, B1 hold the B
+// operands of M = AV P in tile layout; the adjoints accumulate into acc0, acc1
+// (Q[r' = gq + 4 v][c]).  The two right-hand sides share each block's keys,
+// weights and factor-row gathers.  Row data streams in 64-row chunks with the
+// next chunk in flight; AP and AL are the mode-(N-2) and last-mode factors (LDS
+// or global).
+__device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int j1, int q, bool two,
+                                                const double* B0, const double* B1,
                                                 const double* __restrict__ AP, const double* __restrict__ AL,
-                                                int lane, pc_f64x4& acc2) {
+                                                int lane, pc_f64x4& acc0, pc_f64x4& acc1) {
   const Geom& g = d.g;
   const int N = g.N, nrhs = g.nrhs;
   const int RL = g.R[N - 1], RP = g.R[N - 2];
@@ -425,20 +428,21 @@ __device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int 
   const int shP = g.shift[N - 2], shL = g.shift[N - 1];
   const uint64_t mP = (1ull << g.bits[N - 2]) - 1ull, mL = (1ull << g.bits[N - 1]) - 1ull;
   const uint64_t* __restrict__ keys = d.tr.rkey;
-  auto load_chunk = [&](int jc, uint64_t& k, double& om, double& bq) {
+  auto load_chunk = [&](int jc, uint64_t& k, double& om, double& b0, double& b1) {
     const int j = jc + lane;
     const bool ok = j < j1;
     k = ok ? keys[j] : 0ull;
     om = ok ? d.Omega[j] : 0.0;
-    bq = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
+    b0 = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
+    b1 = (ok && two) ? d.bD[(int64_t)j * nrhs + q + 1] : 0.0;
   };
   uint64_t kc = 0;
-  double oc = 0.0, bc = 0.0;
-  if (j0 < j1) load_chunk(j0, kc, oc, bc);
+  double oc = 0.0, bc0 = 0.0, bc1 = 0.0;
+  if (j0 < j1) load_chunk(j0, kc, oc, bc0, bc1);
   for (int jc = j0; jc < j1; jc += 64) {
     uint64_t kn = 0;
-    double on = 0.0, bn = 0.0;
-    if (jc + 64 < j1) load_chunk(jc + 64, kn, on, bn);
+    double on = 0.0, bn0 = 0.0, bn1 = 0.0;
+    if (jc + 64 < j1) load_chunk(jc + 64, kn, on, bn0, bn1);
     const int nblk = (j1 - jc) >= 64 ? 4 : (j1 - jc + 15) / 16;
     for (int ub = 0; ub < nblk; ++ub) {
       const int jb = jc + 16 * ub;
@@ -451,16 +455,20 @@ __device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int 
         const int r1 = 4 * ks + gq;
         Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
       }
-      pc_f64x4 M = {0.0, 0.0, 0.0, 0.0};
+      pc_f64x4 M0 = {0.0, 0.0, 0.0, 0.0}, M1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) M = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], Bf[ks], M, 0, 0, 0);
-      double an[4], Aa[4], om[4], bq[4], W[4], y[4];
+      for (int ks = 0; ks < 4; ++ks) {
+        M0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], B0[ks], M0, 0, 0, 0);
+        if (two) M1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], B1[ks], M1, 0, 0, 0);
+      }
+      double an[4], Aa[4], om[4], y0[4], y1[4], W0[4], W1[4], b0[4], b1[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int src = 16 * ub + gq + 4 * u;
         const uint64_t kd = __shfl(kc, src, 64);
         om[u] = __shfl(oc, src, 64);
-        bq[u] = __shfl(bc, src, 64);
+        b0[u] = __shfl(bc0, src, 64);
+        b1[u] = __shfl(bc1, src, 64);
         const bool vd = jb + gq + 4 * u < j1;
         const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
         an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
@@ -468,20 +476,33 @@ __device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int 
         if (!vd) om[u] = 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) y[u] = an[u] * M[u];
+      for (int u = 0; u < 4; ++u) {
+        y0[u] = an[u] * M0[u];
+        y1[u] = an[u] * M1[u];
+      }
 #pragma unroll
       for (int o = 8; o > 0; o >>= 1) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, 16);
+        for (int u = 0; u < 4; ++u) {
+          y0[u] += __shfl_xor(y0[u], o, 16);
+          y1[u] += __shfl_xor(y1[u], o, 16);
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) W[u] = an[u] * (om[u] * (y[u] - bq[u]));
+      for (int u = 0; u < 4; ++u) {
+        W0[u] = an[u] * (om[u] * (y0[u] - b0[u]));
+        W1[u] = an[u] * (om[u] * (y1[u] - b1[u]));
+      }
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W[ks], acc2, 0, 0, 0);
+      for (int ks = 0; ks < 4; ++ks) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W0[ks], acc0, 0, 0, 0);
+        if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W1[ks], acc1, 0, 0, 0);
+      }
     }
     kc = kn;
     oc = on;
-    bc = bn;
+    bc0 = bn0;
+    bc1 = bn1;
   }
 }
 
@@ -495,11 +516,12 @@ __device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int 
 //   u_j = Omega_j (y_j - b_j)
 //   Q += AV^T diag(u) AN          (the adjoint of both levels, one MFMA chain)
 // and Q is Q_{N-2}[p][:, :, q].  Neither level-(N-1) product is formed.  Lane
-// l = 16 g + c: c indexes the tile's columns, g its row quarter.  Row data
-// (keys, weights, responses) streams in chunks of 64 rows, one row per lane, and
-// reaches the tile layouts by shuffles; the next chunk is loaded while the
-// current one is processed.  The factor rows come from LDS (fa) when the
-// workgroup has staged them, else from global memory (fa = nullptr).
+// l = 16 g + c: c indexes the tile's columns, g its row quarter.  Right-hand
+// sides go in pairs (ls_subtree_rows): row data (keys, weights, responses)
+// streams in chunks of 64 rows, one row per lane, and reaches the tile layouts
+// by shuffles; the next chunk is loaded while the current one is processed.
+// The factor rows come from LDS (fa) when the workgroup has staged them, else
+// from global memory (fa = nullptr).
 __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const double* fa) {
   const Geom& g = d.g;
   const int N = g.N, nrhs = g.nrhs;
@@ -514,9 +536,6 @@ __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const do
   const int j0 = d.tr.fchild[N - 1][c0], j1 = d.tr.fchild[N - 1][c1];
   const double* __restrict__ AP = fa ? fa : d.T.A[N - 2];
   const double* __restrict__ AL = fa ? fa + LS_FACT : d.T.A[N - 1];
-  const int shP = g.shift[N - 2], shL = g.shift[N - 1];
-  const uint64_t mP = (1ull << g.bits[N - 2]) - 1ull, mL = (1ull << g.bits[N - 1]) - 1ull;
-  const uint64_t* __restrict__ keys = d.tr.rkey;
   double* __restrict__ Qo = d.Q[N - 2];
   // B operand of M = AV P for rhs q: P[r' = 4 ks + gq][c]
   auto load_B = [&](int q, double* B) {
@@ -533,89 +552,16 @@ __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const do
       if (r1 < RP && c < RL) Qo[pb + ((int64_t)r1 * RL + c) * nrhs + q] = acc2[u];
     }
   };
-  if (j1 - j0 <= 64) {
-    // the whole subtree in one chunk: keys and weights are loaded once, and two
-    // right-hand sides share each block's factor-row gathers (two independent
-    // MFMA chains per wave)
-    const int j = j0 + lane;
-    const bool ok = j < j1;
-    const uint64_t kc = ok ? keys[j] : 0ull;
-    const double oc = ok ? d.Omega[j] : 0.0;
-    const int nblk = (j1 - j0 + 15) / 16;
-    for (int q = 0; q < nrhs; q += 2) {
-      const bool two = q + 1 < nrhs;
-      double B0[4], B1[4] = {0.0, 0.0, 0.0, 0.0};
-      load_B(q, B0);
-      if (two) load_B(q + 1, B1);
-      const double bc0 = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
-      const double bc1 = (ok && two) ? d.bD[(int64_t)j * nrhs + q + 1] : 0.0;
-      pc_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-      for (int ub = 0; ub < nblk; ++ub) {
-        const int jb = j0 + 16 * ub;
-        const uint64_t ka = __shfl(kc, 16 * ub + c, 64);
-        const bool va = jb + c < j1;
-        const int iPa = (int)((ka >> shP) & mP);
-        double Af[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int r1 = 4 * ks + gq;
-          Af[ks] = (va && r1 < RP) ? AP[iPa * RP + r1] : 0.0;
-        }
-        pc_f64x4 M0 = {0.0, 0.0, 0.0, 0.0}, M1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          M0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], B0[ks], M0, 0, 0, 0);
-          M1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[ks], B1[ks], M1, 0, 0, 0);
-        }
-        double an[4], Aa[4], om[4], y0[4], y1[4], W0[4], W1[4], b0[4], b1[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int src = 16 * ub + gq + 4 * u;
-          const uint64_t kd = __shfl(kc, src, 64);
-          om[u] = __shfl(oc, src, 64);
-          b0[u] = __shfl(bc0, src, 64);
-          b1[u] = __shfl(bc1, src, 64);
-          const bool vd = jb + gq + 4 * u < j1;
-          const int iPd = (int)((kd >> shP) & mP), iLd = (int)((kd >> shL) & mL);
-          an[u] = (vd && c < RL) ? AL[iLd * RL + c] : 0.0;
-          Aa[u] = (vd && c < RP) ? AP[iPd * RP + c] : 0.0;
-          if (!vd) om[u] = 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          y0[u] = an[u] * M0[u];
-          y1[u] = an[u] * M1[u];
-        }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            y0[u] += __shfl_xor(y0[u], o, 16);
-            y1[u] += __shfl_xor(y1[u], o, 16);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          W0[u] = an[u] * (om[u] * (y0[u] - b0[u]));
-          W1[u] = an[u] * (om[u] * (y1[u] - b1[u]));
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W0[ks], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Aa[ks], W1[ks], acc1, 0, 0, 0);
-        }
-      }
-      store(q, acc0);
-      if (two) store(q + 1, acc1);
-    }
-    return;
-  }
-  for (int q = 0; q < nrhs; ++q) {
-    double Bf[4];
-    load_B(q, Bf);
-    pc_f64x4 acc2 = {0.0, 0.0, 0.0, 0.0};
-    ls_subtree_rows(d, j0, j1, q, Bf, AP, AL, lane, acc2);
-    store(q, acc2);
+  // right-hand sides in pairs; each pair walks the subtree's rows once
+  for (int q = 0; q < nrhs; q += 2) {
+    const bool two = q + 1 < nrhs;
+    double B0[4], B1[4] = {0.0, 0.0, 0.0, 0.0};
+    load_B(q, B0);
+    if (two) load_B(q + 1, B1);
+    pc_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    ls_subtree_rows(d, j0, j1, q, two, B0, B1, AP, AL, lane, acc0, acc1);
+    store(q, acc0);
+    if (two) store(q + 1, acc1);
   }
 }
 
