@@ -417,9 +417,16 @@ __device__ bool ls_stage_factors(const BatchDesc& d, int i, double* fa, int* tag
 // weights and factor-row gathers.  Row data streams in 64-row chunks with the
 // next chunk in flight; AP and AL are the mode-(N-2) and last-mode factors (LDS
 // or global).
+typedef const __attribute__((address_space(1))) double* ls_gd;     // global
+typedef const __attribute__((address_space(1))) uint64_t* ls_gu;   // global
+typedef const __attribute__((address_space(3))) double* ls_ld;     // LDS
+
+// FP is ls_ld (factors staged in LDS) or ls_gd: a pointer of one address space,
+// so that the gathers compile to ds_read or global_load (a generic pointer would
+// make them flat loads, whose waits also drain the streamed rows in flight).
+template <typename FP>
 __device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int j1, int q, bool two,
-                                                const double* B0, const double* B1,
-                                                const double* __restrict__ AP, const double* __restrict__ AL,
+                                                const double* B0, const double* B1, FP AP, FP AL,
                                                 int lane, pc_f64x4& acc0, pc_f64x4& acc1) {
   const Geom& g = d.g;
   const int N = g.N, nrhs = g.nrhs;
@@ -427,14 +434,16 @@ __device__ __forceinline__ void ls_subtree_rows(const BatchDesc& d, int j0, int 
   const int c = lane & 15, gq = lane >> 4;
   const int shP = g.shift[N - 2], shL = g.shift[N - 1];
   const uint64_t mP = (1ull << g.bits[N - 2]) - 1ull, mL = (1ull << g.bits[N - 1]) - 1ull;
-  const uint64_t* __restrict__ keys = d.tr.rkey;
+  const ls_gu keys = (ls_gu)d.tr.rkey;
+  const ls_gd Om = (ls_gd)d.Omega;
+  const ls_gd bD = (ls_gd)d.bD;
   auto load_chunk = [&](int jc, uint64_t& k, double& om, double& b0, double& b1) {
     const int j = jc + lane;
     const bool ok = j < j1;
     k = ok ? keys[j] : 0ull;
-    om = ok ? d.Omega[j] : 0.0;
-    b0 = ok ? d.bD[(int64_t)j * nrhs + q] : 0.0;
-    b1 = (ok && two) ? d.bD[(int64_t)j * nrhs + q + 1] : 0.0;
+    om = ok ? Om[j] : 0.0;
+    b0 = ok ? bD[(int64_t)j * nrhs + q] : 0.0;
+    b1 = (ok && two) ? bD[(int64_t)j * nrhs + q + 1] : 0.0;
   };
   uint64_t kc = 0;
   double oc = 0.0, bc0 = 0.0, bc1 = 0.0;
@@ -534,8 +543,6 @@ __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const do
   const double* __restrict__ Pn2 = d.P[N - 2];
   const int c0 = d.tr.fchild[N - 2][p], c1 = d.tr.fchild[N - 2][p + 1];
   const int j0 = d.tr.fchild[N - 1][c0], j1 = d.tr.fchild[N - 1][c1];
-  const double* __restrict__ AP = fa ? fa : d.T.A[N - 2];
-  const double* __restrict__ AL = fa ? fa + LS_FACT : d.T.A[N - 1];
   double* __restrict__ Qo = d.Q[N - 2];
   // B operand of M = AV P for rhs q: P[r' = 4 ks + gq][c]
   auto load_B = [&](int q, double* B) {
@@ -559,7 +566,10 @@ __device__ __forceinline__ void ls_rows2(const BatchDesc& d, int64_t v, const do
     load_B(q, B0);
     if (two) load_B(q + 1, B1);
     pc_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    ls_subtree_rows(d, j0, j1, q, two, B0, B1, AP, AL, lane, acc0, acc1);
+    if (fa)
+      ls_subtree_rows(d, j0, j1, q, two, B0, B1, (ls_ld)fa, (ls_ld)(fa + LS_FACT), lane, acc0, acc1);
+    else
+      ls_subtree_rows(d, j0, j1, q, two, B0, B1, (ls_gd)d.T.A[N - 2], (ls_gd)d.T.A[N - 1], lane, acc0, acc1);
     store(q, acc0);
     if (two) store(q + 1, acc1);
   }
