@@ -1,5 +1,5 @@
 // Batched Algorithm 2: many independent ridge problems of uneven N, I_n, R_n and
-// right-hand sides in one persistent launch.
+// right-hand sides, iterated by two persistent kernels.
 //
 // Each problem's setup and sketch (Gram, leverage, sampling, sort, sample tree,
 // gathered rows) is enqueued with the single-problem kernels.  The Richardson
@@ -14,9 +14,11 @@
 //          rows, adjoint levels, root, one stage per preconditioner mode product,
 //          update); at every step each active problem runs its next stage, and
 //          the work items of all those stages form one index space that the team
-//          strides over.  A team-wide barrier separates steps.  Problems with
-//          short stage lists simply iterate more often; a problem leaves the
-//          index space when its stopping rule holds.
+//          strides over (workgroup w takes item blocks w, w + teams, ...: every
+//          workgroup samples every problem, which balances stages of very
+//          different cost).  A team-wide barrier separates steps.  Problems
+//          with short stage lists simply iterate more often; a problem leaves
+//          the index space when its stopping rule holds.
 //
 // Every output of a stage has one owning thread (or lane group) with a fixed
 // summation order, and the update's norms are reduced in chunk order, so results
@@ -826,7 +828,7 @@ __device__ void batched_team(const BatchArgs& a, unsigned rank, unsigned nteam, 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int64_t t = 0;; ++t) {
     // work items of every active problem's stage at step t (multiples of
-    // BT_THREADS), and their exclusive prefix sums
+    // TM_THREADS), and their exclusive prefix sums
     if (threadIdx.x == 0) { any_s = 0; off[0] = 0; }
     __syncthreads();
     int64_t carry = 0;

@@ -1,5 +1,5 @@
-"""GPU parity of kron_ridge_batched (many uneven problems, one persistent
-iteration launch) against the oracle.
+"""GPU parity of kron_ridge_batched (many uneven problems; their iterations in
+a queue kernel and a team kernel, both persistent) against the oracle.
 
 Problem i of a batch draws its sample with Philox stream `stream + i`; the
 oracle sketches each problem from its own leverage tables with the same key and
@@ -102,9 +102,9 @@ def test_batched_rlnr_rule_and_larger_problems(gpu_lib):
 
 
 def test_batched_mixes_large_and_small_problems(gpu_lib):
-    """A problem with many sampled rows takes the multi-kernel path inside the
-    batch; the small ones run in the persistent launch.  Results must not depend
-    on the route."""
+    """A problem with many sampled rows is iterated by the team, the small ones
+    by the queue kernel; the large one alone through the single-problem entry
+    point reaches the same minimiser."""
     import torch
     big = workloads.random_problem((300, 300), (8, 8), seed=41, nrhs=2, sigma=0.05)
     probs = [(big["As"], big["b"], 0.05, 0)]
