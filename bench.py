@@ -20,7 +20,8 @@ eps = 0.1, m = ceil(R ln R / eps) = 340,696, Philox seed 0.
 Also times the batched ridge workload (256 uneven problems per call; the
 "batched" object of the line; --no-batched skips it) and, as context, the
 paper's own synthetic workload at its largest cell ("paper_e1_context";
---no-paper-e1 skips it).
+--no-paper-e1 skips it) and Tucker ALS on the 400^3 tensor ("tucker"; factor
+updates of Algorithm 3 and the core update; --no-tucker skips it).
 
 Prints one JSON line.  --gpus above 1 is refused (single-GPU build).
 """
@@ -210,6 +211,30 @@ def paper_e1_leg(kr, torch, n=16384, d=64, steps=5):
                     "(status WMAXITER), while the loss stays within 1.1 OPT"}
 
 
+def tucker_leg(kr, torch):
+    """Tucker ALS (Algorithm 1) on the 400^3 FP32 tensor of rank (16, 16, 16) plus
+    1% noise: per sweep, the three factor updates of Algorithm 3 (a fresh sketch of
+    m = ceil(256 ln 256 / 0.1) draws per factor row) and the core update by
+    Algorithm 2 (m = ceil(4096 ln 4096 / 0.1), ridge 1e-3), then the relative
+    reconstruction error; 10 sweeps from the seeded random start."""
+    import workloads
+    w = workloads.tucker_tensor()
+    X = torch.from_numpy(w["X"]).cuda()
+    G0 = torch.tensor(w["G_init"], device="cuda")
+    A0 = [torch.tensor(A, device="cuda") for A in w["A_init"]]
+    kr.tucker_als(X, G0, A0, w["lam"], 1, eps=w["eps"], m_core=w["m_core"], m_factor=w["m_factor"], seed=w["seed"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G, As, trace = kr.tucker_als(X, G0, A0, w["lam"], w["sweeps"], eps=w["eps"], m_core=w["m_core"],
+                                 m_factor=w["m_factor"], seed=w["seed"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": w["name"] + ", FP32, 1%% noise, lambda = 1e-3, eps = 0.1, m_factor = %d per row, "
+                                     "m_core = %d, %d sweeps" % (w["m_factor"], w["m_core"], w["sweeps"]),
+            "ms_per_sweep": round(1000.0 * dt / w["sweeps"], 3), "sweeps_per_s": round(w["sweeps"] / dt, 3),
+            "rre_per_sweep": [float("%.6g" % r) for r in trace], "dtype": "f64 (FP32 tensor)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +245,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ridge workload")
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--no-paper-e1", action="store_true", help="skip the paper's own workload (context)")
+    ap.add_argument("--no-tucker", action="store_true", help="skip the Tucker ALS workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -362,6 +388,8 @@ def main():
         out["batched"] = batched_leg(kr, torch, args.batched_steps)
     if not args.no_paper_e1:
         out["paper_e1_context"] = paper_e1_leg(kr, torch)
+    if not args.no_tucker:
+        out["tucker"] = tucker_leg(kr, torch)
     if not args.no_cpu_baseline:
         del tA, tb
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
