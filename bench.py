@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--no-paper-e1", action="store_true", help="skip the paper's own workload (context)")
     ap.add_argument("--no-tucker", action="store_true", help="skip the Tucker ALS workload")
+    ap.add_argument("--only", choices=["batched", "paper-e1", "tucker"], default=None,
+                    help="run only this leg and print its JSON object (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -270,6 +272,13 @@ def main():
 
     import paper_2209_04876_amd as kr
     import workloads
+
+    if args.only:
+        leg = {"batched": lambda: batched_leg(kr, torch, args.batched_steps),
+               "paper-e1": lambda: paper_e1_leg(kr, torch),
+               "tucker": lambda: tucker_leg(kr, torch)}[args.only]
+        print(json.dumps(leg()), flush=True)
+        return
 
     t = time.perf_counter()
     w = workloads.skewed_regression()
