@@ -133,21 +133,35 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
       }
     };
     load4(j0 + gi);
-    // P_{N-1}[p][lane][q]
+    // P_{N-1}[p][lane][q]; from a parent level, group gi sums the terms
+    // s = gi, gi + NGR, ... of the contraction over R_{N-2} and the groups' partial
+    // sums are combined by a butterfly (the same rounding in every group)
     double pv = 0.0;
-    if (ln) {
-      if (N == 1) {
-        pv = Pprev[(int64_t)lane * nrhs + q];
-      } else if (N == 2 && g.seg_root) {
-        pv = Pprev[((int64_t)tr.idx[1][p] * R + lane) * nrhs + q];
-      } else {
-        const int Rp = g.R[N - 2];
-        const int64_t par = N >= 3 ? tr.parent[N - 1][p] : 0;
-        const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
-        const double* __restrict__ src = Pprev + par * (int64_t)Rp * R * nrhs + (int64_t)lane * nrhs + q;
-        const int64_t step = (int64_t)R * nrhs;
-        pv = dot_batched(a, src, step, Rp);
+    if (N == 1) {
+      if (ln) pv = Pprev[(int64_t)lane * nrhs + q];
+    } else if (N == 2 && g.seg_root) {
+      if (ln) pv = Pprev[((int64_t)tr.idx[1][p] * R + lane) * nrhs + q];
+    } else {
+      const int Rp = g.R[N - 2];
+      const int64_t par = N >= 3 ? tr.parent[N - 1][p] : 0;
+      const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
+      const int64_t step = (int64_t)R * nrhs;
+      const double* __restrict__ src = Pprev + par * (int64_t)Rp * step + (int64_t)lane * nrhs + q;
+      if (ln) {
+        for (int s0 = gi; s0 < Rp; s0 += 4 * NGR) {
+          double as[4], sv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * NGR;
+            as[u] = s < Rp ? a[s] : 0.0;
+            sv[u] = s < Rp ? src[(int64_t)s * step] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pv = fma(as[u], sv[u], pv);
+        }
       }
+#pragma unroll
+      for (int o = G; o < 64; o <<= 1) pv += __shfl_xor(pv, o, 64);
     }
     T acc = 0;
     // rows j0 + gi + NGR k, four per step; absent rows carry zero weight
