@@ -173,6 +173,10 @@ static int ceil_log2(int64_t v) {
   return b;
 }
 
+// workgroups of the rows kernel at most (4 waves each; 1280 and 2048 measured no better)
+#ifndef KR_ROWS_GRID_CAP
+#define KR_ROWS_GRID_CAP 1024
+#endif
 static int64_t grid_for(int64_t work, int64_t threads, int64_t cap = 4096) {
   int64_t b = (work + threads - 1) / threads;
   return std::max<int64_t>(1, std::min<int64_t>(b, cap));
@@ -505,7 +509,7 @@ static int launch_level_products(kr_handle h, const ModeTables& TT, const Geom& 
     T* qlast = Q[g.N - 1];
     const double* plast = P[g.N >= 2 ? g.N - 2 : 0];
     // one wave per (node, rhs), grid-stride, at most a few workgroups per CU
-    const dim3 rg(grid_for(tr.ncnt[g.N - 1] * g.nrhs, 4, 1024));
+    const dim3 rg(grid_for(tr.ncnt[g.N - 1] * g.nrhs, 4, KR_ROWS_GRID_CAP));
     switch (G) {
       case 8:
         KLN(h, f32 ? "k_rows_adj<8,f32>" : "k_rows_adj<8>", (k_rows_adj<8, T>), rg, dim3(256), 0, s, TT, g, tr, plast,

@@ -57,6 +57,54 @@ __device__ __forceinline__ double dot_batched(const double* __restrict__ a, cons
   return acc;
 }
 
+// base[byte offset]: a 32-bit offset from a (wave-uniform) base pointer.
+__device__ __forceinline__ double ld_at(const double* __restrict__ base, unsigned off) {
+  return *(const double*)((const char*)base + off);
+}
+
+// Lane exchanges of float64 values inside a wave, without LDS address registers:
+// DPP moves within a row of 16 lanes, swizzles within 32, a permute across 32.
+template <int CTRL> __device__ __forceinline__ double dpp64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int PAT> __device__ __forceinline__ double swz64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(uint32_t)b, PAT);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(uint32_t)(b >> 32), PAT);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// the value of lane (lane ^ O)
+template <int O> __device__ __forceinline__ double xor_lane(double v) {
+  if constexpr (O == 1) return dpp64<0xB1>(v);        // quad_perm [1,0,3,2]
+  else if constexpr (O == 2) return dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  else if constexpr (O == 8) return dpp64<0x128>(v);  // row_ror:8
+  else if constexpr (O == 32) return __shfl_xor(v, 32, 64);
+  else return swz64<0x1F | (O << 10)>(v);             // bit-mode swizzle, xor mask O
+}
+// Sum over each aligned group of G lanes; every lane of a group ends with the same
+// bits (each step adds a pair in either order, and addition commutes).
+template <int G> __device__ __forceinline__ double grp_sum(double v) {
+  if constexpr (G > 1) v += xor_lane<1>(v);
+  if constexpr (G > 2) v += xor_lane<2>(v);
+  if constexpr (G > 4) v += dpp64<0x141>(v);  // row_half_mirror: the other quad of 8 lanes
+  if constexpr (G > 8) v += xor_lane<8>(v);
+  if constexpr (G > 16) v += xor_lane<16>(v);
+  if constexpr (G > 32) v += xor_lane<32>(v);
+  return v;
+}
+// Sum of lane l's value over the 64 / G groups (lanes l ^ G k), in the order G, 2G, ...
+template <int G> __device__ __forceinline__ double xgrp_sum(double v) {
+  static_assert(G >= 4 && G <= 64, "group width");
+  if constexpr (G <= 4) v += xor_lane<4>(v);
+  if constexpr (G <= 8) v += xor_lane<8>(v);
+  if constexpr (G <= 16) v += xor_lane<16>(v);
+  if constexpr (G <= 32) v += xor_lane<32>(v);
+  return v;
+}
+
 // The level kernels do not test for convergence: the host stops launching them,
 // and the few passes launched after the last iteration only rewrite scratch
 // levels (the preconditioner kernel leaves x unchanged then).  Level counts come
@@ -95,10 +143,16 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree t
 // two >= R_{N-1}) first form P_{N-1}[p][r][q] in lane r: from P_{N-2}[parent(p)]
 // and the gathered factor row a_{N-2}[i(p)] (P_0 = x with the root as parent;
 // for N = 1 it is x itself; for a segment root it is the segment's own iterate).
-// Group gi then takes rows j0 + gi, j0 + gi + NGR, ... of p, four per step (the
-// first four requested before the node's forward value, later ones one step ahead):
+// Group gi then takes rows j0 + gi, j0 + gi + NGR, ... of p, KR_ROWS_PER_STEP per
+// step (the first step's requested before the node's forward value):
 // u_j = <a_{N-1}[i(j)], P_{N-1}[p]> - b_j in float64 and Q[p][r][q] +=
 // (Omega_j u_j) a_{N-1}[i(j)][r] in T; the groups' sums are added in a fixed order.
+// Measured: the wave-uniform task with scalar row bases, DPP group sums and one
+// register set (92 VGPRs, 5 waves per SIMD) beat a prefetching second set; the
+// compiler waits for all loads at the loop head either way.
+#ifndef KR_ROWS_PER_STEP
+#define KR_ROWS_PER_STEP 4
+#endif
 template <int G, typename T>
 __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr,
                                                  const double* __restrict__ Pprev,
@@ -107,6 +161,7 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
                                                  T* __restrict__ Qout,
                                                  const IterState* __restrict__ st) {
   constexpr int NGR = 64 / G;
+  constexpr int RPS = KR_ROWS_PER_STEP;
   const int N = g.N, nrhs = g.nrhs;
   const int R = g.R[N - 1];
   const double* __restrict__ AL = tr.arow[N];
@@ -115,24 +170,45 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
   const int gi = (threadIdx.x & 63) / G;
   const bool ln = lane < R;
   const int64_t wpb = blockDim.x >> 6;
-  for (int64_t task = blockIdx.x * wpb + (threadIdx.x >> 6); task < ntask; task += (int64_t)gridDim.x * wpb) {
+  // the task index is wave-uniform, so the node's bounds and row bases live in
+  // scalar registers and every lane addresses its rows by a small 32-bit offset
+  const int64_t w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (int64_t task = blockIdx.x * wpb + w; task < ntask; task += (int64_t)gridDim.x * wpb) {
     const int64_t p = task / nrhs;
     const int q = (int)(task - p * nrhs);
-    // the first four rows of this group are requested before the forward value
-    // of the node, so that both memory round trips overlap
     const int j0 = tr.fchild[N - 1][p], j1 = tr.fchild[N - 1][p + 1];
-    double av[4], om[4], bb[4];
-    auto load4 = [&](int jb) {
+    const double* __restrict__ ab = AL + (int64_t)j0 * R;
+    const double* __restrict__ ob = Omega + j0;
+    const double* __restrict__ bp = bD + (int64_t)j0 * nrhs + q;
+    // Steps of RPS NGR rows; group gi takes rows gi + NGR u (u < RPS) of a step,
+    // all requested at once.  The loads are unconditional: an absent row re-reads
+    // the step's first row and gets weight 0 where it is used, and lanes r >= R
+    // re-read entry R - 1, which meets P_{N-1} = 0 there.  32-bit offsets from
+    // the scalar bases.
+    const int nrow = j1 - j0;
+    if (nrow <= 0) {  // a node always has rows; kept for safety (uniform branch)
+      if (gi == 0 && ln) Qout[(p * R + lane) * nrhs + q] = (T)0;
+      continue;
+    }
+    const unsigned lc = ln ? lane : R - 1;
+    auto load_step = [&](double (&av)[RPS], double (&om)[RPS], double (&bb)[RPS], int k) {
+      const int nl = nrow - k * RPS * NGR;
+      const double* __restrict__ abk = ab + (int64_t)k * RPS * NGR * R;
+      const double* __restrict__ obk = ob + k * RPS * NGR;
+      const double* __restrict__ bpk = bp + (int64_t)k * RPS * NGR * nrhs;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int jj = jb + u * NGR;
-        const bool ok = jj < j1;
-        av[u] = (ok && ln) ? AL[(int64_t)jj * R + lane] : 0.0;
-        om[u] = ok ? Omega[jj] : 0.0;
-        bb[u] = ok ? bD[(int64_t)jj * nrhs + q] : 0.0;
+      for (int u = 0; u < RPS; ++u) {
+        const int jl = gi + u * NGR;
+        const unsigned jc = jl < nl ? (unsigned)jl : 0u;
+        av[u] = ld_at(abk, (jc * (unsigned)R + lc) * 8u);
+        om[u] = ld_at(obk, jc * 8u);
+        bb[u] = ld_at(bpk, jc * (unsigned)nrhs * 8u);
       }
     };
-    load4(j0 + gi);
+    double aA[RPS], oA[RPS], bA[RPS];
+    // the first step's rows are requested before the forward value of the node,
+    // so that both memory round trips overlap
+    load_step(aA, oA, bA, 0);
     // P_{N-1}[p][lane][q]; from a parent level, group gi sums the terms
     // s = gi, gi + NGR, ... of the contraction over R_{N-2} and the groups' partial
     // sums are combined by a butterfly (the same rounding in every group)
@@ -146,7 +222,7 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
       const int64_t par = N >= 3 ? tr.parent[N - 1][p] : 0;
       const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
       const int64_t step = (int64_t)R * nrhs;
-      const double* __restrict__ src = Pprev + par * (int64_t)Rp * step + (int64_t)lane * nrhs + q;
+      const double* __restrict__ src = Pprev + par * (int64_t)Rp * step + q;
       if (ln) {
         for (int s0 = gi; s0 < Rp; s0 += 4 * NGR) {
           double as[4], sv[4];
@@ -154,35 +230,31 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
           for (int u = 0; u < 4; ++u) {
             const int s = s0 + u * NGR;
             as[u] = s < Rp ? a[s] : 0.0;
-            sv[u] = s < Rp ? src[(int64_t)s * step] : 0.0;
+            sv[u] = s < Rp ? src[(int64_t)s * step + lane * nrhs] : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) pv = fma(as[u], sv[u], pv);
         }
       }
-#pragma unroll
-      for (int o = G; o < 64; o <<= 1) pv += __shfl_xor(pv, o, 64);
+      pv = xgrp_sum<G>(pv);
     }
     T acc = 0;
-    // rows j0 + gi + NGR k, four per step; absent rows carry zero weight
-    for (int j = j0 + gi; j < j1; j += 4 * NGR) {
-      double y[4];
+    auto step = [&](const double (&av)[RPS], const double (&om)[RPS], const double (&bb)[RPS], int k) {
+      const int nl = nrow - k * RPS * NGR;
+      double y[RPS];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) y[u] = av[u] * pv;
+      for (int u = 0; u < RPS; ++u) y[u] = grp_sum<G>(av[u] * pv);
 #pragma unroll
-      for (int o = G / 2; o > 0; o >>= 1) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] += __shfl_xor(y[u], o, G);
+      for (int u = 0; u < RPS; ++u) {
+        const double w = gi + u * NGR < nl ? om[u] : 0.0;
+        acc = fma((T)(w * (y[u] - bb[u])), (T)av[u], acc);
       }
-      double t[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) t[u] = om[u] * (y[u] - bb[u]);
-      const double a0 = av[0], a1 = av[1], a2 = av[2], a3 = av[3];
-      if (j + 4 * NGR < j1) load4(j + 4 * NGR);
-      acc = fma((T)t[0], (T)a0, acc);
-      acc = fma((T)t[1], (T)a1, acc);
-      acc = fma((T)t[2], (T)a2, acc);
-      acc = fma((T)t[3], (T)a3, acc);
+    };
+    const int nstep = (nrow + RPS * NGR - 1) / (RPS * NGR);
+    for (int k = 0;;) {
+      step(aA, oA, bA, k);
+      if (++k >= nstep) break;
+      load_step(aA, oA, bA, k);
     }
     // sum over the groups of the wave (fixed pairing order)
 #pragma unroll
