@@ -123,10 +123,11 @@ __device__ void pc_scale(const Geom& g, const double* __restrict__ dinv, TT* cur
 
 // x <- x - eta d for right-hand sides not yet converged; float64 norms, the
 // stopping rule and the divergence test; the iteration counter.
-// it and done_lane (lane q of every wave holds done[q]) are read at kernel start.
+// it, done_lane and dn0_lane (lane q of every wave holds done[q] and dnorm0[q]) are
+// read at kernel start.
 template <typename TT>
 __device__ void pc_update(const Geom& g, const TT* d_t, double* __restrict__ x, double eta, double tol, int max_iter,
-                          IterState* __restrict__ st, double* red, int it, int done_lane) {
+                          IterState* __restrict__ st, double* red, int it, int done_lane, double dn0_lane) {
   int all = 1, div = 0;
   const int64_t bd = blockDim.x;
   for (int q = 0; q < g.nrhs; ++q) {
@@ -153,16 +154,22 @@ __device__ void pc_update(const Geom& g, const TT* d_t, double* __restrict__ x, 
     }
     dd = block_sum(dd, red);
     xx = block_sum(xx, red);
-    if (threadIdx.x == 0 && !done) {
-      const double dn = sqrt(dd), xn = sqrt(xx);
-      const double rel = xn > 0.0 ? eta * dn / xn : (dn > 0.0 ? INFINITY : 0.0);
-      st->rel[q] = rel;
-      if (it == 0) { st->dnorm0[q] = dn; st->rel_first[q] = rel; }
-      const bool bad = !isfinite(dn) || !isfinite(xn) || (it > 0 && dn > 1e6 * st->dnorm0[q] && dn > 0.0);
-      if (bad) div = 1;
-      if (rel <= tol || bad) { st->done[q] = 1; st->it_rhs[q] = it + 1; }
+    // the first norm comes from the launch's first loads (dn0_lane), and the
+    // stopping flags are kept in registers: no global load waits here
+    const double dn0 = __shfl(dn0_lane, q, 64);
+    if (threadIdx.x == 0) {
+      bool dq = done;
+      if (!done) {
+        const double dn = sqrt(dd), xn = sqrt(xx);
+        const double rel = xn > 0.0 ? eta * dn / xn : (dn > 0.0 ? INFINITY : 0.0);
+        st->rel[q] = rel;
+        if (it == 0) { st->dnorm0[q] = dn; st->rel_first[q] = rel; }
+        const bool bad = !isfinite(dn) || !isfinite(xn) || (it > 0 && dn > 1e6 * dn0 && dn > 0.0);
+        if (bad) div = 1;
+        if (rel <= tol || bad) { st->done[q] = 1; st->it_rhs[q] = it + 1; dq = true; }
+      }
+      all &= dq;
     }
-    if (threadIdx.x == 0) all &= (done || st->done[q]);
   }
   if (threadIdx.x == 0) {
     st->iters = it + 1;
@@ -422,6 +429,7 @@ __device__ void pc_step_f64(const ModeTables& T, const Geom& g, const double* __
   const int all_done = st->all_done;
   const int it0 = st->iters;
   const int done_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->done[threadIdx.x & 63] : 1;
+  const double dn0_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->dnorm0[threadIdx.x & 63] : 0.0;
   const int64_t total = g.Rtot * g.nrhs;
   const bool all = pc_mats_fit(g);
   const double* const* Ms = use_ginv ? T.Ginv : T.V;
@@ -446,7 +454,7 @@ __device__ void pc_step_f64(const ModeTables& T, const Geom& g, const double* __
     __syncthreads();
     for (int n = 0; n < g.N; ++n) product(n, 0);
   }
-  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane);
+  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane, dn0_lane);
 }
 
 // Float64 step as its own launch (one workgroup of PC_THREADS threads); the tensor
@@ -485,6 +493,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_precond_mp(ModeTables T, Geom g,
   const int all_done = st->all_done;
   const int it0 = st->iters;
   const int done_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->done[threadIdx.x & 63] : 1;
+  const double dn0_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->dnorm0[threadIdx.x & 63] : 0.0;
   const int64_t total = g.Rtot * g.nrhs;
   float* cur = lds ? mp_dyn : t0;
   float* nxt = lds ? mp_dyn + total : t1;
@@ -525,7 +534,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_precond_mp(ModeTables T, Geom g,
     __syncthreads();
     for (int n = 0; n < g.N; ++n) product(n, 0);
   }
-  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane);
+  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane, dn0_lane);
 }
 
 // dinv[r] = 1 / (prod_n lambda_n[r_n] + lambda), 0 where that sum is not positive.
