@@ -15,6 +15,27 @@ namespace kr {
 
 #define KR_RMAX 64
 
+// dst[e] = src[e] for e < n by the threads of a workgroup: each thread issues
+// SB loads before its LDS stores, so that one memory round trip covers SB
+// entries per thread instead of one.
+template <int SB>
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* __restrict__ src, int n) {
+  const int bd = blockDim.x, tid = threadIdx.x;
+  for (int e0 = tid; e0 < n; e0 += SB * bd) {
+    double v[SB];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = e0 + u * bd;
+      v[u] = src[e < n ? e : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = e0 + u * bd;
+      if (e < n) dst[e] = v[u];
+    }
+  }
+}
+
 __global__ void k_promote(const void* __restrict__ src, int dtype, double* __restrict__ dst,
                           int64_t n, int32_t* __restrict__ flags) {
   int bad = 0;
@@ -42,12 +63,14 @@ __global__ void __launch_bounds__(256) k_gram(ModeTables T, Geom g, double* __re
   for (int r0 = 0; r0 < I; r0 += 64) {
     const int rows = min(64, I - r0);
     __syncthreads();
-    for (int e = threadIdx.x; e < rows * R; e += blockDim.x) tile[e] = A[(size_t)r0 * R + e];
+    copy_to_lds<16>(tile, A + (size_t)r0 * R, rows * R);
     __syncthreads();
     int k = 0;
     for (int pq = threadIdx.x; pq < R * R; pq += blockDim.x, ++k) {
       const int p = pq / R, q = pq % R;
       double s = acc[k];
+      // the LDS reads of 8 rows are issued before their (ordered) multiply-adds
+#pragma unroll 8
       for (int i = 0; i < rows; ++i) s = fma(tile[i * R + p], tile[i * R + q], s);
       acc[k] = s;
     }
@@ -76,10 +99,8 @@ __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* 
   const int R = g.R[n], I = g.I[n];
   const int lane = threadIdx.x;
   const double* G = gram + (size_t)n * KR_RMAX * KR_RMAX;
-  for (int e = lane; e < R * R; e += 64) {
-    a[e] = G[e];
-    v[e] = (e / R == e % R) ? 1.0 : 0.0;
-  }
+  copy_to_lds<16>(a, G, R * R);
+  for (int e = lane; e < R * R; e += 64) v[e] = (e / R == e % R) ? 1.0 : 0.0;
   const int mpl = (R & 1) ? R + 1 : R;   // players in the round-robin (dummy = R when odd)
   const int npair = mpl / 2;
   const int nblk = npair * npair;
@@ -191,7 +212,7 @@ __global__ void __launch_bounds__(64) k_chol(ModeTables T, Geom g, const double*
   const int R = g.R[n], I = g.I[n];
   const int lane = threadIdx.x;
   const double* G = gram + (size_t)n * KR_RMAX * KR_RMAX;
-  for (int e = lane; e < R * R; e += 64) a[e] = G[e];
+  copy_to_lds<16>(a, G, R * R);
   if (lane == 0) sing = 0;
   __syncthreads();
   double dmax = 0.0;
@@ -249,7 +270,7 @@ __global__ void __launch_bounds__(64) k_chol(ModeTables T, Geom g, const double*
 template <int RM>
 __global__ void __launch_bounds__(256) k_leverage(ModeTables T, Geom g, int32_t* __restrict__ flags) {
   __shared__ double vs[KR_RMAX * KR_RMAX];
-  __shared__ double inv[KR_RMAX];
+  __shared__ double inv[2 * KR_RMAX];
   __shared__ double red[8];
   __shared__ unsigned long long ured[4];
   __shared__ unsigned long long umax[4];
@@ -261,14 +282,18 @@ __global__ void __launch_bounds__(256) k_leverage(ModeTables T, Geom g, int32_t*
   double* lev = T.lev[n];
   uint64_t* Q = T.Q[n];
   uint64_t* C = T.C[n];
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) vs[e] = T.V[n][e];
+  copy_to_lds<16>(vs, T.V[n], R * R);
+  if (threadIdx.x < R) inv[threadIdx.x] = T.evals[n][threadIdx.x];
+  __syncthreads();
   if (threadIdx.x < R) {
     double lmax = 0.0;
-    for (int k = 0; k < R; ++k) lmax = fmax(lmax, T.evals[n][k]);
+    for (int k = 0; k < R; ++k) lmax = fmax(lmax, inv[k]);
     const double eps_r = (double)max(I, R) * 2.220446049250313e-16;
-    const double lk = T.evals[n][threadIdx.x];
-    inv[threadIdx.x] = lk > eps_r * eps_r * lmax ? 1.0 / lk : 0.0;
+    const double lk = inv[threadIdx.x];
+    inv[threadIdx.x + KR_RMAX] = lk > eps_r * eps_r * lmax ? 1.0 / lk : 0.0;
   }
+  __syncthreads();
+  if (threadIdx.x < R) inv[threadIdx.x] = inv[threadIdx.x + KR_RMAX];
   __syncthreads();
   // leverage per row (the row held in registers); thread-local partial sums in
   // increasing row order
