@@ -459,8 +459,9 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
   uint64_t* kin = keys;
   uint64_t* kout = keys_alt;
   // the histogram scan is one workgroup, so the wider digit is taken only while
-  // its scan stays small
-  const int rb = ((g.keybits + 8) / 9 < (g.keybits + 7) / 8 && (int64_t)512 * nblocks <= (1 << 20)) ? 9 : 8;
+  // its scan stays small (at 5.7M keys its doubled scan cost more than the pass
+  // it saved: measured)
+  const int rb = ((g.keybits + 8) / 9 < (g.keybits + 7) / 8 && (int64_t)512 * nblocks <= (1 << 16)) ? 9 : 8;
   for (int sh = 0; sh < g.keybits; sh += rb) {
     if (rb == 9) {
       KLN(h, "k_radix_hist", k_radix_hist<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
