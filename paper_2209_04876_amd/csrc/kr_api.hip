@@ -433,7 +433,7 @@ static int64_t level_cap(const Geom& g, int k) {
 // partial-sum buffers.
 static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = false) {
   size_t b = setup_bytes(g);
-  b += 2 * 8 * (size_t)g.m + 4 * SORT_DIGITS_MAX * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
+  b += 2 * 8 * (size_t)g.m + 4 * 256 * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
   const int64_t D = level_cap(g, g.N);
   b += (size_t)D * (8 + 8 * g.nrhs + 4);
   for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
@@ -449,31 +449,20 @@ static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = fa
 }
 
 
-// Stable LSD radix sort of the g.m packed keys (9-bit digits when that takes
-// fewer passes over g.keybits than 8-bit digits and the tiles are few, else
-// 8-bit) and the per-level run-length encoding into the sample tree.
+// Stable LSD radix sort of the g.m packed keys (8-bit digits over g.keybits) and
+// the per-level run-length encoding into the sample tree.  (9-bit digits, three
+// passes instead of four at 27-bit keys, measured no faster: the one-workgroup
+// histogram scan doubles.)
 static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_t* keys_alt, uint32_t* hist,
                              int64_t* tiletot, int nblocks, const Tree& tr) {
   hipStream_t s = h->stream;
   const int64_t m = g.m;
   uint64_t* kin = keys;
   uint64_t* kout = keys_alt;
-  // the histogram scan is one workgroup, so the wider digit is taken only while
-  // its scan stays small (at 5.7M keys its doubled scan cost more than the pass
-  // it saved: measured)
-  const int rb = ((g.keybits + 8) / 9 < (g.keybits + 7) / 8 && (int64_t)512 * nblocks <= (1 << 16)) ? 9 : 8;
-  for (int sh = 0; sh < g.keybits; sh += rb) {
-    if (rb == 9) {
-      KLN(h, "k_radix_hist", k_radix_hist<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
-      KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)512 * nblocks);
-      KLN(h, "k_radix_scatter", k_radix_scatter<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist,
-          nblocks);
-    } else {
-      KLN(h, "k_radix_hist", k_radix_hist<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
-      KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
-      KLN(h, "k_radix_scatter", k_radix_scatter<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist,
-          nblocks);
-    }
+  for (int sh = 0; sh < g.keybits; sh += 8) {
+    KL(h, k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
+    KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
+    KL(h, k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist, nblocks);
     std::swap(kin, kout);
   }
   KL(h, k_tree_count, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot);
@@ -690,7 +679,7 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   carve_setup(a, g, T, &B->s);
   B->keys = a.take<uint64_t>(m);
   B->keys_alt = a.take<uint64_t>(m);
-  B->hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
+  B->hist = a.take<uint32_t>((size_t)256 * nblocks);
   B->tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
   for (int k = 1; k <= g.N; ++k) {
     const int64_t c = level_cap(g, k);
@@ -1816,7 +1805,7 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
 
   // workspace
-  size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * SORT_DIGITS_MAX * (size_t)nblocks +
+  size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * 256 * (size_t)nblocks +
                 8 * (size_t)nblocks * (KR_MAXN + 1) + 4096;
   const int64_t Dcap = level_cap(g, g.N);
   for (int k = 1; k <= g.N; ++k) need += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
@@ -1832,7 +1821,7 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   carve_setup(a, go, &To, &S);
   uint64_t* keys = a.take<uint64_t>(m);
   uint64_t* keys_alt = a.take<uint64_t>(m);
-  uint32_t* hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
+  uint32_t* hist = a.take<uint32_t>((size_t)256 * nblocks);
   int64_t* tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
   Tree tr{};
   for (int k = 1; k <= g.N; ++k) {
