@@ -2,6 +2,7 @@
 // of Algorithm 2 (FastKroneckerRegression) and of the exact KronMatMul
 // baseline and loss.  Single translation unit: the kernel files are included.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <array>
@@ -139,18 +140,30 @@ void prof_clear(kr_handle h) {
 
 }  // namespace
 
-#define KL(h, kern, ...)                      \
-  do {                                        \
-    ProfScope _ps((h), #kern, (h)->stream);   \
-    hipLaunchKernelGGL(kern, __VA_ARGS__);    \
+// Events of a profiled launch (h->prof_on, name matching the filter); false when
+// the launch is not profiled.
+static bool prof_take(kr_handle h, const char* name, hipEvent_t* a, hipEvent_t* b) {
+  if (!(h->prof_on && !h->capturing && prof_match(h->prof_filter, name))) return false;
+  *a = pool_event(h);
+  *b = pool_event(h);
+  h->prof[name].push_back({*a, *b});
+  return true;
+}
+
+// Launch with an explicit profiling name (for kernels instantiated per type).  A
+// profiled launch carries its start and stop events in its own dispatch
+// (hipExtLaunchKernelGGL), so that timing a kernel queues no marker packets
+// around it and does not stretch the stream.
+#define KLN(h, name, kern, grid, block, shm, strm, ...)                          \
+  do {                                                                         \
+    hipEvent_t _pa = nullptr, _pb = nullptr;                                   \
+    if (prof_take((h), (name), &_pa, &_pb))                                    \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, strm, _pa, _pb, 0u, __VA_ARGS__); \
+    else                                                                       \
+      hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);           \
   } while (0)
 
-// Launch with an explicit profiling name (for kernels instantiated per type).
-#define KLN(h, name, kern, ...)               \
-  do {                                        \
-    ProfScope _ps((h), (name), (h)->stream);  \
-    hipLaunchKernelGGL(kern, __VA_ARGS__);    \
-  } while (0)
+#define KL(h, kern, ...) KLN(h, #kern, kern, __VA_ARGS__)
 
 #define KR_FAIL(h, code, ...)                                   \
   do {                                                          \
@@ -433,7 +446,7 @@ static int64_t level_cap(const Geom& g, int k) {
 // partial-sum buffers.
 static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = false) {
   size_t b = setup_bytes(g);
-  b += 2 * 8 * (size_t)g.m + 4 * 256 * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
+  b += 2 * 8 * (size_t)g.m + 4 * SORT_DIGITS_MAX * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
   const int64_t D = level_cap(g, g.N);
   b += (size_t)D * (8 + 8 * g.nrhs + 4);
   for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
@@ -449,20 +462,33 @@ static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = fa
 }
 
 
-// Stable LSD radix sort of the g.m packed keys (8-bit digits over g.keybits) and
-// the per-level run-length encoding into the sample tree.  (9-bit digits, three
-// passes instead of four at 27-bit keys, measured no faster: the one-workgroup
-// histogram scan doubles.)
+// Stable LSD radix sort of the g.m packed keys (9-bit digits when that takes
+// fewer passes over g.keybits than 8-bit digits and the tiles are few, else
+// 8-bit) and the per-level run-length encoding into the sample tree.
 static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_t* keys_alt, uint32_t* hist,
                              int64_t* tiletot, int nblocks, const Tree& tr) {
   hipStream_t s = h->stream;
   const int64_t m = g.m;
   uint64_t* kin = keys;
   uint64_t* kout = keys_alt;
-  for (int sh = 0; sh < g.keybits; sh += 8) {
-    KL(h, k_radix_hist, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
-    KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
-    KL(h, k_radix_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist, nblocks);
+  // The histogram scan is one workgroup, so the wider digit is taken only while
+  // its scan stays small.  Measured: at 340k keys (27-bit) three 9-bit passes
+  // beat four 8-bit ones by ~1.5% of the whole solve (three fewer launch
+  // triples), although the kernels alone take about as long; at 5.7M keys the
+  // doubled scan cost more than the pass it saved.
+  const int rb = ((g.keybits + 8) / 9 < (g.keybits + 7) / 8 && (int64_t)512 * nblocks <= (1 << 16)) ? 9 : 8;
+  for (int sh = 0; sh < g.keybits; sh += rb) {
+    if (rb == 9) {
+      KLN(h, "k_radix_hist", k_radix_hist<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
+      KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)512 * nblocks);
+      KLN(h, "k_radix_scatter", k_radix_scatter<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist,
+          nblocks);
+    } else {
+      KLN(h, "k_radix_hist", k_radix_hist<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
+      KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
+      KLN(h, "k_radix_scatter", k_radix_scatter<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist,
+          nblocks);
+    }
     std::swap(kin, kout);
   }
   KL(h, k_tree_count, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot);
@@ -679,7 +705,7 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   carve_setup(a, g, T, &B->s);
   B->keys = a.take<uint64_t>(m);
   B->keys_alt = a.take<uint64_t>(m);
-  B->hist = a.take<uint32_t>((size_t)256 * nblocks);
+  B->hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
   B->tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
   for (int k = 1; k <= g.N; ++k) {
     const int64_t c = level_cap(g, k);
@@ -1805,7 +1831,7 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
 
   // workspace
-  size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * 256 * (size_t)nblocks +
+  size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * SORT_DIGITS_MAX * (size_t)nblocks +
                 8 * (size_t)nblocks * (KR_MAXN + 1) + 4096;
   const int64_t Dcap = level_cap(g, g.N);
   for (int k = 1; k <= g.N; ++k) need += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
@@ -1821,7 +1847,7 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   carve_setup(a, go, &To, &S);
   uint64_t* keys = a.take<uint64_t>(m);
   uint64_t* keys_alt = a.take<uint64_t>(m);
-  uint32_t* hist = a.take<uint32_t>((size_t)256 * nblocks);
+  uint32_t* hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
   int64_t* tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
   Tree tr{};
   for (int k = 1; k <= g.N; ++k) {

@@ -4,7 +4,7 @@
 // kron_mat_mul_sqrt_decomp).
 //
 //   k_sample        Philox4x64-10 words -> per-mode inverse-CDF draws -> packed key
-//   k_radix_*       stable LSD radix sort of the packed keys (8-bit digits)
+//   k_radix_*       stable LSD radix sort of the packed keys (8- or 9-bit digits)
 //   k_tree_*        run-length encoding of the sorted keys at every prefix length:
 //                   the nodes of level k are the distinct (i_0..i_{k-1})
 //   k_rows          per distinct row: multiplicity, merged weight
@@ -20,6 +20,7 @@ namespace kr {
 #define SORT_THREADS 256
 #define SORT_ITEMS 16
 #define SORT_TILE (SORT_THREADS * SORT_ITEMS)
+#define SORT_DIGITS_MAX 512   // histogram rows per tile (9-bit digits at most)
 
 // ---------------------------------------------------------------------------
 // Sampling.  CDF tables are staged in LDS when they fit (cdf_in_lds != 0).
@@ -65,21 +66,26 @@ __global__ void __launch_bounds__(256) k_sample(ModeTables T, Geom g, uint64_t s
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort, 8-bit digits.  hist is digit-major: hist[d * nblocks + b].
+// LSD radix sort, RB-bit digits (8 or 9: 27-bit keys sort in three passes of 9
+// bits instead of four of 8).  hist is digit-major: hist[d * nblocks + b], with
+// room for SORT_DIGITS_MAX digits.
 // ---------------------------------------------------------------------------
+template <int RB>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
                                                             int shift, uint32_t* __restrict__ hist,
                                                             int nblocks) {
-  __shared__ uint32_t cnt[256];
-  cnt[threadIdx.x] = 0;
+  constexpr int NB = 1 << RB;
+  static_assert(NB <= SORT_DIGITS_MAX && NB % SORT_THREADS == 0, "digit count");
+  __shared__ uint32_t cnt[NB];
+  for (int d = threadIdx.x; d < NB; d += SORT_THREADS) cnt[d] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
   for (int k = 0; k < SORT_ITEMS; ++k) {
     const int64_t t = base + (int64_t)k * SORT_THREADS + threadIdx.x;
-    if (t < m) atomicAdd(&cnt[(keys[t] >> shift) & 255u], 1u);
+    if (t < m) atomicAdd(&cnt[(keys[t] >> shift) & (uint64_t)(NB - 1)], 1u);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+  for (int d = threadIdx.x; d < NB; d += SORT_THREADS) hist[(size_t)d * nblocks + blockIdx.x] = cnt[d];
 }
 
 // Exclusive scan of n uint32 values in place, one workgroup of 1024 threads:
@@ -132,19 +138,25 @@ __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int
   }
 }
 
-// Stable scatter.  The tile is processed in rounds of 256 consecutive keys; in a
-// round, a key's rank among equal digits is (earlier waves' counts) + (earlier
-// lanes in its wave with the same digit, found by ballot matching).
+// Stable scatter.  The tile is processed in rounds of SORT_THREADS consecutive
+// keys; in a round, a key's rank among equal digits is (earlier waves' counts) +
+// (earlier lanes in its wave with the same digit, found by ballot matching over
+// the RB + 1 bits of the digit, NB marking an absent key).
+template <int RB>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t* __restrict__ in,
                                                                uint64_t* __restrict__ out, int64_t m,
                                                                int shift, const uint32_t* __restrict__ hist,
                                                                int nblocks) {
-  __shared__ uint32_t base_[256];
-  __shared__ uint32_t wcnt[SORT_THREADS / 64][257];
+  constexpr int NB = 1 << RB;
+  constexpr int NW = SORT_THREADS / 64;
+  __shared__ uint32_t base_[NB];
+  __shared__ uint32_t wcnt[NW][NB + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  base_[threadIdx.x] = hist[(size_t)threadIdx.x * nblocks + blockIdx.x];
-  for (int k = 0; k < SORT_THREADS / 64; ++k) wcnt[k][threadIdx.x] = 0;
-  if (threadIdx.x < SORT_THREADS / 64) wcnt[threadIdx.x][256] = 0;
+  for (int d = threadIdx.x; d < NB; d += SORT_THREADS) {
+    base_[d] = hist[(size_t)d * nblocks + blockIdx.x];
+    for (int k = 0; k < NW; ++k) wcnt[k][d] = 0;
+  }
+  if (threadIdx.x < NW) wcnt[threadIdx.x][NB] = 0;
   __syncthreads();
   const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   const int64_t tbase = (int64_t)blockIdx.x * SORT_TILE;
@@ -152,10 +164,10 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t* 
     const int64_t t = tbase + (int64_t)r * SORT_THREADS + threadIdx.x;
     const bool valid = t < m;
     const uint64_t key = valid ? in[t] : 0ull;
-    const uint32_t d = valid ? (uint32_t)((key >> shift) & 255u) : 256u;
+    const uint32_t d = valid ? (uint32_t)((key >> shift) & (uint64_t)(NB - 1)) : (uint32_t)NB;
     unsigned long long peers = ~0ull;
 #pragma unroll
-    for (int b = 0; b < 9; ++b) {
+    for (int b = 0; b <= RB; ++b) {
       const bool bit = (d >> b) & 1u;
       const unsigned long long bal = __ballot(bit);
       peers &= bit ? bal : ~bal;
@@ -169,12 +181,12 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t* 
       out[pos] = key;
     }
     __syncthreads();
-    {
+    for (int dd = threadIdx.x; dd < NB; dd += SORT_THREADS) {
       uint32_t add = 0;
-      for (int k = 0; k < SORT_THREADS / 64; ++k) { add += wcnt[k][threadIdx.x]; wcnt[k][threadIdx.x] = 0; }
-      base_[threadIdx.x] += add;
-      if (threadIdx.x < SORT_THREADS / 64) wcnt[threadIdx.x][256] = 0;
+      for (int k = 0; k < NW; ++k) { add += wcnt[k][dd]; wcnt[k][dd] = 0; }
+      base_[dd] += add;
     }
+    if (threadIdx.x < NW) wcnt[threadIdx.x][NB] = 0;
     __syncthreads();
   }
 }
