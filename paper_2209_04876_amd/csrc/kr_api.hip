@@ -2,7 +2,6 @@
 // of Algorithm 2 (FastKroneckerRegression) and of the exact KronMatMul
 // baseline and loss.  Single translation unit: the kernel files are included.
 #include <hip/hip_runtime.h>
-#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <array>
@@ -150,16 +149,19 @@ static bool prof_take(kr_handle h, const char* name, hipEvent_t* a, hipEvent_t* 
   return true;
 }
 
-// Launch with an explicit profiling name (for kernels instantiated per type).  A
-// profiled launch carries its start and stop events in its own dispatch
-// (hipExtLaunchKernelGGL), so that timing a kernel queues no marker packets
-// around it and does not stretch the stream.
+// Launch with an explicit profiling name (for kernels instantiated per type); a
+// profiled launch is bracketed by two events on its stream.  (Events carried in
+// the dispatch itself, hipExtLaunchKernelGGL, time the kernel alone but measured
+// 4-6% slower per bf16 solve: its host path is longer and the iteration is
+// launch-bound.)
 #define KLN(h, name, kern, grid, block, shm, strm, ...)                          \
   do {                                                                         \
     hipEvent_t _pa = nullptr, _pb = nullptr;                                   \
-    if (prof_take((h), (name), &_pa, &_pb))                                    \
-      hipExtLaunchKernelGGL(kern, grid, block, shm, strm, _pa, _pb, 0u, __VA_ARGS__); \
-    else                                                                       \
+    if (prof_take((h), (name), &_pa, &_pb)) {                                  \
+      hipEventRecord(_pa, strm);                                               \
+      hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);           \
+      hipEventRecord(_pb, strm);                                               \
+    } else                                                                     \
       hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);           \
   } while (0)
 
@@ -375,17 +377,27 @@ static size_t setup_bytes(const Geom& g) {
   return b + 8 * (size_t)g.N * 4096 + 1024;
 }
 
+// FP64 copies of every factor (one launch; blockIdx.y is the mode).
+static void launch_promote(kr_handle h, const kr_problem* p, const Geom& g, double* const* dst, int32_t* flags,
+                           hipStream_t s) {
+  PromoteArgs pa{};
+  int64_t cmax = 1;
+  for (int n = 0; n < g.N; ++n) {
+    pa.src[n] = p->A[n];
+    pa.dst[n] = dst[n];
+    pa.cnt[n] = (int64_t)g.I[n] * g.R[n];
+    cmax = std::max(cmax, pa.cnt[n]);
+  }
+  KL(h, k_promote_all, dim3(grid_for(cmax, 256, 1024), g.N), dim3(256), 0, s, pa, p->a_dtype, flags);
+}
+
 // Factor setup: float64 copies, Grams, then the eigen-decomposition (eig) or, when
 // only G^{-1} is needed (lambda = 0 solves), the Cholesky route; then the
 // leverage tables.
 static kr_status launch_setup(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T,
                               const SetupBufs& s, bool leverage, bool eig = true) {
   KL(h, k_zero_bytes, dim3(1), dim3(64), 0, h->stream, (uint32_t*)s.flags, (int64_t)64);
-  for (int n = 0; n < g.N; ++n) {
-    const int64_t cnt = (int64_t)g.I[n] * g.R[n];
-    KL(h, k_promote, dim3(grid_for(cnt, 256, 1024)), dim3(256), 0, h->stream, p->A[n], p->a_dtype,
-                       s.A64[n], cnt, s.flags);
-  }
+  launch_promote(h, p, g, s.A64, s.flags, h->stream);
   KL(h, k_gram, dim3(g.N), dim3(256), 0, h->stream, T, g, s.gram);
   int maxR = 1;
   for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
@@ -1649,11 +1661,7 @@ kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void*
   double* out = a.take<double>(64);
   hipStream_t s = h->stream;
   KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)S.flags, (int64_t)64);
-  for (int n = 0; n < g.N; ++n) {
-    const int64_t cnt = (int64_t)g.I[n] * g.R[n];
-    KL(h, k_promote, dim3(grid_for(cnt, 256, 1024)), dim3(256), 0, s, p->A[n], p->a_dtype, S.A64[n],
-                       cnt, S.flags);
-  }
+  launch_promote(h, p, g, S.A64, S.flags, s);
   const double* cur = (const double*)d_x;
   for (int n = 0; n < g.N; ++n) dims[n] = g.R[n];
   double* dst = buf0;

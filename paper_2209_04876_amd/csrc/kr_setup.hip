@@ -1,7 +1,7 @@
 // Factor preprocessing of Algorithm 2 (lines computing the Gram matrix, its
 // eigen-decomposition and the leverage scores, and the product-distribution
 // data structure), one mode per workgroup:
-//   k_promote   : factor -> FP64 workspace copy, finiteness check
+//   k_promote_all : factors -> FP64 workspace copies (one launch), finiteness check
 //   k_gram      : G_n = A_n^T A_n (FP64, LDS row tiles, fixed summation order)
 //   k_eig       : cyclic Jacobi eigen-decomposition G_n = V diag(lambda) V^T in one
 //                 wave, plus G_n^{-1} = V diag(1/lambda) V^T
@@ -36,11 +36,19 @@ __device__ __forceinline__ void copy_to_lds(double* dst, const double* __restric
   }
 }
 
-__global__ void k_promote(const void* __restrict__ src, int dtype, double* __restrict__ dst,
-                          int64_t n, int32_t* __restrict__ flags) {
+// Every mode's factor -> FP64 copy in one launch: blockIdx.y is the mode.
+struct PromoteArgs {
+  const void* src[KR_MAXN];
+  double* dst[KR_MAXN];
+  int64_t cnt[KR_MAXN];
+};
+__global__ void k_promote_all(PromoteArgs a, int dtype, int32_t* __restrict__ flags) {
+  const int n = blockIdx.y;
+  const void* __restrict__ src = a.src[n];
+  double* __restrict__ dst = a.dst[n];
+  const int64_t cnt = a.cnt[n];
   int bad = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const double v = dtype == KR_F32 ? (double)((const float*)src)[i] : ((const double*)src)[i];
     dst[i] = v;
     bad |= !isfinite(v);
