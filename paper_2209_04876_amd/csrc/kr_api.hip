@@ -10,7 +10,9 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -76,6 +78,7 @@ struct kr_handle_s {
   // optional per-kernel timing with HIP events on the handle's stream
   bool prof_on = false;
   std::string prof_filter;
+  std::unordered_map<const char*, bool> prof_hit;   // filter match per kernel-name literal
   std::vector<hipEvent_t> ev_pool;
   std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
 };
@@ -108,13 +111,23 @@ static bool prof_match(const std::string& filter, const char* n) {
   return false;
 }
 
+// prof_match, cached per name literal (launch names are string literals), so
+// that a profiled run's launches pay one hash lookup each.
+static bool prof_wanted(kr_handle h, const char* n) {
+  auto it = h->prof_hit.find(n);
+  if (it != h->prof_hit.end()) return it->second;
+  const bool hit = prof_match(h->prof_filter, n);
+  h->prof_hit.emplace(n, hit);
+  return hit;
+}
+
 struct ProfScope {
   kr_handle h;
   const char* name;
   hipStream_t s;
   hipEvent_t a = nullptr;
   ProfScope(kr_handle h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) {
-    if (h->prof_on && !h->capturing && prof_match(h->prof_filter, n)) {
+    if (h->prof_on && !h->capturing && prof_wanted(h, n)) {
       a = pool_event(h);
       hipEventRecord(a, s);
     }
@@ -142,7 +155,7 @@ void prof_clear(kr_handle h) {
 // Events of a profiled launch (h->prof_on, name matching the filter); false when
 // the launch is not profiled.
 static bool prof_take(kr_handle h, const char* name, hipEvent_t* a, hipEvent_t* b) {
-  if (!(h->prof_on && !h->capturing && prof_match(h->prof_filter, name))) return false;
+  if (!(h->prof_on && !h->capturing && prof_wanted(h, name))) return false;
   *a = pool_event(h);
   *b = pool_event(h);
   h->prof[name].push_back({*a, *b});
@@ -308,6 +321,14 @@ kr_status kr_profile_enable(kr_handle h, int32_t enable, const char* filter) {
   prof_clear(h);
   h->prof_on = enable != 0;
   h->prof_filter = filter ? filter : "";
+  h->prof_hit.clear();
+  // events are created here rather than inside a profiled (timed) stretch
+  if (h->prof_on)
+    while (h->ev_pool.size() < 4096) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      h->ev_pool.push_back(e);
+    }
   return KR_OK;
 }
 
@@ -598,7 +619,18 @@ static size_t precond_lds(const Geom& g, size_t elem) {
 // when the device refuses, and the caller then works without it.
 static bool allow_dynamic_lds(const void* fn, size_t bytes) {
   if (bytes == 0) return true;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+  // the attribute persists per function and device: set it once per size
+  // (the preconditioner launches every iteration, and the call is host time)
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> granted;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = granted.find({fn, dev});
+  if (it != granted.end() && it->second >= bytes) return true;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return false;
+  granted[{fn, dev}] = bytes;
+  return true;
 }
 
 // Number of 16-blocks along the widest mode (1..4).
