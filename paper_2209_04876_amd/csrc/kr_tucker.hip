@@ -308,13 +308,21 @@ __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, Tuc
   double* buf = sm + 2 * Rr;
   for (int e = threadIdx.x; e < Rr; e += blockDim.x) z[e] = Z[(size_t)i * Rr + e];
   __syncthreads();
-  // vv = V z
-  for (int a = threadIdx.x; a < Rn; a += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < Rr; ++c) s = fma(Vw[a * Rr + c], z[c], s);
-    vv[a] = s;
-  }
-  __syncthreads();
+  // vv[a] = sum_c V[a][c] v[c] by 16 lanes per output a: lane p sums the terms
+  // c = p, p + 16, ... and a butterfly over the 16 lanes adds the partial sums
+  // (fixed order; the 16 lanes of a group always run the same a)
+  auto v_times = [&](const double* v) {
+    const int p = threadIdx.x & 15;
+    for (int a = threadIdx.x >> 4; a < Rn; a += blockDim.x >> 4) {
+      double s = 0.0;
+      for (int c = p; c < Rr; c += 16) s = fma(Vw[a * Rr + c], v[c], s);
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+      if (p == 0) vv[a] = s;
+    }
+    __syncthreads();
+  };
+  v_times(z);
   // h = Q1 + w z + G^+ vv   (G^+ = GtP^T)
   for (int e = threadIdx.x; e < Rr; e += blockDim.x) {
     double s = Q1[(size_t)i * Rr + e] + w * z[e];
@@ -323,12 +331,7 @@ __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, Tuc
   }
   __syncthreads();
   wg_apply_Ainv(g, T, w, h, buf);          // h <- A^-1 h
-  for (int a = threadIdx.x; a < Rn; a += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < Rr; ++c) s = fma(Vw[a * Rr + c], h[c], s);
-    vv[a] = s;
-  }
-  __syncthreads();
+  v_times(h);
   for (int a = threadIdx.x; a < Rn; a += blockDim.x) {
     double s = 0.0;
     for (int b = 0; b < Rn; ++b) s = fma(Cinv[a * Rn + b], vv[b], s);
