@@ -22,8 +22,10 @@ Kronecker-regression tables) via the factor SVDs; loss evaluates f.
 
 Pinned by tests/test_oracle_regression.py: explicit sketch-matrix normal
 equations, lstsq on the explicit K, convergence to the direct solution at the
-rate predicted from the spectrum, and the (1 + eps) guarantee at the theory
-sample count on a tiny problem.
+rate predicted from the spectrum, the (1 + eps) guarantee at the theory
+sample count on a tiny problem (delta = 1/e, 0.1 and 0.5), and the theory count
+itself against the rows-sampled percentages the paper prints in its Table 2
+(eps = 0.1, delta = 0.01, scaled by alpha = 1e-5).
 """
 
 import math
@@ -36,7 +38,9 @@ from .sampling import merge, sample_product
 
 
 def theory_sample_count(R, eps, delta):
-    """s = ceil(1680 R ln(40 R) ln(1/delta) / eps) (Algorithm 2)."""
+    """s = ceil(1680 R ln(40 R) ln(1/delta) / eps) (Algorithm 2, sample-count line).
+
+    Pinned by the paper's Table 2 rows-sampled column (see the module header)."""
     return int(math.ceil(1680.0 * R * math.log(40.0 * R) * math.log(1.0 / delta) / eps))
 
 

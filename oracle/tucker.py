@@ -25,7 +25,8 @@ Readings:
 Pinned by tests/test_oracle_tucker.py: explicit inv(M) for the Woodbury form,
 the equivalence of the constrained and original row problems, Lemma
 constraint-reg's inequality, the exact row update against lstsq on explicit
-K G^T, and monotone exact ALS.
+K G^T, monotone exact ALS, and rre / tucker_loss against the reconstruction
+written out entry by entry.
 """
 
 import math

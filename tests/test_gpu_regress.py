@@ -71,6 +71,12 @@ def test_regress_parity(gpu_lib, case):
         assert np.linalg.norm(res) <= 1e-9 * np.linalg.norm(ref)
         return
     xo = sketched_solution(As, b, rows, ridx, Omega, lam)
+    # the fitted values sqrt(Omega) K_D x of the sketched problem: their error is
+    # about kappa u for a normal-equation method, where x's is kappa^2 u
+    from oracle.regression import kron_rows
+    KW = kron_rows(As, ridx) * np.sqrt(Omega)[:, None]
+    fit = rel_l2(KW @ xg.reshape(KW.shape[1], -1), KW @ xo.reshape(KW.shape[1], -1))
+    print("rel-L2 x %.3e (bar %.1e), fitted values %.3e" % (rel_l2(xg, xo), xtol, fit), flush=True)
     assert rel_l2(xg, xo) < xtol, (name, rel_l2(xg, xo), xtol)
 
 
@@ -168,3 +174,22 @@ def test_cooperative_iteration_matches(gpu_lib, case):
     xp, ip = gpu_lib.kron_ridge(tA, tb, lam, m=m, seed=7, stream=3, tol=1e-12, max_iter=400)
     assert im["status"] == ip["status"] == "OK"
     assert rel_l2(xm.cpu().numpy(), xp.cpu().numpy()) < 1e-11
+
+
+def test_default_sample_count_is_algorithm_2s(gpu_lib):
+    """opts.m = 0 takes Algorithm 2's count ceil(1680 R ln(40 R) ln(1/delta) / eps)
+    (the oracle's theory_sample_count, pinned to the paper's printed rows-sampled
+    column); the sketch drawn with it is the oracle's, bit for bit."""
+    from oracle.regression import theory_sample_count
+    w = workloads.random_problem((9, 7), (2, 2), seed=21)
+    As, b = w["As"], w["b"]
+    tA, tb = _torch_inputs(As, b)
+    m = theory_sample_count(4, 0.1, 0.01)
+    print("case default sample count m=%d" % m, flush=True)
+    x, info = gpu_lib.kron_regress(tA, tb, eps=0.1, delta=0.01, m=0, seed=5, stream=0)
+    assert info["m"] == m, (info["m"], m)
+    sk = gpu_lib.export_sketch([9, 7])
+    rows, ridx, counts, Omega = check_sketch(As, sk, m, seed=5, stream=0)
+    assert counts.sum() == m
+    xo = sketched_solution(As, b, rows, ridx, Omega, 0.0)
+    assert rel_l2(x.cpu().numpy(), xo) < 1e-10

@@ -133,4 +133,28 @@ def test_exact_als_monotone_and_recovers_planted():
     assert all(b <= a + 1e-12 for a, b in zip(trace, trace[1:]))
     assert trace[-1] < 2e-4
     assert abs(rre(X, G, As) - trace[-1]) < 1e-15
-    assert tucker_loss(X, G, As, lam) >= 0
+
+
+def test_tucker_loss_and_rre_brute_force():
+    # both against the definition written out entry by entry (no mode products):
+    # Xhat[i,j,k] = sum_{a,b,c} G[a,b,c] A1[i,a] A2[j,b] A3[k,c]
+    rng = np.random.default_rng(12)
+    I, R = (3, 4, 2), (2, 3, 2)
+    As = [rng.standard_normal((i, r)) for i, r in zip(I, R)]
+    G = rng.standard_normal(R)
+    X = rng.standard_normal(I)
+    lam = 0.37
+    sq, xx = 0.0, 0.0
+    for i in range(I[0]):
+        for j in range(I[1]):
+            for k in range(I[2]):
+                xh = 0.0
+                for a in range(R[0]):
+                    for b in range(R[1]):
+                        for c in range(R[2]):
+                            xh += G[a, b, c] * As[0][i, a] * As[1][j, b] * As[2][k, c]
+                sq += (X[i, j, k] - xh) ** 2
+                xx += X[i, j, k] ** 2
+    reg = sum(v * v for v in G.ravel()) + sum(v * v for A in As for v in A.ravel())
+    assert abs(tucker_loss(X, G, As, lam) - (sq + lam * reg)) <= 1e-12 * (sq + lam * reg)
+    assert abs(rre(X, G, As) - sq / xx) <= 1e-12 * (sq / xx)
