@@ -15,8 +15,10 @@ Functions mirror the C entry points:
   export_sketch(handle)                    last solve's sketch (tests)
 """
 
+import atexit
 import ctypes
 import os
+import weakref
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkron_regress.so")
 MAX_MODES = 8
@@ -137,6 +139,24 @@ def _torch():
     return torch
 
 
+_live_handles = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    """Destroy every open handle while the interpreter still runs: kr_destroy then
+    releases its streams, events, pinned and device memory before the HIP runtime
+    (and a profiler attached to it) shuts down in the process's exit handlers.
+    Leaving it to garbage collection during interpreter teardown ran those calls
+    after the runtime's own finalisation had begun."""
+    for h in list(_live_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+    _default.clear()
+
+
 class Handle:
     """A library handle bound to a HIP stream (torch's current stream by default)."""
 
@@ -147,6 +167,7 @@ class Handle:
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
         self._check(self.lib.kr_create(ctypes.byref(self.ptr), ctypes.c_void_p(s.cuda_stream)))
+        _live_handles.add(self)
 
     def _check(self, status):
         if status < 0:
