@@ -173,6 +173,22 @@ kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps
 kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void* d_x,
                     double* h_loss);
 
+/* kron_ridge without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as kron_ridge; the workspace
+ * is a fixed device array of kr_noalloc_capacity() bytes (64 MiB) in the library,
+ * one per device, held until the process ends, instead of the handle's
+ * growable workspace.  Problems whose workspace exceeds it return
+ * KR_EUNSUPPORTED (the message gives both sizes) before anything is enqueued.
+ * Every call on a device shares that device's array and overwrites it (the
+ * kernels clear what must start at zero); calls that overlap on one device,
+ * from any handle or thread, race.  kr_export_sketch after such a call reads
+ * the array, so it is valid until the next allocation-free call. */
+kr_status kron_ridge_noalloc(kr_handle h, const kr_problem* p, double lambda, double eps,
+                             double delta, const kr_opts* opts, void* d_x, kr_info* h_info);
+/* Bytes of device scratch behind kron_ridge_noalloc. */
+int64_t kr_noalloc_capacity(void);
+
 /* Many independent ridge problems (Algorithm 2 each; uneven N, I_n, R_n and
  * right-hand sides) in one call: count problems probs[i] with regularisation
  * lambda[i] (host array) and outputs d_x[i] (host array of device pointers, each

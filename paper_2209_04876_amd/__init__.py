@@ -114,6 +114,9 @@ def load_library(path=LIB_PATH):
     P, O, IN = ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.POINTER(Info)
     lib.kron_regress.argtypes = [c_p, P, c_d, c_d, O, c_p, IN]
     lib.kron_ridge.argtypes = [c_p, P, c_d, c_d, c_d, O, c_p, IN]
+    lib.kron_ridge_noalloc.argtypes = [c_p, P, c_d, c_d, c_d, O, c_p, IN]
+    lib.kr_noalloc_capacity.argtypes = []
+    lib.kr_noalloc_capacity.restype = ctypes.c_int64
     lib.kron_ridge_batched.argtypes = [c_p, ctypes.c_int32, P, ctypes.POINTER(c_d), c_d, c_d, O,
                                        ctypes.POINTER(c_p), IN]
     lib.kr_batched_config.argtypes = [c_p, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_int32)]
@@ -125,7 +128,7 @@ def load_library(path=LIB_PATH):
     lib.kr_profile_query.argtypes = [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(c_d)]
     lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
-    for name in ("kr_batched_config", "kron_ridge_batched", "kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_loss",
+    for name in ("kr_batched_config", "kron_ridge_batched", "kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_ridge_noalloc", "kron_loss",
                  "kron_exact", "kr_export_sketch", "tucker_factor_update"):
         getattr(lib, name).restype = c_i
     _lib = lib
@@ -271,6 +274,27 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
     if st == KR_WMAXITER and not allow_maxiter:
         raise KronRegressError(st, "iteration limit reached")
     return x, info.as_dict()
+
+
+def kron_ridge_noalloc(As, b, lam, x, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
+                       check_every=8, handle=None, precision="f64"):
+    """kron_ridge through the allocation-free entry point: the library's fixed
+    device scratch (noalloc_capacity() bytes per device) replaces the handle's
+    workspace.  x (float64 CUDA tensor, prod(R) or prod(R) x nrhs) is the output,
+    allocated by the caller.  Returns (x, info dict)."""
+    h = handle or default_handle()
+    p, _keep = _problem(As, b)
+    info = Info()
+    st = h.lib.kron_ridge_noalloc(h.ptr, ctypes.byref(p), lam, eps, delta,
+                                  ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every, 0, 0, precision)),
+                                  ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
+    h._check(st)
+    return x, info.as_dict()
+
+
+def noalloc_capacity():
+    """Bytes of device scratch behind kron_ridge_noalloc."""
+    return int(load_library().kr_noalloc_capacity())
 
 
 def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
@@ -461,7 +485,8 @@ def export_sketch(sizes, handle=None, cap=None):
             "Omega": Omega, "counts": counts.astype(np.int64)}
 
 
-__all__ = ["Handle", "KronRegressError", "ResponseGen", "kron_regress", "kron_ridge", "kron_loss", "kron_exact",
+__all__ = ["Handle", "KronRegressError", "ResponseGen", "kron_regress", "kron_ridge", "kron_ridge_noalloc",
+           "noalloc_capacity", "kron_ridge_noalloc", "kron_loss", "kron_exact",
            "tucker_factor_update", "tucker_als", "als_stream",
            "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query",
            "profile_names", "profile_breakdown"]

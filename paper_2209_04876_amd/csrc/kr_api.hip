@@ -270,9 +270,36 @@ static kr_status make_geom(kr_handle h, const kr_problem* p, Geom* g) {
   return KR_OK;
 }
 
+// Device scratch of the allocation-free entry point: one copy per device, held
+// until the process ends.  Host code never uses the array's name as an address
+// (it is a host-side stand-in); it uses the device address that
+// hipGetSymbolAddress returns, fetched once per device (at kr_create, or on the
+// entry point's first call on a device) and kept in g_scratch_ptr.
+#define KR_SCRATCH_BYTES (size_t(64) << 20)
+#define KR_SCRATCH_DEVICES 64
+static __device__ __align__(256) char kr_scratch[KR_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[KR_SCRATCH_DEVICES] = {};
+
+static kr_status scratch_address(kr_handle h, void** out) {
+  int dev = 0;
+  HIPCHK(h, hipGetDevice(&dev));
+  if (dev < 0 || dev >= KR_SCRATCH_DEVICES) KR_FAIL(h, KR_EUNSUPPORTED, "device %d has no scratch slot", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(kr_scratch));
+    if (e != hipSuccess || !p)
+      KR_FAIL(h, KR_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KR_OK;
+}
+
 extern "C" {
 
-const char* kr_version(void) { return "kron_regress gfx950 0.1"; }
+const char* kr_version(void) { return "kron_regress gfx950 0.2"; }
 
 kr_status kr_create(kr_handle* out, void* stream) {
   if (!out) return KR_EINVAL;
@@ -283,6 +310,11 @@ kr_status kr_create(kr_handle* out, void* stream) {
     delete h;
     return KR_ENOMEM;
   }
+  // the scratch address of the current device (the entry point fetches it on its
+  // first call on another device; a failure here is reported by that call)
+  void* sp = nullptr;
+  (void)scratch_address(h, &sp);
+  h->err.clear();
   *out = h;
   return KR_OK;
 }
@@ -821,8 +853,12 @@ static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, 
   return KR_OK;
 }
 
+// ext_ws/ext_cap: a caller-provided device workspace used instead of the
+// handle's (which is then neither allocated nor grown); the solve fails with
+// KR_EUNSUPPORTED when it needs more than ext_cap bytes.
 static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
-                       const kr_opts* opts, void* d_x, kr_info* info) {
+                       const kr_opts* opts, void* d_x, kr_info* info, void* ext_ws = nullptr,
+                       size_t ext_cap = 0) {
   if (!h) return KR_EINVAL;
   kr_opts o{};
   if (opts) o = *opts;
@@ -842,9 +878,17 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   const double eta = 1.0 - std::sqrt(eps);
 
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
-  st = ensure(h, &h->ws, &h->ws_bytes, solve_bytes(g, nblocks, nblocks));
-  if (st != KR_OK) return st;
-  Arena a{(char*)h->ws, h->ws_bytes, 0};
+  const size_t need = solve_bytes(g, nblocks, nblocks);
+  if (ext_ws) {
+    if (need > ext_cap)
+      KR_FAIL(h, KR_EUNSUPPORTED,
+              "this problem needs %zu bytes of device scratch; the allocation-free entry point holds %zu", need,
+              ext_cap);
+  } else {
+    st = ensure(h, &h->ws, &h->ws_bytes, need);
+    if (st != KR_OK) return st;
+  }
+  Arena a{ext_ws ? (char*)ext_ws : (char*)h->ws, ext_ws ? ext_cap : h->ws_bytes, 0};
   ModeTables T{};
   SolveBufs B{};
   Tree tr{};
@@ -1538,6 +1582,17 @@ kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps
                      const kr_opts* opts, void* d_x, kr_info* info) {
   return solve(h, p, lambda, eps, delta, opts, d_x, info);
 }
+
+kr_status kron_ridge_noalloc(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
+                             const kr_opts* opts, void* d_x, kr_info* info) {
+  if (!h) return KR_EINVAL;
+  void* ws = nullptr;
+  const kr_status st = scratch_address(h, &ws);
+  if (st != KR_OK) return st;
+  return solve(h, p, lambda, eps, delta, opts, d_x, info, ws, KR_SCRATCH_BYTES);
+}
+
+int64_t kr_noalloc_capacity(void) { return (int64_t)KR_SCRATCH_BYTES; }
 
 kr_status kron_ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
                              double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {

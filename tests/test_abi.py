@@ -12,7 +12,7 @@ LIB = os.path.join(ROOT, "paper_2209_04876_amd", "libkron_regress.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:kr_status|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:kr_status|const char\*|int64_t)\s+(\w+)\s*\(", text, flags=re.M)))
 
 
 def test_header_declares_the_boundary():
