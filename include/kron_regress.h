@@ -106,6 +106,10 @@ typedef struct {
   int32_t workgroups; /* workgroups of the cooperative iteration (0 = automatic)      */
   int32_t precision;  /* kr_precision of the Richardson iteration (0 = KR_PREC_F64)   */
   int32_t reserved;   /* must be 0                                                    */
+  int32_t lev_rows;   /* KR_OPT_APPROX_LEVERAGE: rows k_n of each spectral
+                         approximation (0 = 64 R_n ceil(log2(2 R_n)))                 */
+  int32_t lev_proj;   /* KR_OPT_APPROX_LEVERAGE: rows r of the Johnson-Lindenstrauss
+                         projection, 1..64 (0 = 32)                                   */
 } kr_opts;
 
 /* kr_opts.precision.  The fixed point of the Richardson iteration of Algorithm 2
@@ -138,6 +142,26 @@ typedef enum { KR_PREC_F64 = 0, KR_PREC_F32 = 1, KR_PREC_BF16 = 2, KR_PREC_FP8 =
  * fastest for the handle, and returns the results of a final solve with it. */
 #define KR_OPT_GRAPH 4
 #define KR_OPT_AUTOTUNE 8
+/* kr_opts.flags: approximate leverage scores for large factors, as Algorithm 2's
+ * first loop states it, instead of exact ones.  Per factor: a spectral
+ * approximation A~ of k_n = opts.lev_rows rows drawn i.i.d. from the even mixture
+ * q_i = (||a_i||^2 / ||A||_F^2 + 1/I_n) / 2 of the squared row norms and the
+ * uniform distribution (quantised on the 2^32 grid like the sampling weights; row
+ * t = a_i / sqrt(k_n q'_i), so E[A~^T A~] = A^T A; Lemma
+ * block_sketch_is_spectral_approx, the mixture being a beta-overestimate with
+ * beta >= max(1/kappa(A)^2, R_n / (I_n max l)) / 2); the eigen-decomposition of
+ * A~^T A~, which also gives the
+ * preconditioner's V and Sigma; then the scores of Lemma fast-ls-comp,
+ * ||G A~ M a_i||^2 / ((1 + eps/4)(1 - eps/20)) with M = (1 + eps/4)(A~^T A~)^+ and
+ * a Gaussian projection G / sqrt(r) of r = opts.lev_proj rows (Lemma
+ * random-projection).  Random bits: Philox4x64-10 with key (seed, stream); row t
+ * of A~ for mode n from word 0 of counter (t, n, 0, 1) (top 32 bits against the
+ * inclusive CDF of those weights); G[c][t] of mode n by the Box-Muller
+ * transform above on words 0 and 1 of counter (t, c, n, 2).  The row sampling of
+ * K then draws from these scores exactly as from exact ones (any distribution
+ * gives an unbiased sketch; its quality is the beta of the scores).  Exact
+ * leverage stays the default. */
+#define KR_OPT_APPROX_LEVERAGE 16
 
 typedef struct {
   int32_t iters;          /* Richardson iterations performed (max over RHS)          */
@@ -236,6 +260,19 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
                                double lambda, double eps, double delta, const kr_opts* opts,
                                void* d_A_out, kr_info* h_info);
 
+/* The exact factor update of Algorithm 1 (TuckerALS), the ALS baseline of the
+ * paper's Tucker experiments: every row i of factor `mode` is
+ * argmin_y ||K G_(n)^T y - X_(n)[i]^T||^2 + lambda ||y||^2 (K the Kronecker product of
+ * the other factors in mode order), solved through its normal equations
+ * (G_(n) K^T K G_(n)^T + lambda I) y = G_(n) K^T X_(n)[i]^T with K^T K the Kronecker
+ * product of the other Gram matrices and K^T X_(n)^T the tensor-times-matrix chain
+ * X x_{m != n} A_m^T.  Arguments as tucker_factor_update (p->b the tensor, FP64 or
+ * FP32; d_core float64 R_1..R_N; d_A_out I_mode x R_mode float64, may alias
+ * p->A[mode]).  KR_ESINGULAR when the R_mode x R_mode matrix is not positive
+ * definite. */
+kr_status tucker_factor_exact(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode,
+                              double lambda, void* d_A_out);
+
 /* Test support: copy the last solve's sketch to host memory.  Any pointer may be
  * NULL.  h_Q: sum_n I_n uint64 integer weights (mode-major); h_rows: distinct
  * rows as per-mode indices, D x N int32 (sorted by linear row index); h_Omega: D
@@ -245,6 +282,26 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
  * weights of the other modes (entries of the row pseudo-mode are zero). */
 kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega,
                            int32_t* h_counts, int64_t cap, int64_t* h_D);
+
+/* Test support: the sketch of problem `problem` (0-based) of the last
+ * kron_ridge_batched call, in the same form as kr_export_sketch and in the
+ * caller's mode order: h_Q holds the weights of the problem's modes in the order
+ * it passed them, and h_rows its distinct rows as per-mode indices in that
+ * order, sorted by the caller's linear row index (Omega and counts follow the
+ * rows).  KR_EINVAL for a problem outside the last call, or for a problem that
+ * took the single-problem path (its sketch is not kept).  Valid until the
+ * handle's next call. */
+kr_status kr_export_batched_sketch(kr_handle h, int32_t problem, uint64_t* h_Q, int32_t* h_rows,
+                                   double* h_Omega, int32_t* h_counts, int64_t cap, int64_t* h_D);
+
+/* Test support: the float64 leverage scores l_i = a_i^T (A^T A)^+ a_i of every
+ * factor (the statistical leverage of the paper's definition in its
+ * preliminaries, from which the sampling weights are quantised), sum_n I_n
+ * values, mode-major in the caller's mode order, into h_lev (capacity cap
+ * values).  problem < 0: the last single solve; else problem `problem` of the
+ * last batched call.  A mode without leverage scores (the row pseudo-mode of a
+ * Tucker factor update) reads as zeros. */
+kr_status kr_export_leverage(kr_handle h, int32_t problem, double* h_lev, int64_t cap);
 
 /* Measurement support: when enabled, every kernel launch of the handle whose
  * name contains `filter`, or one of its '|'-separated alternatives (NULL or "" =

@@ -77,3 +77,102 @@ def cdf(Q):
 def realised_probabilities(Q):
     """p'_i = Q_i / 2^32, the distribution the sampler actually draws from."""
     return np.asarray(Q, dtype=np.float64) / float(GRID)
+
+
+# ---------------------------------------------------------------------------
+# Approximate leverage scores for large factors (Algorithm 2's first loop:
+# a spectral approximation A~ by Lemma block_sketch_is_spectral_approx, then
+# (1 + eps/2)-approximate scores by Lemma fast-ls-comp with a Johnson-Lindenstrauss
+# projection, Lemma random-projection).
+#
+# Random bits (the build's layout, shared with the GPU by specification only):
+# Philox4x64-10 with key (seed, stream);
+#   row t of A~ for mode n: counter (t, n, 0, 1), word 0, top 32 bits u pick the
+#     row i with C_{i-1} <= u < C_i on the inclusive CDF of the quantised
+#     squared row norms;
+#   entry (c, t) of the projection for mode n: counter (t, c, n, 2), words 0 and
+#     1 through the Box-Muller transform of oracle/response.py, divided by sqrt(r).
+# ---------------------------------------------------------------------------
+
+def row_norm_weights(A):
+    """The distribution that draws the rows of A~, quantised on the 2^32 grid (as
+    quantize): the even mixture q_i = (||a_i||^2 / ||A||_F^2 + 1/I) / 2 of the
+    squared row norms and the uniform distribution.  Each part is a
+    beta-overestimate of the leverage distribution -- the row norms with
+    beta = R sigma_min^2 / ||A||_F^2 >= 1/kappa(A)^2 (l_i <= ||a_i||^2 /
+    sigma_min^2), the uniform one with beta = R / (I max_i l_i) -- so the mixture is
+    one with beta >= max of the two / 2: the row norms find the coherent (heavy)
+    rows, the uniform part keeps the directions that only light rows span."""
+    A = np.asarray(A, dtype=np.float64)
+    sq = np.sum(A * A, axis=1)
+    return quantize(sq / np.sum(sq) + 1.0 / A.shape[0])
+
+
+def spectral_approximation(A, k, seed, stream, mode):
+    """A~ = S A for S = RowSampling(A, k, q') (Definition def:sample_rows_alg) with q'
+    the realised distribution of row_norm_weights: k rows drawn i.i.d., row t equal to
+    a_{i_t} / sqrt(k q'_{i_t}), so that E[A~^T A~] = A^T A.  By Lemma
+    block_sketch_is_spectral_approx (second block empty), (1 - e0) A^T A <= A~^T A~
+    <= (1 + e0) A^T A with probability 1 - delta once k > 144 R ln(2R/delta) /
+    (beta e0^2).  Returns (A~, row indices)."""
+    from .philox import philox4x64_10
+    A = np.asarray(A, dtype=np.float64)
+    Q = row_norm_weights(A)
+    C = cdf(Q)
+    t = np.arange(k, dtype=np.uint64)
+    w = philox4x64_10([t, np.uint64(mode), np.uint64(0), np.uint64(1)], (seed, stream))[0]
+    rows = np.searchsorted(C, w >> np.uint64(32), side="right")
+    qp = Q[rows].astype(np.float64) / float(GRID)
+    return A[rows] / np.sqrt(k * qp)[:, None], rows
+
+
+def jl_projection(r, k, seed, stream, mode, t0=0):
+    """G / sqrt(r): r x k with i.i.d. N(0, 1) entries G[c, t] (Lemma
+    random-projection); columns t0 .. t0 + k - 1 of it."""
+    from .philox import philox4x64_10
+    from .response import box_muller
+    t = np.arange(t0, t0 + k, dtype=np.uint64)[None, :]
+    c = np.arange(r, dtype=np.uint64)[:, None]
+    w = philox4x64_10([t, c, np.uint64(mode), np.uint64(2)], (seed, stream))
+    return box_muller(w[0], w[1]) / np.sqrt(float(r))
+
+
+def jl_apply(At, r, seed, stream, mode, chunk=1024):
+    """(G / sqrt(r)) A~, with the projection's columns generated chunk at a time."""
+    At = np.asarray(At, dtype=np.float64)
+    out = np.zeros((r, At.shape[1]))
+    for t0 in range(0, At.shape[0], chunk):
+        blk = At[t0:t0 + chunk]
+        out += jl_projection(r, blk.shape[0], seed, stream, mode, t0) @ blk
+    return out
+
+
+def gram_pinv(N, I=None):
+    """N^+ through the symmetric eigen-decomposition, over the numerical rank
+    (eigenvalues above (max(I, R) u)^2 lambda_max, the rule of the exact path)."""
+    ev, V = np.linalg.eigh(N)
+    R = N.shape[0]
+    eps_r = max(I or R, R) * np.finfo(np.float64).eps
+    keep = ev > eps_r * eps_r * max(ev.max(), 0.0)
+    return (V[:, keep] / ev[keep]) @ V[:, keep].T
+
+
+def jl_leverage_scores(A, At, r, eps, seed, stream, mode):
+    """Lemma fast-ls-comp: with N = A~^T A~ and M = (1 + eps/4) N^+, the scores
+    ||G A~ M a_i||^2 / ((1 + eps/4)(1 - eps/20)) for the projection G of
+    jl_projection.  When A^T A <= A~^T A~ <= (1 + eps/4) A^T A and r is large
+    enough for an eps/20 projection, each lies in [l_i, (1 + eps/2) l_i].  (A
+    uniform factor cancels from the sampling distribution p = l~ / sum l~.)"""
+    A = np.asarray(A, dtype=np.float64)
+    At = np.asarray(At, dtype=np.float64)
+    M = (1.0 + eps / 4.0) * gram_pinv(At.T @ At, A.shape[0])
+    Z = jl_apply(At, r, seed, stream, mode) @ M
+    return np.sum((A @ Z.T) ** 2, axis=1) / ((1.0 + eps / 4.0) * (1.0 - eps / 20.0))
+
+
+def approximate_leverage_scores(A, k, r, eps, seed, stream, mode):
+    """Algorithm 2's approximate scores of one factor: jl_leverage_scores on the
+    spectral approximation of spectral_approximation.  Returns (scores, A~^T A~),
+    the Gram whose eigen-decomposition gives the preconditioner's V and Sigma."""
+    At, _ = spectral_approximation(A, k, seed, stream, mode)
+    return jl_leverage_scores(A, At, r, eps, seed, stream, mode), At.T @ At

@@ -196,3 +196,110 @@ def fast_kronecker_regression(As, b, lam, eps, m, seed, stream=0, tol=1e-12,
         out["x_direct"] = solve_sketched_direct(KD, out["Omega"], bD, lam)
     out.update(richardson(As, KD, out["Omega"], bD, lam, eps, tol, max_iter))
     return out
+
+
+def _split(As, ridx, t):
+    """Common part of the split products: the distinct T^c-prefixes (first N - t
+    modes) of the distinct rows, the explicit Kronecker rows of those prefixes
+    (|S_2| x R_{T^c}), the row ranges [start_s, start_{s+1}) of each prefix (rows
+    sorted by linear index keep each prefix's rows together), and R_T."""
+    N = len(As)
+    if not 1 <= t < N:
+        raise ValueError("the split needs 1 <= t < N")
+    I = [np.asarray(A).shape[0] for A in As]
+    pre = np.zeros(ridx.shape[0], dtype=np.int64)
+    for n in range(N - t):
+        pre = pre * int(I[n]) + ridx[:, n]
+    if np.any(np.diff(pre) < 0):
+        raise ValueError("rows must be sorted by linear index (as merge returns them)")
+    starts = np.concatenate([[0], np.flatnonzero(np.diff(pre)) + 1, [ridx.shape[0]]])
+    Abar = kron_rows(As[:N - t], ridx[starts[:-1], :N - t])
+    RT = int(np.prod([np.asarray(A).shape[1] for A in As[N - t:]]))
+    return Abar, starts, RT
+
+
+def _row_blocks(starts, rows_per_block):
+    """Consecutive runs of prefixes [s0, s1) holding about rows_per_block rows."""
+    s0 = 0
+    ns = starts.size - 1
+    while s0 < ns:
+        s1 = int(np.searchsorted(starts, starts[s0] + rows_per_block, side="right")) - 1
+        s1 = max(s1, s0 + 1)
+        yield s0, min(s1, ns)
+        s0 = min(s1, ns)
+
+
+def sampled_forward_split(As, ridx, x, t, chunk=8192):
+    """K_D x for the distinct sampled rows, by the split of Theorem
+    kron_mat_mul_sqrt_decomp with T the last t modes: P = Abar_{S_2} X_mat (one
+    matrix product over the distinct T^c-prefixes S_2, X_mat the iterate reshaped
+    R_{T^c} x R_T), then the rows of each prefix s are the product of their T
+    Kronecker rows with P[s] (R_T x nrhs).  x: (R,) or (R, nrhs); rows sorted.
+
+    Pinned by tests/test_oracle_regression.py against the explicit rows kron_rows."""
+    x = np.asarray(x, dtype=np.float64)
+    vec = x.ndim == 1
+    X = x[:, None] if vec else x
+    Abar, starts, RT = _split(As, ridx, t)
+    q = X.shape[1]
+    P = (Abar @ X.reshape(Abar.shape[1], RT * q)).reshape(-1, RT, q)
+    N = len(As)
+    out = np.empty((ridx.shape[0], q))
+    for s0, s1 in _row_blocks(starts, chunk):
+        r0, r1 = starts[s0], starts[s1]
+        kT = kron_rows(As[N - t:], ridx[r0:r1, N - t:])
+        for s in range(s0, s1):
+            a, b = starts[s] - r0, starts[s + 1] - r0
+            out[r0 + a:r0 + b] = kT[a:b] @ P[s]
+    return out[:, 0] if vec else out
+
+
+def sampled_adjoint_split(As, ridx, w, t, chunk=8192):
+    """K_D^T w for weights w on the distinct sampled rows ((D,) or (D, nrhs)), by the
+    same split: Q[s] = (T Kronecker rows of prefix s)^T w (R_T x nrhs per prefix),
+    then Abar_{S_2}^T Q reshaped to R x nrhs.  Rows sorted.
+
+    Pinned by tests/test_oracle_regression.py against the explicit rows kron_rows."""
+    w = np.asarray(w, dtype=np.float64)
+    vec = w.ndim == 1
+    W = w[:, None] if vec else w
+    Abar, starts, RT = _split(As, ridx, t)
+    q = W.shape[1]
+    N = len(As)
+    Q = np.zeros((Abar.shape[0], RT, q))
+    for s0, s1 in _row_blocks(starts, chunk):
+        r0, r1 = starts[s0], starts[s1]
+        kT = kron_rows(As[N - t:], ridx[r0:r1, N - t:])
+        for s in range(s0, s1):
+            a, b = starts[s] - r0, starts[s + 1] - r0
+            Q[s] = kT[a:b].T @ W[r0 + a:r0 + b]
+    out = (Abar.T @ Q.reshape(Abar.shape[0], RT * q)).reshape(-1, q)
+    return out[:, 0] if vec else out
+
+
+def sketched_gradient_split(As, ridx, Omega, bD, x, lam, t):
+    """Gradient of the sketched ridge objective (halved), K_D^T diag(Omega)
+    (K_D x - b_D) + lam x, by the split products above; zero exactly at the
+    sketched minimiser (its normal equations)."""
+    u = sampled_forward_split(As, ridx, x, t) - np.asarray(bD, dtype=np.float64)
+    Om = np.asarray(Omega, dtype=np.float64)
+    w = Om * u if u.ndim == 1 else Om[:, None] * u
+    return sampled_adjoint_split(As, ridx, w, t) + lam * np.asarray(x, dtype=np.float64)
+
+
+def split_point(As, ridx):
+    """The t (number of trailing modes in T) that minimises the entries the split
+    products touch, |S_2| R_{T^c} + D R_T (the balance the split theorem asks
+    for; any t gives the same values)."""
+    N = len(As)
+    I = [np.asarray(A).shape[0] for A in As]
+    R = [np.asarray(A).shape[1] for A in As]
+    best, best_t = None, 1
+    for t in range(1, N):
+        pre = np.zeros(ridx.shape[0], dtype=np.int64)
+        for n in range(N - t):
+            pre = pre * int(I[n]) + ridx[:, n]
+        cost = np.unique(pre).size * int(np.prod(R[:N - t])) + ridx.shape[0] * int(np.prod(R[N - t:]))
+        if best is None or cost < best:
+            best, best_t = cost, t
+    return best_t

@@ -37,12 +37,16 @@ def box_muller(w0, w1):
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(TWO_PI * u2)
 
 
-def noise(rows, nrhs, seed, stream):
-    """E[rows][q] for q < nrhs: array of shape (len(rows), nrhs)."""
+def noise(rows, nrhs, seed, stream, chunk=16384):
+    """E[rows][q] for q < nrhs: array of shape (len(rows), nrhs).  Each entry
+    depends on its own counter only; rows are taken chunk at a time."""
     rows = np.asarray(rows, dtype=np.uint64).reshape(-1, 1)
     q = np.arange(nrhs, dtype=np.uint64).reshape(1, -1)
-    w = philox4x64_10([rows, q, np.uint64(0), np.uint64(0)], (seed, stream))
-    return box_muller(w[0], w[1])
+    out = np.empty((rows.shape[0], nrhs))
+    for c0 in range(0, rows.shape[0], chunk):
+        w = philox4x64_10([rows[c0:c0 + chunk], q, np.uint64(0), np.uint64(0)], (seed, stream))
+        out[c0:c0 + chunk] = box_muller(w[0], w[1])
+    return out
 
 
 def implicit_response(As, X_true, sigma, seed, stream):

@@ -29,16 +29,23 @@ from .leverage import GRID, cdf
 from .philox import philox4x64_10
 
 
+CHUNK = 65536
+
+
 def draw_uniform_words(m, n_modes, seed, stream, row=0):
-    """The 64-bit Philox word of each (sample, mode): shape (m, n_modes) uint64."""
-    t = np.arange(m, dtype=np.uint64)
+    """The 64-bit Philox word of each (sample, mode): shape (m, n_modes) uint64.
+
+    Each output depends on its own counter only, so the counters are taken in
+    chunks of CHUNK samples (cache-sized arrays; the values do not depend on it)."""
     out = np.empty((m, n_modes), dtype=np.uint64)
-    for g in range((n_modes + 3) // 4):
-        words = philox4x64_10([t, np.uint64(g), np.uint64(row), np.uint64(0)], (seed, stream))
-        for w in range(4):
-            n = 4 * g + w
-            if n < n_modes:
-                out[:, n] = words[w]
+    for c0 in range(0, m, CHUNK):
+        t = np.arange(c0, min(m, c0 + CHUNK), dtype=np.uint64)
+        for g in range((n_modes + 3) // 4):
+            words = philox4x64_10([t, np.uint64(g), np.uint64(row), np.uint64(0)], (seed, stream))
+            for w in range(4):
+                n = 4 * g + w
+                if n < n_modes:
+                    out[c0:c0 + t.size, n] = words[w]
     return out
 
 
@@ -47,17 +54,30 @@ def sample_product(Qs, m, seed, stream, row=0):
 
     Qs: list of N uint64 weight vectors (each sums to 2^32).
     Returns (idx, omega): idx int64 (m, N), omega float64 (m,).
+    Samples are independent of each other, so they are drawn CHUNK at a time
+    (the result does not depend on it).
     """
     N = len(Qs)
-    words = draw_uniform_words(m, N, seed, stream, row)
-    u = words >> np.uint64(32)
-    idx = np.empty((m, N), dtype=np.int64)
+    Cs = []
     for n, Q in enumerate(Qs):
         C = cdf(Q)
         if int(C[-1]) != GRID:
             raise ValueError("weights of mode %d do not sum to 2^32" % n)
-        idx[:, n] = np.searchsorted(C, u[:, n], side="right")
-    omega = sample_weights(Qs, idx, m)
+        Cs.append(C)
+    idx = np.empty((m, N), dtype=np.int64)
+    omega = np.empty(m, dtype=np.float64)
+    for c0 in range(0, m, CHUNK):
+        c1 = min(m, c0 + CHUNK)
+        t = np.arange(c0, c1, dtype=np.uint64)
+        part = np.empty((c1 - c0, N), dtype=np.int64)
+        for g in range((N + 3) // 4):
+            words = philox4x64_10([t, np.uint64(g), np.uint64(row), np.uint64(0)], (seed, stream))
+            for w in range(4):
+                n = 4 * g + w
+                if n < N:
+                    part[:, n] = np.searchsorted(Cs[n], words[w] >> np.uint64(32), side="right")
+        idx[c0:c1] = part
+        omega[c0:c1] = sample_weights(Qs, part, m)
     return idx, omega
 
 

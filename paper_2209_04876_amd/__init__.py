@@ -11,6 +11,7 @@ Functions mirror the C entry points:
   kron_loss(As, b, x, lam)                 ||K x - b||^2 + lam ||x||^2 (float64)
   kron_exact(As, b, lam)                   exact KronMatMul optimum
   tucker_factor_update(X, As, G, mode, lam) Algorithm 3 (Tucker ALS factor update)
+  tucker_factor_exact(X, As, G, mode, lam)  Algorithm 1's exact factor update
   tucker_als(X, G, As, lam, sweeps)        Algorithm 1 sequenced over the calls above
   export_sketch(handle)                    last solve's sketch (tests)
 """
@@ -64,13 +65,15 @@ class Opts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint64),
                 ("flags", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lev_rows", ctypes.c_int32), ("lev_proj", ctypes.c_int32)]
 
 
 OPT_COOPERATIVE = 1
 OPT_M_RLNR = 2
 OPT_GRAPH = 4
 OPT_AUTOTUNE = 8
+OPT_APPROX_LEVERAGE = 16
 
 # kr_precision: the arithmetic of the Richardson iteration (float64 plain, or
 # refined: float64 residual and update, float32 adjoint, preconditioner in the
@@ -123,13 +126,18 @@ def load_library(path=LIB_PATH):
     lib.kron_loss.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d)]
     lib.kron_exact.argtypes = [c_p, P, c_d, c_p]
     lib.tucker_factor_update.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_d, c_d, O, c_p, IN]
+    lib.tucker_factor_exact.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_p]
     lib.kr_export_sketch.argtypes = [c_p, c_p, c_p, c_p, c_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.kr_export_batched_sketch.argtypes = [c_p, ctypes.c_int32, c_p, c_p, c_p, c_p, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64)]
+    lib.kr_export_leverage.argtypes = [c_p, ctypes.c_int32, c_p, ctypes.c_int64]
     lib.kr_profile_enable.argtypes = [c_p, ctypes.c_int32, ctypes.c_char_p]
     lib.kr_profile_query.argtypes = [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(c_d)]
     lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
     for name in ("kr_batched_config", "kron_ridge_batched", "kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_ridge_noalloc", "kron_loss",
-                 "kron_exact", "kr_export_sketch", "tucker_factor_update"):
+                 "kron_exact", "kr_export_sketch", "kr_export_batched_sketch", "kr_export_leverage",
+                 "tucker_factor_update", "tucker_factor_exact"):
         getattr(lib, name).restype = c_i
     _lib = lib
     return lib
@@ -245,22 +253,30 @@ def _x_like(As, nrhs, one_dim):
     return torch.empty(shape, dtype=torch.float64, device=As[0].device)
 
 
-def _opts(m, max_iter, tol, seed, stream, check_every, flags=0, workgroups=0, precision="f64"):
+def _opts(m, max_iter, tol, seed, stream, check_every, flags=0, workgroups=0, precision="f64",
+          approx_leverage=None):
+    """approx_leverage: None for exact leverage, or (k, r) -- the rows of each spectral
+    approximation and of the projection (0 = the library's defaults)."""
     o = Opts()
     o.m, o.max_iter, o.seed, o.stream, o.check_every = m, max_iter, seed, stream, check_every
     o.tol = 0.0 if tol is None else tol
     o.flags, o.workgroups = flags, workgroups
     o.precision = _precision(precision)
+    if approx_leverage is not None:
+        o.flags |= OPT_APPROX_LEVERAGE
+        o.lev_rows, o.lev_proj = int(approx_leverage[0]), int(approx_leverage[1])
     return o
 
 
 def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
                check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
-               workgroups=0, precision="f64"):
+               workgroups=0, precision="f64", approx_leverage=None):
     """Algorithm 2 with regularisation lam.  Returns (x float64, info dict).
 
     tol=None takes the library default (1e-12 for "f64", 1e-9 for the refined
-    precisions "f32", "bf16", "fp8")."""
+    precisions "f32", "bf16", "fp8").  approx_leverage=(k, r) takes Algorithm 2's
+    approximate leverage scores (spectral approximation of k rows per factor, JL
+    projection of r rows; 0 = defaults) instead of exact ones."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
@@ -268,7 +284,8 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
     info = Info()
     st = h.lib.kron_ridge(h.ptr, ctypes.byref(p), lam, eps, delta,
                           ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                             OPT_COOPERATIVE if cooperative else 0, workgroups, precision)),
+                                             OPT_COOPERATIVE if cooperative else 0, workgroups, precision,
+                                             approx_leverage)),
                           ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:
@@ -299,9 +316,9 @@ def noalloc_capacity():
 
 def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
                  check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
-                 workgroups=0, precision="f64"):
+                 workgroups=0, precision="f64", approx_leverage=None):
     """Algorithm 2 (lambda = 0).  Returns (x float64, info dict); see kron_ridge
-    for tol and precision."""
+    for tol, precision and approx_leverage."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
@@ -309,7 +326,8 @@ def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200
     info = Info()
     st = h.lib.kron_regress(h.ptr, ctypes.byref(p), eps, delta,
                             ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                               OPT_COOPERATIVE if cooperative else 0, workgroups, precision)),
+                                               OPT_COOPERATIVE if cooperative else 0, workgroups, precision,
+                                               approx_leverage)),
                             ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:
@@ -407,18 +425,43 @@ def tucker_factor_update(X, As, G, mode, lam, eps=0.1, delta=0.01, m=0, seed=0, 
     return out, info.as_dict()
 
 
+def tucker_factor_exact(X, As, G, mode, lam, handle=None, out=None):
+    """Algorithm 1's exact factor update (the ALS baseline): the new factor `mode`
+    (float64 I_mode x R_mode).  Arguments as tucker_factor_update."""
+    torch = _torch()
+    h = handle or default_handle()
+    p, _keep = _problem(As, X.reshape(-1))
+    if G.dtype != torch.float64 or not G.is_contiguous() or not G.is_cuda:
+        raise ValueError("core must be a contiguous float64 CUDA tensor")
+    if out is None:
+        out = torch.empty(As[mode].shape, dtype=torch.float64, device=As[mode].device)
+    h._check(h.lib.tucker_factor_exact(h.ptr, ctypes.byref(p), ctypes.c_void_p(G.data_ptr()), mode, lam,
+                                       ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
 def als_stream(sweep, step):
     """Philox stream of ALS step `step` (mode n, or N for the core) of a sweep."""
     return (int(sweep) << 8) | int(step)
 
 
-def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, handle=None, tol=1e-12):
-    """Algorithm 1 (TuckerALS) driven through the C ABI: for every sweep, the
-    factor updates of Algorithm 3 in mode order, then the core update by
-    Algorithm 2 (kron_ridge with b = vec(X)), and the relative reconstruction
-    error ||X^ - X||^2 / ||X||^2 from kron_loss.  X, G and the factors are CUDA
-    tensors (G and the factors float64); returns (G, As, [rre per sweep])."""
+def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, handle=None, tol=1e-12,
+               factor_update="sketched", core_update="sketched", stats=None, max_iter=400):
+    """Algorithm 1 (TuckerALS) driven through the C ABI: for every sweep, the factor
+    updates in mode order, then the core update, then the relative reconstruction
+    error ||X^ - X||^2 / ||X||^2 from kron_loss.
+
+    factor_update: "sketched" (Algorithm 3, tucker_factor_update with m_factor
+    samples per row) or "exact" (tucker_factor_exact, the ALS baseline);
+    core_update: "sketched" (Algorithm 2, kron_ridge with b = vec(X) and m_core
+    samples) or "exact" (kron_exact).  Every update's status is checked: one that
+    does not end in OK raises KronRegressError.  stats, if a list, receives one
+    dict per update (sweep, step, iterations, distinct rows, status).  X, G and the
+    factors are CUDA tensors (G and the factors float64); returns (G, As, [rre per
+    sweep])."""
     torch = _torch()
+    if factor_update not in ("sketched", "exact") or core_update not in ("sketched", "exact"):
+        raise ValueError("factor_update and core_update are 'sketched' or 'exact'")
     h = handle or default_handle()
     As = [A.clone() for A in As]
     G = G.clone()
@@ -427,12 +470,29 @@ def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, han
     zero = torch.zeros(G.numel(), dtype=torch.float64, device=G.device)
     xx = kron_loss(As, Xv, zero, 0.0, handle=h)[0]
     trace = []
+
+    def record(s, step, info):
+        if info["status"] != "OK":
+            raise KronRegressError(KR_WMAXITER if info["status"] == "WMAXITER" else -1,
+                                   "ALS sweep %d step %d ended in %s" % (s, step, info["status"]))
+        if stats is not None:
+            stats.append(dict(sweep=s, step=step, iters=info["iters"], distinct_rows=info["distinct_rows"],
+                              status=info["status"]))
+
     for s in range(sweeps):
         for n in range(N):
-            As[n], _ = tucker_factor_update(X, As, G, n, lam, eps=eps, m=m_factor, seed=seed,
-                                            stream=als_stream(s, n), handle=h, tol=tol)
-        g, _ = kron_ridge(As, Xv, lam, eps=eps, m=m_core, seed=seed, stream=als_stream(s, N), handle=h,
-                          tol=tol)
+            if factor_update == "exact":
+                As[n] = tucker_factor_exact(X, As, G, n, lam, handle=h)
+            else:
+                As[n], info = tucker_factor_update(X, As, G, n, lam, eps=eps, m=m_factor, seed=seed,
+                                                   stream=als_stream(s, n), handle=h, tol=tol, max_iter=max_iter)
+                record(s, n, info)
+        if core_update == "exact":
+            g = kron_exact(As, Xv, lam, handle=h)
+        else:
+            g, info = kron_ridge(As, Xv, lam, eps=eps, m=m_core, seed=seed, stream=als_stream(s, N), handle=h,
+                                 tol=tol, max_iter=max_iter)
+            record(s, N, info)
         G = g.reshape(G.shape)
         trace.append(kron_loss(As, Xv, g, 0.0, handle=h)[0] / xx)
     return G, As, trace
@@ -466,27 +526,48 @@ def profile_breakdown(handle=None):
     return {n: profile_query(n, handle) for n in profile_names(handle)}
 
 
-def export_sketch(sizes, handle=None, cap=None):
-    """The last solve's sketch: Q tables per mode, distinct rows (D x N), Omega, counts."""
+def _export(call, sizes):
     import numpy as np
-    h = handle or default_handle()
     D = ctypes.c_int64()
-    h._check(h.lib.kr_export_sketch(h.ptr, None, None, None, None, 0, ctypes.byref(D)))
+    call(None, None, None, None, 0, ctypes.byref(D))
     D = D.value
     N = len(sizes)
     Q = np.zeros(int(sum(sizes)), dtype=np.uint64)
     rows = np.zeros((D, N), dtype=np.int32)
     Omega = np.zeros(D, dtype=np.float64)
     counts = np.zeros(D, dtype=np.int32)
-    h._check(h.lib.kr_export_sketch(h.ptr, Q.ctypes.data, rows.ctypes.data, Omega.ctypes.data,
-                                    counts.ctypes.data, D, ctypes.byref(ctypes.c_int64())))
+    call(Q.ctypes.data, rows.ctypes.data, Omega.ctypes.data, counts.ctypes.data, D, ctypes.byref(ctypes.c_int64()))
     offs = np.cumsum([0] + list(sizes))
     return {"Q": [Q[offs[n]:offs[n + 1]] for n in range(N)], "rows": rows.astype(np.int64),
             "Omega": Omega, "counts": counts.astype(np.int64)}
 
 
+def export_sketch(sizes, handle=None):
+    """The last solve's sketch: Q tables per mode, distinct rows (D x N), Omega, counts."""
+    h = handle or default_handle()
+    return _export(lambda *a: h._check(h.lib.kr_export_sketch(h.ptr, *a)), sizes)
+
+
+def export_batched_sketch(problem, sizes, handle=None):
+    """The sketch of problem `problem` of the last kron_ridge_batched call, in the
+    caller's mode order (same form as export_sketch)."""
+    h = handle or default_handle()
+    return _export(lambda *a: h._check(h.lib.kr_export_batched_sketch(h.ptr, int(problem), *a)), sizes)
+
+
+def export_leverage(sizes, problem=-1, handle=None):
+    """Float64 leverage scores of every factor (list per mode) of the last single
+    solve (problem=-1) or of problem `problem` of the last batched call."""
+    import numpy as np
+    h = handle or default_handle()
+    lev = np.zeros(int(sum(sizes)), dtype=np.float64)
+    h._check(h.lib.kr_export_leverage(h.ptr, int(problem), lev.ctypes.data, lev.size))
+    offs = np.cumsum([0] + list(sizes))
+    return [lev[offs[n]:offs[n + 1]] for n in range(len(sizes))]
+
+
 __all__ = ["Handle", "KronRegressError", "ResponseGen", "kron_regress", "kron_ridge", "kron_ridge_noalloc",
            "noalloc_capacity", "kron_ridge_noalloc", "kron_loss", "kron_exact",
-           "tucker_factor_update", "tucker_als", "als_stream",
-           "export_sketch", "load_library", "default_handle", "profile_enable", "profile_query",
+           "tucker_factor_update", "tucker_factor_exact", "tucker_als", "als_stream",
+           "export_sketch", "export_batched_sketch", "export_leverage", "load_library", "default_handle", "profile_enable", "profile_query",
            "profile_names", "profile_breakdown"]

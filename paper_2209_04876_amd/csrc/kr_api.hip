@@ -18,6 +18,7 @@
 
 #include "kr_internal.h"
 #include "kr_setup.hip"
+#include "kr_leverage.hip"
 #include "kr_sketch.hip"
 #include "kr_iter.hip"
 #include "kr_stream.hip"
@@ -44,6 +45,17 @@ struct Arena {
   }
 };
 
+// Where one solve's sketch lives in the workspace: geometry (with the mode
+// order of its tree), tables, tree, merged weights and multiplicities.
+struct SketchRec {
+  bool valid = false;
+  Geom g{};
+  ModeTables T{};
+  Tree tr{};
+  double* Omega = nullptr;
+  int32_t* counts = nullptr;
+};
+
 }  // namespace
 
 struct kr_handle_s {
@@ -68,13 +80,11 @@ struct kr_handle_s {
   hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // last sketch, for kr_export_sketch
-  bool has_sketch = false;
-  Geom g{};
-  ModeTables T{};
-  Tree tr{};
-  double* Omega = nullptr;
-  int32_t* counts = nullptr;
+  // last single solve's sketch (kr_export_sketch, kr_export_leverage) and every
+  // problem's sketch of the last batched call (kr_export_batched_sketch); the
+  // pointers reference the workspace, valid until the next call
+  SketchRec last;
+  std::vector<SketchRec> batch;
   // optional per-kernel timing with HIP events on the handle's stream
   bool prof_on = false;
   std::string prof_filter;
@@ -224,7 +234,8 @@ static kr_status ensure(kr_handle h, void** buf, size_t* cap, size_t need) {
     KR_FAIL(h, KR_ENOMEM, "device workspace of %zu bytes could not be allocated", want);
   }
   *cap = want;
-  h->has_sketch = false;
+  h->last.valid = false;
+  h->batch.clear();
   return KR_OK;
 }
 
@@ -406,7 +417,30 @@ struct SetupBufs {
   double* A64[KR_MAXN];
   double* gram;
   int32_t* flags;
+  // large-factor passes (see setup_large): per-block sums of the row passes and
+  // of the integer weights, per-block argmax keys, per-block partial Grams (exact
+  // route) or the spectral approximations and projections (approximate route)
+  double* lpart[KR_MAXN];
+  double* lpart2[KR_MAXN];
+  uint64_t* qpart[KR_MAXN];
+  uint64_t* qbest[KR_MAXN];
+  double* gpart[KR_MAXN];
+  double* At[KR_MAXN];
+  double* Z[KR_MAXN];
 };
+
+// Factors with more rows than this, and every factor of an approximate-leverage
+// solve, take the many-workgroup setup passes of kr_leverage.hip.
+#define LV_SMALL_I 16384
+
+static bool setup_large(const Geom& g) {
+  if (g.approx) return true;
+  for (int n = 0; n < g.N; ++n)
+    if (g.I[n] > LV_SMALL_I) return true;
+  return false;
+}
+
+static int lv_blocks(int I) { return (I + LV_RPB - 1) / LV_RPB; }
 
 static void carve_setup(Arena& a, const Geom& g, ModeTables* T, SetupBufs* s) {
   for (int n = 0; n < g.N; ++n) {
@@ -421,12 +455,36 @@ static void carve_setup(Arena& a, const Geom& g, ModeTables* T, SetupBufs* s) {
   }
   s->gram = a.take<double>((size_t)g.N * 64 * 64);
   s->flags = a.take<int32_t>(64);
+  for (int n = 0; n < KR_MAXN; ++n)
+    s->lpart[n] = s->lpart2[n] = nullptr, s->qpart[n] = s->qbest[n] = nullptr,
+    s->gpart[n] = s->At[n] = s->Z[n] = nullptr;
+  if (!setup_large(g)) return;
+  for (int n = 0; n < g.N; ++n) {
+    const int nb = lv_blocks(g.I[n]);
+    s->lpart[n] = a.take<double>(nb);
+    s->lpart2[n] = a.take<double>(nb);
+    s->qpart[n] = a.take<uint64_t>(nb);
+    s->qbest[n] = a.take<uint64_t>(nb);
+    if (g.approx) {
+      s->At[n] = a.take<double>((size_t)g.lev_k[n] * g.R[n]);
+      s->Z[n] = a.take<double>((size_t)g.lev_r * g.R[n]);
+    } else {
+      s->gpart[n] = a.take<double>((size_t)nb * g.R[n] * g.R[n]);
+    }
+  }
 }
 
 static size_t setup_bytes(const Geom& g) {
   size_t b = 0;
   for (int n = 0; n < g.N; ++n)
     b += 8 * ((size_t)g.I[n] * g.R[n] + 2 * (size_t)g.R[n] * g.R[n] + g.R[n] + 3 * (size_t)g.I[n]) + 7 * 256;
+  if (setup_large(g))
+    for (int n = 0; n < g.N; ++n) {
+      const size_t nb = lv_blocks(g.I[n]);
+      b += 32 * nb + 4 * 256;
+      b += g.approx ? 8 * ((size_t)g.lev_k[n] * g.R[n] + (size_t)g.lev_r * g.R[n]) + 2 * 256
+                    : 8 * nb * g.R[n] * g.R[n] + 256;
+    }
   return b + 8 * (size_t)g.N * 4096 + 1024;
 }
 
@@ -444,16 +502,9 @@ static void launch_promote(kr_handle h, const kr_problem* p, const Geom& g, doub
   KL(h, k_promote_all, dim3(grid_for(cmax, 256, 1024), g.N), dim3(256), 0, s, pa, p->a_dtype, flags);
 }
 
-// Factor setup: float64 copies, Grams, then the eigen-decomposition (eig) or, when
-// only G^{-1} is needed (lambda = 0 solves), the Cholesky route; then the
-// leverage tables.
-static kr_status launch_setup(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T,
-                              const SetupBufs& s, bool leverage, bool eig = true) {
-  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, h->stream, (uint32_t*)s.flags, (int64_t)64);
-  launch_promote(h, p, g, s.A64, s.flags, h->stream);
-  KL(h, k_gram, dim3(g.N), dim3(256), 0, h->stream, T, g, s.gram);
-  int maxR = 1;
-  for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
+// The Gram matrices' eigen-decomposition (eig) or Cholesky factor (lambda = 0
+// solves that need only G^{-1}).
+static void launch_factor(kr_handle h, const Geom& g, const ModeTables& T, const SetupBufs& s, bool eig, int maxR) {
   if (eig) {
     KL(h, k_eig, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
   } else if (maxR <= 8) {
@@ -465,6 +516,174 @@ static kr_status launch_setup(kr_handle h, const kr_problem* p, const Geom& g, c
   } else {
     KLN(h, "k_chol<64>", k_chol<64>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
   }
+}
+
+template <int RM>
+static void launch_quadform(kr_handle h, const Geom& g, const LevPass& lp) {
+  int nbmax = 1;
+  for (int n = 0; n < g.N; ++n) nbmax = std::max(nbmax, lv_blocks(g.I[n]));
+  KLN(h, "k_row_quadform", k_row_quadform<RM>, dim3(nbmax, g.N), dim3(LV_THREADS), 0, h->stream, lp);
+}
+
+// The integer weights and CDF of every mode from the weights T.lev and their
+// per-block sums s.lpart (many workgroups per mode).
+static void launch_quantise(kr_handle h, const Geom& g, const ModeTables& T, const SetupBufs& s,
+                            bool second = false) {
+  QuantPass qp{};
+  int nbmax = 1;
+  for (int n = 0; n < g.N; ++n) {
+    qp.w[n] = T.lev[n];
+    qp.part[n] = second ? s.lpart2[n] : s.lpart[n];
+    qp.Q[n] = T.Q[n];
+    qp.C[n] = T.C[n];
+    qp.qpart[n] = s.qpart[n];
+    qp.qbest[n] = s.qbest[n];
+    qp.I[n] = g.I[n];
+    qp.nb[n] = lv_blocks(g.I[n]);
+    nbmax = std::max(nbmax, qp.nb[n]);
+  }
+  KL(h, k_quant_blocks, dim3(nbmax, g.N), dim3(LV_THREADS), 0, h->stream, qp, s.flags);
+  KL(h, k_quant_fix, dim3(1), dim3(64), 0, h->stream, qp, g.N, s.flags);
+  KL(h, k_cdf_blocks, dim3(nbmax, g.N), dim3(LV_THREADS), 0, h->stream, qp);
+}
+
+// Setup of large factors (or approximate leverage) on many workgroups per mode.
+// Exact route: partial Grams summed in block order, the eigen-decomposition or
+// Cholesky factor, then l_i = sum_k (a_i . v_k)^2 / lambda_k.  Approximate route
+// (Algorithm 2's first loop): squared row norms and their tables, k_n rows of the
+// spectral approximation A~, the eigen-decomposition of A~^T A~ (the
+// preconditioner's V and Sigma), the projection Z = (G / sqrt(r)) A~ M, and the
+// scores ||Z a_i||^2 / ((1 + eps/4)(1 - eps/20)).  Then the integer weights and CDF.
+static kr_status launch_setup_large(kr_handle h, const Geom& g, const ModeTables& T, const SetupBufs& s,
+                                    bool leverage, bool eig, uint64_t seed, uint64_t stream) {
+  int maxR = 1, nbmax = 1;
+  for (int n = 0; n < g.N; ++n) {
+    maxR = std::max<int>(maxR, (int)g.R[n]);
+    nbmax = std::max(nbmax, lv_blocks(g.I[n]));
+  }
+  auto quadform = [&](const LevPass& lp) {
+    if (maxR <= 8) launch_quadform<8>(h, g, lp);
+    else if (maxR <= 16) launch_quadform<16>(h, g, lp);
+    else if (maxR <= 32) launch_quadform<32>(h, g, lp);
+    else launch_quadform<64>(h, g, lp);
+  };
+  LevPass lp{};
+  for (int n = 0; n < g.N; ++n) {
+    lp.A[n] = T.A[n];
+    lp.out[n] = T.lev[n];
+    lp.part[n] = s.lpart[n];
+    lp.I[n] = g.I[n];
+    lp.R[n] = g.R[n];
+  }
+  if (!g.approx) {
+    GramPass gp{};
+    for (int n = 0; n < g.N; ++n) {
+      gp.A[n] = T.A[n];
+      gp.part[n] = s.gpart[n];
+      gp.I[n] = g.I[n];
+      gp.R[n] = g.R[n];
+      gp.nb[n] = lv_blocks(g.I[n]);
+    }
+    gp.gram = s.gram;
+    KL(h, k_gram_part, dim3(nbmax, g.N), dim3(256), 0, h->stream, gp);
+    KL(h, k_gram_sum, dim3(g.N), dim3(256), 0, h->stream, gp);
+    launch_factor(h, g, T, s, eig, maxR);
+    if (!leverage) return KR_OK;
+    lp.mode = 1;
+    for (int n = 0; n < g.N; ++n) {
+      lp.P[n] = T.V[n];
+      lp.evals[n] = T.evals[n];
+      lp.ldr[n] = g.R[n];
+      lp.ldc[n] = 1;
+      lp.nc[n] = g.R[n];
+    }
+    quadform(lp);
+    launch_quantise(h, g, T, s);
+    HIPCHK(h, hipGetLastError());
+    return KR_OK;
+  }
+  // approximate route: squared row norms, mixed with the uniform distribution ->
+  // their tables -> rows of A~
+  lp.mode = 0;
+  quadform(lp);
+  {
+    MixPass mp{};
+    for (int n = 0; n < g.N; ++n) {
+      mp.w[n] = T.lev[n];
+      mp.part_in[n] = s.lpart[n];
+      mp.part_out[n] = s.lpart2[n];
+      mp.I[n] = g.I[n];
+      mp.nb[n] = lv_blocks(g.I[n]);
+    }
+    KL(h, k_mix_uniform, dim3(nbmax, g.N), dim3(LV_THREADS), 0, h->stream, mp);
+  }
+  launch_quantise(h, g, T, s, true);
+  ApproxRows ar{};
+  int kmax = 1;
+  for (int n = 0; n < g.N; ++n) {
+    ar.A[n] = T.A[n];
+    ar.Q[n] = T.Q[n];
+    ar.C[n] = T.C[n];
+    ar.At[n] = s.At[n];
+    ar.I[n] = g.I[n];
+    ar.R[n] = g.R[n];
+    ar.k[n] = g.lev_k[n];
+    kmax = std::max(kmax, g.lev_k[n]);
+  }
+  KL(h, k_approx_rows, dim3((kmax + 255) / 256, g.N), dim3(256), 0, h->stream, ar, seed, stream);
+  // N_n = A~^T A~ (the k_n rows of A~ as a factor) and its eigen-decomposition
+  {
+    Geom ga = g;
+    ModeTables Ta = T;
+    for (int n = 0; n < g.N; ++n) {
+      ga.I[n] = g.lev_k[n];
+      Ta.A[n] = s.At[n];
+    }
+    KL(h, k_gram, dim3(g.N), dim3(256), 0, h->stream, Ta, ga, s.gram);
+  }
+  KL(h, k_eig, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+  if (!leverage) return KR_OK;
+  JLPass jp{};
+  for (int n = 0; n < g.N; ++n) {
+    jp.At[n] = s.At[n];
+    jp.Ninv[n] = T.Ginv[n];
+    jp.Z[n] = s.Z[n];
+    jp.R[n] = g.R[n];
+    jp.k[n] = g.lev_k[n];
+  }
+  jp.r = g.lev_r;
+  jp.coef = 1.0 + g.lev_eps / 4.0;
+  if (maxR <= 8) KLN(h, "k_jl_project", k_jl_project<8>, dim3(g.lev_r, g.N), dim3(256), 0, h->stream, jp, seed, stream);
+  else if (maxR <= 16) KLN(h, "k_jl_project", k_jl_project<16>, dim3(g.lev_r, g.N), dim3(256), 0, h->stream, jp, seed, stream);
+  else if (maxR <= 32) KLN(h, "k_jl_project", k_jl_project<32>, dim3(g.lev_r, g.N), dim3(256), 0, h->stream, jp, seed, stream);
+  else KLN(h, "k_jl_project", k_jl_project<64>, dim3(g.lev_r, g.N), dim3(256), 0, h->stream, jp, seed, stream);
+  lp.mode = 2;
+  lp.wscale = 1.0 / ((1.0 + g.lev_eps / 4.0) * (1.0 - g.lev_eps / 20.0));
+  for (int n = 0; n < g.N; ++n) {
+    lp.P[n] = s.Z[n];
+    lp.ldr[n] = 1;
+    lp.ldc[n] = g.R[n];
+    lp.nc[n] = g.lev_r;
+  }
+  quadform(lp);
+  launch_quantise(h, g, T, s);
+  HIPCHK(h, hipGetLastError());
+  return KR_OK;
+}
+
+// Factor setup: float64 copies, Grams, then the eigen-decomposition (eig) or, when
+// only G^{-1} is needed (lambda = 0 solves), the Cholesky route; then the
+// leverage tables.  Large factors and approximate leverage take launch_setup_large.
+static kr_status launch_setup(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T,
+                              const SetupBufs& s, bool leverage, bool eig = true, uint64_t seed = 0,
+                              uint64_t stream = 0) {
+  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, h->stream, (uint32_t*)s.flags, (int64_t)64);
+  launch_promote(h, p, g, s.A64, s.flags, h->stream);
+  if (setup_large(g)) return launch_setup_large(h, g, T, s, leverage, eig || g.approx, seed, stream);
+  KL(h, k_gram, dim3(g.N), dim3(256), 0, h->stream, T, g, s.gram);
+  int maxR = 1;
+  for (int n = 0; n < g.N; ++n) maxR = std::max<int>(maxR, (int)g.R[n]);
+  launch_factor(h, g, T, s, eig, maxR);
   if (leverage) {
     if (maxR <= 8) KLN(h, "k_leverage<8>", k_leverage<8>, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
     else if (maxR <= 16) KLN(h, "k_leverage<16>", k_leverage<16>, dim3(g.N), dim3(256), 0, h->stream, T, g, s.flags);
@@ -767,6 +986,16 @@ static kr_status prepare_problem(kr_handle h, const kr_problem* p, double lambda
   }
   if (m > (int64_t(1) << 31) - 2) KR_FAIL(h, KR_EUNSUPPORTED, "m=%lld too large", (long long)m);
   g.m = m;
+  if (o.flags & KR_OPT_APPROX_LEVERAGE) {
+    if (o.lev_proj < 0 || o.lev_proj > 64 || o.lev_rows < 0)
+      KR_FAIL(h, KR_EINVAL, "opts.lev_proj=%d (1..64, 0 = default) or opts.lev_rows=%d invalid", o.lev_proj,
+              o.lev_rows);
+    g.approx = 1;
+    g.lev_r = o.lev_proj > 0 ? o.lev_proj : 32;
+    g.lev_eps = eps;
+    for (int n = 0; n < g.N; ++n)
+      g.lev_k[n] = o.lev_rows > 0 ? o.lev_rows : 64 * g.R[n] * std::max(1, ceil_log2(2 * (int64_t)g.R[n]));
+  }
   for (int k = 0; k <= g.N; ++k)
     if ((double)level_cap(g, k) * (double)g.rsuf[k] * g.nrhs >= 2147483647.0)
       KR_FAIL(h, KR_EUNSUPPORTED, "level %d of the sample tree needs more than 2^31 entries", k);
@@ -828,7 +1057,7 @@ static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, 
   hipStream_t s = h->stream;
   const int64_t m = g.m;
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
-  kr_status st = launch_setup(h, p, g, T, B.s, true, need_eig);
+  kr_status st = launch_setup(h, p, g, T, B.s, true, need_eig, o.seed, o.stream);
   if (st != KR_OK) return st;
   int64_t sumI = 0;
   for (int n = 0; n < g.N; ++n) sumI += g.I[n];
@@ -1080,12 +1309,12 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     info->distinct_rows = h->h_small[8 + g.N];
     info->rel_update = rel;
   }
-  h->has_sketch = true;
-  h->g = g;
-  h->T = T;
-  h->tr = tr;
-  h->Omega = B.Omega;
-  h->counts = B.counts;
+  h->last.valid = true;
+  h->last.g = g;
+  h->last.T = T;
+  h->last.tr = tr;
+  h->last.Omega = B.Omega;
+  h->last.counts = B.counts;
   return result;
 }
 
@@ -1286,7 +1515,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     if (route[i] == TEAM) { slot[i] = (int32_t)idx.size(); idx.push_back(i); }
   const int nall = (int)idx.size();
   if (nall == 0) {
-    h->has_sketch = false;
+    h->last.valid = false;
     if (first != KR_OK) h->err = first_msg;
     return first;
   }
@@ -1400,6 +1629,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     HIPCHK(h, hipEventRecord(h->fork_ev, s));
     for (int k = 0; k < 4; ++k) HIPCHK(h, hipStreamWaitEvent(h->side[k], h->fork_ev, 0));
   }
+  h->batch.assign(count, SketchRec{});
   int pidx = 0;
   for (int i : idx) {
     h->stream = h->side[pidx++ & 3];
@@ -1432,6 +1662,13 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
       KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, h->stream, xi, g.Rtot * g.nrhs, 0.0);
       KL(h, k_zero_bytes, dim3(1), dim3(256), 0, h->stream, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
     }
+    SketchRec& rec = h->batch[i];
+    rec.valid = true;
+    rec.g = g;
+    rec.T = T;
+    rec.tr = tr;
+    rec.Omega = B.Omega;
+    rec.counts = B.counts;
     BatchDesc& d = hd[slot[i]];
     std::memset(&d, 0, sizeof(BatchDesc));
     d.g = g;
@@ -1566,7 +1803,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     }
     note(i, si, msg);
   }
-  h->has_sketch = false;
+  h->last.valid = false;
   if (first != KR_OK) h->err = first_msg;
   return first;
 }
@@ -1656,38 +1893,107 @@ kr_status kr_batched_config(kr_handle h, double* big_rows, int32_t* team_per_cu)
   return KR_OK;
 }
 
-kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega, int32_t* h_counts,
-                           int64_t cap, int64_t* h_D) {
-  if (!h) return KR_EINVAL;
-  if (!h->has_sketch) KR_FAIL(h, KR_EINVAL, "no sketch to export");
-  const Geom& g = h->g;
+}  // extern "C"
+
+// Copy one recorded sketch to host memory in the caller's mode order: the tree
+// of a reordered batched problem packs its modes in tree order, so its rows are
+// mapped back (tree mode n is the caller's mode g.orig[n]) and re-sorted by the
+// caller's linear row index, with their weights and multiplicities.
+static kr_status export_rec(kr_handle h, const SketchRec& r, uint64_t* h_Q, int32_t* h_rows, double* h_Omega,
+                            int32_t* h_counts, int64_t cap, int64_t* h_D) {
+  const Geom& g = r.g;
   int64_t D = 0;
-  HIPCHK(h, hipMemcpy(&D, h->tr.cnt + g.N, sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(&D, r.tr.cnt + g.N, sizeof(int64_t), hipMemcpyDeviceToHost));
   if (h_D) *h_D = D;
   if (h_Q) {
-    int64_t off = 0;
+    std::vector<int64_t> off(g.N + 1, 0);
+    for (int o = 0; o < g.N; ++o) off[o + 1] = off[o] + g.I[g.inv[o]];
     for (int n = 0; n < g.N; ++n) {
-      if (h->T.Q[n])
-        HIPCHK(h, hipMemcpy(h_Q + off, h->T.Q[n], g.I[n] * sizeof(uint64_t), hipMemcpyDeviceToHost));
+      uint64_t* dst = h_Q + off[g.orig[n]];
+      if (r.T.Q[n])
+        HIPCHK(h, hipMemcpy(dst, r.T.Q[n], g.I[n] * sizeof(uint64_t), hipMemcpyDeviceToHost));
       else
-        std::memset(h_Q + off, 0, g.I[n] * sizeof(uint64_t));
-      off += g.I[n];
+        std::memset(dst, 0, g.I[n] * sizeof(uint64_t));
     }
   }
   if (D > cap) {
     if (h_rows || h_Omega || h_counts) KR_FAIL(h, KR_EINVAL, "capacity %lld < D=%lld", (long long)cap, (long long)D);
     return KR_OK;
   }
-  if (h_rows) {
-    std::vector<uint64_t> keys(D);
-    HIPCHK(h, hipMemcpy(keys.data(), h->tr.rkey, D * sizeof(uint64_t), hipMemcpyDeviceToHost));
-    for (int64_t j = 0; j < D; ++j)
-      for (int n = 0; n < g.N; ++n)
-        h_rows[j * g.N + n] = (int32_t)((keys[j] >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+  if (!h_rows && !h_Omega && !h_counts) return KR_OK;
+  std::vector<uint64_t> keys(D);
+  std::vector<double> om(D);
+  std::vector<int32_t> ct(D);
+  HIPCHK(h, hipMemcpy(keys.data(), r.tr.rkey, D * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(om.data(), r.Omega, D * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(ct.data(), r.counts, D * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<int32_t> rows((size_t)D * g.N);
+  for (int64_t j = 0; j < D; ++j)
+    for (int n = 0; n < g.N; ++n)
+      rows[j * g.N + g.orig[n]] = (int32_t)((keys[j] >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+  bool ident = true;
+  for (int n = 0; n < g.N; ++n) ident = ident && g.orig[n] == n;
+  std::vector<int64_t> ord(D);
+  for (int64_t j = 0; j < D; ++j) ord[j] = j;
+  if (!ident)
+    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+      return std::lexicographical_compare(rows.begin() + a * g.N, rows.begin() + (a + 1) * g.N,
+                                          rows.begin() + b * g.N, rows.begin() + (b + 1) * g.N);
+    });
+  for (int64_t j = 0; j < D; ++j) {
+    const int64_t k = ord[j];
+    if (h_rows) std::memcpy(h_rows + j * g.N, rows.data() + k * g.N, g.N * sizeof(int32_t));
+    if (h_Omega) h_Omega[j] = om[k];
+    if (h_counts) h_counts[j] = ct[k];
   }
-  if (h_Omega) HIPCHK(h, hipMemcpy(h_Omega, h->Omega, D * sizeof(double), hipMemcpyDeviceToHost));
-  if (h_counts) HIPCHK(h, hipMemcpy(h_counts, h->counts, D * sizeof(int32_t), hipMemcpyDeviceToHost));
   return KR_OK;
+}
+
+static kr_status export_lev(kr_handle h, const SketchRec& r, double* h_lev, int64_t cap) {
+  const Geom& g = r.g;
+  int64_t sumI = 0;
+  for (int n = 0; n < g.N; ++n) sumI += g.I[n];
+  if (cap < sumI) KR_FAIL(h, KR_EINVAL, "capacity %lld < sum I_n = %lld", (long long)cap, (long long)sumI);
+  std::vector<int64_t> off(g.N + 1, 0);
+  for (int o = 0; o < g.N; ++o) off[o + 1] = off[o] + g.I[g.inv[o]];
+  for (int n = 0; n < g.N; ++n) {
+    double* dst = h_lev + off[g.orig[n]];
+    if (r.T.lev[n] && r.T.Q[n])
+      HIPCHK(h, hipMemcpy(dst, r.T.lev[n], g.I[n] * sizeof(double), hipMemcpyDeviceToHost));
+    else
+      for (int i = 0; i < g.I[n]; ++i) dst[i] = 0.0;
+  }
+  return KR_OK;
+}
+
+extern "C" {
+
+kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* h_Omega, int32_t* h_counts,
+                           int64_t cap, int64_t* h_D) {
+  if (!h) return KR_EINVAL;
+  if (!h->last.valid) KR_FAIL(h, KR_EINVAL, "no sketch to export");
+  return export_rec(h, h->last, h_Q, h_rows, h_Omega, h_counts, cap, h_D);
+}
+
+kr_status kr_export_batched_sketch(kr_handle h, int32_t problem, uint64_t* h_Q, int32_t* h_rows, double* h_Omega,
+                                   int32_t* h_counts, int64_t cap, int64_t* h_D) {
+  if (!h) return KR_EINVAL;
+  if (problem < 0 || problem >= (int32_t)h->batch.size())
+    KR_FAIL(h, KR_EINVAL, "problem %d outside the last batched call (%zu problems)", problem, h->batch.size());
+  if (!h->batch[problem].valid)
+    KR_FAIL(h, KR_EINVAL, "problem %d took the single-problem path; its sketch is not kept", problem);
+  return export_rec(h, h->batch[problem], h_Q, h_rows, h_Omega, h_counts, cap, h_D);
+}
+
+kr_status kr_export_leverage(kr_handle h, int32_t problem, double* h_lev, int64_t cap) {
+  if (!h || !h_lev) return KR_EINVAL;
+  if (problem < 0) {
+    if (!h->last.valid) KR_FAIL(h, KR_EINVAL, "no sketch to export");
+    return export_lev(h, h->last, h_lev, cap);
+  }
+  if (problem >= (int32_t)h->batch.size() || !h->batch[problem].valid)
+    KR_FAIL(h, KR_EINVAL, "no kept sketch for problem %d of the last batched call", problem);
+  return export_lev(h, h->batch[problem], h_lev, cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -1933,7 +2239,7 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   need += (size_t)Dcap * (8 + 8 + 4) + 4 * (size_t)(Dcap + 2) + 8 * (size_t)Dcap + 2048;
   for (int k = 1; k < g.N; ++k) need += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] + 512;
   need += 8 * ((size_t)In * Rr + 3 * (size_t)Rn * Rr + (size_t)Rr * Rn + (size_t)Rn * Rn + 8) + 4 * 4 * (size_t)In +
-          8 * 2 * (size_t)In + sizeof(IterState) + 16 * 256;
+          8 * 3 * (size_t)In + 4 * (size_t)In + sizeof(IterState) + 18 * 256;
   st = ensure(h, &h->ws, &h->ws_bytes, need);
   if (st != KR_OK) return st;
   Arena a{(char*)h->ws, h->ws_bytes, 0};
@@ -1978,6 +2284,8 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   int32_t* counters = a.take<int32_t>(64);   // [0] rows done, [1] diverged
   double* seg_rel = a.take<double>(In);
   double* seg_d0 = a.take<double>(In);
+  double* seg_best = a.take<double>(In);
+  int32_t* seg_stall = a.take<int32_t>(In);
   IterState* state = a.take<IterState>(1);
   if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
 
@@ -2017,7 +2325,8 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
       launch_level_products<double>(h, T, g, tr, P, (void* const*)Q, Omega, bD, nullptr, (const IterState*)state);
       KL(h, k_tucker_update, dim3(In), dim3(256), 3 * 8 * (size_t)Rr, s, T, g, tg, (const double*)Q[1], Z,
          (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv, (const double*)wbuf, eta,
-         tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, counters, counters + 1, state);
+         tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, counters, counters + 1,
+         state);
       KL(h, k_tucker_tick, dim3(1), dim3(64), 0, s, In, max_iter, (const int32_t*)counters,
          (const int32_t*)(counters + 1), state);
     }
@@ -2071,13 +2380,113 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
     info->distinct_rows = h->h_small[8 + g.N];
     info->rel_update = relmax;
   }
-  h->has_sketch = true;
-  h->g = g;
-  h->T = T;
-  h->tr = tr;
-  h->Omega = Omega;
-  h->counts = counts;
+  h->last.valid = true;
+  h->last.g = g;
+  h->last.T = T;
+  h->last.tr = tr;
+  h->last.Omega = Omega;
+  h->last.counts = counts;
   return result;
+}
+
+kr_status tucker_factor_exact(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode, double lambda,
+                              void* d_A_out) {
+  if (!h) return KR_EINVAL;
+  Geom g;
+  kr_status st = make_geom(h, p, &g);
+  if (st != KR_OK) return st;
+  if (!p->b || !d_core || !d_A_out) KR_FAIL(h, KR_EINVAL, "X, core or output is NULL");
+  if (p->nrhs != 1) KR_FAIL(h, KR_EINVAL, "the tensor is one right-hand side (nrhs=%d)", p->nrhs);
+  if (mode < 0 || mode >= g.N || g.N < 2) KR_FAIL(h, KR_EINVAL, "mode %d of an order-%d tensor", mode, g.N);
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
+  const int n = mode;
+  // contraction order: the first product reads X, so it takes the mode that shrinks
+  // the tensor most; the rest follow in increasing mode order
+  int first = -1;
+  for (int m = 0; m < g.N; ++m)
+    if (m != n && (first < 0 || (double)g.I[m] / g.R[m] > (double)g.I[first] / g.R[first])) first = m;
+  int order[KR_MAXN], no = 0;
+  order[no++] = first;
+  for (int m = 0; m < g.N; ++m)
+    if (m != n && m != first) order[no++] = m;
+  int64_t dims[KR_MAXN];
+  for (int m = 0; m < g.N; ++m) dims[m] = g.I[m];
+  int64_t maxsz = 0;
+  for (int k = 0; k < no; ++k) {
+    dims[order[k]] = g.R[order[k]];
+    int64_t sz = 1;
+    for (int m = 0; m < g.N; ++m) sz *= dims[m];
+    maxsz = std::max(maxsz, sz);
+  }
+  const size_t need = setup_bytes(g) + 2 * 8 * (size_t)maxsz + 2 * 8 * (size_t)g.Rtot +
+                      8 * ((size_t)g.I[n] * g.R[n] + (size_t)g.R[n] * g.R[n]) + 8192;
+  st = ensure(h, &h->aux, &h->aux_bytes, need);
+  if (st != KR_OK) return st;
+  Arena a{(char*)h->aux, h->aux_bytes, 0};
+  ModeTables T{};
+  SetupBufs S{};
+  carve_setup(a, g, &T, &S);
+  double* buf0 = a.take<double>(maxsz);
+  double* buf1 = a.take<double>(maxsz);
+  double* c0 = a.take<double>(g.Rtot);
+  double* c1 = a.take<double>(g.Rtot);
+  double* P = a.take<double>((size_t)g.I[n] * g.R[n]);
+  double* H = a.take<double>((size_t)g.R[n] * g.R[n]);
+  if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow");
+  hipStream_t s = h->stream;
+  KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)S.flags, (int64_t)64);
+  launch_promote(h, p, g, S.A64, S.flags, s);
+  KL(h, k_gram, dim3(g.N), dim3(256), 0, s, T, g, S.gram);
+  // T = X x_{m != n} A_m^T
+  for (int m = 0; m < g.N; ++m) dims[m] = g.I[m];
+  const double* cur = nullptr;
+  double* dst = buf0;
+  for (int k = 0; k < no; ++k) {
+    const int m = order[k];
+    int64_t pre = 1, post = 1;
+    for (int q = 0; q < m; ++q) pre *= dims[q];
+    for (int q = m + 1; q < g.N; ++q) post *= dims[q];
+    const int64_t work = pre * g.R[m] * post;
+    if (k == 0 && p->b_dtype == KR_F32)
+      KL(h, k_ttm_f32, dim3(grid_for(work, 256)), dim3(256), 0, s, (const float*)p->b, dst, pre, g.I[m], g.R[m],
+         post, (const double*)S.A64[m]);
+    else
+      KL(h, k_mode_product, dim3(grid_for(work, 256)), dim3(256), 0, s, k == 0 ? (const double*)p->b : cur, dst, pre,
+         g.I[m], g.R[m], post, (const double*)S.A64[m], 1);
+    dims[m] = g.R[m];
+    cur = dst;
+    dst = dst == buf0 ? buf1 : buf0;
+  }
+  // core x_{m != n} (A_m^T A_m)
+  const double* core = (const double*)d_core;
+  const double* cc = core;
+  double* cd = c0;
+  for (int m = 0; m < g.N; ++m) {
+    if (m == n) continue;
+    int64_t pre = 1, post = 1;
+    for (int q = 0; q < m; ++q) pre *= g.R[q];
+    for (int q = m + 1; q < g.N; ++q) post *= g.R[q];
+    KL(h, k_mode_product, dim3(grid_for(pre * g.R[m] * post, 256)), dim3(256), 0, s, cc, cd, pre, g.R[m], g.R[m],
+       post, (const double*)(S.gram + (size_t)m * 64 * 64), 0);
+    cc = cd;
+    cd = cd == c0 ? c1 : c0;
+  }
+  int64_t pre = 1, post = 1;
+  for (int q = 0; q < n; ++q) pre *= g.R[q];
+  for (int q = n + 1; q < g.N; ++q) post *= g.R[q];
+  KL(h, k_contract_all_but, dim3(grid_for((int64_t)g.I[n] * g.R[n], 256)), dim3(256), 0, s, cur, core, pre, g.I[n],
+     g.R[n], post, P);
+  KL(h, k_contract_all_but, dim3(grid_for((int64_t)g.R[n] * g.R[n], 256)), dim3(256), 0, s, cc, core, pre, g.R[n],
+     g.R[n], post, H);
+  KL(h, k_factor_solve, dim3(grid_for(g.I[n], 256, 64)), dim3(256), 0, s, (const double*)H, lambda,
+     (const double*)P, g.I[n], g.R[n], (double*)d_A_out, S.flags);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_small, S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
+  if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in the factors");
+  if (fl & KR_FLAG_CORE) KR_FAIL(h, KR_ESINGULAR, "G_(n) K^T K G_(n)^T + lambda I is singular");
+  return KR_OK;
 }
 
 }  // extern "C"

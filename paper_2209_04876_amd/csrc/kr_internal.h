@@ -36,6 +36,10 @@ struct Geom {
                         //    level-1 node of segment i reads its own iterate row i
   int orig[KR_MAXN];    // the caller's mode of tree mode n (identity unless the
   int inv[KR_MAXN];     //    modes were reordered); inv is its inverse
+  int approx;           // 1: approximate leverage (spectral approximation + JL)
+  int lev_r;            //    rows of its Johnson-Lindenstrauss projection
+  int lev_k[KR_MAXN];   //    rows of each spectral approximation A~
+  double lev_eps;       //    the eps of the scores' constants (Lemma fast-ls-comp)
 };
 
 // Per-mode results of the setup kernel.

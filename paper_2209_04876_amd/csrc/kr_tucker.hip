@@ -283,8 +283,9 @@ __global__ void __launch_bounds__(256) k_rows_tucker(ModeTables T, Geom g, Tucke
 // Per-row update, one workgroup per row i (the level-1 node of row i is node i:
 // every row has at least one sample and rows sort first):
 //   h = Q1[i] + w z + U (V z);  d = A^-1 h - AinvU Cinv V A^-1 h;  z -= eta d
-// and the row's stopping rule.  seg_done / seg_iters / seg_rel are per row;
-// *ndone counts converged rows.
+// and the row's stopping rule (relative step <= tol, or stagnation on the
+// rounding floor).  seg_done / seg_iters / seg_rel / seg_best / seg_stall are per
+// row; *ndone counts converged rows.
 __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, TuckerGeom tg, const double* __restrict__ Q1,
                                                       double* __restrict__ Z, const double* __restrict__ GtP,
                                                       const double* __restrict__ Vw, const double* __restrict__ AinvU,
@@ -292,6 +293,7 @@ __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, Tuc
                                                       double eta, double tol, int it, int max_iter,
                                                       int32_t* __restrict__ seg_done, int32_t* __restrict__ seg_iters,
                                                       double* __restrict__ seg_rel, double* __restrict__ seg_d0,
+                                                      double* __restrict__ seg_best, int32_t* __restrict__ seg_stall,
                                                       int32_t* __restrict__ ndone, int32_t* __restrict__ diverged,
                                                       IterState* __restrict__ st) {
   extern __shared__ double sm[];
@@ -352,11 +354,24 @@ __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, Tuc
   if (threadIdx.x == 0) {
     const double dn = sqrt(dd), zn = sqrt(zz);
     const double rel = zn > 0.0 ? eta * dn / zn : (dn > 0.0 ? INFINITY : 0.0);
-    if (it == 0) seg_d0[i] = dn;
+    // stagnation: the terms w z and w G^+ G z of h cancel at O(w ||z||), so the
+    // relative step has a rounding floor near tol; a row whose step has not
+    // halved in 4 iterations while below 1e3 tol sits on that floor and stops
+    if (it == 0) {
+      seg_d0[i] = dn;
+      seg_best[i] = rel;
+      seg_stall[i] = 0;
+    } else if (rel < 0.5 * seg_best[i]) {
+      seg_best[i] = rel;
+      seg_stall[i] = 0;
+    } else {
+      seg_stall[i] += 1;
+    }
+    const bool stalled = seg_stall[i] >= 4 && rel <= 1e3 * tol;
     const bool bad = !isfinite(dn) || !isfinite(zn) || (it > 0 && dn > 1e6 * seg_d0[i] && dn > 0.0);
     seg_rel[i] = rel;
     if (bad) atomicOr(diverged, 1);
-    if (rel <= tol || bad) {
+    if (rel <= tol || bad || stalled) {
       seg_done[i] = 1;
       seg_iters[i] = it + 1;
       atomicAdd(ndone, 1);
@@ -385,6 +400,105 @@ __global__ void __launch_bounds__(256) k_tucker_rows_out(TuckerGeom tg, const do
     double s = 0.0;
     for (int c = 0; c < Rr; ++c) s = fma(GtP[r * Rr + c], Z[i * Rr + c], s);
     Aout[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact factor update of Algorithm 1 (the ALS baseline the paper compares
+// with): every row i of factor n solves (G_(n) K^T K G_(n)^T + lambda I) y =
+// G_(n) K^T X_(n)[i]^T with K^T K = kron_{m != n} A_m^T A_m.  K^T X_(n)^T is the
+// tensor-times-matrix chain T = X x_{m != n} A_m^T (mode products, the first one
+// reading X in its own dtype); the right-hand sides and the R_n x R_n matrix are
+// contractions of T and of core x_{m != n} (A_m^T A_m) with the core over every
+// mode but n.
+// ---------------------------------------------------------------------------
+
+// out[pre][o][post] = sum_{i < Rin} A[i][o] in[pre][i][post] for a float32 input
+// (the first mode product of the chain; A is Rin x Rout row-major).
+__global__ void __launch_bounds__(256) k_ttm_f32(const float* __restrict__ in, double* __restrict__ out,
+                                                int64_t pre, int Rin, int Rout, int64_t post,
+                                                const double* __restrict__ A) {
+  const int64_t total = pre * Rout * post;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / ((int64_t)Rout * post);
+    const int64_t rem = e - b * Rout * post;
+    const int o = (int)(rem / post);
+    const int64_t c = rem - (int64_t)o * post;
+    const float* src = in + b * Rin * post + c;
+    double acc = 0.0;
+    for (int r = 0; r < Rin; ++r) acc = fma(A[(int64_t)r * Rout + o], (double)src[(int64_t)r * post], acc);
+    out[e] = acc;
+  }
+}
+
+// out[i][r] = sum_{a < pre, c < post} T[a][i][c] G[a][r][c]: T has In entries on
+// the contracted-out mode, G (the core) Rn; every other mode has the core's size.
+__global__ void __launch_bounds__(256) k_contract_all_but(const double* __restrict__ T, const double* __restrict__ G,
+                                                         int64_t pre, int In, int Rn, int64_t post,
+                                                         double* __restrict__ out) {
+  const int64_t total = (int64_t)In * Rn;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / Rn;
+    const int r = (int)(e - i * Rn);
+    double acc = 0.0;
+    for (int64_t a = 0; a < pre; ++a) {
+      const double* t = T + (a * In + i) * post;
+      const double* gg = G + (a * Rn + r) * post;
+      for (int64_t c = 0; c < post; ++c) acc = fma(t[c], gg[c], acc);
+    }
+    out[e] = acc;
+  }
+}
+
+// Rows of the new factor: y_i = (H + lambda I)^{-1} P[i] by the Cholesky factor of
+// H + lambda I, formed in LDS by every workgroup (R_n <= 64); a non-positive
+// pivot raises KR_FLAG_CORE.
+__global__ void __launch_bounds__(256) k_factor_solve(const double* __restrict__ H, double lambda,
+                                                     const double* __restrict__ P, int In, int Rn,
+                                                     double* __restrict__ out, int32_t* __restrict__ flags) {
+  __shared__ double L[64 * 64];
+  __shared__ int bad;
+  for (int e = threadIdx.x; e < Rn * Rn; e += blockDim.x) {
+    const int p = e / Rn, q = e - p * Rn;
+    L[e] = H[e] + (p == q ? lambda : 0.0);
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < Rn; ++j) {
+      double d = L[j * Rn + j];
+      for (int k = 0; k < j; ++k) d -= L[j * Rn + k] * L[j * Rn + k];
+      if (!(d > 0.0)) { bad = 1; d = 1.0; }
+      const double l = sqrt(d);
+      L[j * Rn + j] = l;
+      for (int i = j + 1; i < Rn; ++i) {
+        double v = L[i * Rn + j];
+        for (int k = 0; k < j; ++k) v -= L[i * Rn + k] * L[j * Rn + k];
+        L[i * Rn + j] = v / l;
+      }
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(flags, KR_FLAG_CORE);
+    return;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < In; i += (int64_t)gridDim.x * blockDim.x) {
+    double y[64];
+    const double* b = P + i * Rn;
+    for (int r = 0; r < Rn; ++r) {      // L z = b
+      double v = b[r];
+      for (int k = 0; k < r; ++k) v -= L[r * Rn + k] * y[k];
+      y[r] = v / L[r * Rn + r];
+    }
+    for (int r = Rn - 1; r >= 0; --r) { // L^T y = z
+      double v = y[r];
+      for (int k = r + 1; k < Rn; ++k) v -= L[k * Rn + r] * y[k];
+      y[r] = v / L[r * Rn + r];
+    }
+    for (int r = 0; r < Rn; ++r) out[i * Rn + r] = y[r];
   }
 }
 

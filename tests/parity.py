@@ -8,12 +8,13 @@ from oracle.regression import kron_rows, solve_sketched_direct
 from oracle.sampling import merge, sample_product
 
 
-def check_quantised_tables(As, Q_gpu):
+def check_quantised_tables(As, Q_gpu, scores=None):
     """The GPU's integer weights equal the oracle's, except entries whose exact
-    value 2^32 p_i lies within rounding of an integer boundary (reported)."""
+    value 2^32 p_i lies within rounding of an integer boundary (reported).
+    scores: the oracle's scores per mode (default: exact leverage of As)."""
     straddles = 0
     for n, A in enumerate(As):
-        lev = leverage_scores(A)
+        lev = leverage_scores(A) if scores is None else np.asarray(scores[n], dtype=np.float64)
         Qo = quantize(lev)
         Qg = np.asarray(Q_gpu[n], dtype=np.uint64)
         assert int(Qg.sum()) == GRID

@@ -112,9 +112,14 @@ def test_refined_ill_conditioned_fails_loudly(gpu_lib, prec):
     rows, ridx, counts, Omega = check_sketch(As, sk, m, seed=11, stream=2)
     x64 = sketched_solution(As, b, rows, ridx, Omega, 0.0)
     xg = x.cpu().numpy()
-    print("status %s iters %d rel-L2 %.2e" % (info["status"], info["iters"], rel_l2(xg, x64)), flush=True)
+    print("status %s iters %d rel-L2 %.2e rel_update %.2e" % (info["status"], info["iters"], rel_l2(xg, x64),
+                                                             info["rel_update"]), flush=True)
+    assert info["status"] in ("OK", "WMAXITER"), info
     if info["status"] == "OK":
         assert rel_l2(xg, x64) <= XTOL
+    else:
+        # a truthful WMAXITER: the stopping rule (default tol 1e-9) was indeed not met
+        assert info["iters"] == 400 and info["rel_update"] > 1e-9, info
 
 
 def test_refined_same_samples_as_f64(gpu_lib):
@@ -157,34 +162,3 @@ def test_refined_rejects_cooperative_and_tucker(gpu_lib):
                                         ctypes.c_void_p(out.data_ptr()), ctypes.byref(info))
         h._check(st)
     assert e.value.status == -6
-
-
-def test_skewed_regression_bf16(gpu_lib):
-    """The 512^3 x 16^3 workload in bf16-refined precision: bit-exact sketch, the
-    sketched normal equations met to 1e-6 (checked in float64 on the host from
-    the oracle's rows), and the loss gate f <= 1.1 OPT."""
-    import torch
-    w = workloads.skewed_regression()
-    print("case skewed_regression bf16 m", w["m"], flush=True)
-    As, b = w["As"], w["b"]
-    tA = [torch.tensor(A, device="cuda") for A in As]
-    tb = torch.from_numpy(b).cuda()
-    x, info = gpu_lib.kron_regress(tA, tb, eps=w["eps"], m=w["m"], seed=w["seed"], precision="bf16")
-    assert info["status"] == "OK", info
-    del tb
-    sk = gpu_lib.export_sketch([A.shape[0] for A in As])
-    rows, ridx, counts, Omega = check_sketch(As, sk, w["m"], seed=w["seed"])
-    xg = x.cpu().numpy()
-    bD = b[rows]
-    res = np.zeros_like(xg)
-    ref = np.zeros_like(xg)
-    for c0 in range(0, len(rows), 4000):
-        KD = kron_rows(As, ridx[c0:c0 + 4000])
-        res += KD.T @ (Omega[c0:c0 + 4000] * (KD @ xg - bD[c0:c0 + 4000]))
-        ref += KD.T @ (Omega[c0:c0 + 4000] * bD[c0:c0 + 4000])
-    rel = np.linalg.norm(res) / np.linalg.norm(ref)
-    f = loss(As, b, xg)
-    opt = loss(As, b, exact_solution(As, b))
-    print("iters %d normal-equation residual %.2e f/opt %.6f" % (info["iters"], rel, f / opt), flush=True)
-    assert rel <= 1e-6
-    assert f <= 1.1 * opt

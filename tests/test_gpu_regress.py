@@ -4,7 +4,11 @@ Each case prints its name before touching the GPU.  Sample indices, multipliciti
 and merged weights must match the oracle bit for bit (using the GPU's quantised
 tables, which must themselves equal the oracle's up to boundary straddles); the
 solution must match the oracle's direct sketched minimiser to rel-L2 1e-10 in
-float64 (kappa(K)^2 u is below 1e-11 at these shapes)."""
+float64 where kappa(K)^2 u is below that.  For the ill-conditioned cases (square
+factors, heavy rows) the attainable accuracy of x from the normal-equation form
+that Richardson iterates is about kappa(K)^2 u; there x is held to 20 kappa^2 u,
+the fitted values sqrt(Omega) K_D x to max(1e-10, 20 kappa u) and the sketched
+loss to a relative gap of 1e-10 in every case."""
 
 import zlib
 
@@ -76,8 +80,20 @@ def test_regress_parity(gpu_lib, case):
     from oracle.regression import kron_rows
     KW = kron_rows(As, ridx) * np.sqrt(Omega)[:, None]
     fit = rel_l2(KW @ xg.reshape(KW.shape[1], -1), KW @ xo.reshape(KW.shape[1], -1))
-    print("rel-L2 x %.3e (bar %.1e), fitted values %.3e" % (rel_l2(xg, xo), xtol, fit), flush=True)
+    # the loss of the sketched problem at both points: its relative gap is
+    # second order in the error of the fitted values
+    kappau = float(np.prod([np.linalg.cond(A) for A in As])) * 2.2e-16
+    fit_tol = max(1e-10, 20 * kappau)
+    bW = np.asarray(b)[rows].reshape(len(rows), -1) * np.sqrt(Omega)[:, None]
+    fs = np.sum((KW @ xg.reshape(KW.shape[1], -1) - bW) ** 2) + lam * np.sum(xg ** 2)
+    fso = np.sum((KW @ xo.reshape(KW.shape[1], -1) - bW) ** 2) + lam * np.sum(xo ** 2)
+    print("rel-L2 x %.3e (bar %.1e), fitted values %.3e (bar %.1e), sketched-loss gap %.2e" % (
+        rel_l2(xg, xo), xtol, fit, fit_tol, abs(fs - fso) / fso), flush=True)
     assert rel_l2(xg, xo) < xtol, (name, rel_l2(xg, xo), xtol)
+    assert fit < fit_tol, (name, fit, fit_tol)
+    # (a consistent sketched problem -- square factors -- has fso ~ 0: the gap is
+    # then measured against the scale of b~)
+    assert abs(fs - fso) <= 1e-10 * fso + 1e-14 * float(np.sum(bW ** 2))
 
 
 def test_small_regression_workload(gpu_lib):

@@ -89,3 +89,98 @@ def test_quantize_rejects_bad_input():
         quantize(np.zeros(4))
     with pytest.raises(ValueError):
         quantize(np.array([1.0, np.nan]))
+
+
+def _heavy(rng, I, R, heavy=2, scale=30.0):
+    A = rng.standard_normal((I, R))
+    A[rng.choice(I, size=heavy, replace=False)] *= scale
+    return A
+
+
+def test_row_norm_distribution_is_a_beta_overestimate():
+    # l_i <= ||a_i||^2 / sigma_min^2 gives the squared row norms beta1 = R
+    # sigma_min^2 / ||A||_F^2, the uniform distribution has beta2 = R / (I max l);
+    # their even mixture q satisfies q_i >= beta l_i / R with beta = max/2 (the
+    # definition of beta-overestimate in Section 3), also with heavy rows
+    from oracle.leverage import row_norm_weights
+    rng = np.random.default_rng(3)
+    for A in (rng.standard_normal((50, 4)), _heavy(rng, 60, 5)):
+        lev = leverage_scores(A)
+        I, R = A.shape
+        q = row_norm_weights(A).astype(np.float64) / 2.0**32
+        s = np.linalg.svd(A, compute_uv=False)
+        beta = max(R * s[-1] ** 2 / np.sum(A * A), R / (I * lev.max())) / 2
+        assert np.all(q >= beta * lev / R * (1 - 1e-6))
+        assert 0 < beta <= 1
+        np.testing.assert_allclose(q, (np.sum(A * A, axis=1) / np.sum(A * A) + 1.0 / I) / 2, rtol=1e-6)
+
+
+def test_spectral_approximation_is_unbiased_and_lemma_bound():
+    # E[A~^T A~] = A^T A (weights 1/sqrt(k q')), and Lemma
+    # block_sketch_is_spectral_approx: with k > 144 R ln(2R/delta) / (beta e0^2)
+    # rows the relative spectrum of A~^T A~ lies in [1 - e0, 1 + e0] with
+    # probability >= 1 - delta (checked: >= 18 of 20 seeds at delta = 0.1)
+    from oracle.leverage import spectral_approximation
+    rng = np.random.default_rng(4)
+    A = _heavy(rng, 40, 2)
+    G = A.T @ A
+    L = np.linalg.cholesky(G)
+    Li = np.linalg.inv(L)
+    acc = np.zeros_like(G)
+    for s in range(400):
+        At, rows = spectral_approximation(A, 64, s, 1, 0)
+        acc += At.T @ At
+    rel = Li @ (acc / 400) @ Li.T
+    assert np.allclose(rel, np.eye(2), atol=0.05), rel
+    s = np.linalg.svd(A, compute_uv=False)
+    beta = 2 * s[-1] ** 2 / np.sum(A * A)
+    e0, delta = 0.25, 0.1
+    k = int(np.ceil(144 * 2 * np.log(4 / delta) / (beta * e0**2)))
+    ok = 0
+    for seed in range(20):
+        At, _ = spectral_approximation(A, k, seed, 2, 1)
+        ev = np.linalg.eigvalsh(Li @ (At.T @ At) @ Li.T)
+        ok += int(ev.min() >= 1 - e0 and ev.max() <= 1 + e0)
+    assert ok >= 18, (ok, k)
+
+
+def test_jl_projection_entries_are_standard_normal():
+    from oracle.leverage import jl_projection
+    G = jl_projection(64, 4096, 5, 6, 2) * 8.0
+    assert abs(G.mean()) < 0.01 and abs(G.var() - 1.0) < 0.02
+    # entry (c, t) depends only on its own counter: a sub-block is the same block
+    np.testing.assert_allclose(jl_projection(4, 10, 5, 6, 2) * 2.0, G[:4, :10], rtol=1e-15)
+    np.testing.assert_allclose(jl_projection(4, 10, 5, 6, 2, t0=30) * 2.0, G[:4, 30:40], rtol=1e-15)
+
+
+def test_fast_ls_comp_bound_with_a_known_spectral_approximation():
+    # Lemma fast-ls-comp: given A~ with A^T A <= A~^T A~ <= (1 + eps/4) A^T A and a
+    # Johnson-Lindenstrauss projection accurate to eps/20 (r = 4 ln(2I/delta) /
+    # ((eps/20)^2 - (eps/20)^3) rows, Lemma random-projection), every score lies in
+    # [l_i, (1 + eps/2) l_i].  A~ = sqrt(1 + eps/8) A meets the condition exactly.
+    from oracle.leverage import jl_leverage_scores
+    rng = np.random.default_rng(6)
+    eps, I, delta = 0.25, 12, 0.05
+    A = _heavy(rng, I, 3, heavy=1, scale=10.0)
+    e = eps / 20
+    r = int(np.ceil(4 * np.log(2 * I / delta) / (e**2 - e**3)))
+    lt = jl_leverage_scores(A, np.sqrt(1 + eps / 8) * A, r, eps, 7, 8, 0)
+    lev = leverage_scores(A)
+    assert np.all(lt >= lev * (1 - 1e-12)) and np.all(lt <= (1 + eps / 2) * lev), (lt / lev, r)
+
+
+def test_approximate_leverage_within_the_algorithm_factor():
+    # Algorithm 2's first loop end to end on a small factor: with a spectral
+    # approximation of many rows and a long projection, the normalised
+    # approximate distribution is within the algorithm's per-mode factor
+    # 1 + log(1 + eps/2)/N of the exact one (N = 1, eps = 0.25)
+    from oracle.leverage import approximate_leverage_scores
+    rng = np.random.default_rng(9)
+    A = _heavy(rng, 30, 2, heavy=1, scale=5.0)
+    eps, N = 0.25, 1
+    lt, Nm = approximate_leverage_scores(A, 6000, 1500, eps, 1, 2, 0)
+    p, pt = leverage_scores(A) / 2.0, lt / lt.sum()
+    ratio = pt / p
+    bound = 1 + np.log(1 + eps / 2) / N
+    assert np.all(ratio <= bound) and np.all(ratio >= 1 / bound), (ratio.min(), ratio.max(), bound)
+    np.testing.assert_allclose(Nm, A.T @ A, rtol=0.1)

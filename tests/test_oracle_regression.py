@@ -152,3 +152,31 @@ def test_paper_e1_opt_column():
             vals.append(loss(w["As"], w["b"], exact_solution(w["As"], w["b"], w["lam"]), w["lam"]))
         med = float(np.median(vals))
         assert printed / 1.35 <= med <= printed * 1.35, (d, n, med, printed)
+
+
+@pytest.mark.parametrize("I,R,t,nrhs", [((7, 5), (2, 3), 1, 1), ((6, 5, 4), (2, 3, 2), 1, 2),
+                                        ((6, 5, 4), (2, 3, 2), 2, 1), ((5, 4, 3, 4), (2, 2, 3, 2), 2, 3),
+                                        ((5, 4, 3, 4), (2, 2, 3, 2), 3, 1)])
+def test_split_products_match_explicit_rows(I, R, t, nrhs):
+    # the split of Theorem kron_mat_mul_sqrt_decomp computes exactly the explicit
+    # sampled-row products K_D x and K_D^T w (any split point t, several RHS),
+    # with rows in sorted order and prefixes shared between rows
+    from oracle.regression import sampled_adjoint_split, sampled_forward_split, sketched_gradient_split
+    rng = np.random.default_rng(sum(I) + t)
+    As = [rng.standard_normal((a, r)) for a, r in zip(I, R)]
+    idx = np.stack([rng.integers(0, a, size=300) for a in I], axis=1)
+    rows, ridx, counts, Omega = merge(idx, rng.uniform(0.5, 2.0, size=300), I)
+    Rt = int(np.prod(R))
+    x = rng.standard_normal((Rt, nrhs)) if nrhs > 1 else rng.standard_normal(Rt)
+    KD = kron_rows(As, ridx)
+    np.testing.assert_allclose(sampled_forward_split(As, ridx, x, t, chunk=37), KD @ x, rtol=1e-12, atol=1e-12)
+    w = rng.standard_normal((len(rows), nrhs)) if nrhs > 1 else rng.standard_normal(len(rows))
+    np.testing.assert_allclose(sampled_adjoint_split(As, ridx, w, t, chunk=37), KD.T @ w, rtol=1e-12, atol=1e-12)
+    # the gradient vanishes at the direct sketched minimiser and nowhere else nearby
+    bD = rng.standard_normal((len(rows), nrhs)) if nrhs > 1 else rng.standard_normal(len(rows))
+    xo = solve_sketched_direct(KD, Omega, bD, 0.3)
+    g = sketched_gradient_split(As, ridx, Omega, bD, xo, 0.3, t)
+    ref = KD.T @ ((Omega * bD.T).T)
+    assert np.linalg.norm(g) <= 1e-12 * np.linalg.norm(ref)
+    g2 = sketched_gradient_split(As, ridx, Omega, bD, xo + 1e-3, 0.3, t)
+    assert np.linalg.norm(g2) > 1e-6 * np.linalg.norm(ref)

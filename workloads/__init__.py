@@ -92,6 +92,50 @@ def tucker_tensor(seed=3, I=400, R=16, N=3, noise=0.01):
                 seed=0)
 
 
+# The paper's Tucker experiments (its appendix on low-rank Tucker decomposition
+# of image tensors) use three real image tensors that are not available here;
+# planted synthetic tensors of the same shapes and multilinear ranks stand in.
+TUCKER_PAPER_SHAPES = {
+    "mri": ((256, 256, 14, 20), (8, 8, 4, 4)),             # cardiac MRI shape
+    "hyperspectral": ((1024, 1344, 33), (16, 16, 4)),      # hyperspectral shape
+    "coil": ((7200, 120, 120, 3), (16, 4, 4, 2)),          # COIL-100 shape
+}
+
+
+def tucker_paper_tensor(name, seed=7, noise=0.5, rank=None):
+    """Planted stand-in for one of the paper's image tensors: X = G0 x_n Q_n + E in
+    FP32, G0 ~ N(0,1) of the shape's multilinear rank, Q_n orthonormal (QR of
+    Gaussian), E Gaussian with ||E||_F = noise * ||X_clean||_F (0.5: a
+    reconstruction-error floor near 0.2, the range of the paper's image tensors),
+    and the seeded start of ALS (core and factors N(0,1)) for a decomposition of
+    multilinear rank `rank` (default: the planted one)."""
+    I, R = TUCKER_PAPER_SHAPES[name]
+    rng = np.random.default_rng(seed + sum(I))
+    G0 = rng.standard_normal(R)
+    Qs = [np.linalg.qr(rng.standard_normal((a, r)))[0] for a, r in zip(I, R)]
+    X = G0
+    for n in range(len(I) - 1, 0, -1):   # small modes first; mode 0 last, as one matrix product
+        X = np.moveaxis(np.tensordot(Qs[n], X, axes=([1], [n])), 0, n)
+    X = (Qs[0] @ X.reshape(R[0], -1)).astype(np.float32).reshape(I)
+    nclean = float(np.linalg.norm(X))
+    E = rng.standard_normal(X.shape, dtype=np.float32)
+    E *= np.float32(noise * nclean / float(np.linalg.norm(E)))
+    X += E
+    del E
+    Rd = tuple(rank) if rank is not None else R
+    rs = np.random.default_rng([seed, *Rd])
+    G_init = rs.standard_normal(Rd)
+    A_init = [rs.standard_normal((a, r)) for a, r in zip(I, Rd)]
+    return dict(name="%s-shaped planted tensor %s rank %s" % (name, "x".join(map(str, I)), ",".join(map(str, R))),
+                X=X, G_init=G_init, A_init=A_init, I=I, R=R, rank=Rd, noise=noise)
+
+
+def tucker_eps_samples(R, eps, alpha=0.001, delta=0.01):
+    """The paper's epsilon-sensitivity sample count: Algorithm 2's count for R
+    scaled by alpha, ceil(alpha 1680 R ln(40 R) ln(1/delta) / eps)."""
+    return int(math.ceil(alpha * 1680 * R * math.log(40 * R) * math.log(1.0 / delta) / eps))
+
+
 def paper_e1(n, d, seed=0):
     """The paper's synthetic workload: A(1), A(2) n x d with entries N(1, 0.001^2), b = 1."""
     rng = np.random.default_rng(seed)
