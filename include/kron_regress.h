@@ -68,8 +68,9 @@ typedef struct kr_handle_s* kr_handle;
  *   u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1],  u2 = (w1 >> 11) 2^-53 in [0, 1),
  *   E  = sqrt(-2 ln u1) cos(2 pi u2).
  * X_true is a device pointer to prod(R) x nrhs float64 (row-major); the struct
- * itself is read during the call only.  kron_loss and tucker_factor_update need
- * a dense b and reject problems that carry a generator. */
+ * itself is read during the call only.  kron_loss and kron_exact accept a
+ * generator (they stream every row's noise once: s = K^T E and ||E||^2, see
+ * there); tucker_factor_update needs a dense b. */
 typedef struct {
   const double* X_true;
   double sigma;
@@ -96,7 +97,10 @@ typedef struct {
   int64_t m;          /* number of row samples; 0 selects Algorithm 2's
                          ceil(1680 R ln(40R) ln(1/delta)/eps)                         */
   int32_t max_iter;   /* Richardson iteration limit (default 200 when <= 0)           */
-  int32_t check_every;/* iterations between convergence checks (default 8 when <= 0) */
+  int32_t check_every;/* iterations before the first convergence check (when <= 0:
+                         the iterations the handle's last solve of the same shape
+                         and parameters took, else 8); later checks come after the
+                         number the observed contraction rate predicts             */
   double tol;         /* stop when (1-sqrt(eps)) ||d|| <= tol ||x||, per RHS
                          (default when <= 0: 1e-12 for KR_PREC_F64, 1e-9 for the
                          refined precisions)                                          */
@@ -162,6 +166,10 @@ typedef enum { KR_PREC_F64 = 0, KR_PREC_F32 = 1, KR_PREC_BF16 = 2, KR_PREC_FP8 =
  * gives an unbiased sketch; its quality is the beta of the scores).  Exact
  * leverage stays the default. */
 #define KR_OPT_APPROX_LEVERAGE 16
+/* kr_opts.flags (kron_regress, kron_ridge): fill kr_info.loss with the float64
+ * loss of the returned x (one kron_loss pass over b, or over the implicit
+ * response's noise, after the solve). */
+#define KR_OPT_LOSS 32
 
 typedef struct {
   int32_t iters;          /* Richardson iterations performed (max over RHS)          */
@@ -169,6 +177,10 @@ typedef struct {
   int64_t m;              /* samples drawn                                            */
   int64_t distinct_rows;  /* distinct sampled rows of K                               */
   double rel_update;      /* final (1-sqrt(eps))||d|| / ||x|| (max over RHS)          */
+  double loss;            /* with KR_OPT_LOSS: f(x) = ||K x - b||^2 + lambda ||x||^2
+                             in float64 (max over RHS; kron_loss after the solve),
+                             else NaN                                                 */
+  double ms;              /* host wall-clock milliseconds of the call                 */
 } kr_info;
 
 /* Handle lifetime.  `hip_stream` is a hipStream_t (NULL = default stream). */
@@ -193,9 +205,19 @@ kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps
 
 /* f(x) = ||K x - b||^2 + lambda ||x||^2 in float64 (the quantity of the
  * guarantee of Theorem fast_kronecker_regression), streaming b once.  x is
- * float64 prod(R) x nrhs; h_loss receives nrhs values. */
+ * float64 prod(R) x nrhs; h_loss receives nrhs values.  With an implicit response
+ * (p->gen, b = K X_true + sigma E) every noise entry is generated once for
+ * s = K^T E and e2 = ||E||^2, and with v = x - X_true
+ *   f(x) = v^T (kron A_n^T A_n) v - 2 sigma v^T s + sigma^2 e2 + lambda ||x||^2. */
 kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void* d_x,
                     double* h_loss);
+
+/* The loss gate of an implicit-response problem in one pass over its noise: the
+ * loss f(x) of kron_loss and OPT = f(x*) at the exact minimiser of kron_exact,
+ * nrhs values each (h_loss, h_opt).  p must carry a generator (KR_EINVAL
+ * otherwise; with a dense b call kron_exact and kron_loss). */
+kr_status kron_loss_opt(kr_handle h, const kr_problem* p, double lambda, const void* d_x, double* h_loss,
+                        double* h_opt);
 
 /* kron_ridge without any device allocation, for callers that cannot allocate
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -241,7 +263,9 @@ kr_status kr_batched_config(kr_handle h, double* big_rows, int32_t* team_per_cu)
 
 /* The exact minimiser via the factor thin SVDs and KronMatMul (the paper's
  * exact baseline): x* = (kron V) diag(kron s / (kron s^2 + lambda)) (kron U)^T b.
- * Writes d_x (float64, prod(R) x nrhs). */
+ * Writes d_x (float64, prod(R) x nrhs).  With an implicit response, K^T b =
+ * (kron A_n^T A_n) X_true + sigma K^T E (one pass generating the noise) and
+ * x* = (kron V) diag(1 / (kron s^2 + lambda)) (kron V)^T K^T b. */
 kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x);
 
 /* Algorithm 3 (FastFactorMatrixUpdate): the ALS update of factor `mode` of a

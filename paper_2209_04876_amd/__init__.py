@@ -74,6 +74,7 @@ OPT_M_RLNR = 2
 OPT_GRAPH = 4
 OPT_AUTOTUNE = 8
 OPT_APPROX_LEVERAGE = 16
+OPT_LOSS = 32
 
 # kr_precision: the arithmetic of the Richardson iteration (float64 plain, or
 # refined: float64 residual and update, float32 adjoint, preconditioner in the
@@ -89,11 +90,13 @@ def _precision(name):
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("m", ctypes.c_int64),
-                ("distinct_rows", ctypes.c_int64), ("rel_update", ctypes.c_double)]
+                ("distinct_rows", ctypes.c_int64), ("rel_update", ctypes.c_double), ("loss", ctypes.c_double),
+                ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {"iters": self.iters, "status": STATUS_NAMES.get(self.status, self.status),
-                "m": self.m, "distinct_rows": self.distinct_rows, "rel_update": self.rel_update}
+                "m": self.m, "distinct_rows": self.distinct_rows, "rel_update": self.rel_update,
+                "loss": self.loss, "ms": self.ms}
 
 
 _lib = None
@@ -125,6 +128,7 @@ def load_library(path=LIB_PATH):
     lib.kr_batched_config.argtypes = [c_p, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_int32)]
     lib.kron_loss.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d)]
     lib.kron_exact.argtypes = [c_p, P, c_d, c_p]
+    lib.kron_loss_opt.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d), ctypes.POINTER(c_d)]
     lib.tucker_factor_update.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_d, c_d, O, c_p, IN]
     lib.tucker_factor_exact.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_p]
     lib.kr_export_sketch.argtypes = [c_p, c_p, c_p, c_p, c_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
@@ -136,7 +140,7 @@ def load_library(path=LIB_PATH):
                                      ctypes.POINTER(c_d)]
     lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
     for name in ("kr_batched_config", "kron_ridge_batched", "kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_ridge_noalloc", "kron_loss",
-                 "kron_exact", "kr_export_sketch", "kr_export_batched_sketch", "kr_export_leverage",
+                 "kron_loss_opt", "kron_exact", "kr_export_sketch", "kr_export_batched_sketch", "kr_export_leverage",
                  "tucker_factor_update", "tucker_factor_exact"):
         getattr(lib, name).restype = c_i
     _lib = lib
@@ -269,14 +273,15 @@ def _opts(m, max_iter, tol, seed, stream, check_every, flags=0, workgroups=0, pr
 
 
 def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
-               check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
-               workgroups=0, precision="f64", approx_leverage=None):
+               check_every=0, handle=None, x=None, allow_maxiter=True, cooperative=False,
+               workgroups=0, precision="f64", approx_leverage=None, compute_loss=False):
     """Algorithm 2 with regularisation lam.  Returns (x float64, info dict).
 
     tol=None takes the library default (1e-12 for "f64", 1e-9 for the refined
     precisions "f32", "bf16", "fp8").  approx_leverage=(k, r) takes Algorithm 2's
     approximate leverage scores (spectral approximation of k rows per factor, JL
-    projection of r rows; 0 = defaults) instead of exact ones."""
+    projection of r rows; 0 = defaults) instead of exact ones.  compute_loss=True
+    fills info["loss"] with the float64 loss of x (max over right-hand sides)."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
@@ -284,8 +289,8 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
     info = Info()
     st = h.lib.kron_ridge(h.ptr, ctypes.byref(p), lam, eps, delta,
                           ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                             OPT_COOPERATIVE if cooperative else 0, workgroups, precision,
-                                             approx_leverage)),
+                                             (OPT_COOPERATIVE if cooperative else 0) | (OPT_LOSS if compute_loss else 0),
+                                             workgroups, precision, approx_leverage)),
                           ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:
@@ -294,7 +299,7 @@ def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=
 
 
 def kron_ridge_noalloc(As, b, lam, x, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
-                       check_every=8, handle=None, precision="f64"):
+                       check_every=0, handle=None, precision="f64"):
     """kron_ridge through the allocation-free entry point: the library's fixed
     device scratch (noalloc_capacity() bytes per device) replaces the handle's
     workspace.  x (float64 CUDA tensor, prod(R) or prod(R) x nrhs) is the output,
@@ -315,10 +320,10 @@ def noalloc_capacity():
 
 
 def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
-                 check_every=8, handle=None, x=None, allow_maxiter=True, cooperative=False,
-                 workgroups=0, precision="f64", approx_leverage=None):
+                 check_every=0, handle=None, x=None, allow_maxiter=True, cooperative=False,
+                 workgroups=0, precision="f64", approx_leverage=None, compute_loss=False):
     """Algorithm 2 (lambda = 0).  Returns (x float64, info dict); see kron_ridge
-    for tol, precision and approx_leverage."""
+    for tol, precision, approx_leverage and compute_loss."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
@@ -326,7 +331,8 @@ def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200
     info = Info()
     st = h.lib.kron_regress(h.ptr, ctypes.byref(p), eps, delta,
                             ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                               OPT_COOPERATIVE if cooperative else 0, workgroups, precision,
+                                               (OPT_COOPERATIVE if cooperative else 0) |
+                                               (OPT_LOSS if compute_loss else 0), workgroups, precision,
                                                approx_leverage)),
                             ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
@@ -393,6 +399,19 @@ def kron_loss(As, b, x, lam=0.0, handle=None):
     out = (ctypes.c_double * p.nrhs)()
     h._check(h.lib.kron_loss(h.ptr, ctypes.byref(p), lam, ctypes.c_void_p(x.data_ptr()), out))
     return list(out)
+
+
+def kron_loss_opt(As, gen, x, lam=0.0, handle=None):
+    """(losses, OPTs) per right-hand side of an implicit-response problem in one
+    pass over its noise: f(x) and f(x*) with x* the exact minimiser."""
+    h = handle or default_handle()
+    p, _keep = _problem(As, gen)
+    if x.dtype != _torch().float64 or not x.is_contiguous():
+        raise ValueError("x must be contiguous float64")
+    f = (ctypes.c_double * p.nrhs)()
+    o = (ctypes.c_double * p.nrhs)()
+    h._check(h.lib.kron_loss_opt(h.ptr, ctypes.byref(p), lam, ctypes.c_void_p(x.data_ptr()), f, o))
+    return list(f), list(o)
 
 
 def kron_exact(As, b, lam=0.0, handle=None):
@@ -567,6 +586,7 @@ def export_leverage(sizes, problem=-1, handle=None):
 
 
 __all__ = ["Handle", "KronRegressError", "ResponseGen", "kron_regress", "kron_ridge", "kron_ridge_noalloc",
+           "kron_loss_opt",
            "noalloc_capacity", "kron_ridge_noalloc", "kron_loss", "kron_exact",
            "tucker_factor_update", "tucker_factor_exact", "tucker_als", "als_stream",
            "export_sketch", "export_batched_sketch", "export_leverage", "load_library", "default_handle", "profile_enable", "profile_query",

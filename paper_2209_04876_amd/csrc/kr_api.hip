@@ -26,7 +26,6 @@
 #include "kr_tucker.hip"
 #include "kr_precond.hip"
 #include "kr_batched.hip"
-#include "kr_mixed.hip"
 
 using namespace kr;
 
@@ -74,6 +73,8 @@ struct kr_handle_s {
   hipGraphExec_t bgraph = nullptr;
   std::vector<uint64_t> bgraph_sig;
   std::map<std::vector<int64_t>, std::pair<double, int>> tune;
+  // iterations the last solve of a problem shape took (the first chunk of the next)
+  std::map<std::vector<int64_t>, int> iter_hint;
   bool capturing = false;
   // side streams (default priority) over which a batched call spreads the
   // problems' setup and sketch, forked from and joined to the handle's stream
@@ -1240,6 +1241,23 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     int iters_enqueued = 0;
     bool flags_checked = false;
     int chunk = std::min(check_every, max_iter);
+    // a solve of the same shape and parameters took iter_hint iterations last
+    // time: enqueue that many before the first host check (one round trip per
+    // solve instead of two when it holds; passes enqueued after convergence
+    // return at once)
+    std::vector<int64_t> hint_key = {g.N, g.nrhs, g.m, prec, lambda > 0.0 ? 1 : 0, (int64_t)g.approx};
+    for (int n = 0; n < g.N; ++n) { hint_key.push_back(g.I[n]); hint_key.push_back(g.R[n]); }
+    {
+      int64_t tb, eb;
+      std::memcpy(&tb, &tol, 8);
+      std::memcpy(&eb, &eps, 8);
+      hint_key.push_back(tb);
+      hint_key.push_back(eb);
+    }
+    if (o.check_every <= 0) {
+      auto hit = h->iter_hint.find(hint_key);
+      if (hit != h->iter_hint.end()) chunk = std::max(1, std::min(hit->second, max_iter));
+    }
     while (iters_enqueued < max_iter) {
       chunk = std::max(1, std::min(chunk, max_iter - iters_enqueued));
       for (int it = 0; it < chunk; ++it) {
@@ -1284,6 +1302,10 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
         predict = std::max(predict, std::max(1, need));
       }
       chunk = predict;
+    }
+    if (h->h_state->all_done && !h->h_state->diverged) {
+      if (h->iter_hint.size() > 64) h->iter_hint.clear();
+      h->iter_hint[hint_key] = h->h_state->iters;
     }
   }
   HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1810,29 +1832,75 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
 
 extern "C" {
 
+}  // extern "C"
+
+// The timed solve behind the entry points: kr_info.ms (host wall clock of the
+// whole call) and, with KR_OPT_LOSS, kr_info.loss (max over RHS of f(x)).
+static kr_status solve_entry(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
+                             const kr_opts* opts, void* d_x, kr_info* info, void* ext_ws = nullptr,
+                             size_t ext_cap = 0) {
+  const auto t0 = std::chrono::steady_clock::now();
+  kr_status st = solve(h, p, lambda, eps, delta, opts, d_x, info, ext_ws, ext_cap);
+  if (info) info->loss = std::nan("");
+  if ((st == KR_OK || st == KR_WMAXITER) && info && opts && (opts->flags & KR_OPT_LOSS)) {
+    double f[KR_MAX_RHS];
+    const std::string keep = h->err;
+    const kr_status sl = kron_loss(h, p, lambda, d_x, f);
+    if (sl != KR_OK) return sl;
+    double mx = f[0];
+    for (int q = 1; q < p->nrhs; ++q) mx = std::max(mx, f[q]);
+    info->loss = mx;
+    h->err = keep;
+  }
+  if (info) info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+extern "C" {
+
 kr_status kron_regress(kr_handle h, const kr_problem* p, double eps, double delta, const kr_opts* opts,
                        void* d_x, kr_info* info) {
-  return solve(h, p, 0.0, eps, delta, opts, d_x, info);
+  return solve_entry(h, p, 0.0, eps, delta, opts, d_x, info);
 }
 
 kr_status kron_ridge(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
                      const kr_opts* opts, void* d_x, kr_info* info) {
-  return solve(h, p, lambda, eps, delta, opts, d_x, info);
+  return solve_entry(h, p, lambda, eps, delta, opts, d_x, info);
 }
 
 kr_status kron_ridge_noalloc(kr_handle h, const kr_problem* p, double lambda, double eps, double delta,
                              const kr_opts* opts, void* d_x, kr_info* info) {
   if (!h) return KR_EINVAL;
+  if (opts && (opts->flags & KR_OPT_LOSS))
+    KR_FAIL(h, KR_EUNSUPPORTED, "KR_OPT_LOSS allocates the loss pass's workspace; not available here");
   void* ws = nullptr;
   const kr_status st = scratch_address(h, &ws);
   if (st != KR_OK) return st;
-  return solve(h, p, lambda, eps, delta, opts, d_x, info, ws, KR_SCRATCH_BYTES);
+  return solve_entry(h, p, lambda, eps, delta, opts, d_x, info, ws, KR_SCRATCH_BYTES);
 }
 
 int64_t kr_noalloc_capacity(void) { return (int64_t)KR_SCRATCH_BYTES; }
 
+static kr_status ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
+                               double delta, const kr_opts* opts, void* const* d_x, kr_info* info);
+
 kr_status kron_ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
                              double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const kr_status st = ridge_batched(h, count, probs, lambda, eps, delta, opts, d_x, info);
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info)
+    for (int i = 0; i < count; ++i) {
+      info[i].ms = ms;
+      info[i].loss = std::nan("");
+    }
+  return st;
+}
+
+}  // extern "C"
+
+static kr_status ridge_batched(kr_handle h, int32_t count, const kr_problem* probs, const double* lambda, double eps,
+                               double delta, const kr_opts* opts, void* const* d_x, kr_info* info) {
   if (!h) return KR_EINVAL;
   kr_opts o{};
   if (opts) o = *opts;
@@ -1878,6 +1946,8 @@ kr_status kron_ridge_batched(kr_handle h, int32_t count, const kr_problem* probs
   }
   return solve_batched(h, count, probs, lambda, eps, delta, opts, d_x, info, cfg, graph);
 }
+
+extern "C" {
 
 kr_status kr_batched_config(kr_handle h, double* big_rows, int32_t* team_per_cu) {
   if (!h) return KR_EINVAL;
@@ -2021,11 +2091,200 @@ static void launch_mode_product(kr_handle h, const double* in, double* out, int6
   }
 }
 
+}  // extern "C"
+
+// Bytes of the implicit-response statistics (noise_stats) of a problem.
+static size_t noise_bytes(const Geom& g) {
+  int64_t P = 1;
+  for (int n = 0; n + 2 < g.N; ++n) P *= g.I[n];
+  const int R1 = g.N >= 2 ? g.R[g.N - 2] : 1;
+  size_t b = 8 * (size_t)P * R1 * g.R[g.N - 1] * g.nrhs * 2 + 8 * (size_t)P * g.nrhs + 8 * 64 + 3 * 256;
+  return b + 8 * (size_t)g.Rtot * g.nrhs * 4 + 4 * 256;
+}
+
+// s = K^T E (Rtot x nrhs) and e2[q] = ||E[:, q]||^2 of the implicit response's noise,
+// every E entry generated once (k_noise_adjoint), then the prefix modes' products.
+static kr_status noise_stats(kr_handle h, const kr_problem* p, const Geom& g, const SetupBufs& S, Arena& a,
+                             double* s_out, double* e2) {
+  hipStream_t st = h->stream;
+  const int N = g.N;
+  int64_t P = 1;
+  for (int n = 0; n + 2 < N; ++n) P *= g.I[n];
+  NoiseArgs na{};
+  double* one = a.take<double>(1);
+  if (N == 1) {
+    KL(h, k_fill, dim3(1), dim3(64), 0, st, one, (int64_t)1, 1.0);
+    na.A1 = one; na.M1 = 1; na.R1 = 1;
+  } else {
+    na.A1 = S.A64[N - 2]; na.M1 = g.I[N - 2]; na.R1 = g.R[N - 2];
+  }
+  na.A2 = S.A64[N - 1]; na.M2 = g.I[N - 1]; na.R2 = g.R[N - 1];
+  na.nrhs = g.nrhs;
+  na.seed = p->gen->seed;
+  na.stream = p->gen->stream;
+  const size_t ysz = (size_t)P * na.R1 * na.R2 * g.nrhs;
+  double* Y = a.take<double>(ysz);
+  double* Y2 = a.take<double>(ysz);
+  na.Y = Y;
+  na.e2part = a.take<double>((size_t)P * g.nrhs);
+  if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow");
+  if (P > 2147483647LL) KR_FAIL(h, KR_EUNSUPPORTED, "too many row prefixes for the noise pass");
+  KL(h, k_noise_adjoint, dim3((unsigned)P, g.nrhs), dim3(256), 0, st, na);
+  KL(h, k_noise_e2, dim3(g.nrhs), dim3(256), 0, st, (const double*)na.e2part, P, g.nrhs, e2);
+  // prefix modes N-3 .. 0: I_n -> R_n
+  int64_t dims[KR_MAXN];
+  for (int n = 0; n + 2 < N; ++n) dims[n] = g.I[n];
+  const double* cur = Y;
+  double* dst = Y2;
+  const int64_t tail = (int64_t)na.R1 * na.R2 * g.nrhs;
+  for (int n = N - 3; n >= 0; --n) {
+    int64_t pre = 1, post = tail;
+    for (int k = 0; k < n; ++k) pre *= dims[k];
+    for (int k = n + 1; k + 2 < N; ++k) post *= dims[k];
+    double* o = n == 0 ? s_out : dst;
+    KL(h, k_mode_product, dim3(grid_for(pre * g.R[n] * post, 256)), dim3(256), 0, st, cur, o, pre, g.I[n], g.R[n],
+       post, (const double*)S.A64[n], 1);
+    dims[n] = g.R[n];
+    cur = o;
+    dst = (o == Y2) ? Y : Y2;
+  }
+  if (N <= 2)
+    KL(h, k_axpy_into, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, st, (const double*)nullptr,
+       (const double*)Y, 1.0, g.Rtot * g.nrhs, s_out);
+  return KR_OK;
+}
+
+// out = (kron M_n) in over the R-tensor (nrhs innermost); M_n (R_n x R_n) at
+// mats + n * stride, transposed when trans.
+static void kron_apply(kr_handle h, const Geom& g, const double* const* M, int trans, const double* in, double* out,
+                       double* tmp) {
+  const double* cur = in;
+  for (int n = 0; n < g.N; ++n) {
+    int64_t pre = 1, post = g.nrhs;
+    for (int k = 0; k < n; ++k) pre *= g.R[k];
+    for (int k = n + 1; k < g.N; ++k) post *= g.R[k];
+    double* o = ((g.N - 1 - n) % 2 == 0) ? out : tmp;
+    KL(h, k_mode_product, dim3(grid_for(pre * g.R[n] * post, 256)), dim3(256), 0, h->stream, cur, o, pre, g.R[n],
+       g.R[n], post, M[n], trans);
+    cur = o;
+  }
+}
+
+// kron_loss for an implicit response: f(x) = v^T (kron G) v - 2 sigma v^T s +
+// sigma^2 e2 + lambda ||x||^2, v = x - X_true.
+static kr_status gen_loss(kr_handle h, const kr_problem* p, const Geom& g, double lambda, const double* x,
+                          double* h_loss, double* h_opt = nullptr) {
+  const size_t need = setup_bytes(g) + noise_bytes(g) + 8 * 3 * (size_t)g.Rtot * g.nrhs + 4096;
+  kr_status st = ensure(h, &h->aux, &h->aux_bytes, need);
+  if (st != KR_OK) return st;
+  Arena a{(char*)h->aux, h->aux_bytes, 0};
+  ModeTables T{};
+  SetupBufs S{};
+  carve_setup(a, g, &T, &S);
+  const int64_t RT = g.Rtot * g.nrhs;
+  double* sv = a.take<double>(RT);
+  double* v = a.take<double>(RT);
+  double* w = a.take<double>(RT);
+  double* t = a.take<double>(RT);
+  double* e2 = a.take<double>(64);
+  double* out = a.take<double>(128);
+  double* xs = a.take<double>(RT);
+  double* u0 = a.take<double>(RT);
+  double* u1 = a.take<double>(RT);
+  hipStream_t s = h->stream;
+  if (h_opt) {
+    // Gram eigen-decompositions for x*, then x* = (kron V) D (kron V)^T K^T b
+    st = launch_setup(h, p, g, T, S, false, true);
+    if (st != KR_OK) return st;
+  } else {
+    KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)S.flags, (int64_t)64);
+    launch_promote(h, p, g, S.A64, S.flags, s);
+    KL(h, k_gram, dim3(g.N), dim3(256), 0, s, T, g, S.gram);
+  }
+  st = noise_stats(h, p, g, S, a, sv, e2);
+  if (st != KR_OK) return st;
+  const double* X = p->gen->X_true;
+  const double* Gm[KR_MAXN];
+  for (int n = 0; n < g.N; ++n) Gm[n] = S.gram + (size_t)n * 64 * 64;
+  KL(h, k_axpy_into, dim3(grid_for(RT, 256, 1024)), dim3(256), 0, s, x, X, -1.0, RT, v);
+  kron_apply(h, g, Gm, 0, v, w, t);
+  KL(h, k_gen_loss_finish, dim3(g.nrhs), dim3(256), 0, s, x, X, (const double*)w, (const double*)sv,
+     (const double*)e2, g.Rtot, g.nrhs, p->gen->sigma, lambda, out);
+  if (h_opt) {
+    const double* Vm[KR_MAXN];
+    for (int n = 0; n < g.N; ++n) Vm[n] = T.V[n];
+    kron_apply(h, g, Gm, 0, X, w, t);
+    KL(h, k_axpy_into, dim3(grid_for(RT, 256, 1024)), dim3(256), 0, s, (const double*)w, (const double*)sv,
+       p->gen->sigma, RT, u0);
+    kron_apply(h, g, Vm, 1, u0, w, t);
+    KL(h, k_gen_exact_scale, dim3(grid_for(RT, 256)), dim3(256), 0, s, T, g, lambda, w);
+    kron_apply(h, g, Vm, 0, w, xs, t);
+    KL(h, k_axpy_into, dim3(grid_for(RT, 256, 1024)), dim3(256), 0, s, (const double*)xs, X, -1.0, RT, u1);
+    kron_apply(h, g, Gm, 0, u1, w, t);
+    KL(h, k_gen_loss_finish, dim3(g.nrhs), dim3(256), 0, s, (const double*)xs, X, (const double*)w,
+       (const double*)sv, (const double*)e2, g.Rtot, g.nrhs, p->gen->sigma, lambda, out + 64);
+  }
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h_loss, out, g.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (h_opt) HIPCHK(h, hipMemcpyAsync(h_opt, out + 64, g.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(h->h_small, S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if ((int32_t)(h->h_small[0] & 0xFFFFFFFF) & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A");
+  return KR_OK;
+}
+
+// kron_exact for an implicit response: x* = (kron V) diag(1 / (kron Lambda + lambda))
+// (kron V)^T ((kron G) X_true + sigma s).
+static kr_status gen_exact(kr_handle h, const kr_problem* p, const Geom& g, double lambda, double* x) {
+  const size_t need = setup_bytes(g) + noise_bytes(g) + 4096;
+  kr_status st = ensure(h, &h->aux, &h->aux_bytes, need);
+  if (st != KR_OK) return st;
+  Arena a{(char*)h->aux, h->aux_bytes, 0};
+  ModeTables T{};
+  SetupBufs S{};
+  carve_setup(a, g, &T, &S);
+  const int64_t RT = g.Rtot * g.nrhs;
+  double* sv = a.take<double>(RT);
+  double* w = a.take<double>(RT);
+  double* t0 = a.take<double>(RT);
+  double* t1 = a.take<double>(RT);
+  double* e2 = a.take<double>(64);
+  hipStream_t s = h->stream;
+  st = launch_setup(h, p, g, T, S, false, true);
+  if (st != KR_OK) return st;
+  st = noise_stats(h, p, g, S, a, sv, e2);
+  if (st != KR_OK) return st;
+  const double* Gm[KR_MAXN];
+  const double* Vm[KR_MAXN];
+  for (int n = 0; n < g.N; ++n) {
+    Gm[n] = S.gram + (size_t)n * 64 * 64;
+    Vm[n] = T.V[n];
+  }
+  kron_apply(h, g, Gm, 0, p->gen->X_true, w, t0);
+  KL(h, k_axpy_into, dim3(grid_for(RT, 256, 1024)), dim3(256), 0, s, (const double*)w, (const double*)sv,
+     p->gen->sigma, RT, t1);
+  kron_apply(h, g, Vm, 1, t1, w, t0);
+  KL(h, k_gen_exact_scale, dim3(grid_for(RT, 256)), dim3(256), 0, s, T, g, lambda, w);
+  kron_apply(h, g, Vm, 0, w, x, t0);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_small, S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if ((int32_t)(h->h_small[0] & 0xFFFFFFFF) & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A");
+  return KR_OK;
+}
+
+extern "C" {
+
 kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void* d_x, double* h_loss) {
   if (!h) return KR_EINVAL;
   Geom g;
   kr_status st = make_geom(h, p, &g);
   if (st != KR_OK) return st;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
+  if (p->gen && !p->b && d_x && h_loss) {
+    if (!p->gen->X_true || !std::isfinite(p->gen->sigma)) KR_FAIL(h, KR_EINVAL, "invalid response generator");
+    return gen_loss(h, p, g, lambda, (const double*)d_x, h_loss);
+  }
   if (!p->b || !d_x || !h_loss) KR_FAIL(h, KR_EINVAL, "b, x or loss is NULL");
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
   // largest intermediate of the expansion x x_{N-1} A_{N-1} .. x_1 A_1
@@ -2087,11 +2346,29 @@ kr_status kron_loss(kr_handle h, const kr_problem* p, double lambda, const void*
   return KR_OK;
 }
 
+kr_status kron_loss_opt(kr_handle h, const kr_problem* p, double lambda, const void* d_x, double* h_loss,
+                        double* h_opt) {
+  if (!h) return KR_EINVAL;
+  Geom g;
+  kr_status st = make_geom(h, p, &g);
+  if (st != KR_OK) return st;
+  if (!p->gen || p->b || !d_x || !h_loss || !h_opt)
+    KR_FAIL(h, KR_EINVAL, "kron_loss_opt needs an implicit response, x, and both outputs");
+  if (!p->gen->X_true || !std::isfinite(p->gen->sigma)) KR_FAIL(h, KR_EINVAL, "invalid response generator");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
+  return gen_loss(h, p, g, lambda, (const double*)d_x, h_loss, h_opt);
+}
+
 kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x) {
   if (!h) return KR_EINVAL;
   Geom g;
   kr_status st = make_geom(h, p, &g);
   if (st != KR_OK) return st;
+  if (p->gen && !p->b && d_x) {
+    if (!p->gen->X_true || !std::isfinite(p->gen->sigma)) KR_FAIL(h, KR_EINVAL, "invalid response generator");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
+    return gen_exact(h, p, g, lambda, (double*)d_x);
+  }
   if (!p->b || !d_x) KR_FAIL(h, KR_EINVAL, "b or x is NULL");
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) KR_FAIL(h, KR_EINVAL, "lambda invalid");
   const int64_t C = (g.Itot / g.I[0]) * g.nrhs;
@@ -2156,7 +2433,23 @@ kr_status kron_exact(kr_handle h, const kr_problem* p, double lambda, void* d_x)
 // ---------------------------------------------------------------------------
 // Algorithm 3 (FastFactorMatrixUpdate) for one mode of Tucker ALS
 // ---------------------------------------------------------------------------
+static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode, double lambda,
+                               double eps, double delta, const kr_opts* opts, void* d_A_out, kr_info* info);
+
 kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode, double lambda,
+                               double eps, double delta, const kr_opts* opts, void* d_A_out, kr_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const kr_status st = factor_update(h, p, d_core, mode, lambda, eps, delta, opts, d_A_out, info);
+  if (info) {
+    info->loss = std::nan("");
+    info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+}  // extern "C"
+
+static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode, double lambda,
                                double eps, double delta, const kr_opts* opts, void* d_A_out, kr_info* info) {
   if (!h) return KR_EINVAL;
   Geom gx;   // the tensor X with its factors (validated like a regression problem)
@@ -2388,6 +2681,8 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
   h->last.counts = counts;
   return result;
 }
+
+extern "C" {
 
 kr_status tucker_factor_exact(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode, double lambda,
                               void* d_A_out) {

@@ -12,9 +12,28 @@
 // 16x16x32 MFMA with float32 accumulation.  The tensor sits in LDS when two
 // copies fit (else in t0/t1), all factor matrices are staged in LDS once per
 // launch when they fit, and elementwise phases issue their loads in batches.
+//
+// Refined (mixed-precision) iteration.  The fixed point of x <- x - eta M~^+ g(x)
+// is g(x) = 0 for any M~^+ close enough to M^+ for the iteration to contract, so
+// the preconditioner can be applied in low precision and the accuracy is won back
+// by the iteration itself (iterative refinement; the paper only remarks on the
+// bit complexity of its arithmetic).  In the refined modes the residual
+// u = K~x - b~ is float64 (it cancels; see k_rows_adj), the adjoint K~^T Omega u
+// accumulates in float32 over float copies of the adjoint levels' factor rows
+// (k_rows_to_f32), the mode products of M^+ run as described above, and the
+// update, norms and stopping rule stay float64.
 #include "kr_internal.h"
 
 namespace kr {
+
+// float copies of the gathered factor rows of levels 1..N-1 (the adjoint levels).
+__global__ void k_rows_to_f32(Geom g, Tree tr) {
+  for (int k = 1; k < g.N; ++k) {
+    const int64_t n = tr.cnt[k] * g.R[k - 1];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+      tr.arow32[k][i] = (float)tr.arow[k][i];
+  }
+}
 
 typedef double pc_f64x4 __attribute__((ext_vector_type(4)));
 typedef short pc_bf16x4 __attribute__((ext_vector_type(4)));

@@ -92,13 +92,15 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __r
 // each thread scans a contiguous chunk, chunk totals are scanned in LDS.
 __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int64_t n) {
   // exclusive scan in tiles of 1024 x SCAN_K entries: coalesced loads into LDS,
-  // each thread scans SCAN_K consecutive entries, a block scan of the thread
-  // totals, coalesced stores; a running carry links the tiles.
+  // each thread scans SCAN_K consecutive entries, the thread totals are scanned
+  // inside each wave by shuffles and the 16 wave totals by one wave (three
+  // workgroup barriers per tile), coalesced stores; a running carry links the tiles.
   constexpr int SCAN_K = 8;
   __shared__ uint32_t tile[1024 * SCAN_K + 1024 * SCAN_K / 32];
-  __shared__ uint32_t s[1024];
+  __shared__ uint32_t wsum[16];
   __shared__ uint32_t carry;
   auto ix = [](int i) { return i + (i >> 5); };   // one pad word per 32: conflict-free column reads
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) carry = 0u;
   for (int64_t t0 = 0; t0 < n; t0 += 1024 * SCAN_K) {
     uint32_t ld[SCAN_K];
@@ -116,15 +118,26 @@ __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int
       loc[j] = tot;
       tot += tile[ix(threadIdx.x * SCAN_K + j)];
     }
-    s[threadIdx.x] = tot;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s[threadIdx.x] += add;
-      __syncthreads();
+    // inclusive scan of the thread totals within the wave
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t up = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += up;
     }
-    const uint32_t base = carry + s[threadIdx.x] - tot;
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    if (wv == 0) {
+      uint32_t w = lane < 16 ? wsum[lane] : 0u;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const uint32_t up = __shfl_up(w, o, 64);
+        if (lane >= o) w += up;
+      }
+      if (lane < 16) wsum[lane] = w;   // inclusive wave prefix
+    }
+    __syncthreads();
+    const uint32_t base = carry + (wv > 0 ? wsum[wv - 1] : 0u) + inc - tot;
 #pragma unroll
     for (int j = 0; j < SCAN_K; ++j) tile[ix(threadIdx.x * SCAN_K + j)] = base + loc[j];
     __syncthreads();
@@ -133,7 +146,7 @@ __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int
       const int64_t i = t0 + (int64_t)j * 1024 + threadIdx.x;
       if (i < n) v[i] = tile[ix(j * 1024 + threadIdx.x)];
     }
-    if (threadIdx.x == 1023) carry += s[1023];
+    if (threadIdx.x == 0) carry += wsum[15];
     __syncthreads();
   }
 }

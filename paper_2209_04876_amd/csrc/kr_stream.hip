@@ -269,4 +269,148 @@ template __global__ void k_stream_contract0<16>(const double*, int, int, const v
 template __global__ void k_stream_contract0<32>(const double*, int, int, const void*, int, int64_t, double*);
 template __global__ void k_stream_contract0<64>(const double*, int, int, const void*, int, int64_t, double*);
 
+// ---------------------------------------------------------------------------
+// Implicit responses b = K X_true + sigma E (E[i][q] the Philox Box-Muller normal
+// of K's row i, see kron_regress.h): the loss and the exact minimiser need only
+// s = K^T E (R x nrhs) and e2 = ||E||^2 per right-hand side, since with
+// v = x - X_true
+//   f(x)    = v^T (kron G) v - 2 sigma v^T s + sigma^2 e2 + lambda ||x||^2,
+//   K^T b   = (kron G) X_true + sigma s,   x* = (kron G + lambda I)^+ K^T b,
+// so one pass generates every E entry once.  k_noise_adjoint contracts the last
+// two modes while generating: workgroup (p, q) covers the rows whose first N-2
+// indices form prefix p, 16 rows of mode N-2 by 256 columns of mode N-1 at a time
+// in LDS; the other modes follow as mode products.
+// ---------------------------------------------------------------------------
+struct NoiseArgs {
+  const double* A1;   // factor of mode N-2 (M1 x R1)
+  const double* A2;   // factor of mode N-1 (M2 x R2)
+  int M1, M2, R1, R2;
+  int nrhs;
+  uint64_t seed, stream;
+  double* Y;          // P x R1 x R2 x nrhs
+  double* e2part;     // P x nrhs
+};
+
+#define NA_ROWS 16
+#define NA_COLS 256
+__global__ void __launch_bounds__(256) k_noise_adjoint(NoiseArgs a) {
+  __shared__ double tile[NA_ROWS * NA_COLS];
+  __shared__ double zt[NA_ROWS * 64];
+  __shared__ double red[4];
+  const int64_t p = blockIdx.x;
+  const int q = blockIdx.y;
+  const int M1 = a.M1, M2 = a.M2, R1 = a.R1, R2 = a.R2;
+  const int nout = R1 * R2;
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  double e2 = 0.0;
+  const uint64_t base = (uint64_t)p * (uint64_t)M1 * (uint64_t)M2;
+  for (int i0 = 0; i0 < M1; i0 += NA_ROWS) {
+    const int rows = min(NA_ROWS, M1 - i0);
+    for (int e = threadIdx.x; e < rows * R2; e += blockDim.x) zt[e] = 0.0;
+    for (int j0 = 0; j0 < M2; j0 += NA_COLS) {
+      const int cols = min(NA_COLS, M2 - j0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
+        const int ii = e / cols, jj = e - ii * cols;
+        const uint64_t row = base + (uint64_t)(i0 + ii) * (uint64_t)M2 + (uint64_t)(j0 + jj);
+        const u64x4 w = philox4x64_10(row, (uint64_t)q, 0ull, 0ull, a.seed, a.stream);
+        const double u1 = (double)((w.v[0] >> 11) + 1ull) * 0x1p-53;
+        const double u2 = (double)(w.v[1] >> 11) * 0x1p-53;
+        const double v = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+        tile[ii * NA_COLS + jj] = v;
+        e2 = fma(v, v, e2);
+      }
+      __syncthreads();
+      // zt[ii][r2] += sum_jj tile[ii][jj] A2[j0 + jj][r2]
+      for (int o = threadIdx.x; o < rows * R2; o += blockDim.x) {
+        const int ii = o / R2, r2 = o - ii * R2;
+        double z = zt[o];
+        for (int jj = 0; jj < cols; ++jj) z = fma(tile[ii * NA_COLS + jj], a.A2[(int64_t)(j0 + jj) * R2 + r2], z);
+        zt[o] = z;
+      }
+    }
+    __syncthreads();
+    // acc[r1][r2] += sum_ii A1[i0 + ii][r1] zt[ii][r2]
+    int k = 0;
+    for (int o = threadIdx.x; o < nout; o += blockDim.x, ++k) {
+      const int r1 = o / R2, r2 = o - r1 * R2;
+      double s = acc[k];
+      for (int ii = 0; ii < rows; ++ii) s = fma(a.A1[(int64_t)(i0 + ii) * R1 + r1], zt[ii * R2 + r2], s);
+      acc[k] = s;
+    }
+    __syncthreads();
+  }
+  int k = 0;
+  for (int o = threadIdx.x; o < nout; o += blockDim.x, ++k) a.Y[(p * nout + o) * a.nrhs + q] = acc[k];
+  const double t = block_sum(e2, red);
+  if (threadIdx.x == 0) a.e2part[p * a.nrhs + q] = t;
+}
+
+// e2[q] = sum_p e2part[p][q] in prefix order; one workgroup per right-hand side.
+__global__ void __launch_bounds__(256) k_noise_e2(const double* __restrict__ part, int64_t P, int nrhs,
+                                                 double* __restrict__ e2) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) s += part[p * nrhs + q];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) e2[q] = s;
+}
+
+// out[e] = a[e] + c * b[e] (a may be NULL for 0)
+__global__ void __launch_bounds__(256) k_axpy_into(const double* __restrict__ a, const double* __restrict__ b,
+                                                  double c, int64_t n, double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (a ? a[e] : 0.0) + c * b[e];
+}
+
+// f[q] = v^T w - 2 sigma v^T s + sigma^2 e2[q] + lambda ||x||^2 with v = x - X_true
+// and w = (kron G) v (one workgroup per right-hand side).
+__global__ void __launch_bounds__(256) k_gen_loss_finish(const double* __restrict__ x, const double* __restrict__ X,
+                                                        const double* __restrict__ w, const double* __restrict__ s,
+                                                        const double* __restrict__ e2, int64_t Rtot, int nrhs,
+                                                        double sigma, double lambda, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  double vw = 0.0, vs = 0.0, xx = 0.0;
+  for (int64_t r = threadIdx.x; r < Rtot; r += blockDim.x) {
+    const int64_t e = r * nrhs + q;
+    const double v = x[e] - X[e];
+    vw = fma(v, w[e], vw);
+    vs = fma(v, s[e], vs);
+    xx = fma(x[e], x[e], xx);
+  }
+  vw = block_sum(vw, red);
+  vs = block_sum(vs, red);
+  xx = block_sum(xx, red);
+  if (threadIdx.x == 0) out[q] = vw - 2.0 * sigma * vs + sigma * sigma * e2[q] + lambda * xx;
+}
+
+// t <- t / (kron lambda + lambda_reg) in the eigenbasis, zero where a mode's
+// eigenvalue is below its rank threshold (the pseudo-inverse of kron G + lambda I
+// restricted like the exact path's).
+__global__ void __launch_bounds__(256) k_gen_exact_scale(ModeTables T, Geom g, double lambda, double* __restrict__ t) {
+  const int64_t total = g.Rtot * g.nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e / g.nrhs;
+    double prod = 1.0;
+    bool zero = false;
+    for (int n = g.N - 1; n >= 0; --n) {
+      const int rn = (int)(r % g.R[n]);
+      r /= g.R[n];
+      double lmax = 0.0;
+      for (int k = 0; k < g.R[n]; ++k) lmax = fmax(lmax, T.evals[n][k]);
+      const double eps_r = (double)max(g.I[n], g.R[n]) * 2.220446049250313e-16;
+      const double lk = T.evals[n][rn];
+      if (!(lk > eps_r * eps_r * lmax)) zero = true;
+      prod *= fmax(lk, 0.0);
+    }
+    const double den = prod + lambda;
+    t[e] = (zero || !(den > 0.0)) ? 0.0 : t[e] / den;
+  }
+}
+
 }  // namespace kr

@@ -209,3 +209,27 @@ def test_default_sample_count_is_algorithm_2s(gpu_lib):
     assert counts.sum() == m
     xo = sketched_solution(As, b, rows, ridx, Omega, 0.0)
     assert rel_l2(x.cpu().numpy(), xo) < 1e-10
+
+
+def test_info_loss_and_time(gpu_lib):
+    """KR_OPT_LOSS fills kr_info.loss with f(x) of the returned x (the oracle's loss
+    on the same x), for a dense and an implicit response; kr_info.ms is the call's
+    wall clock."""
+    import torch
+    from oracle.response import implicit_response
+    print("case info loss", flush=True)
+    w = workloads.small_regression()
+    tA, tb = _torch_inputs(w["As"], w["b"])
+    x, info = gpu_lib.kron_regress(tA, tb, eps=w["eps"], m=w["m"], seed=w["seed"], compute_loss=True)
+    assert abs(info["loss"] - loss(w["As"], w["b"], x.cpu().numpy())) <= 1e-12 * info["loss"]
+    assert info["ms"] > 0
+    _, info2 = gpu_lib.kron_regress(tA, tb, eps=w["eps"], m=w["m"], seed=w["seed"])
+    assert np.isnan(info2["loss"])
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((64, 2))
+    b = implicit_response(w["As"], X, 0.1, 2, 3)
+    gen = gpu_lib.ResponseGen(torch.tensor(X, device="cuda"), 0.1, seed=2, stream=3)
+    x, info = gpu_lib.kron_ridge(tA, gen, 0.01, m=3000, compute_loss=True)
+    xh = x.cpu().numpy()
+    ref = max(loss(w["As"], b[:, q], xh[:, q], 0.01) for q in range(2))
+    assert abs(info["loss"] - ref) <= 1e-10 * ref

@@ -73,10 +73,53 @@ def test_implicit_response_in_a_batch(gpu_lib):
         assert rel_l2(x.cpu().numpy(), x64) < 1e-10
 
 
-def test_implicit_response_rejected_where_dense_data_is_needed(gpu_lib):
+def test_loss_opt_needs_an_implicit_response(gpu_lib):
+    """kron_loss_opt is the implicit response's one-pass gate; with a dense b it
+    refuses (kron_exact and kron_loss serve that case)."""
     import torch
+    print("case loss_opt argument check", flush=True)
     As, rng = _factors((10, 9), (3, 2), 1)
     tA = [torch.tensor(A, device="cuda") for A in As]
-    gen = gpu_lib.ResponseGen(torch.tensor(rng.standard_normal(6), device="cuda"), 0.1)
-    with pytest.raises(gpu_lib.KronRegressError):
-        gpu_lib.kron_loss(tA, gen, torch.zeros(6, dtype=torch.float64, device="cuda"))
+    b = torch.tensor(rng.standard_normal(90), device="cuda")
+    with pytest.raises(gpu_lib.KronRegressError) as e:
+        gpu_lib.kron_loss_opt(tA, b, torch.zeros(6, dtype=torch.float64, device="cuda"))
+    assert e.value.status == -1
+
+
+LOSS_CASES = [((40,), (6,), 1, 0.0), ((30, 20), (5, 4), 3, 0.01), ((12, 10, 9), (3, 4, 3), 2, 0.0),
+              ((8, 7, 6, 5), (2, 3, 2, 3), 1, 0.2), ((9, 300, 7), (2, 5, 3), 2, 0.05)]
+
+
+@pytest.mark.parametrize("case", range(len(LOSS_CASES)))
+def test_implicit_loss_and_exact(gpu_lib, case):
+    """kron_loss and kron_exact with an implicit response (one pass over the
+    generated noise for K^T E and ||E||^2, closed forms in R-space) against the
+    oracle's loss and exact minimiser on the dense b; the loss also at a random x
+    and at the exact minimiser (OPT)."""
+    import torch
+    from oracle.regression import exact_solution, loss
+    I, R, nrhs, lam = LOSS_CASES[case]
+    As, rng = _factors(I, R, 90 + case)
+    Rt = int(np.prod(R))
+    X = rng.standard_normal((Rt, nrhs))
+    sigma = 0.3
+    print("case implicit loss/exact", I, R, nrhs, lam, flush=True)
+    b = implicit_response(As, X, sigma, seed=5, stream=40 + case)
+    tA = [torch.tensor(A, device="cuda") for A in As]
+    gen = gpu_lib.ResponseGen(torch.tensor(X, device="cuda"), sigma, seed=5, stream=40 + case)
+    xo = exact_solution(As, b, lam)
+    xg = gpu_lib.kron_exact(tA, gen, lam).cpu().numpy()
+    print("exact rel-L2 %.2e" % rel_l2(xg, xo), flush=True)
+    assert rel_l2(xg, xo) < 1e-10
+    for xt in (xo, X + 0.1 * rng.standard_normal(X.shape)):
+        fg = gpu_lib.kron_loss(tA, gen, torch.tensor(np.ascontiguousarray(xt), device="cuda"), lam)
+        for q in range(nrhs):
+            fo = loss(As, b[:, q], xt[:, q], lam)
+            print("q %d loss gpu %.12e oracle %.12e" % (q, fg[q], fo), flush=True)
+            assert abs(fg[q] - fo) <= 1e-10 * fo
+    # the gate in one pass: f(x) and OPT = f(x*)
+    xt = X + 0.05 * rng.standard_normal(X.shape)
+    f, opt = gpu_lib.kron_loss_opt(tA, gen, torch.tensor(np.ascontiguousarray(xt), device="cuda"), lam)
+    for q in range(nrhs):
+        fo, oo = loss(As, b[:, q], xt[:, q], lam), loss(As, b[:, q], xo[:, q], lam)
+        assert abs(f[q] - fo) <= 1e-10 * fo and abs(opt[q] - oo) <= 1e-10 * oo, (f, opt, fo, oo)

@@ -26,7 +26,10 @@ def _case(gpu_lib, name, w, lam, m, nrhs_cols=None):
     x = torch.full(shape, float("nan"), dtype=torch.float64, device="cuda")
     x, info = gpu_lib.kron_ridge_noalloc(tA, tb, lam, x, eps=0.1, m=m, seed=3, stream=1, tol=1e-13)
     torch.cuda.synchronize()
-    assert info == info_ref, (info, info_ref)
+    # every solver field equal; loss is NaN (not requested) and ms is each call's own clock
+    keys = ("iters", "status", "m", "distinct_rows", "rel_update")
+    assert {k: info[k] for k in keys} == {k: info_ref[k] for k in keys}, (info, info_ref)
+    assert np.isnan(info["loss"]) and np.isnan(info_ref["loss"]) and info["ms"] > 0
     assert torch.equal(x, x_ref), float((x - x_ref).abs().max())
     return info
 
