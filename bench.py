@@ -49,15 +49,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(I, R, S):
+def algorithmic_bytes(I, R, S, nc=None):
     """Bytes each iteration / loss kernel must move per launch for an N = 3 problem
     with one right-hand side: its inputs read once and outputs written once.
-    S = [1, S1, S2, D]: nodes per level of the sample tree (D = distinct rows)."""
+    S = [1, S1, S2, D]: nodes per level of the sample tree (D = distinct rows);
+    nc: runs of level-2 nodes of the fused pass (None: S1)."""
     R0, R1, R2 = R
     Rtot = R0 * R1 * R2
     Itot = I[0] * I[1] * I[2]
     C = Itot // I[0]
     S1, S2, D = S[1], S[2], S[3]
+    nc = S1 if nc is None else nc
     mats = 8 * (R0 * R0 + R1 * R1 + R2 * R2)
     out = {
         # b once, Y = x x_2 A_2 x_3 A_3 (R_0 x C) once, A_0 once
@@ -75,9 +77,24 @@ def algorithmic_bytes(I, R, S):
         # float32 level-2 rows of A_1 and Q_2, links; Q_1 (S1 x R1 R2, float32) written
         "k_adj_level<f32>": S2 * R1 * 4 + S2 * R2 * 4 + 2 * S1 * 4 + S1 * R1 * R2 * 4,
         # float32 level-1 rows of A_0 and Q_1; the gradient (Rtot, float32) written
-        "k_adj_root_partial<f32>": S1 * R0 * 4 + S1 * R1 * R2 * 4 + Rtot * 4,
+        "k_adj_root_partial<f32>": nc * R0 * 4 + nc * R1 * R2 * 4 + Rtot * 4,
+        # fused pass: x, level-1 rows of A_0, level-2 rows of A_1 (float64 for
+        # the forward value, float32 for the adjoint), rows of A_2, Omega and b at
+        # the distinct rows, tree links and the run table; Q_1 of each run
+        # (float32) written
+        "k_subtree3<16,f32>": Rtot * 8 + S1 * R0 * 8 + S2 * R1 * 12 + D * R2 * 8 + 2 * D * 8 + S2 * 4
+                              + 2 * nc * 4 + nc * R1 * R2 * 4,
     }
     return out
+
+
+def fused_runs(rows, ch=8):
+    """Runs of the fused three-factor pass: each level-1 node's children split into
+    ceil(children / ch) runs (ch = 8 for one right-hand side)."""
+    import numpy as np
+    l2 = np.unique(rows[:, :2], axis=0)
+    _, nch = np.unique(l2[:, 0], return_counts=True)
+    return int(np.sum((nch + ch - 1) // ch))
 
 
 def recorded_traffic(name="skewed_regression_hbm_counters.md"):
@@ -204,11 +221,12 @@ def batched_leg(kr, torch, steps):
     # the two persistent kernels' durations, from one more call launched eagerly
     # (a replayed graph carries no per-kernel events)
     with torch.cuda.stream(stream):
-        kr.profile_enable(True, "k_batched_team|k_batched_queue", handle=hb)
+        kr.profile_enable(True, "k_batched_team|k_batched_queue|k_sample_batched", handle=hb)
         kr.kron_ridge_batched(probs, lams, eps=0.1, m_rule="rlnr", seed=0, max_iter=400, autotune=True, xs=xs,
                               handle=hb)
         nt, tms = kr.profile_query("k_batched_team", handle=hb)
         nq, qms = kr.profile_query("k_batched_queue", handle=hb)
+        nsb, sbms = kr.profile_query("k_sample_batched", handle=hb)
         kr.profile_enable(False, handle=hb)
     stream.synchronize()
     iter_ms = tms + qms
@@ -225,6 +243,15 @@ def batched_leg(kr, torch, steps):
     bytes_iter = sum(inf["iters"] * inf["distinct_rows"] * (16 + 8 * q) for inf, q in zip(infos, nrhs))
     ach = bytes_iter / (iter_ms * 1e-3) / 1e9 if iter_ms > 0 else None
     it = [inf["iters"] for inf in infos]
+    # the sampling launch: every problem's packed keys written once (8 B per sample);
+    # Philox4x64-10 (64-bit multiplies) and the CDF searches make it integer-ALU heavy
+    sum_m = int(sum(inf["m"] for inf in infos))
+    samp = None
+    if nsb and sbms > 0:
+        gbs = sum_m * 8 / (sbms / nsb * 1e-3) / 1e9
+        samp = {"kernel": "k_sample_batched", "launches": nsb, "avg_launch_ms": round(sbms / nsb, 4),
+                "algorithmic_bytes_per_launch": sum_m * 8, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "samples": sum_m}
     return {
         "workload": "batched ridge: %d problems, N~U{2,3,4}, I_n~U{32..256}, R_n~U{4..16}, 1-8 RHS, "
                     "lambda=10^U(-4,0), FP32 factors, implicit b = K X_true + 0.01 e, "
@@ -237,6 +264,7 @@ def batched_leg(kr, torch, steps):
         "loss_ratio_max": round(max(ratios), 6), "loss_ratio_mean": round(float(np.mean(ratios)), 6),
         "gate_passed": bool(max(ratios) <= 1.1), "solves_gated": len(ratios), "gate_seconds": round(gate_s, 2),
         "iteration_kernels_ms": round(iter_ms, 3),
+        "sampling": samp,
         "launch": "autotuned configuration %s (team threshold, team workgroups per CU), replayed from a HIP graph"
                   % (list(kr.batched_config(handle=hb)),),
         "roofline": {"kernel": "k_batched_team+k_batched_queue", "bound": "hbm",
@@ -331,11 +359,17 @@ def tucker_paper_leg(kr, torch, sweeps=5, ms=(1024, 4096, 16384)):
         res = {"workload": w["name"] + ", FP32, 50%% noise, lambda = 0, %d iterations" % sweeps}
 
         def run(core, m=0):
-            kr.tucker_als(X, G0, A0, 0.0, 1, m_core=m, factor_update="exact", core_update=core)   # warm
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, trace = kr.tucker_als(X, G0, A0, 0.0, sweeps, m_core=m, factor_update="exact", core_update=core)
-            torch.cuda.synchronize()
+            # a sketch too small for the core's R unknowns can make Richardson diverge
+            # (the paper's tables mark such runs with a dash)
+            try:
+                kr.tucker_als(X, G0, A0, 0.0, 1, m_core=m, factor_update="exact", core_update=core)   # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, trace = kr.tucker_als(X, G0, A0, 0.0, sweeps, m_core=m, factor_update="exact",
+                                            core_update=core)
+                torch.cuda.synchronize()
+            except kr.KronRegressError as e:
+                return {"status": "failed: %s" % str(e).split(":")[0]}
             return {"ms_per_iteration": round(1000.0 * (time.perf_counter() - t0) / sweeps, 3),
                     "rre": [float("%.6g" % v) for v in trace]}
 
@@ -356,9 +390,12 @@ def tucker_paper_leg(kr, torch, sweeps=5, ms=(1024, 4096, 16384)):
                        kr.tucker_als(X, G0, A0, 0.0, sweeps, factor_update="exact", core_update="exact")[2]]}
         for eps in (0.8, 0.4, 0.2, 0.1, 0.05):
             m = workloads.tucker_eps_samples(R, eps)
-            tr = kr.tucker_als(X, G0, A0, 0.0, sweeps, eps=eps, m_core=m, factor_update="exact",
-                               core_update="sketched")[2]
-            row["eps%g_m%d" % (eps, m)] = [float("%.6g" % v) for v in tr]
+            try:
+                tr = kr.tucker_als(X, G0, A0, 0.0, sweeps, eps=eps, m_core=m, factor_update="exact",
+                                   core_update="sketched")[2]
+                row["eps%g_m%d" % (eps, m)] = [float("%.6g" % v) for v in tr]
+            except kr.KronRegressError as e:
+                row["eps%g_m%d" % (eps, m)] = "failed: %s" % str(e).split(":")[0]
         sens["rank" + "".join(map(str, rank))] = row
         del X
     out["eps_sensitivity_mri"] = sens
@@ -443,7 +480,7 @@ def main():
         prec, tol = legs[leg]
         return kr.kron_regress(tA, tb, eps=w["eps"], m=w["m"], seed=w["seed"], precision=prec, tol=tol, x=x)
 
-    iter_kernels = ("k_fwd_level", "k_rows_adj", "k_adj_level", "k_adj_root_partial", "k_precond")
+    iter_kernels = ("k_fwd_level", "k_rows_adj", "k_adj_level", "k_subtree3", "k_adj_root_partial", "k_precond")
     breakdowns, launches, per_iter = {}, {}, {}
     for leg in legs:
         for _ in range(args.warmup):
@@ -464,21 +501,24 @@ def main():
     # sample-tree level counts of this workload's sketch (same for every step)
     sk = kr.export_sketch(I)
     S = [1, len(np.unique(sk["rows"][:, 0])), len(np.unique(sk["rows"][:, :2], axis=0)), len(sk["rows"])]
-    alg = algorithmic_bytes(I, R, S)
+    nc = fused_runs(sk["rows"]) if any(k.startswith("k_subtree3") for k in breakdown) else None
+    alg = algorithmic_bytes(I, R, S, nc)
     stream_kernel = "k_stream_loss<16>"
 
     def timed(leg, roof_filter=None):
         """K solves into K output buffers, host-timed as a whole (and per solve, each
-        of which synchronises on its info); with roof_filter the matching kernels
-        are bracketed by HIP events (left enabled for the caller to query).  The
-        loss gate runs afterwards on every solve's x."""
+        of which synchronises on its info); with roof_filter the matching kernels of
+        the last PROF_SOLVES solves of the timed region are bracketed by HIP events
+        (left enabled for the caller to query; bracketing every launch would slow
+        the timed region by about 5%).  The loss gate runs afterwards on every
+        solve's x."""
         xs = [torch.empty(Rtot, dtype=torch.float64, device=dev) for _ in range(args.steps)]
-        if roof_filter:
-            kr.profile_enable(True, roof_filter)
         torch.cuda.synchronize()
         per, iters, D = [], [], []
         t0 = time.perf_counter()
         for k in range(args.steps):
+            if roof_filter and k == max(0, args.steps - PROF_SOLVES):
+                kr.profile_enable(True, roof_filter)
             t1 = time.perf_counter()
             _, info = solve(leg, xs[k])
             per.append(time.perf_counter() - t1)
@@ -490,13 +530,19 @@ def main():
         return dict(dt=dt, median_ms=1000.0 * float(np.median(per)), ratios=ratios, iters=iters, D=D, x=xs[-1])
 
     # timed region of `value`: K bf16-refined solves; the step's dominant kernel is
-    # bracketed by HIP events on the library's stream
+    # bracketed by HIP events on the library's stream in the last solves; the
+    # float64 legs are timed the same way (their own dominant kernel bracketed)
+    PROF_SOLVES = 4
     r = timed("bf16", dominant)
     nl, lms = kr.profile_query(dominant)
     kr.profile_enable(False)
     ms_per_step = 1000.0 * r["dt"] / args.steps
     value = args.steps / r["dt"]
-    others = {leg: timed(leg) for leg in ("f64_same_tol", "f64")}
+    others = {}
+    for leg in ("f64_same_tol", "f64"):
+        bd = breakdowns[leg]
+        others[leg] = timed(leg, max(bd, key=lambda k: bd[k]["ms"]))
+        kr.profile_enable(False)
 
     # the loss gate's float64 stream, timed on its own (K launches, events)
     kr.profile_enable(True, stream_kernel)
@@ -586,6 +632,7 @@ def main():
         "roofline": roofline(dominant, nl, lms),
         "hbm_stream": roofline(stream_kernel, ns_, sms),
         "sample_tree_levels": S,
+        "fused_runs": nc,
     }
     if not args.no_batched:
         out["batched"] = batched_leg(kr, torch, args.batched_steps)

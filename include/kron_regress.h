@@ -107,7 +107,7 @@ typedef struct {
   uint64_t seed;      /* Philox key word 0                                            */
   uint64_t stream;    /* Philox key word 1                                            */
   int32_t flags;      /* KR_OPT_* bits                                                */
-  int32_t workgroups; /* workgroups of the cooperative iteration (0 = automatic)      */
+  int32_t workgroups; /* unused; must be 0                                           */
   int32_t precision;  /* kr_precision of the Richardson iteration (0 = KR_PREC_F64)   */
   int32_t reserved;   /* must be 0                                                    */
   int32_t lev_rows;   /* KR_OPT_APPROX_LEVERAGE: rows k_n of each spectral
@@ -123,15 +123,11 @@ typedef struct {
  * K~^T Omega u in float32 and apply the preconditioner's mode products in
  * KR_PREC_F32: float32; KR_PREC_BF16: bf16 MFMA; KR_PREC_FP8: e4m3 MFMA with
  * per-operand scaling; all with float32 accumulation.  The result is still
- * float64.  Refined precisions are not available with KR_OPT_COOPERATIVE or in
- * tucker_factor_update (KR_EUNSUPPORTED). */
+ * float64.  Refined precisions are not available in tucker_factor_update or
+ * kron_ridge_batched (KR_EUNSUPPORTED). */
 typedef enum { KR_PREC_F64 = 0, KR_PREC_F32 = 1, KR_PREC_BF16 = 2, KR_PREC_FP8 = 3 } kr_precision;
 
-/* kr_opts.flags: run the whole iteration as one cooperative launch with grid
- * barriers (N >= 2 and the iterate small enough to fit in LDS; otherwise the
- * flag is ignored) instead of one kernel launch per phase with host
- * convergence checks every check_every iterations. */
-#define KR_OPT_COOPERATIVE 1
+/* kr_opts.flags bit 0 (value 1) is reserved and rejected (KR_EINVAL). */
 /* kr_opts.flags: with opts.m == 0, take m = ceil(R ln R / eps) samples (R = prod R_n,
  * natural log) instead of Algorithm 2's theory count. */
 #define KR_OPT_M_RLNR 2
@@ -170,6 +166,17 @@ typedef enum { KR_PREC_F64 = 0, KR_PREC_F32 = 1, KR_PREC_BF16 = 2, KR_PREC_FP8 =
  * loss of the returned x (one kron_loss pass over b, or over the implicit
  * response's noise, after the solve). */
 #define KR_OPT_LOSS 32
+/* kr_opts.flags (kron_regress, kron_ridge): for three-factor problems, run the
+ * sampled products level by level (forward level, rows, adjoint level: three
+ * launches per iteration) even where the fused pass applies.  The fused pass
+ * (three factors, R_3 <= 16, R_2 R_3 nrhs <= 4096, R_3 nrhs <= 256) forms the
+ * first forward level, the rows and the last adjoint level in one launch, one
+ * workgroup per run of at most max(1, 8 / nrhs) level-2 prefixes of one level-1
+ * prefix; the root adjoint then sums those runs.  Both compute the same sums; the
+ * grouping of the last adjoint level's terms differs, so results agree to
+ * rounding.  The fused pass is skipped, as if this flag were set, when the runs
+ * outnumber 2 S_1 + 4096 (S_1 level-1 prefixes). */
+#define KR_OPT_LEVEL_PASSES 64
 
 typedef struct {
   int32_t iters;          /* Richardson iterations performed (max over RHS)          */

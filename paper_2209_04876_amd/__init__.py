@@ -69,12 +69,12 @@ class Opts(ctypes.Structure):
                 ("lev_rows", ctypes.c_int32), ("lev_proj", ctypes.c_int32)]
 
 
-OPT_COOPERATIVE = 1
 OPT_M_RLNR = 2
 OPT_GRAPH = 4
 OPT_AUTOTUNE = 8
 OPT_APPROX_LEVERAGE = 16
 OPT_LOSS = 32
+OPT_LEVEL_PASSES = 64
 
 # kr_precision: the arithmetic of the Richardson iteration (float64 plain, or
 # refined: float64 residual and update, float32 adjoint, preconditioner in the
@@ -273,24 +273,26 @@ def _opts(m, max_iter, tol, seed, stream, check_every, flags=0, workgroups=0, pr
 
 
 def kron_ridge(As, b, lam, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
-               check_every=0, handle=None, x=None, allow_maxiter=True, cooperative=False,
-               workgroups=0, precision="f64", approx_leverage=None, compute_loss=False):
+               check_every=0, handle=None, x=None, allow_maxiter=True,
+               precision="f64", approx_leverage=None, compute_loss=False, level_passes=False):
     """Algorithm 2 with regularisation lam.  Returns (x float64, info dict).
 
     tol=None takes the library default (1e-12 for "f64", 1e-9 for the refined
     precisions "f32", "bf16", "fp8").  approx_leverage=(k, r) takes Algorithm 2's
     approximate leverage scores (spectral approximation of k rows per factor, JL
     projection of r rows; 0 = defaults) instead of exact ones.  compute_loss=True
-    fills info["loss"] with the float64 loss of x (max over right-hand sides)."""
+    fills info["loss"] with the float64 loss of x (max over right-hand sides).
+    level_passes=True runs three-factor problems level by level instead of the
+    fused pass (KR_OPT_LEVEL_PASSES)."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
         x = _x_like(As, p.nrhs, b.dim() == 1)
     info = Info()
+    flags = (OPT_LOSS if compute_loss else 0) | (OPT_LEVEL_PASSES if level_passes else 0)
     st = h.lib.kron_ridge(h.ptr, ctypes.byref(p), lam, eps, delta,
                           ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                             (OPT_COOPERATIVE if cooperative else 0) | (OPT_LOSS if compute_loss else 0),
-                                             workgroups, precision, approx_leverage)),
+                                             flags, 0, precision, approx_leverage)),
                           ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:
@@ -320,20 +322,19 @@ def noalloc_capacity():
 
 
 def kron_regress(As, b, eps=0.1, delta=0.01, m=0, seed=0, stream=0, max_iter=200, tol=None,
-                 check_every=0, handle=None, x=None, allow_maxiter=True, cooperative=False,
-                 workgroups=0, precision="f64", approx_leverage=None, compute_loss=False):
+                 check_every=0, handle=None, x=None, allow_maxiter=True,
+                 precision="f64", approx_leverage=None, compute_loss=False, level_passes=False):
     """Algorithm 2 (lambda = 0).  Returns (x float64, info dict); see kron_ridge
-    for tol, precision, approx_leverage and compute_loss."""
+    for tol, precision, approx_leverage, compute_loss and level_passes."""
     h = handle or default_handle()
     p, _keep = _problem(As, b)
     if x is None:
         x = _x_like(As, p.nrhs, b.dim() == 1)
     info = Info()
+    flags = (OPT_LOSS if compute_loss else 0) | (OPT_LEVEL_PASSES if level_passes else 0)
     st = h.lib.kron_regress(h.ptr, ctypes.byref(p), eps, delta,
                             ctypes.byref(_opts(m, max_iter, tol, seed, stream, check_every,
-                                               (OPT_COOPERATIVE if cooperative else 0) |
-                                               (OPT_LOSS if compute_loss else 0), workgroups, precision,
-                                               approx_leverage)),
+                                               flags, 0, precision, approx_leverage)),
                             ctypes.c_void_p(x.data_ptr()), ctypes.byref(info))
     h._check(st)
     if st == KR_WMAXITER and not allow_maxiter:

@@ -2,6 +2,7 @@
 // of Algorithm 2 (FastKroneckerRegression) and of the exact KronMatMul
 // baseline and loss.  Single translation unit: the kernel files are included.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <array>
@@ -22,7 +23,6 @@
 #include "kr_sketch.hip"
 #include "kr_iter.hip"
 #include "kr_stream.hip"
-#include "kr_persist.hip"
 #include "kr_tucker.hip"
 #include "kr_precond.hip"
 #include "kr_batched.hip"
@@ -174,17 +174,17 @@ static bool prof_take(kr_handle h, const char* name, hipEvent_t* a, hipEvent_t* 
 }
 
 // Launch with an explicit profiling name (for kernels instantiated per type); a
-// profiled launch is bracketed by two events on its stream.  (Events carried in
-// the dispatch itself, hipExtLaunchKernelGGL, time the kernel alone but measured
-// 4-6% slower per bf16 solve: its host path is longer and the iteration is
-// launch-bound.)
+// profiled launch carries its two events in the dispatch itself
+// (hipExtLaunchKernelGGL), so they time the kernel alone, without the dispatch
+// gap that marker events around the launch would include.  Its host path is
+// longer (4-6% per bf16 solve when every launch is profiled), so callers profile
+// a few solves, not the whole timed stretch.
 #define KLN(h, name, kern, grid, block, shm, strm, ...)                          \
   do {                                                                         \
     hipEvent_t _pa = nullptr, _pb = nullptr;                                   \
     if (prof_take((h), (name), &_pa, &_pb)) {                                  \
-      hipEventRecord(_pa, strm);                                               \
-      hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);           \
-      hipEventRecord(_pb, strm);                                               \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, strm, _pa, _pb, 0u,        \
+                            __VA_ARGS__);                                      \
     } else                                                                     \
       hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);           \
   } while (0)
@@ -712,10 +712,10 @@ struct SolveBufs {
   double* t0;
   double* t1;
   double* dinv;
-  double* wrow;
   double* part;
-  int64_t* rs1;
   IterState* state;
+  Chunks ck;      // fused three-mode pass (ck.cap = 0: not carved)
+  void* Q1c;      // its per-chunk level-1 adjoints (float64 or float32)
 };
 
 static int64_t level_cap(const Geom& g, int k) {
@@ -724,6 +724,34 @@ static int64_t level_cap(const Geom& g, int k) {
   double prod = 1.0;
   for (int n = 0; n < k; ++n) prod *= (double)g.I[n];
   return (int64_t)std::min<double>((double)g.m, prod);
+}
+
+// The fused three-mode pass (k_subtree3): three factors without segment roots,
+// R_2 <= 16 (one lane group per row), its LDS (P_1, and the factor rows and
+// Q_2 of at most ch children) within 48 KB, and at most 65536 level-1 nodes
+// (the chunk table is one workgroup's scan).
+static int fused3_ch(const Geom& g) { return std::max(1, 8 / g.nrhs); }
+static size_t fused3_lds(const Geom& g, size_t elem) {
+  const size_t W2 = (size_t)g.R[2] * g.nrhs;
+  return 8 * (size_t)g.R[1] * W2 + elem * (size_t)fused3_ch(g) * ((size_t)g.R[1] + W2);
+}
+static bool fused3_eligible(const Geom& g) {
+  return g.N == 3 && !g.seg_root && g.R[2] <= 16 && (int64_t)g.R[1] * g.R[2] * g.nrhs <= 4096 &&
+         (int64_t)g.R[2] * g.nrhs <= 256 && fused3_lds(g, 8) <= 48 * 1024 && level_cap(g, 1) <= 65536;
+}
+// Chunks the table may hold: beyond about two per level-1 node the root adjoint
+// over the chunks costs more than the adjoint level it replaces, and the
+// level-wise passes are used.
+static int64_t fused3_cap(const Geom& g) {
+  const int64_t ch = fused3_ch(g);
+  return std::min<int64_t>(level_cap(g, 1) + (level_cap(g, 2) + ch - 1) / ch, 2 * level_cap(g, 1) + 4096);
+}
+
+// Partial blocks of the root adjoint (see root_npb): one per 32 level-1 nodes,
+// and up to 64 when the fused pass's chunks take their place.
+static int64_t part_blocks(const Geom& g) {
+  const int64_t b = (level_cap(g, 1) + 31) / 32;
+  return fused3_eligible(g) ? std::max<int64_t>(b, 64) : b;
 }
 
 // Workspace of one solve.  lean: the batched team's layout, which never forms
@@ -738,10 +766,14 @@ static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = fa
   b += 4 * (size_t)(D + 2) + 8 * (size_t)D;
   for (int k = 1; k < g.N; ++k)
     if (!(lean && g.N >= 3 && k == g.N - 1)) b += 2 * 8 * (size_t)level_cap(g, k) * g.rsuf[k] * g.nrhs + 512;
-  b += 3 * 8 * (size_t)g.Rtot * g.nrhs + 8 * (size_t)g.Rtot + sizeof(IterState) + 8 * (KR_MAXN + 1) + 768;
+  b += 3 * 8 * (size_t)g.Rtot * g.nrhs + 8 * (size_t)g.Rtot + sizeof(IterState) + 8 * (KR_MAXN + 2) + 768;
   if (lean) return b + 8 * (size_t)(level_cap(g, 1) + 2) + 64 * 256 + 8192;
   b += 8 * (size_t)D * g.nrhs + 8 * (size_t)(level_cap(g, 1) + 2) + 512;
-  b += 8 * (size_t)((level_cap(g, 1) + 31) / 32) * g.Rtot * g.nrhs + 512;
+  b += 8 * (size_t)part_blocks(g) * g.Rtot * g.nrhs + 512;
+  if (fused3_eligible(g)) {
+    const size_t c = (size_t)fused3_cap(g);
+    b += 8 * (c + 2) + 12 * c * g.R[0] + 8 * c * (size_t)g.R[1] * g.R[2] * g.nrhs + 6 * 256;
+  }
   for (int k = 1; k < g.N; ++k) b += 4 * (size_t)level_cap(g, k) * g.R[k - 1] + 256;
   return b + 64 * 256 + 4096;
 }
@@ -858,6 +890,39 @@ static int launch_level_products(kr_handle h, const ModeTables& TT, const Geom& 
     return npb;
   }
   return 0;
+}
+
+// The fused three-mode pass over nchunk chunks (k_subtree3: forward level 1,
+// rows and adjoint level 2 in one launch), then the root adjoint over the chunks
+// as if they were level-1 nodes.  Returns the root adjoint's chunks per partial
+// block.
+template <typename T>
+static int launch_fused3(kr_handle h, const Geom& g, const Tree& tr, const Chunks& ck, int64_t nchunk,
+                         const double* x, const double* Omega, const double* bD, void* Q1cv, void* partv,
+                         const IterState* state) {
+  hipStream_t s = h->stream;
+  T* Q1c = (T*)Q1cv;
+  T* part = (T*)partv;
+  const bool f32 = sizeof(T) == 4;
+  const size_t lds = fused3_lds(g, sizeof(T));
+  const dim3 grid((unsigned)nchunk);
+  if (g.R[2] <= 8)
+    KLN(h, f32 ? "k_subtree3<8,f32>" : "k_subtree3<8>", (k_subtree3<8, T>), grid, dim3(256), lds, s, g, tr, ck, x,
+        Omega, bD, Q1c);
+  else
+    KLN(h, f32 ? "k_subtree3<16,f32>" : "k_subtree3<16>", (k_subtree3<16, T>), grid, dim3(256), lds, s, g, tr, ck,
+        x, Omega, bD, Q1c);
+  Tree trc = tr;
+  trc.ncnt[1] = nchunk;
+  trc.arow[1] = ck.arow;
+  trc.arow32[1] = ck.arow32;
+  const int npb = root_npb(trc);
+  const int64_t CEr = adj_cols((int)g.R[0]);
+  const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
+  const int64_t nnb = (nchunk + npb - 1) / npb;
+  KLN(h, f32 ? "k_adj_root_partial<f32>" : "k_adj_root_partial", k_adj_root_partial<T>,
+      dim3(grid_for(ncb * nnb, 1, 4096)), dim3(ADJ_THREADS), 0, s, g, trc, (const T*)Q1c, part, npb, state);
+  return npb;
 }
 
 // Dynamic LDS for the two tensor buffers of a preconditioner kernel, or 0 (then
@@ -1005,7 +1070,7 @@ static kr_status prepare_problem(kr_handle h, const kr_problem* p, double lambda
 
 // Workspace of one problem's solve, carved from a.  P[0] is the caller's x.
 static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTables* T, SolveBufs* B, Tree* tr,
-                        unsigned** bar, bool lean = false) {
+                        bool lean = false) {
   const int64_t m = g.m;
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
   carve_setup(a, g, T, &B->s);
@@ -1024,7 +1089,7 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   const int64_t Dcap = level_cap(g, g.N);
   tr->rstart = a.take<int32_t>(Dcap + 2);
   tr->rkey = a.take<uint64_t>(Dcap + 1);
-  tr->cnt = a.take<int64_t>(KR_MAXN + 1);
+  tr->cnt = a.take<int64_t>(KR_MAXN + 2);   // [KR_MAXN + 1]: chunks of the fused pass
   B->Omega = a.take<double>(Dcap);
   B->counts = a.take<int32_t>(Dcap);
   B->bD = a.take<double>((size_t)Dcap * g.nrhs);
@@ -1041,30 +1106,31 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   B->t0 = a.take<double>((size_t)g.Rtot * g.nrhs);
   B->t1 = a.take<double>((size_t)g.Rtot * g.nrhs);
   B->dinv = a.take<double>((size_t)g.Rtot);
-  B->wrow = lean ? nullptr : a.take<double>((size_t)Dcap * g.nrhs);
-  B->part = lean ? nullptr : a.take<double>((size_t)((level_cap(g, 1) + RA_NODES - 1) / RA_NODES) * g.Rtot * g.nrhs);
-  B->rs1 = a.take<int64_t>(level_cap(g, 1) + 2);
+  B->part = lean ? nullptr : a.take<double>((size_t)part_blocks(g) * g.Rtot * g.nrhs);
   B->state = a.take<IterState>(1);
-  *bar = a.take<unsigned>(64);
   if (f32rows)
     for (int k = 1; k < g.N; ++k) tr->arow32[k] = a.take<float>((size_t)level_cap(g, k) * g.R[k - 1]);
+  B->ck = Chunks{};
+  B->Q1c = nullptr;
+  if (!lean && fused3_eligible(g)) {
+    const int64_t c = fused3_cap(g);
+    B->ck.beg = a.take<int32_t>(c + 1);
+    B->ck.par = a.take<int32_t>(c);
+    B->ck.arow = a.take<double>((size_t)c * g.R[0]);
+    B->ck.arow32 = a.take<float>((size_t)c * g.R[0]);
+    B->ck.count = tr->cnt + KR_MAXN + 1;
+    B->ck.cap = (int)c;
+    B->ck.ch = fused3_ch(g);
+    B->Q1c = a.take<double>((size_t)c * g.R[1] * g.R[2] * g.nrhs);
+  }
 }
 
-// Setup (Gram, eigen or Cholesky route, leverage tables), sampling, the stable
-// radix sort, the sample tree and the gathered rows of one problem, enqueued on
-// the handle's stream without host synchronisation.
-static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T, SolveBufs& B,
-                               Tree& tr, const kr_opts& o, bool need_eig) {
+// The part of a sketch after sampling: stable radix sort, sample tree, gathered
+// rows and weights, and (implicit response) the rows of b.
+static kr_status launch_sketch_rest(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T,
+                                    SolveBufs& B, Tree& tr) {
   hipStream_t s = h->stream;
-  const int64_t m = g.m;
-  const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
-  kr_status st = launch_setup(h, p, g, T, B.s, true, need_eig, o.seed, o.stream);
-  if (st != KR_OK) return st;
-  int64_t sumI = 0;
-  for (int n = 0; n < g.N; ++n) sumI += g.I[n];
-  const int in_lds = sumI * 8 <= 48 * 1024;
-  KL(h, k_sample, dim3(grid_for(m, 256, 2048)), dim3(256), in_lds ? sumI * 8 : 0, s, T, g, o.seed, o.stream,
-     (uint64_t)0, in_lds, B.keys);
+  const int nblocks = (int)((g.m + SORT_TILE - 1) / SORT_TILE);
   launch_sort_tree(h, g, B.keys, B.keys_alt, B.hist, B.tiletot, nblocks, tr);
   const int64_t Dcap = level_cap(g, g.N);
   KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
@@ -1081,6 +1147,23 @@ static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, 
   }
   HIPCHK(h, hipGetLastError());
   return KR_OK;
+}
+
+// Setup (Gram, eigen or Cholesky route, leverage tables), sampling, the stable
+// radix sort, the sample tree and the gathered rows of one problem, enqueued on
+// the handle's stream without host synchronisation.
+static kr_status launch_sketch(kr_handle h, const kr_problem* p, const Geom& g, const ModeTables& T, SolveBufs& B,
+                               Tree& tr, const kr_opts& o, bool need_eig) {
+  hipStream_t s = h->stream;
+  const int64_t m = g.m;
+  kr_status st = launch_setup(h, p, g, T, B.s, true, need_eig, o.seed, o.stream);
+  if (st != KR_OK) return st;
+  int64_t sumI = 0;
+  for (int n = 0; n < g.N; ++n) sumI += g.I[n];
+  const int in_lds = sumI * 8 <= 48 * 1024;
+  KL(h, k_sample, dim3(grid_for(m, 256, 2048)), dim3(256), in_lds ? sumI * 8 : 0, s, T, g, o.seed, o.stream,
+     (uint64_t)0, in_lds, B.keys);
+  return launch_sketch_rest(h, p, g, T, B, tr);
 }
 
 // ext_ws/ext_cap: a caller-provided device workspace used instead of the
@@ -1100,8 +1183,7 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   const int prec = o.precision;
   if (prec < KR_PREC_F64 || prec > KR_PREC_FP8 || o.reserved != 0)
     KR_FAIL(h, KR_EINVAL, "opts.precision=%d invalid (or opts.reserved != 0)", prec);
-  if (prec != KR_PREC_F64 && (o.flags & KR_OPT_COOPERATIVE))
-    KR_FAIL(h, KR_EUNSUPPORTED, "the cooperative iteration runs in float64 only");
+  if (o.flags & 1) KR_FAIL(h, KR_EINVAL, "opts.flags bit 0 is reserved");
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
   const int check_every = o.check_every > 0 ? o.check_every : 8;
   const double tol = o.tol > 0.0 ? o.tol : (prec == KR_PREC_F64 ? 1e-12 : 1e-9);
@@ -1122,19 +1204,21 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   ModeTables T{};
   SolveBufs B{};
   Tree tr{};
-  unsigned* bar = nullptr;
-  carve_solve(a, g, prec != KR_PREC_F64, d_x, &T, &B, &tr, &bar);
+  carve_solve(a, g, prec != KR_PREC_F64, d_x, &T, &B, &tr);
   if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
 
   hipStream_t s = h->stream;
   // the eigenvectors are needed for lambda > 0 (the (kron Lambda + lambda)^+ form),
-  // fp8 (eigenvector form) and the cooperative iteration; otherwise G^{-1} suffices
-  const bool need_eig = lambda > 0.0 || prec == KR_PREC_FP8 || (o.flags & KR_OPT_COOPERATIVE);
+  // fp8 (eigenvector form); otherwise G^{-1} suffices
+  const bool need_eig = lambda > 0.0 || prec == KR_PREC_FP8;
   st = launch_sketch(h, p, g, T, B, tr, o, need_eig);
   if (st != KR_OK) return st;
-  // one host round trip: the setup flags and the level counts of the sample tree,
-  // which the iteration kernels take by value
-  HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  const bool fused = B.ck.cap > 0 && !(o.flags & KR_OPT_LEVEL_PASSES);
+  if (fused)
+    KL(h, k_chunk_table, dim3(1), dim3(CH_THREADS), 0, s, tr, B.ck, (int)g.R[0], prec != KR_PREC_F64 ? 1 : 0);
+  // one host round trip: the setup flags, the level counts of the sample tree
+  // (which the iteration kernels take by value) and the fused pass's chunks
+  HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 2) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   {
@@ -1145,6 +1229,8 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
       KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
     for (int k = 0; k <= KR_MAXN; ++k) tr.ncnt[k] = (int64_t)h->h_small[8 + k];
   }
+  int64_t nchunk = fused ? (int64_t)h->h_small[8 + KR_MAXN + 1] : 0;
+  if (nchunk < 1 || nchunk > B.ck.cap) nchunk = 0;   // more chunks than the table holds: level passes
   if (prec != KR_PREC_F64 && g.N >= 2) {
     int64_t rows32 = 0;
     for (int k = 1; k < g.N; ++k) rows32 = std::max<int64_t>(rows32, level_cap(g, k) * g.R[k - 1]);
@@ -1158,69 +1244,8 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)B.state,
                      (int64_t)(sizeof(IterState) / 4));
   HIPCHK(h, hipGetLastError());
-  const int Rl = g.R[g.N - 1];
-  const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
-  const int64_t RT = g.Rtot * g.nrhs;
-  size_t mats = 0;
-  for (int n = 0; n < g.N; ++n) mats += (size_t)g.R[n] * g.R[n];
-  const int PT = 1024;   // threads per workgroup of the cooperative iteration
-  const size_t plds = 8 * (3 * (size_t)std::max<int64_t>(RT, PT) + (lambda > 0.0 ? (size_t)RT : 0) + mats);
   kr_status result = KR_OK;
-  if (g.N >= 2 && plds <= 150 * 1024 && (o.flags & KR_OPT_COOPERATIVE)) {
-    // one cooperative launch runs every iteration
-    PArgs pa{};
-    pa.T = T;
-    pa.g = g;
-    pa.tr = tr;
-    pa.Omega = B.Omega;
-    pa.bD = B.bD;
-    for (int k = 1; k < g.N; ++k) { pa.P[k] = B.P[k]; pa.Q[k] = B.Q[k]; }
-    pa.gp = B.t0;
-    pa.wrow = B.wrow;
-    pa.rs1 = B.rs1;
-    KL(h, k_level1_rows, dim3(grid_for(level_cap(g, 1) + 1, 256, 1024)), dim3(256), 0, s, g, tr, B.rs1);
-    pa.xout = (double*)d_x;
-    pa.st = B.state;
-    pa.bar = bar;
-    pa.abortf = (int32_t*)(bar + 16);
-    pa.setup_flags = B.s.flags;
-    pa.lambda = lambda;
-    pa.eta = eta;
-    pa.tol = tol;
-    pa.max_iter = max_iter;
-    pa.use_ginv = lambda == 0.0 ? 1 : 0;
-    KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)bar, (int64_t)64);
-    const void* fn = G == 8 ? (const void*)k_richardson_persistent<8>
-                   : G == 16 ? (const void*)k_richardson_persistent<16>
-                   : G == 32 ? (const void*)k_richardson_persistent<32>
-                             : (const void*)k_richardson_persistent<64>;
-    int dev = 0, ncu = 0, per_cu = 0;
-    HIPCHK(h, hipGetDevice(&dev));
-    HIPCHK(h, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
-    HIPCHK(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PT, plds));
-    if (per_cu < 1) KR_FAIL(h, KR_EUNSUPPORTED, "persistent kernel does not fit on a compute unit");
-    // fences of the grid barrier cost grow with the number of workgroups; 16
-    // workgroups of 1024 threads keep a barrier near 3 us
-    const int64_t CE = g.R[0] >= PT ? 1 : PT / g.R[0];
-    const int64_t want = std::max<int64_t>(level_cap(g, 1), (g.rsuf[1] * g.nrhs + CE - 1) / CE);
-    const int64_t cap = o.workgroups > 0 ? o.workgroups : 16;
-    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((int64_t)per_cu * ncu, want), cap));
-    void* args[] = {&pa};
-    {
-      ProfScope ps(h, "k_richardson_persistent", s);
-      HIPCHK(h, hipLaunchCooperativeKernel(fn, dim3(nblk), dim3(PT), args, (unsigned)plds, s));
-    }
-    HIPCHK(h, hipMemcpyAsync(h->h_state, B.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
-    if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A or b");
-    if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
-    if ((fl & KR_FLAG_SINGULAR) && lambda == 0.0)
-      KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
-    if (h->h_state->diverged == 2) KR_FAIL(h, KR_EHIP, "grid barrier timed out in the persistent iteration");
-  } else {
+  {
     PrecondArgs pa{};
     pa.grad = B.Q[0];
     pa.nnb = 1;
@@ -1261,14 +1286,21 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     while (iters_enqueued < max_iter) {
       chunk = std::max(1, std::min(chunk, max_iter - iters_enqueued));
       for (int it = 0; it < chunk; ++it) {
-        const int npb =
-            prec == KR_PREC_F64
-                ? launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
-                                                (const IterState*)B.state)
-                : launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
-                                               (const IterState*)B.state);
+        int npb;
+        if (nchunk > 0)
+          npb = prec == KR_PREC_F64
+                    ? launch_fused3<double>(h, g, tr, B.ck, nchunk, B.P[0], B.Omega, B.bD, B.Q1c, B.part,
+                                            (const IterState*)B.state)
+                    : launch_fused3<float>(h, g, tr, B.ck, nchunk, B.P[0], B.Omega, B.bD, B.Q1c, B.part,
+                                           (const IterState*)B.state);
+        else
+          npb = prec == KR_PREC_F64
+                    ? launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
+                                                    (const IterState*)B.state)
+                    : launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
+                                                   (const IterState*)B.state);
         pa.grad = npb > 0 ? (const void*)B.part : (const void*)B.Q[0];
-        pa.nnb = npb > 0 ? (unsigned)((tr.ncnt[1] + npb - 1) / npb) : 1u;
+        pa.nnb = npb > 0 ? (unsigned)(((nchunk > 0 ? nchunk : tr.ncnt[1]) + npb - 1) / npb) : 1u;
         launch_precond(h, prec, T, g, pa);
       }
       iters_enqueued += chunk;
@@ -1548,11 +1580,11 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     if (permuted[i]) total += 2 * 8 * (size_t)G[i].Rtot * G[i].nrhs + 1024;   // x and X_true in tree order
     if (route[i] == TEAM) nparts += (size_t)((G[i].Rtot + TM_THREADS - 1) / TM_THREADS) * G[i].nrhs * 2;
   }
-  total += (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) + 4096;
+  total += (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + sizeof(SampleJob) + 8) + 4096 + 256;
   total += (size_t)nteam_p * (sizeof(LExtra) + 8 + 4) + nparts * 8 + 8192;
   kr_status st = ensure(h, &h->ws, &h->ws_bytes, total);
   if (st != KR_OK) return st;
-  const size_t host_bytes = (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + 8) +
+  const size_t host_bytes = (size_t)nall * (sizeof(BatchDesc) + sizeof(BatchResult) + sizeof(SampleJob) + 8) + 64 +
                             (size_t)nteam_p * sizeof(LExtra) + 1024;
   if (host_bytes > h->h_batch_bytes) {
     if (h->h_batch) HIPCHK(h, hipHostFree(h->h_batch));
@@ -1567,6 +1599,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   int32_t* horder = (int32_t*)(hl + nteam_p);
   BatchResult* hres = (BatchResult*)(((uintptr_t)(horder + nall) + 15) & ~(uintptr_t)15);
   int32_t* habort = (int32_t*)(hres + nall);
+  SampleJob* hjobs = (SampleJob*)(((uintptr_t)(habort + 4) + 15) & ~(uintptr_t)15);
   Arena a{(char*)h->ws, h->ws_bytes, 0};
   BatchDesc* d_descs = a.take<BatchDesc>(nall);
   LExtra* d_l = a.take<LExtra>(std::max(1, nteam_p));
@@ -1582,6 +1615,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   int32_t* d_ticket = (int32_t*)(d_cnt + 64);
   int64_t* d_done = a.take<int64_t>(std::max(1, nteam_p));
   double* d_part = a.take<double>(std::max<size_t>(1, nparts));
+  SampleJob* d_jobs = a.take<SampleJob>(nall);
   hipStream_t s = h->stream;
   // graph mode: the work enqueued below (everything but the multi-kernel
   // problems above) is captured once and replayed while the signature -- every
@@ -1652,6 +1686,10 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     for (int k = 0; k < 4; ++k) HIPCHK(h, hipStreamWaitEvent(h->side[k], h->fork_ev, 0));
   }
   h->batch.assign(count, SketchRec{});
+  std::vector<ModeTables> pT(count);
+  std::vector<SolveBufs> pB(count);
+  std::vector<Tree> ptr(count);
+  std::vector<double*> pxi(count, nullptr);
   int pidx = 0;
   for (int i : idx) {
     h->stream = h->side[pidx++ & 3];
@@ -1660,7 +1698,6 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     ModeTables T{};
     SolveBufs B{};
     Tree tr{};
-    unsigned* bar = nullptr;
     double* xi = (double*)d_x[i];
     double* Xt = nullptr;
     if (permuted[i]) {
@@ -1669,7 +1706,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
       xtree[i] = xi;
       if (pp[i].gen) pgen[i].X_true = Xt;
     }
-    carve_solve(a, g, false, xi, &T, &B, &tr, &bar, team);
+    carve_solve(a, g, false, xi, &T, &B, &tr, team);
     if (a.off > a.cap) KR_FAIL(h, KR_EHIP, "internal: workspace overflow (%zu > %zu)", a.off, a.cap);
     kr_opts oi = o;
     oi.stream = o.stream + (uint64_t)i;
@@ -1677,13 +1714,29 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
       if (permuted[i] && pp[i].gen)
         KL(h, k_permute_modes, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, h->stream, g,
            probs[i].gen->X_true, Xt, 1);
-      st = launch_sketch(h, &pp[i], g, T, B, tr, oi, lambda[i] > 0.0);
+      st = launch_setup(h, &pp[i], g, T, B.s, true, lambda[i] > 0.0, oi.seed, oi.stream);
       if (st != KR_OK) return st;
-      if (lambda[i] > 0.0)
-        KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, h->stream, T, g, lambda[i], B.dinv);
-      KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, h->stream, xi, g.Rtot * g.nrhs, 0.0);
-      KL(h, k_zero_bytes, dim3(1), dim3(256), 0, h->stream, (uint32_t*)B.state, (int64_t)(sizeof(IterState) / 4));
     }
+    // this problem's share of the batched sampling launch
+    {
+      SampleJob& jb = hjobs[slot[i]];
+      std::memset(&jb, 0, sizeof(SampleJob));
+      for (int n = 0; n < g.N; ++n) {
+        jb.C[n] = T.C[n];
+        jb.I[n] = g.I[n];
+        jb.shift[n] = g.shift[n];
+        jb.inv[n] = g.inv[n];
+      }
+      jb.N = g.N;
+      jb.m = g.m;
+      jb.seed = oi.seed;
+      jb.stream = oi.stream;
+      jb.keys = B.keys;
+    }
+    pT[i] = T;
+    pB[i] = B;
+    ptr[i] = tr;
+    pxi[i] = xi;
     SketchRec& rec = h->batch[i];
     rec.valid = true;
     rec.g = g;
@@ -1717,11 +1770,43 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
     }
   }
   h->stream = s;
-  if (enq)
+  // every problem's samples in one launch (8 samples per thread), then the rest of
+  // each sketch on the side streams again.  The job table is rebuilt on every call
+  // (a replayed graph copies it from the pinned staging again).
+  int64_t nb = 0;
+  for (int j = 0; j < nall; ++j) {
+    hjobs[j].b0 = nb;
+    nb += std::max<int64_t>(1, (hjobs[j].m + 2047) / 2048);
+  }
+  if (enq) {
     for (int k = 0; k < 4; ++k) {
       HIPCHK(h, hipEventRecord(h->join_ev[k], h->side[k]));
       HIPCHK(h, hipStreamWaitEvent(s, h->join_ev[k], 0));
     }
+    HIPCHK(h, hipMemcpyAsync(d_jobs, hjobs, nall * sizeof(SampleJob), hipMemcpyHostToDevice, s));
+    if (nb > 2147483647LL) KR_FAIL(h, KR_EUNSUPPORTED, "too many samples in one batch");
+    KL(h, k_sample_batched, dim3((unsigned)nb), dim3(256), 0, s, (const SampleJob*)d_jobs, nall);
+    HIPCHK(h, hipEventRecord(h->fork_ev, s));
+    for (int k = 0; k < 4; ++k) HIPCHK(h, hipStreamWaitEvent(h->side[k], h->fork_ev, 0));
+    pidx = 0;
+    for (int i : idx) {
+      h->stream = h->side[pidx++ & 3];
+      const Geom& g = G[i];
+      st = launch_sketch_rest(h, &pp[i], g, pT[i], pB[i], ptr[i]);
+      if (st != KR_OK) return st;
+      if (lambda[i] > 0.0)
+        KL(h, k_precond_diag, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, h->stream, pT[i], g, lambda[i],
+           pB[i].dinv);
+      KL(h, k_fill, dim3(grid_for(g.Rtot * g.nrhs, 256, 1024)), dim3(256), 0, h->stream, pxi[i], g.Rtot * g.nrhs,
+         0.0);
+      KL(h, k_zero_bytes, dim3(1), dim3(256), 0, h->stream, (uint32_t*)pB[i].state, (int64_t)(sizeof(IterState) / 4));
+    }
+    h->stream = s;
+    for (int k = 0; k < 4; ++k) {
+      HIPCHK(h, hipEventRecord(h->join_ev[k], h->side[k]));
+      HIPCHK(h, hipStreamWaitEvent(s, h->join_ev[k], 0));
+    }
+  }
   // queue problems largest first
   std::vector<int32_t> ord(nq);
   for (int k = 0; k < nq; ++k) ord[k] = k;

@@ -76,6 +76,22 @@ struct Tree {
                                 // built and passed by value to the iteration kernels
 };
 
+// Chunks of the level-2 nodes for the fused pass of three-mode problems: chunk c
+// covers the level-2 nodes [beg[c], beg[c+1]), all children of the level-1 node
+// par[c] (a node's children are split into runs of at most `ch` nodes), and
+// arow[c] / arow32[c] hold that node's factor row a_0[i_0(par[c])].  Built on the
+// device once the tree is; *count is the number of chunks (written even when it
+// exceeds cap, in which case the table is not).
+struct Chunks {
+  int32_t* beg;
+  int32_t* par;
+  double* arow;
+  float* arow32;
+  int64_t* count;
+  int cap;
+  int ch;
+};
+
 // Solver state shared between the iteration kernels (device memory).
 struct IterState {
   int32_t iters;        // iterations completed

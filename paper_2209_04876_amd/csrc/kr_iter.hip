@@ -138,21 +138,80 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree t
   }
 }
 
+#ifndef KR_ROWS_PER_STEP
+#define KR_ROWS_PER_STEP 4
+#endif
+
+// The rows of one (level-(N-1) node, rhs) task, owned by one wave whose lane
+// group gi takes rows gi + NGR u (u < RPS) of each step of RPS NGR rows, all
+// requested at once.  The loads are unconditional: an absent row re-reads the
+// step's first row and gets weight 0 where it is used, and lanes r >= R re-read
+// entry R - 1, which meets P_{N-1} = 0 there.  Rows are addressed by 32-bit
+// offsets from wave-uniform (scalar) bases.  load(0) is issued before the node's
+// forward value is formed, so that both memory round trips overlap; run(pv)
+// then returns the wave's sum of (Omega_j u_j) a_{N-1}[i(j)][lane] over the node's
+// rows, u_j = <a_{N-1}[i(j)], P_{N-1}> - b_j formed in float64.
+template <int G, int RPS>
+struct RowsTask {
+  static constexpr int NGR = 64 / G;
+  const double* __restrict__ ab;
+  const double* __restrict__ ob;
+  const double* __restrict__ bp;
+  int nrow, R, nrhs, gi;
+  unsigned lc;
+  double aA[RPS], oA[RPS], bA[RPS];
+  __device__ __forceinline__ RowsTask(const double* AL, const double* Omega, const double* bD, int j0, int j1,
+                                      int R_, int nrhs_, int q, int lane, int gi_)
+      : ab(AL + (int64_t)j0 * R_), ob(Omega + j0), bp(bD + (int64_t)j0 * nrhs_ + q), nrow(j1 - j0), R(R_),
+        nrhs(nrhs_), gi(gi_), lc(lane < R_ ? (unsigned)lane : (unsigned)(R_ - 1)) {}
+  __device__ __forceinline__ void load(int k) {
+    const int nl = nrow - k * RPS * NGR;
+    const double* __restrict__ abk = ab + (int64_t)k * RPS * NGR * R;
+    const double* __restrict__ obk = ob + k * RPS * NGR;
+    const double* __restrict__ bpk = bp + (int64_t)k * RPS * NGR * nrhs;
+#pragma unroll
+    for (int u = 0; u < RPS; ++u) {
+      const int jl = gi + u * NGR;
+      const unsigned jc = jl < nl ? (unsigned)jl : 0u;
+      aA[u] = ld_at(abk, (jc * (unsigned)R + lc) * 8u);
+      oA[u] = ld_at(obk, jc * 8u);
+      bA[u] = ld_at(bpk, jc * (unsigned)nrhs * 8u);
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ T run(double pv) {
+    T acc = 0;
+    const int nstep = (nrow + RPS * NGR - 1) / (RPS * NGR);
+    for (int k = 0;;) {
+      const int nl = nrow - k * RPS * NGR;
+      double y[RPS];
+#pragma unroll
+      for (int u = 0; u < RPS; ++u) y[u] = grp_sum<G>(aA[u] * pv);
+#pragma unroll
+      for (int u = 0; u < RPS; ++u) {
+        const double w = gi + u * NGR < nl ? oA[u] : 0.0;
+        acc = fma((T)(w * (y[u] - bA[u])), (T)aA[u], acc);
+      }
+      if (++k >= nstep) break;
+      load(k);
+    }
+    // sum over the groups of the wave (fixed pairing order)
+#pragma unroll
+    for (int o = G; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    return acc;
+  }
+};
+
 // The last forward level, the rows and the last adjoint level, fused.  One wave
 // owns one (level-(N-1) node p, rhs q).  Its NGR = 64/G lane groups (G a power of
 // two >= R_{N-1}) first form P_{N-1}[p][r][q] in lane r: from P_{N-2}[parent(p)]
 // and the gathered factor row a_{N-2}[i(p)] (P_0 = x with the root as parent;
 // for N = 1 it is x itself; for a segment root it is the segment's own iterate).
-// Group gi then takes rows j0 + gi, j0 + gi + NGR, ... of p, KR_ROWS_PER_STEP per
-// step (the first step's requested before the node's forward value):
-// u_j = <a_{N-1}[i(j)], P_{N-1}[p]> - b_j in float64 and Q[p][r][q] +=
-// (Omega_j u_j) a_{N-1}[i(j)][r] in T; the groups' sums are added in a fixed order.
+// The rows then follow as in RowsTask: Q[p][r][q] = sum_j (Omega_j u_j)
+// a_{N-1}[i(j)][r] in T, the groups' sums added in a fixed order.
 // Measured: the wave-uniform task with scalar row bases, DPP group sums and one
 // register set (92 VGPRs, 5 waves per SIMD) beat a prefetching second set; the
 // compiler waits for all loads at the loop head either way.
-#ifndef KR_ROWS_PER_STEP
-#define KR_ROWS_PER_STEP 4
-#endif
 template <int G, typename T>
 __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr,
                                                  const double* __restrict__ Pprev,
@@ -161,7 +220,6 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
                                                  T* __restrict__ Qout,
                                                  const IterState* __restrict__ st) {
   constexpr int NGR = 64 / G;
-  constexpr int RPS = KR_ROWS_PER_STEP;
   const int N = g.N, nrhs = g.nrhs;
   const int R = g.R[N - 1];
   const double* __restrict__ AL = tr.arow[N];
@@ -171,44 +229,18 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
   const bool ln = lane < R;
   const int64_t wpb = blockDim.x >> 6;
   // the task index is wave-uniform, so the node's bounds and row bases live in
-  // scalar registers and every lane addresses its rows by a small 32-bit offset
+  // scalar registers
   const int64_t w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   for (int64_t task = blockIdx.x * wpb + w; task < ntask; task += (int64_t)gridDim.x * wpb) {
     const int64_t p = task / nrhs;
     const int q = (int)(task - p * nrhs);
     const int j0 = tr.fchild[N - 1][p], j1 = tr.fchild[N - 1][p + 1];
-    const double* __restrict__ ab = AL + (int64_t)j0 * R;
-    const double* __restrict__ ob = Omega + j0;
-    const double* __restrict__ bp = bD + (int64_t)j0 * nrhs + q;
-    // Steps of RPS NGR rows; group gi takes rows gi + NGR u (u < RPS) of a step,
-    // all requested at once.  The loads are unconditional: an absent row re-reads
-    // the step's first row and gets weight 0 where it is used, and lanes r >= R
-    // re-read entry R - 1, which meets P_{N-1} = 0 there.  32-bit offsets from
-    // the scalar bases.
-    const int nrow = j1 - j0;
-    if (nrow <= 0) {  // a node always has rows; kept for safety (uniform branch)
+    if (j1 <= j0) {  // a node always has rows; kept for safety (uniform branch)
       if (gi == 0 && ln) Qout[(p * R + lane) * nrhs + q] = (T)0;
       continue;
     }
-    const unsigned lc = ln ? lane : R - 1;
-    auto load_step = [&](double (&av)[RPS], double (&om)[RPS], double (&bb)[RPS], int k) {
-      const int nl = nrow - k * RPS * NGR;
-      const double* __restrict__ abk = ab + (int64_t)k * RPS * NGR * R;
-      const double* __restrict__ obk = ob + k * RPS * NGR;
-      const double* __restrict__ bpk = bp + (int64_t)k * RPS * NGR * nrhs;
-#pragma unroll
-      for (int u = 0; u < RPS; ++u) {
-        const int jl = gi + u * NGR;
-        const unsigned jc = jl < nl ? (unsigned)jl : 0u;
-        av[u] = ld_at(abk, (jc * (unsigned)R + lc) * 8u);
-        om[u] = ld_at(obk, jc * 8u);
-        bb[u] = ld_at(bpk, jc * (unsigned)nrhs * 8u);
-      }
-    };
-    double aA[RPS], oA[RPS], bA[RPS];
-    // the first step's rows are requested before the forward value of the node,
-    // so that both memory round trips overlap
-    load_step(aA, oA, bA, 0);
+    RowsTask<G, KR_ROWS_PER_STEP> rt(AL, Omega, bD, j0, j1, R, nrhs, q, lane, gi);
+    rt.load(0);
     // P_{N-1}[p][lane][q]; from a parent level, group gi sums the terms
     // s = gi, gi + NGR, ... of the contraction over R_{N-2} and the groups' partial
     // sums are combined by a butterfly (the same rounding in every group)
@@ -238,28 +270,157 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
       }
       pv = xgrp_sum<G>(pv);
     }
-    T acc = 0;
-    auto step = [&](const double (&av)[RPS], const double (&om)[RPS], const double (&bb)[RPS], int k) {
-      const int nl = nrow - k * RPS * NGR;
-      double y[RPS];
-#pragma unroll
-      for (int u = 0; u < RPS; ++u) y[u] = grp_sum<G>(av[u] * pv);
-#pragma unroll
-      for (int u = 0; u < RPS; ++u) {
-        const double w = gi + u * NGR < nl ? om[u] : 0.0;
-        acc = fma((T)(w * (y[u] - bb[u])), (T)av[u], acc);
-      }
-    };
-    const int nstep = (nrow + RPS * NGR - 1) / (RPS * NGR);
-    for (int k = 0;;) {
-      step(aA, oA, bA, k);
-      if (++k >= nstep) break;
-      load_step(aA, oA, bA, k);
-    }
-    // sum over the groups of the wave (fixed pairing order)
-#pragma unroll
-    for (int o = G; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    const T acc = rt.template run<T>(pv);
     if (gi == 0 && ln) Qout[(p * R + lane) * nrhs + q] = acc;
+  }
+}
+
+// The chunk table of the fused three-mode pass: the children of level-1 node p
+// (n_p of them) split into k_p = ceil(n_p / ch) runs, run j starting at child
+// floor(j n_p / k_p), numbered in node order by an exclusive scan of k_p over
+// the level-1 nodes.  One workgroup of CH_THREADS threads.
+#define CH_THREADS 1024
+__global__ void __launch_bounds__(CH_THREADS) k_chunk_table(Tree tr, Chunks ck, int R0, int f32) {
+  __shared__ int wsum[CH_THREADS / 64];
+  const int S1 = (int)tr.cnt[1];
+  const int32_t* __restrict__ fc = tr.fchild[1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int running = 0;
+  for (int b0 = 0; b0 < S1; b0 += CH_THREADS) {
+    const int p = b0 + (int)threadIdx.x;
+    int f = 0, n = 0, k = 0;
+    if (p < S1) {
+      f = fc[p];
+      n = fc[p + 1] - f;
+      k = (n + ck.ch - 1) / ck.ch;
+    }
+    int v = k;   // inclusive scan of k over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(v, o, 64);
+      if (lane >= o) v += t;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int i = 0; i < CH_THREADS / 64; ++i) {
+      const int t = wsum[i];
+      before += i < w ? t : 0;
+      total += t;
+    }
+    const int off = running + before + v - k;
+    if (off + k <= ck.cap)
+      for (int j = 0; j < k; ++j) {
+        ck.beg[off + j] = f + (int)(((int64_t)j * n) / k);
+        ck.par[off + j] = p;
+      }
+    running += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *ck.count = running;
+    if (running <= ck.cap) ck.beg[running] = (int)tr.cnt[2];
+  }
+  if (running > ck.cap) return;
+  __syncthreads();
+  const double* __restrict__ a0 = tr.arow[1];
+  for (int e = threadIdx.x; e < running * R0; e += CH_THREADS) {
+    const int c = e / R0;
+    const double a = a0[(int64_t)ck.par[c] * R0 + (e - c * R0)];
+    ck.arow[e] = a;
+    if (f32) ck.arow32[e] = (float)a;
+  }
+}
+
+// The fused pass of a three-mode problem (no segment roots), one workgroup of
+// 256 threads per chunk c (the children s in [beg[c], beg[c+1]) of the level-1
+// node p = par[c]):
+//   P_1[p] = x contracted with a_0[i(p)], in LDS, summed as the forward level;
+//   per (child s, rhs), one wave: P_2[s] from P_1[p] and a_1[i(s)], then the rows
+//   of s as in the rows kernel, giving Q_2[s] in LDS;
+//   Q1c[c][r][e] = sum_s a_1[i(s)][r] Q_2[s][e] in increasing s.
+// The root adjoint sums the chunks in place of the level-1 nodes (each with the
+// factor row of its node): the same sum, grouped by chunk.  Workgroups are
+// independent, so the forward level, the rows and the last adjoint level cost
+// one launch.  Dynamic LDS: W1 doubles for P_1, then ch R_1 and ch R_2 nrhs
+// entries of T for the children's factor rows and Q_2.
+template <int G, typename T>
+__global__ void __launch_bounds__(256) k_subtree3(Geom g, Tree tr, Chunks ck, const double* __restrict__ x,
+                                                 const double* __restrict__ Omega,
+                                                 const double* __restrict__ bD, T* __restrict__ Q1c) {
+  extern __shared__ double sub_lds[];
+  constexpr int NGR = 64 / G;
+  const int nrhs = g.nrhs;
+  const int R0 = g.R[0], R1 = g.R[1], R = g.R[2];
+  const unsigned W2 = (unsigned)(R * nrhs);
+  const unsigned W1 = (unsigned)R1 * W2;
+  double* P1 = sub_lds;
+  T* A1 = (T*)(sub_lds + W1);
+  T* Q2 = A1 + ck.ch * R1;
+  const int c = blockIdx.x;
+  const int p = ck.par[c];
+  const int s0 = ck.beg[c], ns = ck.beg[c + 1] - s0;
+  const int lane = threadIdx.x & (G - 1);
+  const int gi = (threadIdx.x & 63) / G;
+  const bool ln = lane < R;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int ntask = ns * nrhs;
+  // the first task's rows are requested before P_1 is formed
+  int task = w;
+  int j0 = 0, j1 = 0;
+  if (task < ntask) {
+    j0 = tr.fchild[2][s0 + task / nrhs];
+    j1 = tr.fchild[2][s0 + task / nrhs + 1];
+  }
+  RowsTask<G, KR_ROWS_PER_STEP> rt(tr.arow[3], Omega, bD, j0, j1, R, nrhs, task < ntask ? task % nrhs : 0, lane,
+                                   gi);
+  if (task < ntask && j1 > j0) rt.load(0);
+  {
+    const double* __restrict__ a0 = tr.arow[1] + (int64_t)p * R0;
+    for (unsigned e = threadIdx.x; e < W1; e += blockDim.x) P1[e] = dot_batched(a0, x + e, W1, R0);
+    const T* __restrict__ a1 = node_rows<T>(tr, 2) + (int64_t)s0 * R1;
+    for (int e = threadIdx.x; e < ns * R1; e += blockDim.x) A1[e] = a1[e];
+  }
+  __syncthreads();
+  for (; task < ntask; task += blockDim.x >> 6) {
+    const int sl = task / nrhs, q = task - sl * nrhs;
+    if (task != w) {
+      j0 = tr.fchild[2][s0 + sl];
+      j1 = tr.fchild[2][s0 + sl + 1];
+      rt = RowsTask<G, KR_ROWS_PER_STEP>(tr.arow[3], Omega, bD, j0, j1, R, nrhs, q, lane, gi);
+      if (j1 > j0) rt.load(0);
+    }
+    if (j1 <= j0) {  // a node always has rows; kept for safety (uniform branch)
+      if (gi == 0 && ln) Q2[sl * W2 + lane * nrhs + q] = (T)0;
+      continue;
+    }
+    // P_2[s][lane][q], summed as in the rows kernel (from LDS)
+    double pv = 0.0;
+    if (ln) {
+      const double* __restrict__ a = tr.arow[2] + (int64_t)(s0 + sl) * R1;
+      const unsigned step = W2;
+      for (int r0 = gi; r0 < R1; r0 += 4 * NGR) {
+        double as[4], sv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + u * NGR;
+          as[u] = r < R1 ? a[r] : 0.0;
+          sv[u] = r < R1 ? P1[r * step + lane * nrhs + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pv = fma(as[u], sv[u], pv);
+      }
+    }
+    pv = xgrp_sum<G>(pv);
+    const T acc = rt.template run<T>(pv);
+    if (gi == 0 && ln) Q2[sl * W2 + lane * nrhs + q] = acc;
+  }
+  __syncthreads();
+  for (unsigned e = threadIdx.x; e < W1; e += blockDim.x) {
+    const unsigned r = e / W2, cq = e - r * W2;
+    T acc = 0;
+    for (int sl = 0; sl < ns; ++sl) acc = fma(A1[sl * R1 + r], Q2[sl * W2 + cq], acc);
+    Q1c[(size_t)c * W1 + e] = acc;
   }
 }
 

@@ -65,6 +65,74 @@ __global__ void __launch_bounds__(256) k_sample(ModeTables T, Geom g, uint64_t s
   }
 }
 
+// Every problem of a batch in one launch: job j owns blocks [b0_j, b0_{j+1}) and
+// draws its m_j samples exactly as k_sample does (the key of sample t depends on t
+// only, so the grid does not change any key).  Each block stages its problem's
+// CDFs in LDS when they fit.
+struct SampleJob {
+  const uint64_t* C[KR_MAXN];
+  int I[KR_MAXN];
+  int shift[KR_MAXN];
+  int inv[KR_MAXN];
+  int N;
+  int64_t m;
+  uint64_t seed, stream;
+  uint64_t* keys;
+  int64_t b0;            // first block of the job
+};
+
+#define SB_LDS_ENTRIES 4096
+__global__ void __launch_bounds__(256) k_sample_batched(const SampleJob* __restrict__ jobs, int njobs) {
+  __shared__ uint64_t cdf[SB_LDS_ENTRIES];
+  __shared__ int jsh;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = njobs - 1;   // last job with b0 <= blockIdx.x
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].b0 <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    jsh = lo;
+  }
+  __syncthreads();
+  const SampleJob& jb = jobs[jsh];
+  const int64_t b1 = jsh + 1 < njobs ? jobs[jsh + 1].b0 : (int64_t)gridDim.x;
+  const int N = jb.N;
+  int sumI = 0;
+  for (int n = 0; n < N; ++n) sumI += jb.I[n];
+  const bool in_lds = sumI <= SB_LDS_ENTRIES;
+  const uint64_t* C[KR_MAXN];
+  int off = 0;
+  for (int n = 0; n < N; ++n) {
+    if (in_lds) {
+      for (int i = threadIdx.x; i < jb.I[n]; i += blockDim.x) cdf[off + i] = jb.C[n][i];
+      C[n] = cdf + off;
+    } else {
+      C[n] = jb.C[n];
+    }
+    off += jb.I[n];
+  }
+  __syncthreads();
+  const int64_t nthr = (b1 - jb.b0) * (int64_t)blockDim.x;
+  for (int64_t t = (blockIdx.x - jb.b0) * (int64_t)blockDim.x + threadIdx.x; t < jb.m; t += nthr) {
+    uint64_t key = 0;
+    for (int grp = 0; grp * 4 < N; ++grp) {
+      const u64x4 w = philox4x64_10((uint64_t)t, (uint64_t)grp, 0ull, 0ull, jb.seed, jb.stream);
+      for (int k = 0; k < 4 && grp * 4 + k < N; ++k) {
+        const int n = jb.inv[grp * 4 + k];
+        const uint64_t u = w.v[k] >> 32;
+        int lo = 0, hi = jb.I[n];
+        const uint64_t* c = C[n];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (c[mid] <= u) lo = mid + 1; else hi = mid;
+        }
+        key |= (uint64_t)lo << jb.shift[n];
+      }
+    }
+    jb.keys[t] = key;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // LSD radix sort, RB-bit digits (8 or 9: 27-bit keys sort in three passes of 9
 // bits instead of four of 8).  hist is digit-major: hist[d * nblocks + b], with

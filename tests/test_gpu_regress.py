@@ -177,21 +177,6 @@ def test_sketch_failure_detected(gpu_lib):
     assert e.value.status == -5
 
 
-@pytest.mark.parametrize("case", [CASES[2], CASES[6], CASES[8], CASES[9]], ids=lambda c: c[0])
-def test_cooperative_iteration_matches(gpu_lib, case):
-    # the single cooperative launch (grid barriers) reaches the same sketched
-    # minimiser as the one-kernel-per-phase iteration
-    name, I, R, m, nrhs, lam, heavy = case
-    print("case cooperative", name, flush=True)
-    w = workloads.random_problem(I, R, seed=zlib.crc32(name.encode()) % 1000, nrhs=nrhs, heavy=heavy)
-    tA, tb = _torch_inputs(w["As"], w["b"])
-    xm, im = gpu_lib.kron_ridge(tA, tb, lam, m=m, seed=7, stream=3, tol=1e-12, max_iter=400,
-                                cooperative=True)
-    xp, ip = gpu_lib.kron_ridge(tA, tb, lam, m=m, seed=7, stream=3, tol=1e-12, max_iter=400)
-    assert im["status"] == ip["status"] == "OK"
-    assert rel_l2(xm.cpu().numpy(), xp.cpu().numpy()) < 1e-11
-
-
 def test_default_sample_count_is_algorithm_2s(gpu_lib):
     """opts.m = 0 takes Algorithm 2's count ceil(1680 R ln(40 R) ln(1/delta) / eps)
     (the oracle's theory_sample_count, pinned to the paper's printed rows-sampled
