@@ -43,6 +43,7 @@ METRIC = "Kronecker solves/s + HBM GB/s, BF16-refined vs FP64 plain, at loss ≤
 HBM_PEAK_GBS = 8000.0
 # MI355X dense peaks (TFLOP/s): the contraction's own dtype sets its roof
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # wave64 VALU instructions: one per CU per clock
 
 
 def log(*a):
@@ -97,10 +98,11 @@ def fused_runs(rows, ch=8):
     return int(np.sum((nch + ch - 1) // ch))
 
 
-def recorded_traffic(name="skewed_regression_hbm_counters.md"):
+def recorded_traffic(name="skewed_regression_hbm_counters.md", kind="traffic", field="bytes"):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain copy), as recorded in profiles/<name>; an entry counts only
-    while its kernel source still hashes as recorded."""
+    scaled by a plain copy), as recorded in profiles/<name> (kind "valu": VALU
+    instructions per launch, SQ_INSTS_VALU); an entry counts only while its kernel
+    source still hashes as recorded."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", name)
@@ -108,7 +110,7 @@ def recorded_traffic(name="skewed_regression_hbm_counters.md"):
     if not os.path.exists(path):
         return out
     for line in open(path):
-        m = re.match(r"- traffic (\S+) bytes=(\d+) source=(\S+) sha256_16=([0-9a-f]+)", line.strip())
+        m = re.match(r"- %s (\S+) %s=(\d+) source=(\S+) sha256_16=([0-9a-f]+)" % (kind, field), line.strip())
         if not m:
             continue
         src = os.path.join(ROOT, "paper_2209_04876_amd", "csrc", m.group(3))
@@ -252,6 +254,13 @@ def batched_leg(kr, torch, steps):
         samp = {"kernel": "k_sample_batched", "launches": nsb, "avg_launch_ms": round(sbms / nsb, 4),
                 "algorithmic_bytes_per_launch": sum_m * 8, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "samples": sum_m}
+        # its bound: VALU issue (SQ_INSTS_VALU per launch from profiles/, 64 lane
+        # operations each) against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+        insts = recorded_traffic("batched_ridge_valu_counters.md", "valu", "insts").get("k_sample_batched")
+        if insts:
+            ops = insts * 64 / (sbms / nsb * 1e-3) / 1e12
+            samp["alu"] = {"bound": "alu", "achieved": round(ops, 2), "peak": VALU_PEAK_TOPS, "unit": "T lane-op/s",
+                           "frac": round(ops / VALU_PEAK_TOPS, 4), "valu_instructions_per_launch": insts}
     return {
         "workload": "batched ridge: %d problems, N~U{2,3,4}, I_n~U{32..256}, R_n~U{4..16}, 1-8 RHS, "
                     "lambda=10^U(-4,0), FP32 factors, implicit b = K X_true + 0.01 e, "

@@ -730,7 +730,10 @@ static int64_t level_cap(const Geom& g, int k) {
 // R_2 <= 16 (one lane group per row), its LDS (P_1, and the factor rows and
 // Q_2 of at most ch children) within 48 KB, and at most 65536 level-1 nodes
 // (the chunk table is one workgroup's scan).
-static int fused3_ch(const Geom& g) { return std::max(1, 8 / g.nrhs); }
+#ifndef KR_FUSED_RUN
+#define KR_FUSED_RUN 8     // (node, rhs) tasks per run of the fused pass
+#endif
+static int fused3_ch(const Geom& g) { return std::max(1, KR_FUSED_RUN / g.nrhs); }
 static size_t fused3_lds(const Geom& g, size_t elem) {
   const size_t W2 = (size_t)g.R[2] * g.nrhs;
   return 8 * (size_t)g.R[1] * W2 + elem * (size_t)fused3_ch(g) * ((size_t)g.R[1] + W2);
@@ -821,26 +824,29 @@ static int root_npb(const Tree& tr) {
   // up to 2048 level-1 nodes: about four partial blocks of at least 128 nodes
   // (their sum costs the preconditioner little, and the root adjoint spreads
   // over more workgroups); beyond, 64 blocks
+#ifndef KR_ROOT_BLOCKS
+#define KR_ROOT_BLOCKS 4   // partial blocks of the root adjoint up to 2048 level-1 nodes
+#endif
   const int64_t S1 = std::max<int64_t>(1, tr.ncnt[1]);
-  const int64_t per = S1 <= 2048 ? std::max<int64_t>(std::min<int64_t>(S1, 128), (S1 + 3) / 4) : (S1 + 63) / 64;
+  const int64_t per = S1 <= 2048 ? std::max<int64_t>(std::min<int64_t>(S1, 512 / KR_ROOT_BLOCKS),
+                                                      (S1 + KR_ROOT_BLOCKS - 1) / KR_ROOT_BLOCKS)
+                                 : (S1 + 63) / 64;
   return (int)(RA_NODES * ((per + RA_NODES - 1) / RA_NODES));
 }
 
 // One pass of the sampled products K~^T Omega (K~ x - b~) down and up the sample
 // tree: forward levels 1..N-2, the last forward level with the rows and the last
-// adjoint level, adjoint
-// levels N-1..2 and, without segment roots, the root adjoint (partial blocks of
-// npb level-1 nodes, then their sum into Q[0]; for N = 1 the rows write Q[0]).
-// P[0] is the iterate; Q[k] and part hold the adjoint type T (float64, or
+// adjoint level, and adjoint levels N-1..2.  Returns whether the root adjoint
+// (launch_root) follows: without segment roots and for N >= 2 (for N = 1 the rows
+// write Q[0]; with segment roots the level-1 adjoints are the per-segment
+// gradients).  P[0] is the iterate; Q[k] holds the adjoint type T (float64, or
 // float32 in the refined precisions).
 template <typename T>
-static int launch_level_products(kr_handle h, const ModeTables& TT, const Geom& g, const Tree& tr, double* const* P,
-                                 void* const* Qv, const double* Omega, const double* bD, void* partv,
-                                 const IterState* state) {
+static bool launch_level_products(kr_handle h, const ModeTables& TT, const Geom& g, const Tree& tr, double* const* P,
+                                  void* const* Qv, const double* Omega, const double* bD, const IterState* state) {
   hipStream_t s = h->stream;
   T* Q[KR_MAXN + 1];
   for (int k = 0; k <= KR_MAXN; ++k) Q[k] = (T*)Qv[k];
-  T* part = (T*)partv;
   const bool f32 = sizeof(T) == 4;
   const int Rl = g.R[g.N - 1];
   const int G = Rl <= 8 ? 8 : Rl <= 16 ? 16 : Rl <= 32 ? 32 : 64;
@@ -880,29 +886,17 @@ static int launch_level_products(kr_handle h, const ModeTables& TT, const Geom& 
           s, TT, g, tr, k, (const T*)Q[k], Q[k - 1], state);
     }
   }
-  if (g.N >= 2 && !g.seg_root) {
-    const int npb = root_npb(tr);
-    const int64_t CEr = adj_cols((int)g.R[0]);
-    const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
-    const int64_t nnb = (tr.ncnt[1] + npb - 1) / npb;
-    KLN(h, f32 ? "k_adj_root_partial<f32>" : "k_adj_root_partial", k_adj_root_partial<T>,
-        dim3(grid_for(ncb * nnb, 1, 4096)), dim3(ADJ_THREADS), 0, s, g, tr, (const T*)Q[1], part, npb, state);
-    return npb;
-  }
-  return 0;
+  return g.N >= 2 && !g.seg_root;
 }
 
 // The fused three-mode pass over nchunk chunks (k_subtree3: forward level 1,
-// rows and adjoint level 2 in one launch), then the root adjoint over the chunks
-// as if they were level-1 nodes.  Returns the root adjoint's chunks per partial
-// block.
+// rows and adjoint level 2 in one launch).  The root adjoint (launch_root) then
+// sums the chunks as if they were level-1 nodes (root_tree).
 template <typename T>
-static int launch_fused3(kr_handle h, const Geom& g, const Tree& tr, const Chunks& ck, int64_t nchunk,
-                         const double* x, const double* Omega, const double* bD, void* Q1cv, void* partv,
-                         const IterState* state) {
+static void launch_fused3(kr_handle h, const Geom& g, const Tree& tr, const Chunks& ck, int64_t nchunk,
+                          const double* x, const double* Omega, const double* bD, void* Q1cv) {
   hipStream_t s = h->stream;
   T* Q1c = (T*)Q1cv;
-  T* part = (T*)partv;
   const bool f32 = sizeof(T) == 4;
   const size_t lds = fused3_lds(g, sizeof(T));
   const dim3 grid((unsigned)nchunk);
@@ -912,17 +906,16 @@ static int launch_fused3(kr_handle h, const Geom& g, const Tree& tr, const Chunk
   else
     KLN(h, f32 ? "k_subtree3<16,f32>" : "k_subtree3<16>", (k_subtree3<16, T>), grid, dim3(256), lds, s, g, tr, ck,
         x, Omega, bD, Q1c);
+}
+
+// The tree the root adjoint sums over after the fused pass: the chunks in place
+// of the level-1 nodes, each with the factor row of its node.
+static Tree root_tree(const Tree& tr, const Chunks& ck, int64_t nchunk) {
   Tree trc = tr;
   trc.ncnt[1] = nchunk;
   trc.arow[1] = ck.arow;
   trc.arow32[1] = ck.arow32;
-  const int npb = root_npb(trc);
-  const int64_t CEr = adj_cols((int)g.R[0]);
-  const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
-  const int64_t nnb = (nchunk + npb - 1) / npb;
-  KLN(h, f32 ? "k_adj_root_partial<f32>" : "k_adj_root_partial", k_adj_root_partial<T>,
-      dim3(grid_for(ncb * nnb, 1, 4096)), dim3(ADJ_THREADS), 0, s, g, trc, (const T*)Q1c, part, npb, state);
-  return npb;
+  return trc;
 }
 
 // Dynamic LDS for the two tensor buffers of a preconditioner kernel, or 0 (then
@@ -1023,6 +1016,21 @@ static void launch_precond(kr_handle h, int prec, const ModeTables& T, const Geo
   else if (prec == KR_PREC_F32) launch_precond_mode<KR_PREC_F32>(h, nb, T, g, a);
   else if (prec == KR_PREC_BF16) launch_precond_mode<KR_PREC_BF16>(h, nb, T, g, a);
   else launch_precond_mode<KR_PREC_FP8>(h, nb, T, g, a);
+}
+
+// The root adjoint over trr's level-1 nodes (nodes, or the fused pass's chunks)
+// into partial blocks of npb nodes, which the preconditioner step sums.  Returns
+// npb.
+template <typename T>
+static int launch_root(kr_handle h, const Geom& g, const Tree& trr, const T* Q1, T* part, const IterState* state) {
+  const bool f32 = sizeof(T) == 4;
+  const int npb = root_npb(trr);
+  const int64_t CEr = adj_cols((int)g.R[0]);
+  const int64_t ncb = (g.rsuf[1] * g.nrhs + CEr - 1) / CEr;
+  const int64_t nnb = (trr.ncnt[1] + npb - 1) / npb;
+  KLN(h, f32 ? "k_adj_root_partial<f32>" : "k_adj_root_partial", k_adj_root_partial<T>,
+      dim3(grid_for(ncb * nnb, 1, 4096)), dim3(ADJ_THREADS), 0, h->stream, g, trr, Q1, part, npb, state);
+  return npb;
 }
 
 // Validation, the sample count and the geometry of one Algorithm 2 problem.
@@ -1286,21 +1294,24 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     while (iters_enqueued < max_iter) {
       chunk = std::max(1, std::min(chunk, max_iter - iters_enqueued));
       for (int it = 0; it < chunk; ++it) {
-        int npb;
-        if (nchunk > 0)
-          npb = prec == KR_PREC_F64
-                    ? launch_fused3<double>(h, g, tr, B.ck, nchunk, B.P[0], B.Omega, B.bD, B.Q1c, B.part,
-                                            (const IterState*)B.state)
-                    : launch_fused3<float>(h, g, tr, B.ck, nchunk, B.P[0], B.Omega, B.bD, B.Q1c, B.part,
-                                           (const IterState*)B.state);
-        else
-          npb = prec == KR_PREC_F64
-                    ? launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
-                                                    (const IterState*)B.state)
-                    : launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, B.part,
-                                                   (const IterState*)B.state);
-        pa.grad = npb > 0 ? (const void*)B.part : (const void*)B.Q[0];
-        pa.nnb = npb > 0 ? (unsigned)(((nchunk > 0 ? nchunk : tr.ncnt[1]) + npb - 1) / npb) : 1u;
+        // the sampled products, the root adjoint (over the chunks after the fused
+        // pass) and the step on its partial blocks (without a root adjoint, on Q[0])
+        const IterState* stc = (const IterState*)B.state;
+        const Tree trr = nchunk > 0 ? root_tree(tr, B.ck, nchunk) : tr;
+        const void* Q1 = nchunk > 0 ? B.Q1c : (const void*)B.Q[1];
+        bool root;
+        int npb = 0;
+        if (prec == KR_PREC_F64) {
+          if (nchunk > 0) launch_fused3<double>(h, g, tr, B.ck, nchunk, B.P[0], B.Omega, B.bD, B.Q1c);
+          root = nchunk > 0 || launch_level_products<double>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, stc);
+          if (root) npb = launch_root<double>(h, g, trr, (const double*)Q1, (double*)B.part, stc);
+        } else {
+          if (nchunk > 0) launch_fused3<float>(h, g, tr, B.ck, nchunk, B.P[0], B.Omega, B.bD, B.Q1c);
+          root = nchunk > 0 || launch_level_products<float>(h, T, g, tr, B.P, (void* const*)B.Q, B.Omega, B.bD, stc);
+          if (root) npb = launch_root<float>(h, g, trr, (const float*)Q1, (float*)B.part, stc);
+        }
+        pa.grad = root ? (const void*)B.part : (const void*)B.Q[0];
+        pa.nnb = root ? (unsigned)((trr.ncnt[1] + npb - 1) / npb) : 1u;
         launch_precond(h, prec, T, g, pa);
       }
       iters_enqueued += chunk;
@@ -2700,7 +2711,7 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   while (enq < max_iter) {
     const int chunk = std::min(check_every, max_iter - enq);
     for (int it = 0; it < chunk; ++it) {
-      launch_level_products<double>(h, T, g, tr, P, (void* const*)Q, Omega, bD, nullptr, (const IterState*)state);
+      launch_level_products<double>(h, T, g, tr, P, (void* const*)Q, Omega, bD, (const IterState*)state);
       KL(h, k_tucker_update, dim3(In), dim3(256), 3 * 8 * (size_t)Rr, s, T, g, tg, (const double*)Q[1], Z,
          (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv, (const double*)wbuf, eta,
          tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, counters, counters + 1,

@@ -902,7 +902,7 @@ __device__ void batched_team(const BatchArgs& a, unsigned rank, unsigned nteam, 
 // Small problems: one workgroup per problem from the queue.
 __global__ void __launch_bounds__(BT_THREADS) k_batched_queue(BatchArgs a) {
   __shared__ double ms[PC_MATS];
-  __shared__ double red[16];
+  __shared__ double red[2 * BT_THREADS / 64];
   batched_queue(a, ms, red);
 }
 

@@ -140,13 +140,54 @@ __device__ void pc_scale(const Geom& g, const double* __restrict__ dinv, TT* cur
   }
 }
 
+// The iterate's entries r = threadIdx.x + u blockDim.x (u < PC_BATCH) of a
+// one-RHS problem whose x fits PC_BATCH entries per thread, loaded at kernel
+// start together with the gradient, so that the update waits on no global load
+// (ok = false: the update loads x itself).
+struct PcX {
+  double v[PC_BATCH];
+  bool ok;
+};
+__device__ __forceinline__ void pc_prefetch_x(const Geom& g, const double* __restrict__ x, PcX& xr) {
+  xr.ok = g.nrhs == 1 && g.Rtot <= (int64_t)PC_BATCH * blockDim.x;
+  if (!xr.ok) return;
+#pragma unroll
+  for (int u = 0; u < PC_BATCH; ++u) {
+    const int64_t r = threadIdx.x + (int64_t)u * blockDim.x;
+    xr.v[u] = r < g.Rtot ? x[r] : 0.0;
+  }
+}
+
+// Block-wide sums of two values with one set of barriers (fixed order, every
+// thread gets both).  red holds 2 blockDim.x / 64 doubles.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * w] = a;
+    red[2 * w + 1] = b;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    ta += red[2 * i];
+    tb += red[2 * i + 1];
+  }
+  __syncthreads();
+  a = ta;
+  b = tb;
+}
+
 // x <- x - eta d for right-hand sides not yet converged; float64 norms, the
 // stopping rule and the divergence test; the iteration counter.
 // it, done_lane and dn0_lane (lane q of every wave holds done[q] and dnorm0[q]) are
-// read at kernel start.
+// read at kernel start; so is xr when xr.ok.
 template <typename TT>
 __device__ void pc_update(const Geom& g, const TT* d_t, double* __restrict__ x, double eta, double tol, int max_iter,
-                          IterState* __restrict__ st, double* red, int it, int done_lane, double dn0_lane) {
+                          IterState* __restrict__ st, double* red, int it, int done_lane, double dn0_lane,
+                          const PcX& xr) {
   int all = 1, div = 0;
   const int64_t bd = blockDim.x;
   for (int q = 0; q < g.nrhs; ++q) {
@@ -157,7 +198,7 @@ __device__ void pc_update(const Geom& g, const TT* d_t, double* __restrict__ x, 
 #pragma unroll
       for (int u = 0; u < PC_BATCH; ++u) {
         const int64_t r = r0 + u * bd;
-        xv[u] = r < g.Rtot ? x[r * g.nrhs + q] : 0.0;
+        xv[u] = xr.ok ? xr.v[u] : (r < g.Rtot ? x[r * g.nrhs + q] : 0.0);
         dv[u] = r < g.Rtot ? (double)d_t[r * g.nrhs + q] : 0.0;
       }
 #pragma unroll
@@ -171,8 +212,7 @@ __device__ void pc_update(const Geom& g, const TT* d_t, double* __restrict__ x, 
         }
       }
     }
-    dd = block_sum(dd, red);
-    xx = block_sum(xx, red);
+    block_sum2(dd, xx, red);
     // the first norm comes from the launch's first loads (dn0_lane), and the
     // stopping flags are kept in registers: no global load waits here
     const double dn0 = __shfl(dn0_lane, q, 64);
@@ -452,6 +492,8 @@ __device__ void pc_step_f64(const ModeTables& T, const Geom& g, const double* __
   const int64_t total = g.Rtot * g.nrhs;
   const bool all = pc_mats_fit(g);
   const double* const* Ms = use_ginv ? T.Ginv : T.V;
+  PcX xr;
+  pc_prefetch_x(g, x, xr);
   if (all) pc_stage(g, Ms, 0, true, ms);
   pc_load_h(grad, nnb, x, lambda, cur, total);
   __syncthreads();
@@ -473,7 +515,7 @@ __device__ void pc_step_f64(const ModeTables& T, const Geom& g, const double* __
     __syncthreads();
     for (int n = 0; n < g.N; ++n) product(n, 0);
   }
-  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane, dn0_lane);
+  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane, dn0_lane, xr);
 }
 
 // Float64 step as its own launch (one workgroup of PC_THREADS threads); the tensor
@@ -486,7 +528,7 @@ __global__ void __launch_bounds__(PC_THREADS) k_precond_update(ModeTables T, Geo
                                                        double lambda, double eta, double tol, int max_iter,
                                                        int use_ginv, IterState* __restrict__ st) {
   extern __shared__ double pd_dyn[];
-  __shared__ double red[16];
+  __shared__ double red[2 * PC_THREADS / 64];
   __shared__ double ms[PC_MATS];
   const int64_t total = g.Rtot * g.nrhs;
   pc_step_f64<NB>(T, g, grad, nnb, dinv, x, lds ? pd_dyn : t0, lds ? pd_dyn + total : t1, lambda, eta, tol, max_iter,
@@ -496,29 +538,26 @@ __global__ void __launch_bounds__(PC_THREADS) k_precond_update(ModeTables T, Geo
 // Refined-precision step: float32 gradient and tensor, mode products in MODE.
 // fp8 takes the eigenvector form also for lambda = 0: its orthogonal factors
 // round far better in e4m3 than the inverse Grams (fewer iterations, measured).
+// One workgroup of any multiple of 64 threads; cur/nxt are the tensor buffers,
+// red holds 2 blockDim.x / 64 doubles, redf blockDim.x / 64 floats, ms PC_MATS
+// floats and mscale KR_MAXN floats (all LDS).  Returns without touching x when
+// the state is already converged.
 template <int MODE, int NB>
-__global__ void __launch_bounds__(PC_THREADS) k_precond_mp(ModeTables T, Geom g, const float* __restrict__ grad,
-                                                   unsigned nnb,
-                                                   const double* __restrict__ dinv, double* __restrict__ x,
-                                                   float* __restrict__ t0, float* __restrict__ t1, int lds,
-                                                   double lambda, double eta, double tol, int max_iter, int use_ginv,
-                                                   IterState* __restrict__ st) {
-  extern __shared__ float mp_dyn[];
-  __shared__ double red[16];
-  __shared__ float redf[16];
-  __shared__ float ms[PC_MATS];
-  __shared__ float mscale[KR_MAXN];
+__device__ void pc_step_mp(const ModeTables& T, const Geom& g, const float* __restrict__ grad, unsigned nnb,
+                           const double* __restrict__ dinv, double* __restrict__ x, float* cur, float* nxt,
+                           double lambda, double eta, double tol, int max_iter, int use_ginv,
+                           IterState* __restrict__ st, double* red, float* redf, float* ms, float* mscale) {
   // state loads issued together with the staging and h loads below
   const int all_done = st->all_done;
   const int it0 = st->iters;
   const int done_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->done[threadIdx.x & 63] : 1;
   const double dn0_lane = (int)(threadIdx.x & 63) < g.nrhs ? st->dnorm0[threadIdx.x & 63] : 0.0;
   const int64_t total = g.Rtot * g.nrhs;
-  float* cur = lds ? mp_dyn : t0;
-  float* nxt = lds ? mp_dyn + total : t1;
   const bool ginv = use_ginv && MODE != KR_PREC_FP8;
   const bool all = pc_mats_fit(g);
   const double* const* Ms = ginv ? T.Ginv : T.V;
+  PcX xr;
+  pc_prefetch_x(g, x, xr);
   if (all) pc_stage(g, Ms, 0, true, ms);
   pc_load_h(grad, nnb, x, lambda, cur, total);
   __syncthreads();
@@ -553,7 +592,26 @@ __global__ void __launch_bounds__(PC_THREADS) k_precond_mp(ModeTables T, Geom g,
     __syncthreads();
     for (int n = 0; n < g.N; ++n) product(n, 0);
   }
-  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane, dn0_lane);
+  pc_update(g, cur, x, eta, tol, max_iter, st, red, it0, done_lane, dn0_lane, xr);
+}
+
+// Refined-precision step as its own launch (one workgroup of PC_THREADS threads);
+// the tensor buffers are in dynamic LDS when lds != 0, else t0/t1.
+template <int MODE, int NB>
+__global__ void __launch_bounds__(PC_THREADS) k_precond_mp(ModeTables T, Geom g, const float* __restrict__ grad,
+                                                   unsigned nnb,
+                                                   const double* __restrict__ dinv, double* __restrict__ x,
+                                                   float* __restrict__ t0, float* __restrict__ t1, int lds,
+                                                   double lambda, double eta, double tol, int max_iter, int use_ginv,
+                                                   IterState* __restrict__ st) {
+  extern __shared__ float mp_dyn[];
+  __shared__ double red[2 * PC_THREADS / 64];
+  __shared__ float redf[PC_THREADS / 64];
+  __shared__ float ms[PC_MATS];
+  __shared__ float mscale[KR_MAXN];
+  const int64_t total = g.Rtot * g.nrhs;
+  pc_step_mp<MODE, NB>(T, g, grad, nnb, dinv, x, lds ? mp_dyn : t0, lds ? mp_dyn + total : t1, lambda, eta, tol,
+                       max_iter, use_ginv, st, red, redf, ms, mscale);
 }
 
 // dinv[r] = 1 / (prod_n lambda_n[r_n] + lambda), 0 where that sum is not positive.
