@@ -216,6 +216,9 @@ static int ceil_log2(int64_t v) {
 #ifndef KR_ROWS_GRID_CAP
 #define KR_ROWS_GRID_CAP 1024
 #endif
+#ifndef KR_ROWS_LDS_GRID
+#define KR_ROWS_LDS_GRID 512    // two workgroups of 512 threads per CU for the LDS-staged rows kernel
+#endif
 static int64_t grid_for(int64_t work, int64_t threads, int64_t cap = 4096) {
   int64_t b = (work + threads - 1) / threads;
   return std::max<int64_t>(1, std::min<int64_t>(b, cap));
@@ -834,6 +837,18 @@ static int root_npb(const Tree& tr) {
   return (int)(RA_NODES * ((per + RA_NODES - 1) / RA_NODES));
 }
 
+// The rows kernel reads the last mode's factor from LDS (rows stream 4-byte
+// indices, not materialised factor rows) when that factor fits 64 KB and the
+// distinct rows outnumber its rows 16 times (staging it once per workgroup then
+// costs little against the row traffic it saves).  Needs tr.ncnt.
+#ifndef KR_ROWS_LDS_MAX
+#define KR_ROWS_LDS_MAX (64 * 1024)
+#endif
+static bool rows_ldsf(const Geom& g, const Tree& tr) {
+  const int64_t IL = g.I[g.N - 1];
+  return IL * g.R[g.N - 1] * 8 <= KR_ROWS_LDS_MAX && tr.ncnt[g.N] >= 16 * IL;
+}
+
 // One pass of the sampled products K~^T Omega (K~ x - b~) down and up the sample
 // tree: forward levels 1..N-2, the last forward level with the rows and the last
 // adjoint level, and adjoint levels N-1..2.  Returns whether the root adjoint
@@ -861,24 +876,23 @@ static bool launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
     const double* plast = P[g.N >= 2 ? g.N - 2 : 0];
     // one wave per (node, rhs), grid-stride, at most a few workgroups per CU
     const dim3 rg(grid_for(tr.ncnt[g.N - 1] * g.nrhs, 4, KR_ROWS_GRID_CAP));
+    const bool ldsf = rows_ldsf(g, tr);
+    const size_t fl = ldsf ? 8 * (size_t)g.I[g.N - 1] * g.R[g.N - 1] : 0;
+    const dim3 rgl(grid_for(tr.ncnt[g.N - 1] * g.nrhs, KR_ROWS_LDS_TPB / 64, KR_ROWS_LDS_GRID));
+#define KR_ROWS_LAUNCH(GG, NAME)                                                                          \
+  if (ldsf)                                                                                               \
+    KLN(h, f32 ? NAME ",f32,lds>" : NAME ",lds>", (k_rows_adj<GG, T, true>), rgl, dim3(KR_ROWS_LDS_TPB), fl, s, \
+        TT, g, tr, plast, Omega, bD, qlast, state);                                                       \
+  else                                                                                                    \
+    KLN(h, f32 ? NAME ",f32>" : NAME ">", (k_rows_adj<GG, T, false>), rg, dim3(256), 0, s, TT, g, tr, plast, \
+        Omega, bD, qlast, state);
     switch (G) {
-      case 8:
-        KLN(h, f32 ? "k_rows_adj<8,f32>" : "k_rows_adj<8>", (k_rows_adj<8, T>), rg, dim3(256), 0, s, TT, g, tr, plast,
-            Omega, bD, qlast, state);
-        break;
-      case 16:
-        KLN(h, f32 ? "k_rows_adj<16,f32>" : "k_rows_adj<16>", (k_rows_adj<16, T>), rg, dim3(256), 0, s, TT, g, tr,
-            plast, Omega, bD, qlast, state);
-        break;
-      case 32:
-        KLN(h, f32 ? "k_rows_adj<32,f32>" : "k_rows_adj<32>", (k_rows_adj<32, T>), rg, dim3(256), 0, s, TT, g, tr,
-            plast, Omega, bD, qlast, state);
-        break;
-      default:
-        KLN(h, f32 ? "k_rows_adj<64,f32>" : "k_rows_adj<64>", (k_rows_adj<64, T>), rg, dim3(256), 0, s, TT, g, tr,
-            plast, Omega, bD, qlast, state);
-        break;
+      case 8: KR_ROWS_LAUNCH(8, "k_rows_adj<8") break;
+      case 16: KR_ROWS_LAUNCH(16, "k_rows_adj<16") break;
+      case 32: KR_ROWS_LAUNCH(32, "k_rows_adj<32") break;
+      default: KR_ROWS_LAUNCH(64, "k_rows_adj<64") break;
     }
+#undef KR_ROWS_LAUNCH
     for (int k = g.N - 1; k >= 2; --k) {
       const int64_t CE = adj_cols((int)g.R[k - 1]);
       const int64_t tasks = tr.ncnt[k - 1] * ((g.rsuf[k] * g.nrhs + CE - 1) / CE);
@@ -1141,7 +1155,7 @@ static kr_status launch_sketch_rest(kr_handle h, const kr_problem* p, const Geom
   const int nblocks = (int)((g.m + SORT_TILE - 1) / SORT_TILE);
   launch_sort_tree(h, g, B.keys, B.keys_alt, B.hist, B.tiletot, nblocks, tr);
   const int64_t Dcap = level_cap(g, g.N);
-  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
+  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr, g.N);
   KL(h, k_rows, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tr, p->b, p->b_dtype, B.Omega, B.bD,
      B.counts, B.s.flags);
   if (p->gen) {
@@ -2693,7 +2707,6 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   KL(h, k_tucker_cinv, dim3(1), dim3(256), 0, s, tg, (const double*)Vw, (const double*)AinvU, Cinv, S.flags);
   KL(h, k_sample_rows, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, T, g, tg, o.seed, o.stream, keys);
   launch_sort_tree(h, g, keys, keys_alt, hist, tiletot, nblocks, tr);
-  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr);
   KL(h, k_rows_tucker, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tg, tr, p->b, p->b_dtype, Omega, bD,
      counts, S.flags);
   // level counts of the sample tree for the iteration kernels (one host round trip)
@@ -2701,6 +2714,10 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   for (int k = 0; k <= KR_MAXN; ++k) tr.ncnt[k] = (int64_t)h->h_small[8 + k];
+  // the rows' own factor rows are materialised only when the rows kernel does not
+  // read them from the LDS-staged factor
+  KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr,
+     rows_ldsf(g, tr) ? g.N - 1 : g.N);
   KL(h, k_fill, dim3(grid_for((int64_t)In * Rr, 256, 1024)), dim3(256), 0, s, Z, (int64_t)In * Rr, 0.0);
   KL(h, k_zero_bytes, dim3(grid_for(In, 256, 64)), dim3(256), 0, s, (uint32_t*)seg_done, (int64_t)In);
   KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)counters, (int64_t)64);

@@ -151,19 +151,25 @@ __global__ void __launch_bounds__(256) k_fwd_level(ModeTables TT, Geom g, Tree t
 // forward value is formed, so that both memory round trips overlap; run(pv)
 // then returns the wave's sum of (Omega_j u_j) a_{N-1}[i(j)][lane] over the node's
 // rows, u_j = <a_{N-1}[i(j)], P_{N-1}> - b_j formed in float64.
-template <int G, int RPS>
+// LDSF: the last mode's factor is staged in LDS (AL points there) and each row
+// streams its 4-byte index i(j) instead of its materialised factor row; the row
+// is then read from LDS.
+template <int G, int RPS, bool LDSF = false>
 struct RowsTask {
   static constexpr int NGR = 64 / G;
   const double* __restrict__ ab;
+  const int32_t* __restrict__ ib;
   const double* __restrict__ ob;
   const double* __restrict__ bp;
   int nrow, R, nrhs, gi;
   unsigned lc;
   double aA[RPS], oA[RPS], bA[RPS];
-  __device__ __forceinline__ RowsTask(const double* AL, const double* Omega, const double* bD, int j0, int j1,
-                                      int R_, int nrhs_, int q, int lane, int gi_)
-      : ab(AL + (int64_t)j0 * R_), ob(Omega + j0), bp(bD + (int64_t)j0 * nrhs_ + q), nrow(j1 - j0), R(R_),
-        nrhs(nrhs_), gi(gi_), lc(lane < R_ ? (unsigned)lane : (unsigned)(R_ - 1)) {}
+  int iA[RPS];
+  __device__ __forceinline__ RowsTask(const double* AL, const int32_t* idxL, const double* Omega, const double* bD,
+                                      int j0, int j1, int R_, int nrhs_, int q, int lane, int gi_)
+      : ab(LDSF ? AL : AL + (int64_t)j0 * R_), ib(LDSF ? idxL + j0 : nullptr), ob(Omega + j0),
+        bp(bD + (int64_t)j0 * nrhs_ + q), nrow(j1 - j0), R(R_), nrhs(nrhs_), gi(gi_),
+        lc(lane < R_ ? (unsigned)lane : (unsigned)(R_ - 1)) {}
   __device__ __forceinline__ void load(int k) {
     const int nl = nrow - k * RPS * NGR;
     const double* __restrict__ abk = ab + (int64_t)k * RPS * NGR * R;
@@ -173,7 +179,10 @@ struct RowsTask {
     for (int u = 0; u < RPS; ++u) {
       const int jl = gi + u * NGR;
       const unsigned jc = jl < nl ? (unsigned)jl : 0u;
-      aA[u] = ld_at(abk, (jc * (unsigned)R + lc) * 8u);
+      if constexpr (LDSF)
+        iA[u] = ib[k * RPS * NGR + jc];
+      else
+        aA[u] = ld_at(abk, (jc * (unsigned)R + lc) * 8u);
       oA[u] = ld_at(obk, jc * 8u);
       bA[u] = ld_at(bpk, jc * (unsigned)nrhs * 8u);
     }
@@ -184,6 +193,10 @@ struct RowsTask {
     const int nstep = (nrow + RPS * NGR - 1) / (RPS * NGR);
     for (int k = 0;;) {
       const int nl = nrow - k * RPS * NGR;
+      if constexpr (LDSF) {
+#pragma unroll
+        for (int u = 0; u < RPS; ++u) aA[u] = ab[(unsigned)iA[u] * (unsigned)R + lc];
+      }
       double y[RPS];
 #pragma unroll
       for (int u = 0; u < RPS; ++u) y[u] = grp_sum<G>(aA[u] * pv);
@@ -212,17 +225,38 @@ struct RowsTask {
 // Measured: the wave-uniform task with scalar row bases, DPP group sums and one
 // register set (92 VGPRs, 5 waves per SIMD) beat a prefetching second set; the
 // compiler waits for all loads at the loop head either way.
-template <int G, typename T>
-__global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr,
+// The LDS-staged variant runs KR_ROWS_LDS_TPB threads per workgroup with at least
+// KR_ROWS_LDS_WPE waves per SIMD, so that more waves share each staged copy of the
+// factor (the kernel is bound by the latency of its dependent row loads).
+// Measured on the Tucker factor updates (ms per 400^3 sweep): materialised rows
+// 46.4; staged, 256 threads 45.0; 512 threads at 5 waves per SIMD 39.6; 1024
+// threads 39.8; 512 threads at 6 waves per SIMD 53.2 (80 VGPRs, spills).
+#ifndef KR_ROWS_LDS_TPB
+#define KR_ROWS_LDS_TPB 512
+#endif
+#ifndef KR_ROWS_LDS_WPE
+#define KR_ROWS_LDS_WPE 5
+#endif
+template <int G, typename T, bool LDSF>
+__global__ void __launch_bounds__(LDSF ? KR_ROWS_LDS_TPB : 256)
+    __attribute__((amdgpu_waves_per_eu(LDSF ? KR_ROWS_LDS_WPE : 1, 8))) k_rows_adj(ModeTables TT, Geom g, Tree tr,
                                                  const double* __restrict__ Pprev,
                                                  const double* __restrict__ Omega,
                                                  const double* __restrict__ bD,
                                                  T* __restrict__ Qout,
                                                  const IterState* __restrict__ st) {
+  extern __shared__ double rows_fac[];
   constexpr int NGR = 64 / G;
   const int N = g.N, nrhs = g.nrhs;
   const int R = g.R[N - 1];
-  const double* __restrict__ AL = tr.arow[N];
+  const double* __restrict__ AL = LDSF ? (const double*)rows_fac : tr.arow[N];
+  if constexpr (LDSF) {
+    // the last mode's whole factor (I_{N-1} x R_{N-1}), once per workgroup
+    const int nf = g.I[N - 1] * R;
+    const double* __restrict__ A = TT.A[N - 1];
+    for (int e = threadIdx.x; e < nf; e += blockDim.x) rows_fac[e] = A[e];
+    __syncthreads();
+  }
   const int64_t ntask = tr.ncnt[N - 1] * nrhs;
   const int lane = threadIdx.x & (G - 1);
   const int gi = (threadIdx.x & 63) / G;
@@ -239,7 +273,7 @@ __global__ void __launch_bounds__(256) k_rows_adj(ModeTables TT, Geom g, Tree tr
       if (gi == 0 && ln) Qout[(p * R + lane) * nrhs + q] = (T)0;
       continue;
     }
-    RowsTask<G, KR_ROWS_PER_STEP> rt(AL, Omega, bD, j0, j1, R, nrhs, q, lane, gi);
+    RowsTask<G, KR_ROWS_PER_STEP, LDSF> rt(AL, tr.idx[N], Omega, bD, j0, j1, R, nrhs, q, lane, gi);
     rt.load(0);
     // P_{N-1}[p][lane][q]; from a parent level, group gi sums the terms
     // s = gi, gi + NGR, ... of the contraction over R_{N-2} and the groups' partial
@@ -372,8 +406,8 @@ __global__ void __launch_bounds__(256) k_subtree3(Geom g, Tree tr, Chunks ck, co
     j0 = tr.fchild[2][s0 + task / nrhs];
     j1 = tr.fchild[2][s0 + task / nrhs + 1];
   }
-  RowsTask<G, KR_ROWS_PER_STEP> rt(tr.arow[3], Omega, bD, j0, j1, R, nrhs, task < ntask ? task % nrhs : 0, lane,
-                                   gi);
+  RowsTask<G, KR_ROWS_PER_STEP> rt(tr.arow[3], nullptr, Omega, bD, j0, j1, R, nrhs, task < ntask ? task % nrhs : 0,
+                                   lane, gi);
   if (task < ntask && j1 > j0) rt.load(0);
   {
     const double* __restrict__ a0 = tr.arow[1] + (int64_t)p * R0;
@@ -387,7 +421,7 @@ __global__ void __launch_bounds__(256) k_subtree3(Geom g, Tree tr, Chunks ck, co
     if (task != w) {
       j0 = tr.fchild[2][s0 + sl];
       j1 = tr.fchild[2][s0 + sl + 1];
-      rt = RowsTask<G, KR_ROWS_PER_STEP>(tr.arow[3], Omega, bD, j0, j1, R, nrhs, q, lane, gi);
+      rt = RowsTask<G, KR_ROWS_PER_STEP>(tr.arow[3], nullptr, Omega, bD, j0, j1, R, nrhs, q, lane, gi);
       if (j1 > j0) rt.load(0);
     }
     if (j1 <= j0) {  // a node always has rows; kept for safety (uniform branch)

@@ -394,9 +394,10 @@ __global__ void __launch_bounds__(SORT_THREADS) k_tree_emit(const uint64_t* __re
   }
 }
 
-// Gather the factor row of every tree node: arow[k][s][r] = A_{k-1}[idx[k][s]][r].
-__global__ void __launch_bounds__(256) k_node_rows(ModeTables T, Geom g, Tree tr) {
-  for (int k = g.seg_root ? 2 : 1; k <= g.N; ++k) {
+// Gather the factor row of every tree node of levels up to kmax:
+// arow[k][s][r] = A_{k-1}[idx[k][s]][r].
+__global__ void __launch_bounds__(256) k_node_rows(ModeTables T, Geom g, Tree tr, int kmax) {
+  for (int k = g.seg_root ? 2 : 1; k <= kmax; ++k) {
     const int R = g.R[k - 1];
     const int64_t total = tr.cnt[k] * R;
     const double* __restrict__ A = T.A[k - 1];
