@@ -335,13 +335,20 @@ def tucker_leg(kr, torch):
     dt = time.perf_counter() - t0
     fit = [st["iters"] for st in stats if st["step"] < len(A0)]
     cit = [st["iters"] for st in stats if st["step"] == len(A0)]
+    # context: the oracle's exact ALS (exact factor and core updates, same start and
+    # lambda) on the same tensor, stored by tests/golden/make_tucker_400_als.py
+    exact = []
+    gold = os.path.join(ROOT, "tests", "golden", "tucker_400_als.txt")
+    if os.path.exists(gold):
+        exact = [float(l.split()[1]) for l in open(gold) if l.strip() and not l.startswith("#")]
     return {"workload": w["name"] + ", FP32, 1%% noise, lambda = 1e-3, eps = 0.1, m_factor = %d per row, "
                                      "m_core = %d, %d sweeps" % (w["m_factor"], w["m_core"], w["sweeps"]),
             "ms_per_sweep": round(1000.0 * dt / w["sweeps"], 3), "sweeps_per_s": round(w["sweeps"] / dt, 3),
             "rre_per_sweep": [float("%.6g" % r) for r in trace], "dtype": "f64 (FP32 tensor)",
             "richardson_iters_per_factor_update": {"mean": round(sum(fit) / max(1, len(fit)), 2), "max": max(fit)},
             "richardson_iters_per_core_update": {"mean": round(sum(cit) / max(1, len(cit)), 2), "max": max(cit)},
-            "updates_all_ok": True}
+            "updates_all_ok": True,
+            "oracle_exact_als_rre_per_sweep": [float("%.6g" % r) for r in exact]}
 
 
 def tucker_paper_leg(kr, torch, sweeps=5, ms=(1024, 4096, 16384)):

@@ -915,10 +915,10 @@ static void launch_fused3(kr_handle h, const Geom& g, const Tree& tr, const Chun
   const size_t lds = fused3_lds(g, sizeof(T));
   const dim3 grid((unsigned)nchunk);
   if (g.R[2] <= 8)
-    KLN(h, f32 ? "k_subtree3<8,f32>" : "k_subtree3<8>", (k_subtree3<8, T>), grid, dim3(256), lds, s, g, tr, ck, x,
+    KLN(h, f32 ? "k_subtree3<8,f32>" : "k_subtree3<8>", (k_subtree3<8, T>), grid, dim3(KR_SUB_THREADS), lds, s, g, tr, ck, x,
         Omega, bD, Q1c);
   else
-    KLN(h, f32 ? "k_subtree3<16,f32>" : "k_subtree3<16>", (k_subtree3<16, T>), grid, dim3(256), lds, s, g, tr, ck,
+    KLN(h, f32 ? "k_subtree3<16,f32>" : "k_subtree3<16>", (k_subtree3<16, T>), grid, dim3(KR_SUB_THREADS), lds, s, g, tr, ck,
         x, Omega, bD, Q1c);
 }
 

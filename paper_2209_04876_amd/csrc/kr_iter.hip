@@ -230,12 +230,14 @@ struct RowsTask {
 // factor (the kernel is bound by the latency of its dependent row loads).
 // Measured on the Tucker factor updates (ms per 400^3 sweep): materialised rows
 // 46.4; staged, 256 threads 45.0; 512 threads at 5 waves per SIMD 39.6; 1024
-// threads 39.8; 512 threads at 6 waves per SIMD 53.2 (80 VGPRs, spills).
+// threads 39.8; 512 threads at 6 waves per SIMD 53.2 (80 VGPRs, spills); with
+// the next task's bounds requested one task ahead (114 VGPRs, 4 waves per SIMD,
+// two 512-thread workgroups per CU) 36.2.
 #ifndef KR_ROWS_LDS_TPB
 #define KR_ROWS_LDS_TPB 512
 #endif
 #ifndef KR_ROWS_LDS_WPE
-#define KR_ROWS_LDS_WPE 5
+#define KR_ROWS_LDS_WPE 4
 #endif
 template <int G, typename T, bool LDSF>
 __global__ void __launch_bounds__(LDSF ? KR_ROWS_LDS_TPB : 256)
@@ -265,10 +267,26 @@ __global__ void __launch_bounds__(LDSF ? KR_ROWS_LDS_TPB : 256)
   // the task index is wave-uniform, so the node's bounds and row bases live in
   // scalar registers
   const int64_t w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  for (int64_t task = blockIdx.x * wpb + w; task < ntask; task += (int64_t)gridDim.x * wpb) {
+  const int64_t tstride = (int64_t)gridDim.x * wpb;
+  // a node's row bounds and parent are requested one task ahead, so that they
+  // are in registers when the task starts (one dependent round trip fewer)
+  int nb0 = 0, nb1 = 0;
+  int64_t npar = 0;
+  auto fetch = [&](int64_t t) {
+    if (t < ntask) {
+      const int64_t pp = t / nrhs;
+      nb0 = tr.fchild[N - 1][pp];
+      nb1 = tr.fchild[N - 1][pp + 1];
+      npar = N >= 3 ? tr.parent[N - 1][pp] : 0;
+    }
+  };
+  fetch(blockIdx.x * wpb + w);
+  for (int64_t task = blockIdx.x * wpb + w; task < ntask; task += tstride) {
     const int64_t p = task / nrhs;
     const int q = (int)(task - p * nrhs);
-    const int j0 = tr.fchild[N - 1][p], j1 = tr.fchild[N - 1][p + 1];
+    const int j0 = nb0, j1 = nb1;
+    const int64_t par = npar;
+    fetch(task + tstride);
     if (j1 <= j0) {  // a node always has rows; kept for safety (uniform branch)
       if (gi == 0 && ln) Qout[(p * R + lane) * nrhs + q] = (T)0;
       continue;
@@ -285,7 +303,6 @@ __global__ void __launch_bounds__(LDSF ? KR_ROWS_LDS_TPB : 256)
       if (ln) pv = Pprev[((int64_t)tr.idx[1][p] * R + lane) * nrhs + q];
     } else {
       const int Rp = g.R[N - 2];
-      const int64_t par = N >= 3 ? tr.parent[N - 1][p] : 0;
       const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
       const int64_t step = (int64_t)R * nrhs;
       const double* __restrict__ src = Pprev + par * (int64_t)Rp * step + q;
@@ -379,7 +396,13 @@ __global__ void __launch_bounds__(CH_THREADS) k_chunk_table(Tree tr, Chunks ck, 
 // one launch.  Dynamic LDS: W1 doubles for P_1, then ch R_1 and ch R_2 nrhs
 // entries of T for the children's factor rows and Q_2.
 template <int G, typename T>
-__global__ void __launch_bounds__(256) k_subtree3(Geom g, Tree tr, Chunks ck, const double* __restrict__ x,
+// Threads per workgroup of the fused pass.  Measured at the 512^3 workload
+// (bf16-refined solves/s): 256 threads 824; 512 781 (runs of 8), 774 (runs of 16);
+// 1024 759 (runs of 16): wider workgroups leave more waves idle on short runs.
+#ifndef KR_SUB_THREADS
+#define KR_SUB_THREADS 256
+#endif
+__global__ void __launch_bounds__(KR_SUB_THREADS) k_subtree3(Geom g, Tree tr, Chunks ck, const double* __restrict__ x,
                                                  const double* __restrict__ Omega,
                                                  const double* __restrict__ bD, T* __restrict__ Q1c) {
   extern __shared__ double sub_lds[];

@@ -179,3 +179,27 @@ def test_als_matches_oracle_small(gpu_lib):
     assert rel_l2(Gg.cpu().numpy(), Go) < 1e-7
     for a, b in zip(Ag, Ao):
         assert rel_l2(a.cpu().numpy(), b) < 1e-7
+
+
+def test_exact_als_400_trajectory(gpu_lib):
+    """Exact ALS (exact factor and core updates, lambda = 1e-3) on the 400^3 tensor
+    the benchmark decomposes: the relative reconstruction error after each of 10
+    sweeps against the oracle's trajectory (tests/golden/tucker_400_als.txt,
+    written by make_tucker_400_als.py from the oracle only)."""
+    import os
+
+    import torch
+    print("case exact ALS 400^3", flush=True)
+    ref = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "tucker_400_als.txt")):
+        if line.strip() and not line.startswith("#"):
+            ref.append(float(line.split()[1]))
+    w = workloads.tucker_tensor()
+    X = torch.from_numpy(w["X"]).cuda()
+    del w["X"]
+    G0 = torch.tensor(w["G_init"], device="cuda")
+    A0 = [torch.tensor(A, device="cuda") for A in w["A_init"]]
+    _, _, trace = gpu_lib.tucker_als(X, G0, A0, w["lam"], len(ref), factor_update="exact", core_update="exact")
+    print("rre", ["%.6g" % v for v in trace], "oracle", ["%.6g" % v for v in ref], flush=True)
+    for a, b in zip(trace, ref):
+        assert abs(a - b) <= 1e-8 * b, (trace, ref)
