@@ -432,6 +432,16 @@ __global__ void __launch_bounds__(KR_SUB_THREADS) k_subtree3(Geom g, Tree tr, Ch
   RowsTask<G, KR_ROWS_PER_STEP> rt(tr.arow[3], nullptr, Omega, bD, j0, j1, R, nrhs, task < ntask ? task % nrhs : 0,
                                    lane, gi);
   if (task < ntask && j1 > j0) rt.load(0);
+  // a wave's later tasks have their bounds requested one task ahead
+  const int tstep = blockDim.x >> 6;
+  int nj0 = 0, nj1 = 0;
+  auto fetch = [&](int t) {
+    if (t < ntask) {
+      nj0 = tr.fchild[2][s0 + t / nrhs];
+      nj1 = tr.fchild[2][s0 + t / nrhs + 1];
+    }
+  };
+  fetch(task + tstep);
   {
     const double* __restrict__ a0 = tr.arow[1] + (int64_t)p * R0;
     for (unsigned e = threadIdx.x; e < W1; e += blockDim.x) P1[e] = dot_batched(a0, x + e, W1, R0);
@@ -439,11 +449,12 @@ __global__ void __launch_bounds__(KR_SUB_THREADS) k_subtree3(Geom g, Tree tr, Ch
     for (int e = threadIdx.x; e < ns * R1; e += blockDim.x) A1[e] = a1[e];
   }
   __syncthreads();
-  for (; task < ntask; task += blockDim.x >> 6) {
+  for (; task < ntask; task += tstep) {
     const int sl = task / nrhs, q = task - sl * nrhs;
     if (task != w) {
-      j0 = tr.fchild[2][s0 + sl];
-      j1 = tr.fchild[2][s0 + sl + 1];
+      j0 = nj0;
+      j1 = nj1;
+      fetch(task + tstep);
       rt = RowsTask<G, KR_ROWS_PER_STEP>(tr.arow[3], nullptr, Omega, bD, j0, j1, R, nrhs, q, lane, gi);
       if (j1 > j0) rt.load(0);
     }
