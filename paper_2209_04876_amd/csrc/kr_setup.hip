@@ -56,36 +56,57 @@ __global__ void k_promote_all(PromoteArgs a, int dtype, int32_t* __restrict__ fl
   if (bad) atomicOr(flags, KR_FLAG_NONFINITE);
 }
 
-// One workgroup (256 threads) per mode.  Thread t owns Gram entries t, t+256, ...
-// (upper triangle mirrored) and sums over rows in increasing order.
+// One workgroup (256 threads, four waves) per mode, on v_mfma_f64_16x16x4: for
+// each 16 x 16 tile (a, b) of G = A^T A, a step takes four rows k..k+3 of A as the
+// A operand (A^T: lane l holds A[k + l/16][16a + l%16]) and the B operand (lane l
+// holds A[k + l/16][16b + l%16]); wave w takes the steps of rows 4w, 4w + 16, ...
+// (coalesced 4-row blocks, eight steps' loads issued together), and the four
+// waves' tiles are added in wave order through LDS.  Only the tiles and entries
+// on and above the diagonal are formed; each is written to both halves.
+typedef double gm_f64x4 __attribute__((ext_vector_type(4)));
+#define GM_UNROLL 8
 __global__ void __launch_bounds__(256) k_gram(ModeTables T, Geom g, double* __restrict__ gram) {
-  __shared__ double tile[64 * KR_RMAX];
+  __shared__ double part[4 * 256];
   const int n = blockIdx.x;
   const int I = g.I[n], R = g.R[n];
-  const double* A = T.A[n];
+  const double* __restrict__ A = T.A[n];
   double* G = gram + (size_t)n * KR_RMAX * KR_RMAX;
-  double acc[16];
-  int npair = 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int nb = (R + 15) / 16;
+  // tiles a <= b only; G[c][r] is written as G[r][c] (exactly symmetric)
+  for (int tile = 0; tile < nb * nb; ++tile) {
+    if (tile / nb > tile % nb) continue;   // uniform
+    const int a0 = 16 * (tile / nb), b0 = 16 * (tile % nb);
+    const int ca = a0 + col, cb = b0 + col;
+    gm_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    // rows k = 16 t + 4 w + kq for step t of this wave
+    for (int t0 = 0; 16 * t0 < I; t0 += GM_UNROLL) {
+      double va[GM_UNROLL], vb[GM_UNROLL];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-  for (int r0 = 0; r0 < I; r0 += 64) {
-    const int rows = min(64, I - r0);
-    __syncthreads();
-    copy_to_lds<16>(tile, A + (size_t)r0 * R, rows * R);
-    __syncthreads();
-    int k = 0;
-    for (int pq = threadIdx.x; pq < R * R; pq += blockDim.x, ++k) {
-      const int p = pq / R, q = pq % R;
-      double s = acc[k];
-      // the LDS reads of 8 rows are issued before their (ordered) multiply-adds
-#pragma unroll 8
-      for (int i = 0; i < rows; ++i) s = fma(tile[i * R + p], tile[i * R + q], s);
-      acc[k] = s;
+      for (int u = 0; u < GM_UNROLL; ++u) {
+        const int k = 16 * (t0 + u) + 4 * w + kq;
+        const bool ok = k < I;
+        va[u] = (ok && ca < R) ? A[(size_t)k * R + ca] : 0.0;
+        vb[u] = (ok && cb < R) ? A[(size_t)k * R + cb] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < GM_UNROLL; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], vb[u], acc, 0, 0, 0);
     }
-    npair = k;
+    // D lane l item v = G[a0 + l/16 + 4v][b0 + l%16]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[w * 256 + (kq + 4 * v) * 16 + col] = acc[v];
+    __syncthreads();
+    {
+      const int e = threadIdx.x, r = a0 + e / 16, c = b0 + e % 16;
+      const double sum = ((part[e] + part[256 + e]) + part[512 + e]) + part[768 + e];
+      if (r < R && c < R && r <= c) {
+        G[r * R + c] = sum;
+        G[c * R + r] = sum;
+      }
+    }
+    __syncthreads();
   }
-  int k = 0;
-  for (int pq = threadIdx.x; pq < R * R && k < npair; pq += blockDim.x, ++k) G[pq] = acc[k];
 }
 
 // One wave per mode.  Two-sided Jacobi with the round-robin (tournament)
