@@ -815,7 +815,7 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
     std::swap(kin, kout);
   }
   KL(h, k_tree_count, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot);
-  KL(h, k_tree_scan, dim3(1), dim3(64), 0, s, tiletot, nblocks, g, tr);
+  KL(h, k_tree_scan, dim3(1), dim3(64 * g.N), 0, s, tiletot, nblocks, g, tr);
   KL(h, k_tree_sentinels, dim3(1), dim3(64), 0, s, g, tr);
   KL(h, k_tree_emit, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot, tr);
 }

@@ -156,38 +156,42 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __r
   for (int d = threadIdx.x; d < NB; d += SORT_THREADS) hist[(size_t)d * nblocks + blockIdx.x] = cnt[d];
 }
 
-// Exclusive scan of n uint32 values in place, one workgroup of 1024 threads:
-// each thread scans a contiguous chunk, chunk totals are scanned in LDS.
+// Exclusive scan of n uint32 values in place, one workgroup of 1024 threads, in
+// tiles of 1024 SCAN_K entries: each thread loads its SCAN_K consecutive entries
+// with 16-byte loads and scans them in registers, the thread totals are scanned
+// inside each wave by shuffles and the 16 wave totals are read by every thread
+// (two workgroup barriers per tile); a running carry links the tiles.  The
+// histogram scans of the sort (512 x 84 entries at 340k keys) take one tile.
+#define SCAN_K 48
 __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int64_t n) {
-  // exclusive scan in tiles of 1024 x SCAN_K entries: coalesced loads into LDS,
-  // each thread scans SCAN_K consecutive entries, the thread totals are scanned
-  // inside each wave by shuffles and the 16 wave totals by one wave (three
-  // workgroup barriers per tile), coalesced stores; a running carry links the tiles.
-  constexpr int SCAN_K = 8;
-  __shared__ uint32_t tile[1024 * SCAN_K + 1024 * SCAN_K / 32];
   __shared__ uint32_t wsum[16];
-  __shared__ uint32_t carry;
-  auto ix = [](int i) { return i + (i >> 5); };   // one pad word per 32: conflict-free column reads
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry = 0u;
+  uint32_t carry = 0u;
   for (int64_t t0 = 0; t0 < n; t0 += 1024 * SCAN_K) {
-    uint32_t ld[SCAN_K];
+    const int64_t c0 = t0 + (int64_t)threadIdx.x * SCAN_K;
+    const bool full = c0 + SCAN_K <= n;   // v is 16-byte aligned and c0 a multiple of 4
+    uint32_t x[SCAN_K];
+    if (full) {
+#pragma unroll
+      for (int q = 0; q < SCAN_K / 4; ++q) {
+        const uint4 u = reinterpret_cast<const uint4*>(v + c0)[q];
+        x[4 * q] = u.x;
+        x[4 * q + 1] = u.y;
+        x[4 * q + 2] = u.z;
+        x[4 * q + 3] = u.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < SCAN_K; ++j) x[j] = c0 + j < n ? v[c0 + j] : 0u;
+    }
+    uint32_t tot = 0u;
 #pragma unroll
     for (int j = 0; j < SCAN_K; ++j) {
-      const int64_t i = t0 + (int64_t)j * 1024 + threadIdx.x;
-      ld[j] = i < n ? v[i] : 0u;
+      const uint32_t t = x[j];
+      x[j] = tot;
+      tot += t;
     }
-#pragma unroll
-    for (int j = 0; j < SCAN_K; ++j) tile[ix(j * 1024 + threadIdx.x)] = ld[j];
-    __syncthreads();
-    uint32_t loc[SCAN_K], tot = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_K; ++j) {
-      loc[j] = tot;
-      tot += tile[ix(threadIdx.x * SCAN_K + j)];
-    }
-    // inclusive scan of the thread totals within the wave
-    uint32_t inc = tot;
+    uint32_t inc = tot;   // inclusive scan of the thread totals within the wave
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t up = __shfl_up(inc, o, 64);
@@ -195,27 +199,31 @@ __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int
     }
     if (lane == 63) wsum[wv] = inc;
     __syncthreads();
-    if (wv == 0) {
-      uint32_t w = lane < 16 ? wsum[lane] : 0u;
+    uint32_t before = 0u, total = 0u;
 #pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        const uint32_t up = __shfl_up(w, o, 64);
-        if (lane >= o) w += up;
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t t = wsum[i];
+      before += i < wv ? t : 0u;
+      total += t;
+    }
+    const uint32_t base = carry + before + inc - tot;
+    if (full) {
+#pragma unroll
+      for (int q = 0; q < SCAN_K / 4; ++q) {
+        uint4 u;
+        u.x = base + x[4 * q];
+        u.y = base + x[4 * q + 1];
+        u.z = base + x[4 * q + 2];
+        u.w = base + x[4 * q + 3];
+        reinterpret_cast<uint4*>(v + c0)[q] = u;
       }
-      if (lane < 16) wsum[lane] = w;   // inclusive wave prefix
-    }
-    __syncthreads();
-    const uint32_t base = carry + (wv > 0 ? wsum[wv - 1] : 0u) + inc - tot;
+    } else {
 #pragma unroll
-    for (int j = 0; j < SCAN_K; ++j) tile[ix(threadIdx.x * SCAN_K + j)] = base + loc[j];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < SCAN_K; ++j) {
-      const int64_t i = t0 + (int64_t)j * 1024 + threadIdx.x;
-      if (i < n) v[i] = tile[ix(j * 1024 + threadIdx.x)];
+      for (int j = 0; j < SCAN_K; ++j)
+        if (c0 + j < n) v[c0 + j] = base + x[j];
     }
-    if (threadIdx.x == 0) carry += wsum[15];
-    __syncthreads();
+    carry += total;
+    __syncthreads();   // wsum is rewritten by the next tile
   }
 }
 
@@ -315,20 +323,29 @@ __global__ void __launch_bounds__(SORT_THREADS) k_tree_count(const uint64_t* __r
 
 // Exclusive scan of tile totals per level (one thread per level), node counts,
 // and the sentinels of the child-range arrays.
+// Exclusive scan over the tiles of each level's node counts: wave k - 1 scans
+// level k (k = 1..N) 64 tiles at a time (a shuffle scan with a running carry),
+// so the tiles' loads are issued 64 at a time instead of one after another.
+// Launched with 64 N threads.
 __global__ void k_tree_scan(int64_t* __restrict__ tiletot, int ntiles, Geom g, Tree tr) {
-  const int k = threadIdx.x;
-  if (k == 0) {
-    tr.cnt[0] = 1;
-    return;
-  }
+  const int lane = threadIdx.x & 63;
+  const int k = (int)(threadIdx.x >> 6) + 1;
+  if (threadIdx.x == 0) tr.cnt[0] = 1;
   if (k > g.N) return;
   int64_t run = 0;
-  for (int b = 0; b < ntiles; ++b) {
-    const int64_t v = tiletot[(size_t)b * (KR_MAXN + 1) + k];
-    tiletot[(size_t)b * (KR_MAXN + 1) + k] = run;
-    run += v;
+  for (int b0 = 0; b0 < ntiles; b0 += 64) {
+    const int b = b0 + lane;
+    const int64_t v = b < ntiles ? tiletot[(size_t)b * (KR_MAXN + 1) + k] : 0;
+    int64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t up = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += up;
+    }
+    if (b < ntiles) tiletot[(size_t)b * (KR_MAXN + 1) + k] = run + inc - v;
+    run += __shfl(inc, 63, 64);
   }
-  tr.cnt[k] = run;
+  if (lane == 0) tr.cnt[k] = run;
 }
 
 __global__ void k_tree_sentinels(Geom g, Tree tr) {
