@@ -763,6 +763,10 @@ static int64_t part_blocks(const Geom& g) {
 // Workspace of one solve.  lean: the batched team's layout, which never forms
 // the level-(N-1) products (N >= 3) nor the single-problem iteration's row and
 // partial-sum buffers.
+// Tiles of the tree kernels over m sorted keys (tiletot holds KR_MAXN + 1 counts
+// per tile).
+static int tree_tiles(int64_t m) { return (int)((m + TREE_TILE - 1) / TREE_TILE); }
+
 static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = false) {
   size_t b = setup_bytes(g);
   b += 2 * 8 * (size_t)g.m + 4 * SORT_DIGITS_MAX * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
@@ -814,10 +818,11 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
     }
     std::swap(kin, kout);
   }
-  KL(h, k_tree_count, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot);
-  KL(h, k_tree_scan, dim3(1), dim3(64 * g.N), 0, s, tiletot, nblocks, g, tr);
+  const int ntree = tree_tiles(m);
+  KL(h, k_tree_count, dim3(ntree), dim3(SORT_THREADS), 0, s, kin, g, tiletot);
+  KL(h, k_tree_scan, dim3(1), dim3(64 * g.N), 0, s, tiletot, ntree, g, tr);
   KL(h, k_tree_sentinels, dim3(1), dim3(64), 0, s, g, tr);
-  KL(h, k_tree_emit, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, g, tiletot, tr);
+  KL(h, k_tree_emit, dim3(ntree), dim3(SORT_THREADS), 0, s, kin, g, tiletot, tr);
 }
 
 // Nodes per root-adjoint block (a multiple of RA_NODES): all level-1 nodes in one
@@ -1099,7 +1104,7 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   B->keys = a.take<uint64_t>(m);
   B->keys_alt = a.take<uint64_t>(m);
   B->hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
-  B->tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
+  B->tiletot = a.take<int64_t>((size_t)tree_tiles(m) * (KR_MAXN + 1));
   for (int k = 1; k <= g.N; ++k) {
     const int64_t c = level_cap(g, k);
     tr->idx[k] = a.take<int32_t>(c + 2);
@@ -1212,7 +1217,7 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   const double eta = 1.0 - std::sqrt(eps);
 
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
-  const size_t need = solve_bytes(g, nblocks, nblocks);
+  const size_t need = solve_bytes(g, tree_tiles(g.m), nblocks);
   if (ext_ws) {
     if (need > ext_cap)
       KR_FAIL(h, KR_EUNSUPPORTED,
@@ -1601,7 +1606,7 @@ static kr_status solve_batched(kr_handle h, int32_t count, const kr_problem* pro
   size_t total = 0, nparts = 0;
   for (int i : idx) {
     const int nb = (int)((G[i].m + SORT_TILE - 1) / SORT_TILE);
-    total += solve_bytes(G[i], nb, nb, route[i] == TEAM) + 1024;
+    total += solve_bytes(G[i], tree_tiles(G[i].m), nb, route[i] == TEAM) + 1024;
     if (permuted[i]) total += 2 * 8 * (size_t)G[i].Rtot * G[i].nrhs + 1024;   // x and X_true in tree order
     if (route[i] == TEAM) nparts += (size_t)((G[i].Rtot + TM_THREADS - 1) / TM_THREADS) * G[i].nrhs * 2;
   }
@@ -2636,7 +2641,7 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
 
   // workspace
   size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * SORT_DIGITS_MAX * (size_t)nblocks +
-                8 * (size_t)nblocks * (KR_MAXN + 1) + 4096;
+                8 * (size_t)tree_tiles(m) * (KR_MAXN + 1) + 4096;
   const int64_t Dcap = level_cap(g, g.N);
   for (int k = 1; k <= g.N; ++k) need += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
   need += (size_t)Dcap * (8 + 8 + 4) + 4 * (size_t)(Dcap + 2) + 8 * (size_t)Dcap + 2048;
@@ -2652,7 +2657,7 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   uint64_t* keys = a.take<uint64_t>(m);
   uint64_t* keys_alt = a.take<uint64_t>(m);
   uint32_t* hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
-  int64_t* tiletot = a.take<int64_t>((size_t)nblocks * (KR_MAXN + 1));
+  int64_t* tiletot = a.take<int64_t>((size_t)tree_tiles(m) * (KR_MAXN + 1));
   Tree tr{};
   for (int k = 1; k <= g.N; ++k) {
     const int64_t c = level_cap(g, k);

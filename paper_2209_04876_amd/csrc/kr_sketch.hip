@@ -20,6 +20,10 @@ namespace kr {
 #define SORT_THREADS 256
 #define SORT_ITEMS 16
 #define SORT_TILE (SORT_THREADS * SORT_ITEMS)
+// The tree kernels take smaller tiles than the sort: their work per key is a few
+// compares, so a launch wants many workgroups rather than long per-thread runs.
+#define TREE_ITEMS 4
+#define TREE_TILE (SORT_THREADS * TREE_ITEMS)
 #define SORT_DIGITS_MAX 512   // histogram rows per tile (9-bit digits at most)
 
 // ---------------------------------------------------------------------------
@@ -299,9 +303,10 @@ __global__ void __launch_bounds__(SORT_THREADS) k_tree_count(const uint64_t* __r
   __shared__ int64_t red[SORT_THREADS / 64][KR_MAXN + 1];
   int cnt[KR_MAXN + 1];
   for (int k = 0; k <= KR_MAXN; ++k) cnt[k] = 0;
-  const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)threadIdx.x * SORT_ITEMS;
-  for (int e = 0; e < SORT_ITEMS; ++e) {
-    const int64_t t = t0 + e;
+  // items t = tile + e SORT_THREADS + thread: the key loads are coalesced
+  const int64_t t0 = (int64_t)blockIdx.x * TREE_TILE + threadIdx.x;
+  for (int e = 0; e < TREE_ITEMS; ++e) {
+    const int64_t t = t0 + (int64_t)e * SORT_THREADS;
     if (t < g.m) {
       const uint32_t f = level_flags(keys, t, g);
       for (int k = 1; k <= g.N; ++k) cnt[k] += (f >> k) & 1u;
@@ -321,8 +326,6 @@ __global__ void __launch_bounds__(SORT_THREADS) k_tree_count(const uint64_t* __r
   }
 }
 
-// Exclusive scan of tile totals per level (one thread per level), node counts,
-// and the sentinels of the child-range arrays.
 // Exclusive scan over the tiles of each level's node counts: wave k - 1 scans
 // level k (k = 1..N) 64 tiles at a time (a shuffle scan with a running carry),
 // so the tiles' loads are issued 64 at a time instead of one after another.
@@ -357,57 +360,67 @@ __global__ void k_tree_sentinels(Geom g, Tree tr) {
   }
 }
 
+// The tree's arrays from the sorted keys, one workgroup per tile.  The tile's
+// items are taken in rounds of SORT_THREADS consecutive keys (coalesced loads):
+// in a round, an item's rank among the round's level-k flags comes from a
+// ballot, the waves' counts are exchanged through LDS, and per-level running
+// counts carry the ranks across rounds; node s of level k is then written at
+// tile offset + rank, with its parent (the level-(k-1) nodes started up to and
+// including the item, less one) and its first child (the level-(k+1) nodes
+// started before the item).
 __global__ void __launch_bounds__(SORT_THREADS) k_tree_emit(const uint64_t* __restrict__ keys, Geom g,
                                                            const int64_t* __restrict__ tiletot, Tree tr) {
-  __shared__ int64_t wsum[SORT_THREADS / 64][KR_MAXN + 1];
-  int cnt[KR_MAXN + 1];
-  uint32_t fl[SORT_ITEMS];
-  for (int k = 0; k <= KR_MAXN; ++k) cnt[k] = 0;
-  const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)threadIdx.x * SORT_ITEMS;
-  for (int e = 0; e < SORT_ITEMS; ++e) {
-    const int64_t t = t0 + e;
-    fl[e] = t < g.m ? level_flags(keys, t, g) : 0u;
-    for (int k = 1; k <= g.N; ++k) cnt[k] += (fl[e] >> k) & 1u;
-  }
-  // block-exclusive prefix per level: wave inclusive scan then wave offsets
+  constexpr int NW = SORT_THREADS / 64;
+  __shared__ int wcnt[2][NW][KR_MAXN + 2];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int64_t excl[KR_MAXN + 1];
-  for (int k = 1; k <= g.N; ++k) {
-    int v = cnt[k];
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(v, o, 64);
-      if (lane >= o) v += y;
+  const uint64_t lt = (1ull << lane) - 1ull;   // lanes below this one
+  const int N = g.N;
+  int64_t base[KR_MAXN + 2];   // level-k nodes before this round (tile offset included)
+  for (int k = 0; k <= KR_MAXN + 1; ++k) base[k] = 0;
+  for (int k = 1; k <= N; ++k) base[k] = tiletot[(size_t)blockIdx.x * (KR_MAXN + 1) + k];
+  const int64_t tb = (int64_t)blockIdx.x * TREE_TILE;
+  for (int e = 0; e < TREE_ITEMS; ++e) {
+    const int64_t t = tb + (int64_t)e * SORT_THREADS + threadIdx.x;
+    const bool in = t < g.m;
+    const uint32_t f = in ? level_flags(keys, t, g) : 0u;
+    const uint64_t key = in ? keys[t] : 0ull;
+    const int buf = e & 1;
+    int before[KR_MAXN + 2];   // level-k flags of earlier items in this round
+    for (int k = 1; k <= N; ++k) {
+      const uint64_t m = __ballot((f >> k) & 1u);
+      before[k] = __popcll(m & lt);
+      if (lane == 0) wcnt[buf][w][k] = __popcll(m);
     }
-    excl[k] = v - cnt[k];
-    if (lane == 63) wsum[w][k] = v;
-  }
-  __syncthreads();
-  for (int k = 1; k <= g.N; ++k) {
-    int64_t off = tiletot[(size_t)blockIdx.x * (KR_MAXN + 1) + k];
-    for (int q = 0; q < w; ++q) off += wsum[q][k];
-    excl[k] += off;
-  }
-  // walk the items: excl[k] is the number of level-k flags before item t
-  for (int e = 0; e < SORT_ITEMS; ++e) {
-    const int64_t t = t0 + e;
-    if (t >= g.m) break;
-    const uint32_t f = fl[e];
-    const uint64_t key = keys[t];
-    for (int k = 1; k <= g.N; ++k) {
-      if ((f >> k) & 1u) {
-        const int64_t s = excl[k];
-        const int n = k - 1;
-        tr.idx[k][s] = (int32_t)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
-        // parent: the level-(k-1) node containing t (inclusive count - 1)
-        tr.parent[k][s] = k == 1 ? 0 : (int32_t)(excl[k - 1] + ((f >> (k - 1)) & 1u) - 1);
-        if (k < g.N) tr.fchild[k][s] = (int32_t)excl[k + 1];
-        if (k == g.N) {
-          tr.rstart[s] = (int32_t)t;
-          tr.rkey[s] = key;
+    __syncthreads();
+    int64_t excl[KR_MAXN + 2];
+    excl[0] = 0;
+    excl[N + 1] = 0;
+    for (int k = 1; k <= N; ++k) {
+      int wb = 0, tot = 0;
+      for (int q = 0; q < NW; ++q) {
+        const int c = wcnt[buf][q][k];
+        wb += q < w ? c : 0;
+        tot += c;
+      }
+      excl[k] = base[k] + wb + before[k];
+      base[k] += tot;
+    }
+    if (in) {
+      for (int k = 1; k <= N; ++k) {
+        if ((f >> k) & 1u) {
+          const int64_t sk = excl[k];
+          const int n = k - 1;
+          tr.idx[k][sk] = (int32_t)((key >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+          tr.parent[k][sk] = k == 1 ? 0 : (int32_t)(excl[k - 1] + ((f >> (k - 1)) & 1u) - 1);
+          if (k < N) tr.fchild[k][sk] = (int32_t)excl[k + 1];
+          if (k == N) {
+            tr.rstart[sk] = (int32_t)t;
+            tr.rkey[sk] = key;
+          }
         }
       }
     }
-    for (int k = 1; k <= g.N; ++k) excl[k] += (f >> k) & 1u;
+    // wcnt[buf] is read again only two rounds later, after the next barrier
   }
 }
 
