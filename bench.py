@@ -496,7 +496,7 @@ def main():
         prec, tol = legs[leg]
         return kr.kron_regress(tA, tb, eps=w["eps"], m=w["m"], seed=w["seed"], precision=prec, tol=tol, x=x)
 
-    iter_kernels = ("k_fwd_level", "k_rows_adj", "k_adj_level", "k_subtree3", "k_adj_root_partial", "k_precond")
+    iter_kernels = ("k_fwd_level", "k_rows_adj", "k_rows_lane", "k_adj_level", "k_subtree3", "k_adj_root_partial", "k_precond")
     breakdowns, launches, per_iter = {}, {}, {}
     for leg in legs:
         for _ in range(args.warmup):

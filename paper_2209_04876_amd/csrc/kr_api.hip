@@ -853,6 +853,15 @@ static bool rows_ldsf(const Geom& g, const Tree& tr) {
   const int64_t IL = g.I[g.N - 1];
   return IL * g.R[g.N - 1] * 8 <= KR_ROWS_LDS_MAX && tr.ncnt[g.N] >= 16 * IL;
 }
+// Padded row width of the lane-per-row kernel (k_rows_lane), 0 where it does not
+// apply: R_{N-1} <= 16 and the factor zero-padded to 8 or 16 columns fits the
+// same LDS budget.
+static int rows_lane_width(const Geom& g, const Tree& tr) {
+  const int Rl = g.R[g.N - 1];
+  const int RP = Rl <= 8 ? 8 : 16;
+  if (Rl > 16 || !rows_ldsf(g, tr) || (int64_t)g.I[g.N - 1] * RP * 8 > KR_ROWS_LDS_MAX) return 0;
+  return RP;
+}
 
 // One pass of the sampled products K~^T Omega (K~ x - b~) down and up the sample
 // tree: forward levels 1..N-2, the last forward level with the rows and the last
@@ -891,6 +900,16 @@ static bool launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
   else                                                                                                    \
     KLN(h, f32 ? NAME ",f32>" : NAME ">", (k_rows_adj<GG, T, false>), rg, dim3(256), 0, s, TT, g, tr, plast, \
         Omega, bD, qlast, state);
+    const int RP = rows_lane_width(g, tr);
+    const size_t flp = 8 * (size_t)g.I[g.N - 1] * RP;
+    const dim3 rgp(grid_for(tr.ncnt[g.N - 1] * g.nrhs, KR_LANE_TPB / 64, KR_ROWS_LDS_GRID));
+    if (RP == 8)
+      KLN(h, f32 ? "k_rows_lane<8,f32>" : "k_rows_lane<8>", (k_rows_lane<8, T>), rgp, dim3(KR_LANE_TPB), flp, s, TT, g,
+          tr, plast, Omega, bD, qlast);
+    else if (RP == 16)
+      KLN(h, f32 ? "k_rows_lane<16,f32>" : "k_rows_lane<16>", (k_rows_lane<16, T>), rgp, dim3(KR_LANE_TPB), flp, s, TT,
+          g, tr, plast, Omega, bD, qlast);
+    else
     switch (G) {
       case 8: KR_ROWS_LAUNCH(8, "k_rows_adj<8") break;
       case 16: KR_ROWS_LAUNCH(16, "k_rows_adj<16") break;

@@ -215,6 +215,46 @@ struct RowsTask {
   }
 };
 
+// P_{N-1}[p][lane][q] of a (level-(N-1) node p, rhs q) task in lane `lane` of
+// every group of G lanes (0 in lanes lane >= R_{N-1}).  From a parent level, group
+// gi sums the terms s = gi, gi + NGR, ... of the contraction over R_{N-2} and the
+// groups' partial sums are combined by a butterfly (the same rounding in every
+// group); P_0 = x with the root as parent; for N = 1 it is x itself; for a
+// segment root it is the segment's own iterate.
+template <int G>
+__device__ __forceinline__ double rows_pnode(const Geom& g, const Tree& tr, const double* __restrict__ Pprev,
+                                             int64_t p, int64_t par, int q, int lane, int gi) {
+  constexpr int NGR = 64 / G;
+  const int N = g.N, nrhs = g.nrhs, R = g.R[N - 1];
+  const bool ln = lane < R;
+  double pv = 0.0;
+  if (N == 1) {
+    if (ln) pv = Pprev[(int64_t)lane * nrhs + q];
+  } else if (N == 2 && g.seg_root) {
+    if (ln) pv = Pprev[((int64_t)tr.idx[1][p] * R + lane) * nrhs + q];
+  } else {
+    const int Rp = g.R[N - 2];
+    const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
+    const int64_t step = (int64_t)R * nrhs;
+    const double* __restrict__ src = Pprev + par * (int64_t)Rp * step + q;
+    if (ln) {
+      for (int s0 = gi; s0 < Rp; s0 += 4 * NGR) {
+        double as[4], sv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int s = s0 + u * NGR;
+          as[u] = s < Rp ? a[s] : 0.0;
+          sv[u] = s < Rp ? src[(int64_t)s * step + lane * nrhs] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pv = fma(as[u], sv[u], pv);
+      }
+    }
+    pv = xgrp_sum<G>(pv);
+  }
+  return pv;
+}
+
 // The last forward level, the rows and the last adjoint level, fused.  One wave
 // owns one (level-(N-1) node p, rhs q).  Its NGR = 64/G lane groups (G a power of
 // two >= R_{N-1}) first form P_{N-1}[p][r][q] in lane r: from P_{N-2}[parent(p)]
@@ -293,36 +333,157 @@ __global__ void __launch_bounds__(LDSF ? KR_ROWS_LDS_TPB : 256)
     }
     RowsTask<G, KR_ROWS_PER_STEP, LDSF> rt(AL, tr.idx[N], Omega, bD, j0, j1, R, nrhs, q, lane, gi);
     rt.load(0);
-    // P_{N-1}[p][lane][q]; from a parent level, group gi sums the terms
-    // s = gi, gi + NGR, ... of the contraction over R_{N-2} and the groups' partial
-    // sums are combined by a butterfly (the same rounding in every group)
-    double pv = 0.0;
-    if (N == 1) {
-      if (ln) pv = Pprev[(int64_t)lane * nrhs + q];
-    } else if (N == 2 && g.seg_root) {
-      if (ln) pv = Pprev[((int64_t)tr.idx[1][p] * R + lane) * nrhs + q];
-    } else {
-      const int Rp = g.R[N - 2];
-      const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
-      const int64_t step = (int64_t)R * nrhs;
-      const double* __restrict__ src = Pprev + par * (int64_t)Rp * step + q;
-      if (ln) {
-        for (int s0 = gi; s0 < Rp; s0 += 4 * NGR) {
-          double as[4], sv[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int s = s0 + u * NGR;
-            as[u] = s < Rp ? a[s] : 0.0;
-            sv[u] = s < Rp ? src[(int64_t)s * step + lane * nrhs] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) pv = fma(as[u], sv[u], pv);
-        }
-      }
-      pv = xgrp_sum<G>(pv);
-    }
+    const double pv = rows_pnode<G>(g, tr, Pprev, p, par, q, lane, gi);
     const T acc = rt.template run<T>(pv);
     if (gi == 0 && ln) Qout[(p * R + lane) * nrhs + q] = acc;
+  }
+}
+
+// Lane exchange (lane ^ O) of a float64 or float32 value.
+template <int O, typename T> __device__ __forceinline__ T xlane(T v) {
+  if constexpr (sizeof(T) == 8) return xor_lane<O>(v);
+  else return __shfl_xor(v, O, 64);
+}
+// One halving step of the transpose sum: a lane with bit MASK set keeps entries
+// H..2H-1 of its first 2H, the other lane of the pair entries 0..H-1, and each adds
+// its partner's copy of the entries it keeps, which land in acc[0..H-1].
+template <int H, int MASK, typename T> __device__ __forceinline__ void tsum_step(T* acc, bool up) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const T keep = up ? acc[H + i] : acc[i];
+    const T give = up ? acc[i] : acc[H + i];
+    acc[i] = keep + xlane<MASK>(give);
+  }
+}
+// Sum over the 64 lanes of each of the RP entries acc[0..RP-1]: entry r ends in
+// lanes r (64 / RP) .. r (64 / RP) + 64 / RP - 1 (all with the same bits).  Every
+// lane pair adds its two values once, so the result does not depend on timing.
+template <int RP, typename T> __device__ __forceinline__ T lane_transpose_sum(T (&acc)[RP], int l64) {
+  static_assert(RP == 8 || RP == 16, "padded row width");
+  tsum_step<RP / 2, 32>(acc, (l64 & 32) != 0);
+  tsum_step<RP / 4, 16>(acc, (l64 & 16) != 0);
+  tsum_step<RP / 8, 8>(acc, (l64 & 8) != 0);
+  if constexpr (RP == 16) tsum_step<1, 4>(acc, (l64 & 4) != 0);
+  T v = acc[0];
+  if constexpr (RP == 8) v += xlane<4>(v);
+  v += xlane<2>(v);
+  v += xlane<1>(v);
+  return v;
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The LDS-staged rows with one row per lane, for R_{N-1} <= RP (8 or 16).  The
+// same sums as k_rows_adj: one wave per (level-(N-1) node p, rhs q) task, Q[p][r][q]
+// = sum_j (Omega_j u_j) a_{N-1}[i(j)][r] with u_j = <a_{N-1}[i(j)], P_{N-1}> - b_j
+// in float64.  The rows of a task are taken 64 at a time, lane l owning row
+// j0 + 64 c + l: its index, Omega and b arrive in one coalesced request per 64
+// rows (the next 64 requested before the current ones are used, the first before
+// the node's forward value is formed), its factor row is read from LDS (the
+// factor staged zero-padded to RP columns), and P_{N-1} is held wave-uniform, so
+// a lane forms u_j alone and accumulates its RP adjoint terms in registers.  A
+// transpose sum across the lanes ends the task.  Against the group-per-row
+// kernel a task of up to 64 rows costs one memory round trip instead of one per
+// 4 G-lane steps, which is what bounds that kernel on short tasks.
+#ifndef KR_LANE_TPB
+#define KR_LANE_TPB 512
+#endif
+#ifndef KR_LANE_WPE
+#define KR_LANE_WPE 4
+#endif
+template <int RP, typename T>
+__global__ void __launch_bounds__(KR_LANE_TPB) __attribute__((amdgpu_waves_per_eu(KR_LANE_WPE, 8)))
+    k_rows_lane(ModeTables TT, Geom g, Tree tr, const double* __restrict__ Pprev, const double* __restrict__ Omega,
+                const double* __restrict__ bD, T* __restrict__ Qout) {
+  extern __shared__ double2 lane_fac2[];
+  double* rows_fac = (double*)lane_fac2;
+  const int N = g.N, nrhs = g.nrhs;
+  const int R = g.R[N - 1];
+  {
+    const int nf = g.I[N - 1] * RP;
+    const double* __restrict__ A = TT.A[N - 1];
+    for (int e = threadIdx.x; e < nf; e += blockDim.x) {
+      const int i = e / RP, r = e % RP;
+      rows_fac[e] = r < R ? A[(int64_t)i * R + r] : 0.0;
+    }
+    __syncthreads();
+  }
+  const int64_t ntask = tr.ncnt[N - 1] * nrhs;
+  const int l64 = threadIdx.x & 63;
+  const int lane = l64 & (RP - 1), gi = l64 / RP;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t tstride = (int64_t)gridDim.x * wpb;
+  const int32_t* __restrict__ idxL = tr.idx[N];
+  int nb0 = 0, nb1 = 0;
+  int64_t npar = 0;
+  auto fetch = [&](int64_t t) {
+    if (t < ntask) {
+      const int64_t pp = t / nrhs;
+      nb0 = tr.fchild[N - 1][pp];
+      nb1 = tr.fchild[N - 1][pp + 1];
+      npar = N >= 3 ? tr.parent[N - 1][pp] : 0;
+    }
+  };
+  fetch(blockIdx.x * wpb + w);
+  for (int64_t task = blockIdx.x * wpb + w; task < ntask; task += tstride) {
+    const int64_t p = task / nrhs;
+    const int q = (int)(task - p * nrhs);
+    const int j0 = nb0, j1 = nb1;
+    const int64_t par = npar;
+    fetch(task + tstride);
+    if (j1 <= j0) {  // a node always has rows; kept for safety (uniform branch)
+      if (l64 < R) Qout[(p * R + l64) * nrhs + q] = (T)0;
+      continue;
+    }
+    // row j0 + l (clamped to j0 past the end, where Omega is taken as 0)
+    auto rowload = [&](int c, int& ix, double& om, double& bb) {
+      const int j = c + l64;
+      const int jj = j < j1 ? j : j0;
+      ix = idxL[jj];
+      om = Omega[jj];
+      bb = bD[(int64_t)jj * nrhs + q];
+      if (j >= j1) om = 0.0;
+    };
+    int ix;
+    double om, bb;
+    rowload(j0, ix, om, bb);
+    const double pv = rows_pnode<RP>(g, tr, Pprev, p, par, q, lane, gi);
+    double pvs[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) pvs[r] = read_lane(pv, r);
+    T acc[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) acc[r] = (T)0;
+    for (int c = j0; c < j1; c += 64) {
+      int ixn = 0;
+      double omn = 0.0, bbn = 0.0;
+      if (c + 64 < j1) rowload(c + 64, ixn, omn, bbn);
+      const double2* __restrict__ row = (const double2*)(rows_fac + (int64_t)ix * RP);
+      double a[RP];
+#pragma unroll
+      for (int k = 0; k < RP / 2; ++k) {
+        const double2 v = row[k];
+        a[2 * k] = v.x;
+        a[2 * k + 1] = v.y;
+      }
+      double y = 0.0;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) y = fma(a[r], pvs[r], y);
+      const T u = (T)(om * (y - bb));
+#pragma unroll
+      for (int r = 0; r < RP; ++r) acc[r] = fma(u, (T)a[r], acc[r]);
+      ix = ixn;
+      om = omn;
+      bb = bbn;
+    }
+    const T qv = lane_transpose_sum<RP>(acc, l64);
+    const int r = l64 / (64 / RP);
+    if ((l64 & (64 / RP - 1)) == 0 && r < R) Qout[(p * R + r) * nrhs + q] = qv;
   }
 }
 
