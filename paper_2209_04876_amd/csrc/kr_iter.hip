@@ -344,15 +344,69 @@ template <int O, typename T> __device__ __forceinline__ T xlane(T v) {
   if constexpr (sizeof(T) == 8) return xor_lane<O>(v);
   else return __shfl_xor(v, O, 64);
 }
-// One halving step of the transpose sum: a lane with bit MASK set keeps entries
-// H..2H-1 of its first 2H, the other lane of the pair entries 0..H-1, and each adds
-// its partner's copy of the entries it keeps, which land in acc[0..H-1].
+// The permlane swaps of gfx950 (per 32-bit half): permlane32_swap exchanges x in
+// lanes 32..63 with y in lanes 0..31, permlane16_swap x in the odd 16-lane rows
+// with y in the even rows below them.
+template <bool P32> __device__ __forceinline__ void swap_u32(uint32_t& x, uint32_t& y) {
+  if constexpr (P32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  }
+}
+template <bool P32, typename T> __device__ __forceinline__ void swap_lanes(T& x, T& y) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y);
+    uint32_t xl = (uint32_t)bx, yl = (uint32_t)by, xh = (uint32_t)(bx >> 32), yh = (uint32_t)(by >> 32);
+    swap_u32<P32>(xl, yl);
+    swap_u32<P32>(xh, yh);
+    x = __builtin_bit_cast(T, ((uint64_t)xh << 32) | xl);
+    y = __builtin_bit_cast(T, ((uint64_t)yh << 32) | yl);
+  } else {
+    uint32_t ux = __builtin_bit_cast(uint32_t, x), uy = __builtin_bit_cast(uint32_t, y);
+    swap_u32<P32>(ux, uy);
+    x = __builtin_bit_cast(T, ux);
+    y = __builtin_bit_cast(T, uy);
+  }
+}
+// DPP row rotate by 8 of a 32- or 64-bit value, written only to the lanes of the
+// banks (4-lane quarters of each 16-lane row) in BANKS; the others keep `old`.
+template <int BANKS, typename T> __device__ __forceinline__ T ror8_into(T old, T v) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t bo = __builtin_bit_cast(uint64_t, old), bv = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)bo, (int)(uint32_t)bv, 0x128, 0xF, BANKS, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(bo >> 32), (int)(uint32_t)(bv >> 32), 0x128, 0xF, BANKS,
+                                               false);
+    return __builtin_bit_cast(T, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                             0x128, 0xF, BANKS, false));
+  }
+}
+// One halving step of the transpose sum over the lane pairs (l, l ^ MASK): the
+// lane with bit MASK clear ends with entries 0..H-1 of the pair's sum, the other
+// with entries H..2H-1, both in acc[0..H-1].  Each entry is one addition of the
+// pair's two values.
 template <int H, int MASK, typename T> __device__ __forceinline__ void tsum_step(T* acc, bool up) {
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    const T keep = up ? acc[H + i] : acc[i];
-    const T give = up ? acc[i] : acc[H + i];
-    acc[i] = keep + xlane<MASK>(give);
+    T x = acc[i], y = acc[H + i];
+    if constexpr (MASK == 32 || MASK == 16) {
+      // after the swap the low lane holds (its x, the partner's x), the high lane
+      // (the partner's y, its y)
+      swap_lanes<MASK == 32>(x, y);
+      acc[i] = x + y;
+    } else if constexpr (MASK == 8) {
+      acc[i] = ror8_into<0x3>(y, x) + ror8_into<0xC>(x, y);
+    } else {
+      const T keep = up ? y : x;
+      const T give = up ? x : y;
+      acc[i] = keep + xlane<MASK>(give);
+    }
   }
 }
 // Sum over the 64 lanes of each of the RP entries acc[0..RP-1]: entry r ends in
