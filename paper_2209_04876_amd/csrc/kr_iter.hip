@@ -233,21 +233,36 @@ __device__ __forceinline__ double rows_pnode(const Geom& g, const Tree& tr, cons
   } else if (N == 2 && g.seg_root) {
     if (ln) pv = Pprev[((int64_t)tr.idx[1][p] * R + lane) * nrhs + q];
   } else {
+    // 32-bit byte offsets from the wave-uniform bases of a_{N-2}[i(p)] and
+    // P_{N-2}[parent(p)][:, :, q]
     const int Rp = g.R[N - 2];
     const double* __restrict__ a = tr.arow[N - 1] + p * Rp;
-    const int64_t step = (int64_t)R * nrhs;
-    const double* __restrict__ src = Pprev + par * (int64_t)Rp * step + q;
+    const unsigned step8 = (unsigned)(R * nrhs) * 8u;
+    const double* __restrict__ src = Pprev + par * (int64_t)Rp * R * nrhs + q;
+    const unsigned lo8 = (unsigned)(lane * nrhs) * 8u;
     if (ln) {
-      for (int s0 = gi; s0 < Rp; s0 += 4 * NGR) {
+      if (Rp == 4 * NGR) {   // one term per lane group and step: no bounds to test
         double as[4], sv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int s = s0 + u * NGR;
-          as[u] = s < Rp ? a[s] : 0.0;
-          sv[u] = s < Rp ? src[(int64_t)s * step + lane * nrhs] : 0.0;
+          const unsigned s = (unsigned)(gi + u * NGR);
+          as[u] = ld_at(a, s * 8u);
+          sv[u] = ld_at(src, s * step8 + lo8);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) pv = fma(as[u], sv[u], pv);
+      } else {
+        for (int s0 = gi; s0 < Rp; s0 += 4 * NGR) {
+          double as[4], sv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * NGR;
+            as[u] = s < Rp ? ld_at(a, (unsigned)s * 8u) : 0.0;
+            sv[u] = s < Rp ? ld_at(src, (unsigned)s * step8 + lo8) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pv = fma(as[u], sv[u], pv);
+        }
       }
     }
     pv = xgrp_sum<G>(pv);
@@ -475,37 +490,49 @@ __global__ void __launch_bounds__(KR_LANE_TPB) __attribute__((amdgpu_waves_per_e
   const int32_t* __restrict__ idxL = tr.idx[N];
   int nb0 = 0, nb1 = 0;
   int64_t npar = 0;
+  // (node, rhs) of a task; one right-hand side needs no division
+  auto node_of = [&](int64_t t) { return nrhs == 1 ? t : t / nrhs; };
   auto fetch = [&](int64_t t) {
     if (t < ntask) {
-      const int64_t pp = t / nrhs;
+      const int64_t pp = node_of(t);
       nb0 = tr.fchild[N - 1][pp];
       nb1 = tr.fchild[N - 1][pp + 1];
       npar = N >= 3 ? tr.parent[N - 1][pp] : 0;
     }
   };
+  const unsigned nrhs8 = (unsigned)nrhs * 8u;
   fetch(blockIdx.x * wpb + w);
   for (int64_t task = blockIdx.x * wpb + w; task < ntask; task += tstride) {
-    const int64_t p = task / nrhs;
+    const int64_t p = node_of(task);
     const int q = (int)(task - p * nrhs);
-    const int j0 = nb0, j1 = nb1;
-    const int64_t par = npar;
+    // the bounds and parent are wave-uniform: in scalar registers they make the
+    // row and parent bases scalar, and the loads take 32-bit lane offsets
+    const int j0 = __builtin_amdgcn_readfirstlane(nb0), j1 = __builtin_amdgcn_readfirstlane(nb1);
+    const int64_t par = __builtin_amdgcn_readfirstlane((int)npar);
     fetch(task + tstride);
+    T* __restrict__ qb = Qout + p * R * nrhs + q;
     if (j1 <= j0) {  // a node always has rows; kept for safety (uniform branch)
-      if (l64 < R) Qout[(p * R + l64) * nrhs + q] = (T)0;
+      if (l64 < R) qb[l64 * nrhs] = (T)0;
       continue;
     }
-    // row j0 + l (clamped to j0 past the end, where Omega is taken as 0)
+    // row j0 + c + l, addressed by 32-bit offsets from the node's wave-uniform
+    // bases (clamped to the node's first row past the end, where Omega is taken
+    // as 0)
+    const int nrow = j1 - j0;
+    const int32_t* __restrict__ ib = idxL + j0;
+    const double* __restrict__ ob = Omega + j0;
+    const double* __restrict__ bq = bD + (int64_t)j0 * nrhs + q;
     auto rowload = [&](int c, int& ix, double& om, double& bb) {
-      const int j = c + l64;
-      const int jj = j < j1 ? j : j0;
-      ix = idxL[jj];
-      om = Omega[jj];
-      bb = bD[(int64_t)jj * nrhs + q];
-      if (j >= j1) om = 0.0;
+      const int k = c + l64;
+      const unsigned kk = k < nrow ? (unsigned)k : 0u;
+      ix = *(const int32_t*)((const char*)ib + kk * 4u);
+      om = ld_at(ob, kk * 8u);
+      bb = ld_at(bq, kk * nrhs8);
+      if (k >= nrow) om = 0.0;
     };
     int ix;
     double om, bb;
-    rowload(j0, ix, om, bb);
+    rowload(0, ix, om, bb);
     const double pv = rows_pnode<RP>(g, tr, Pprev, p, par, q, lane, gi);
     double pvs[RP];
 #pragma unroll
@@ -513,10 +540,10 @@ __global__ void __launch_bounds__(KR_LANE_TPB) __attribute__((amdgpu_waves_per_e
     T acc[RP];
 #pragma unroll
     for (int r = 0; r < RP; ++r) acc[r] = (T)0;
-    for (int c = j0; c < j1; c += 64) {
+    for (int c = 0; c < nrow; c += 64) {
       int ixn = 0;
       double omn = 0.0, bbn = 0.0;
-      if (c + 64 < j1) rowload(c + 64, ixn, omn, bbn);
+      if (c + 64 < nrow) rowload(c + 64, ixn, omn, bbn);
       const double2* __restrict__ row = (const double2*)(rows_fac + (int64_t)ix * RP);
       double a[RP];
 #pragma unroll
@@ -537,7 +564,7 @@ __global__ void __launch_bounds__(KR_LANE_TPB) __attribute__((amdgpu_waves_per_e
     }
     const T qv = lane_transpose_sum<RP>(acc, l64);
     const int r = l64 / (64 / RP);
-    if ((l64 & (64 / RP - 1)) == 0 && r < R) Qout[(p * R + r) * nrhs + q] = qv;
+    if ((l64 & (64 / RP - 1)) == 0 && r < R) qb[r * nrhs] = qv;
   }
 }
 
