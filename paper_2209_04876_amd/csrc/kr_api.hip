@@ -2747,16 +2747,27 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   KL(h, k_zero_bytes, dim3(1), dim3(64), 0, s, (uint32_t*)counters, (int64_t)64);
   KL(h, k_zero_bytes, dim3(1), dim3(256), 0, s, (uint32_t*)state, (int64_t)(sizeof(IterState) / 4));
   HIPCHK(h, hipGetLastError());
+  // the per-row update with its operands staged up front (rows of at most 256
+  // entries, R_n <= 16, the tree modes' eigenvectors and Cinv within 8 KB)
+  int64_t nstage = (int64_t)Rn * Rn;
+  for (int k = 1; k < g.N; ++k) nstage += (int64_t)g.R[k] * g.R[k];
+  const bool staged = Rr <= 256 && Rn <= TU_RN && nstage <= 1024;
   int enq = 0;
   bool checked = false;
   while (enq < max_iter) {
     const int chunk = std::min(check_every, max_iter - enq);
     for (int it = 0; it < chunk; ++it) {
       launch_level_products<double>(h, T, g, tr, P, (void* const*)Q, Omega, bD, (const IterState*)state);
-      KL(h, k_tucker_update, dim3(In), dim3(256), 3 * 8 * (size_t)Rr, s, T, g, tg, (const double*)Q[1], Z,
-         (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv, (const double*)wbuf, eta,
-         tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, counters, counters + 1,
-         state);
+      if (staged)
+        KL(h, k_tucker_update_st, dim3(In), dim3(256), 8 * (3 * (size_t)Rr + (size_t)nstage), s, T, g, tg,
+           (const double*)Q[1], Z, (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv,
+           (const double*)wbuf, eta, tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall,
+           counters, counters + 1, state);
+      else
+        KL(h, k_tucker_update, dim3(In), dim3(256), 3 * 8 * (size_t)Rr, s, T, g, tg, (const double*)Q[1], Z,
+           (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv, (const double*)wbuf, eta,
+           tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, counters, counters + 1,
+           state);
       KL(h, k_tucker_tick, dim3(1), dim3(64), 0, s, In, max_iter, (const int32_t*)counters,
          (const int32_t*)(counters + 1), state);
     }

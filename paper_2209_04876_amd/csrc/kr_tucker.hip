@@ -280,6 +280,12 @@ __global__ void __launch_bounds__(256) k_rows_tucker(ModeTables T, Geom g, Tucke
   if (bad) atomicOr(flags, KR_FLAG_NONFINITE);
 }
 
+__device__ void tucker_row_stop(int i, double dd, double zz, double eta, double tol, int it,
+                                int32_t* __restrict__ seg_done, int32_t* __restrict__ seg_iters,
+                                double* __restrict__ seg_rel, double* __restrict__ seg_d0,
+                                double* __restrict__ seg_best, int32_t* __restrict__ seg_stall,
+                                int32_t* __restrict__ ndone, int32_t* __restrict__ diverged);
+
 // Per-row update, one workgroup per row i (the level-1 node of row i is node i:
 // every row has at least one sample and rows sort first):
 //   h = Q1[i] + w z + U (V z);  d = A^-1 h - AinvU Cinv V A^-1 h;  z -= eta d
@@ -351,7 +357,17 @@ __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, Tuc
   }
   dd = block_sum(dd, red);
   zz = block_sum(zz, red);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
+    tucker_row_stop(i, dd, zz, eta, tol, it, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, ndone, diverged);
+}
+
+// The stopping rule of row i from the squared norms of its step d and new z.
+__device__ void tucker_row_stop(int i, double dd, double zz, double eta, double tol, int it,
+                                int32_t* __restrict__ seg_done, int32_t* __restrict__ seg_iters,
+                                double* __restrict__ seg_rel, double* __restrict__ seg_d0,
+                                double* __restrict__ seg_best, int32_t* __restrict__ seg_stall,
+                                int32_t* __restrict__ ndone, int32_t* __restrict__ diverged) {
+  {
     const double dn = sqrt(dd), zn = sqrt(zz);
     const double rel = zn > 0.0 ? eta * dn / zn : (dn > 0.0 ? INFINITY : 0.0);
     // stagnation: the terms w z and w G^+ G z of h cancel at O(w ||z||), so the
@@ -377,6 +393,156 @@ __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, Tuc
       atomicAdd(ndone, 1);
     }
   }
+}
+
+// The same per-row update with every row-independent operand requested once, up
+// front, for rows of Rr <= 256 entries (one per thread) and R_n <= 16: thread e
+// holds column e of GtP and row e of AinvU, the 16-lane group a holds row a of
+// Vw (lane p its entries p, p + 16, ...), and the tree modes' eigenvectors and
+// Cinv are staged in LDS.  The original reads those operands from global memory
+// inside each step, a chain of about ten dependent round trips per iteration;
+// here the steps wait only on LDS and barriers.  The arithmetic and its order are
+// those of k_tucker_update (the same results, bit for bit).  Dynamic LDS: 3 Rr
+// doubles for z, h and scratch, then sum_k R_k^2 + R_n^2 for the staged matrices.
+#define TU_RN 16
+__global__ void __launch_bounds__(256) k_tucker_update_st(ModeTables T, Geom g, TuckerGeom tg,
+                                                         const double* __restrict__ Q1, double* __restrict__ Z,
+                                                         const double* __restrict__ GtP, const double* __restrict__ Vw,
+                                                         const double* __restrict__ AinvU,
+                                                         const double* __restrict__ Cinv, const double* __restrict__ w_in,
+                                                         double eta, double tol, int it, int max_iter,
+                                                         int32_t* __restrict__ seg_done, int32_t* __restrict__ seg_iters,
+                                                         double* __restrict__ seg_rel, double* __restrict__ seg_d0,
+                                                         double* __restrict__ seg_best, int32_t* __restrict__ seg_stall,
+                                                         int32_t* __restrict__ ndone, int32_t* __restrict__ diverged,
+                                                         IterState* __restrict__ st) {
+  extern __shared__ double sm[];
+  __shared__ double red[8];
+  __shared__ double vv[64];
+  __shared__ double uu[64];
+  if (st->all_done) return;
+  const int i = blockIdx.x;
+  if (seg_done[i]) return;
+  const int Rr = tg.Rr, Rn = tg.Rn;
+  const int e = threadIdx.x;
+  const bool own = e < Rr;
+  double* z = sm;
+  double* h = sm + Rr;
+  double* buf = sm + 2 * Rr;
+  double* Vs = sm + 3 * Rr;
+  int voff[KR_MAXN];
+  int nv = 0;
+  for (int k = 1; k < g.N; ++k) {
+    voff[k] = nv;
+    nv += g.R[k] * g.R[k];
+  }
+  double* Cs = Vs + nv;
+  // every operand requested before the first use
+  for (int k = 1; k < g.N; ++k)
+    for (int t = threadIdx.x; t < g.R[k] * g.R[k]; t += blockDim.x) Vs[voff[k] + t] = T.V[k][t];
+  for (int t = threadIdx.x; t < Rn * Rn; t += blockDim.x) Cs[t] = Cinv[t];
+  const double w = *w_in;
+  const double zq = own ? Z[(size_t)i * Rr + e] : 0.0;
+  const double q1 = own ? Q1[(size_t)i * Rr + e] : 0.0;
+  double gt[TU_RN], au[TU_RN], vw[TU_RN];
+#pragma unroll
+  for (int a = 0; a < TU_RN; ++a) {
+    gt[a] = own && a < Rn ? GtP[a * Rr + e] : 0.0;
+    au[a] = own && a < Rn ? AinvU[e * Rn + a] : 0.0;
+  }
+  const int ga = threadIdx.x >> 4, gp = threadIdx.x & 15;
+#pragma unroll
+  for (int j = 0; j < TU_RN; ++j) {
+    const int c = gp + 16 * j;
+    vw[j] = ga < Rn && c < Rr ? Vw[ga * Rr + c] : 0.0;
+  }
+  // the diagonal of A for entry e (the eigenvalue products plus w)
+  double den = 1.0;
+  if (own) {
+    int r = e;
+    double prod = 1.0;
+    for (int k = g.N - 1; k >= 1; --k) {
+      const int rk = r % g.R[k];
+      r /= g.R[k];
+      prod *= T.evals[k][rk];
+    }
+    den = prod + w;
+  }
+  if (own) z[e] = zq;
+  __syncthreads();
+  // vv[a] = sum_c V[a][c] v[c]: group a, lane p sums c = p, p + 16, ..., then a
+  // butterfly over the group's 16 lanes
+  auto v_times = [&](const double* v) {
+    if (ga < Rn) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < TU_RN; ++j) {
+        const int c = gp + 16 * j;
+        if (c < Rr) s = fma(vw[j], v[c], s);
+      }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+      if (gp == 0) vv[ga] = s;
+    }
+    __syncthreads();
+  };
+  v_times(z);
+  if (own) {
+    double sh = q1 + w * zq;
+#pragma unroll
+    for (int a = 0; a < TU_RN; ++a)
+      if (a < Rn) sh = fma(gt[a], vv[a], sh);
+    h[e] = sh;
+  }
+  __syncthreads();
+  // h <- A^-1 h: the mode products with V_k^T, the diagonal, the products with V_k
+  double* cur = h;
+  double* nxt = buf;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int k = 1; k < g.N; ++k) {
+      const int Rk = g.R[k];
+      const int post = (int)g.rsuf[k + 1];
+      const double* V = Vs + voff[k];
+      if (own) {
+        const int blk = e / (Rk * post), rem = e - blk * Rk * post, a = rem / post, c = rem - a * post;
+        const double* src = cur + blk * Rk * post + c;
+        double acc = 0.0;
+        for (int b = 0; b < Rk; ++b) acc = fma(pass == 0 ? V[b * Rk + a] : V[a * Rk + b], src[b * post], acc);
+        nxt[e] = acc;
+      }
+      __syncthreads();
+      double* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    if (pass == 0) {
+      if (own) cur[e] /= den;
+      __syncthreads();
+    }
+  }
+  const double he = own ? cur[e] : 0.0;
+  v_times(cur);
+  for (int a = threadIdx.x; a < Rn; a += blockDim.x) {
+    double sa = 0.0;
+    for (int b = 0; b < Rn; ++b) sa = fma(Cs[a * Rn + b], vv[b], sa);
+    uu[a] = sa;
+  }
+  __syncthreads();
+  double dd = 0.0, zz = 0.0;
+  if (own) {
+    double d = he;
+#pragma unroll
+    for (int a = 0; a < TU_RN; ++a)
+      if (a < Rn) d = fma(-au[a], uu[a], d);
+    const double zn = fma(-eta, d, zq);
+    Z[(size_t)i * Rr + e] = zn;
+    dd = d * d;
+    zz = zn * zn;
+  }
+  dd = block_sum(dd, red);
+  zz = block_sum(zz, red);
+  if (threadIdx.x == 0)
+    tucker_row_stop(i, dd, zz, eta, tol, it, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, ndone, diverged);
 }
 
 // After each update launch: iteration count and the all-done flag.
