@@ -466,7 +466,8 @@ def als_stream(sweep, step):
 
 
 def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, handle=None, tol=1e-12,
-               factor_update="sketched", core_update="sketched", stats=None, max_iter=400):
+               factor_update="sketched", core_update="sketched", stats=None, max_iter=400, core_precision="f64",
+               core_tol=None):
     """Algorithm 1 (TuckerALS) driven through the C ABI: for every sweep, the factor
     updates in mode order, then the core update, then the relative reconstruction
     error ||X^ - X||^2 / ||X||^2 from kron_loss.
@@ -474,7 +475,12 @@ def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, han
     factor_update: "sketched" (Algorithm 3, tucker_factor_update with m_factor
     samples per row) or "exact" (tucker_factor_exact, the ALS baseline);
     core_update: "sketched" (Algorithm 2, kron_ridge with b = vec(X) and m_core
-    samples) or "exact" (kron_exact).  Every update's status is checked: one that
+    samples) or "exact" (kron_exact); core_precision is the sketched core update's
+    kron_ridge precision ("f64", or a refined "f32", "bf16", "fp8": float64 residual
+    and update around a low-precision preconditioner) and core_tol its stopping
+    tolerance (default: tol in float64, 1e-6 in the refined precisions: their
+    float32 adjoint puts a floor under the relative step, about 3e-7 on a poorly
+    fitted early sweep).  Every update's status is checked: one that
     does not end in OK raises KronRegressError.  stats, if a list, receives one
     dict per update (sweep, step, iterations, distinct rows, status).  X, G and the
     factors are CUDA tensors (G and the factors float64); returns (G, As, [rre per
@@ -483,6 +489,7 @@ def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, han
     if factor_update not in ("sketched", "exact") or core_update not in ("sketched", "exact"):
         raise ValueError("factor_update and core_update are 'sketched' or 'exact'")
     h = handle or default_handle()
+    ctol = core_tol if core_tol is not None else (tol if core_precision == "f64" else max(tol, 1e-6))
     As = [A.clone() for A in As]
     G = G.clone()
     N = len(As)
@@ -511,7 +518,7 @@ def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, han
             g = kron_exact(As, Xv, lam, handle=h)
         else:
             g, info = kron_ridge(As, Xv, lam, eps=eps, m=m_core, seed=seed, stream=als_stream(s, N), handle=h,
-                                 tol=tol, max_iter=max_iter)
+                                 tol=ctol, max_iter=max_iter, precision=core_precision)
             record(s, N, info)
         G = g.reshape(G.shape)
         trace.append(kron_loss(As, Xv, g, 0.0, handle=h)[0] / xx)

@@ -181,6 +181,37 @@ def test_als_matches_oracle_small(gpu_lib):
         assert rel_l2(a.cpu().numpy(), b) < 1e-7
 
 
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_als_refined_core_small(gpu_lib, prec):
+    """Two sketched ALS sweeps with the core update in a refined precision (float64
+    residual and update around a bf16 or float32 preconditioner) against the
+    oracle's sketched ALS.  The float32 adjoint of the refined precisions puts a
+    floor of about 3e-7 under the core solve's relative step here (the first
+    sweep's fit is poor, so the adjoint's terms cancel heavily), so the core stops
+    at 1e-6 (the refined default) and the trajectory agrees to that tolerance's
+    effect."""
+    import torch
+    from oracle.tucker import tucker_als
+    print("case ALS small, core", prec, flush=True)
+    rng = np.random.default_rng(41)
+    I, R = (24, 20, 18), (3, 3, 2)
+    Qs = [np.linalg.qr(rng.standard_normal((i, r)))[0] for i, r in zip(I, R)]
+    X = tucker_reconstruct(rng.standard_normal(R), Qs) + 0.01 * rng.standard_normal(I)
+    G0 = rng.standard_normal(R)
+    A0 = [rng.standard_normal((i, r)) for i, r in zip(I, R)]
+    lam, eps, mc, mf = 1e-3, 0.1, 3000, 400
+    Go, Ao, to = tucker_als(X, G0, A0, lam, 2, sketched=True, eps=eps, m_factor=mf, m_core=mc, seed=0)
+    stats = []
+    Gg, Ag, tg = gpu_lib.tucker_als(torch.tensor(X, device="cuda"), torch.tensor(G0, device="cuda"),
+                                    [torch.tensor(A, device="cuda") for A in A0], lam, 2, eps=eps,
+                                    m_core=mc, m_factor=mf, seed=0, core_precision=prec, stats=stats)
+    print("rre oracle", to, "gpu", tg, "core iterations", [s["iters"] for s in stats if s["step"] == 3], flush=True)
+    np.testing.assert_allclose(tg, to, rtol=1e-5)
+    assert rel_l2(Gg.cpu().numpy(), Go) < 2e-5
+    for a, b in zip(Ag, Ao):
+        assert rel_l2(a.cpu().numpy(), b) < 2e-5
+
+
 def test_exact_als_400_trajectory(gpu_lib):
     """Exact ALS (exact factor and core updates, lambda = 1e-3) on the 400^3 tensor
     the benchmark decomposes: the relative reconstruction error after each of 10
