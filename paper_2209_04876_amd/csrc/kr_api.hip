@@ -763,13 +763,20 @@ static int64_t part_blocks(const Geom& g) {
 // Workspace of one solve.  lean: the batched team's layout, which never forms
 // the level-(N-1) products (N >= 3) nor the single-problem iteration's row and
 // partial-sum buffers.
+// Words of the sort's histogram buffer for nblocks key tiles: SORT_DIGITS_MAX
+// counts per tile, then the tile totals of the many-workgroup scan.
+static size_t hist_words(int64_t nblocks) {
+  const size_t nh = (size_t)SORT_DIGITS_MAX * nblocks;
+  return nh + (nh + SCANP_TILE - 1) / SCANP_TILE + 16;
+}
+
 // Tiles of the tree kernels over m sorted keys (tiletot holds KR_MAXN + 1 counts
 // per tile).
 static int tree_tiles(int64_t m) { return (int)((m + TREE_TILE - 1) / TREE_TILE); }
 
 static size_t solve_bytes(const Geom& g, int ntiles, int nblocks, bool lean = false) {
   size_t b = setup_bytes(g);
-  b += 2 * 8 * (size_t)g.m + 4 * SORT_DIGITS_MAX * (size_t)nblocks + 8 * (size_t)ntiles * (KR_MAXN + 1);
+  b += 2 * 8 * (size_t)g.m + 4 * hist_words(nblocks) + 8 * (size_t)ntiles * (KR_MAXN + 1);
   const int64_t D = level_cap(g, g.N);
   b += (size_t)D * (8 + 8 * g.nrhs + 4);
   for (int k = 1; k <= g.N; ++k) b += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
@@ -798,21 +805,31 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
   const int64_t m = g.m;
   uint64_t* kin = keys;
   uint64_t* kout = keys_alt;
-  // The histogram scan is one workgroup, so the wider digit is taken only while
-  // its scan stays small.  Measured: at 340k keys (27-bit) three 9-bit passes
-  // beat four 8-bit ones by ~1.5% of the whole solve (three fewer launch
-  // triples), although the kernels alone take about as long; at 5.7M keys the
-  // doubled scan cost more than the pass it saved.
-  const int rb = ((g.keybits + 8) / 9 < (g.keybits + 7) / 8 && (int64_t)512 * nblocks <= (1 << 16)) ? 9 : 8;
+  // 9-bit digits when they take fewer passes over g.keybits than 8-bit ones.
+  // Measured: at 340k keys (27-bit) three 9-bit passes beat four 8-bit ones by
+  // ~1.5% of the whole solve (three fewer launch triples), although the kernels
+  // alone take about as long.  The histogram scan is one workgroup while it is
+  // one tile, else many (k_scan_part, k_scan_tiles).
+  const int rb = (g.keybits + 8) / 9 < (g.keybits + 7) / 8 ? 9 : 8;
+  uint32_t* part = hist + (size_t)SORT_DIGITS_MAX * nblocks;
+  auto scan = [&](int64_t nh) {
+    if (nh <= 1024 * SCAN_K) {
+      KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, nh);
+    } else {
+      const int nt = (int)((nh + SCANP_TILE - 1) / SCANP_TILE);
+      KL(h, k_scan_part, dim3(nt), dim3(SCANP_THREADS), 0, s, (const uint32_t*)hist, nh, part);
+      KL(h, k_scan_tiles, dim3(nt), dim3(SCANP_THREADS), 0, s, hist, nh, (const uint32_t*)part);
+    }
+  };
   for (int sh = 0; sh < g.keybits; sh += rb) {
     if (rb == 9) {
       KLN(h, "k_radix_hist", k_radix_hist<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
-      KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)512 * nblocks);
+      scan((int64_t)512 * nblocks);
       KLN(h, "k_radix_scatter", k_radix_scatter<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist,
           nblocks);
     } else {
       KLN(h, "k_radix_hist", k_radix_hist<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
-      KL(h, k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks);
+      scan((int64_t)256 * nblocks);
       KLN(h, "k_radix_scatter", k_radix_scatter<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist,
           nblocks);
     }
@@ -1122,7 +1139,7 @@ static void carve_solve(Arena& a, const Geom& g, bool f32rows, void* d_x, ModeTa
   carve_setup(a, g, T, &B->s);
   B->keys = a.take<uint64_t>(m);
   B->keys_alt = a.take<uint64_t>(m);
-  B->hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
+  B->hist = a.take<uint32_t>(hist_words(nblocks));
   B->tiletot = a.take<int64_t>((size_t)tree_tiles(m) * (KR_MAXN + 1));
   for (int k = 1; k <= g.N; ++k) {
     const int64_t c = level_cap(g, k);
@@ -2659,7 +2676,7 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   const int nblocks = (int)((m + SORT_TILE - 1) / SORT_TILE);
 
   // workspace
-  size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * SORT_DIGITS_MAX * (size_t)nblocks +
+  size_t need = setup_bytes(go) + 2 * 8 * (size_t)m + 4 * hist_words(nblocks) +
                 8 * (size_t)tree_tiles(m) * (KR_MAXN + 1) + 4096;
   const int64_t Dcap = level_cap(g, g.N);
   for (int k = 1; k <= g.N; ++k) need += 3 * 4 * (size_t)(level_cap(g, k) + 2) + 8 * (size_t)level_cap(g, k) * g.R[k - 1] + 1024;
@@ -2675,7 +2692,7 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   carve_setup(a, go, &To, &S);
   uint64_t* keys = a.take<uint64_t>(m);
   uint64_t* keys_alt = a.take<uint64_t>(m);
-  uint32_t* hist = a.take<uint32_t>((size_t)SORT_DIGITS_MAX * nblocks);
+  uint32_t* hist = a.take<uint32_t>(hist_words(nblocks));
   int64_t* tiletot = a.take<int64_t>((size_t)tree_tiles(m) * (KR_MAXN + 1));
   Tree tr{};
   for (int k = 1; k <= g.N; ++k) {

@@ -160,75 +160,133 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __r
   for (int d = threadIdx.x; d < NB; d += SORT_THREADS) hist[(size_t)d * nblocks + blockIdx.x] = cnt[d];
 }
 
-// Exclusive scan of n uint32 values in place, one workgroup of 1024 threads, in
-// tiles of 1024 SCAN_K entries: each thread loads its SCAN_K consecutive entries
-// with 16-byte loads and scans them in registers, the thread totals are scanned
-// inside each wave by shuffles and the 16 wave totals are read by every thread
-// (two workgroup barriers per tile); a running carry links the tiles.  The
-// histogram scans of the sort (512 x 84 entries at 340k keys) take one tile.
+// Exclusive scan of n uint32 values in place, in tiles of NT SCAN_K entries:
+// each thread loads its SCAN_K consecutive entries with 16-byte loads and scans
+// them in registers, the thread totals are scanned inside each wave by shuffles
+// and the NT / 64 wave totals are read by every thread (two workgroup barriers
+// per tile).  scan_tile scans the tile at t0 on top of carry and returns the
+// tile's total.
 #define SCAN_K 48
+template <int NT>
+__device__ __forceinline__ uint32_t scan_tile(uint32_t* __restrict__ v, int64_t n, int64_t t0, uint32_t carry,
+                                              uint32_t* wsum) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c0 = t0 + (int64_t)threadIdx.x * SCAN_K;
+  const bool full = c0 + SCAN_K <= n;   // v is 16-byte aligned and c0 a multiple of 4
+  uint32_t x[SCAN_K];
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < SCAN_K / 4; ++q) {
+      const uint4 u = reinterpret_cast<const uint4*>(v + c0)[q];
+      x[4 * q] = u.x;
+      x[4 * q + 1] = u.y;
+      x[4 * q + 2] = u.z;
+      x[4 * q + 3] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_K; ++j) x[j] = c0 + j < n ? v[c0 + j] : 0u;
+  }
+  uint32_t tot = 0u;
+#pragma unroll
+  for (int j = 0; j < SCAN_K; ++j) {
+    const uint32_t t = x[j];
+    x[j] = tot;
+    tot += t;
+  }
+  uint32_t inc = tot;   // inclusive scan of the thread totals within the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t up = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += up;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  uint32_t before = 0u, total = 0u;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const uint32_t t = wsum[i];
+    before += i < wv ? t : 0u;
+    total += t;
+  }
+  const uint32_t base = carry + before + inc - tot;
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < SCAN_K / 4; ++q) {
+      uint4 u;
+      u.x = base + x[4 * q];
+      u.y = base + x[4 * q + 1];
+      u.z = base + x[4 * q + 2];
+      u.w = base + x[4 * q + 3];
+      reinterpret_cast<uint4*>(v + c0)[q] = u;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_K; ++j)
+      if (c0 + j < n) v[c0 + j] = base + x[j];
+  }
+  __syncthreads();   // wsum is rewritten by the next tile
+  return total;
+}
+
+// One workgroup of 1024 threads over all tiles, a running carry linking them.
+// The histogram scans of the sort at 340k keys (512 x 84 entries) take one tile.
 __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* __restrict__ v, int64_t n) {
   __shared__ uint32_t wsum[16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t carry = 0u;
-  for (int64_t t0 = 0; t0 < n; t0 += 1024 * SCAN_K) {
-    const int64_t c0 = t0 + (int64_t)threadIdx.x * SCAN_K;
-    const bool full = c0 + SCAN_K <= n;   // v is 16-byte aligned and c0 a multiple of 4
-    uint32_t x[SCAN_K];
-    if (full) {
+  for (int64_t t0 = 0; t0 < n; t0 += 1024 * SCAN_K) carry += scan_tile<1024>(v, n, t0, carry, wsum);
+}
+
+// Longer scans over many workgroups, one tile of SCANP_THREADS SCAN_K entries
+// each: k_scan_part writes the tiles' totals, k_scan_tiles scans every tile on
+// top of the sum of the totals before it (integer sums: the same result as one
+// workgroup's running carry).
+#define SCANP_THREADS 256
+#define SCANP_TILE (SCANP_THREADS * SCAN_K)
+__global__ void __launch_bounds__(SCANP_THREADS) k_scan_part(const uint32_t* __restrict__ v, int64_t n,
+                                                            uint32_t* __restrict__ part) {
+  __shared__ uint32_t wsum[SCANP_THREADS / 64];
+  const int64_t c0 = (int64_t)blockIdx.x * SCANP_TILE + (int64_t)threadIdx.x * SCAN_K;
+  uint32_t tot = 0u;
+  if (c0 + SCAN_K <= n) {
 #pragma unroll
-      for (int q = 0; q < SCAN_K / 4; ++q) {
-        const uint4 u = reinterpret_cast<const uint4*>(v + c0)[q];
-        x[4 * q] = u.x;
-        x[4 * q + 1] = u.y;
-        x[4 * q + 2] = u.z;
-        x[4 * q + 3] = u.w;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < SCAN_K; ++j) x[j] = c0 + j < n ? v[c0 + j] : 0u;
+    for (int q = 0; q < SCAN_K / 4; ++q) {
+      const uint4 u = reinterpret_cast<const uint4*>(v + c0)[q];
+      tot += u.x + u.y + u.z + u.w;
     }
-    uint32_t tot = 0u;
-#pragma unroll
-    for (int j = 0; j < SCAN_K; ++j) {
-      const uint32_t t = x[j];
-      x[j] = tot;
-      tot += t;
-    }
-    uint32_t inc = tot;   // inclusive scan of the thread totals within the wave
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t up = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += up;
-    }
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    uint32_t before = 0u, total = 0u;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const uint32_t t = wsum[i];
-      before += i < wv ? t : 0u;
-      total += t;
-    }
-    const uint32_t base = carry + before + inc - tot;
-    if (full) {
-#pragma unroll
-      for (int q = 0; q < SCAN_K / 4; ++q) {
-        uint4 u;
-        u.x = base + x[4 * q];
-        u.y = base + x[4 * q + 1];
-        u.z = base + x[4 * q + 2];
-        u.w = base + x[4 * q + 3];
-        reinterpret_cast<uint4*>(v + c0)[q] = u;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < SCAN_K; ++j)
-        if (c0 + j < n) v[c0 + j] = base + x[j];
-    }
-    carry += total;
-    __syncthreads();   // wsum is rewritten by the next tile
+  } else {
+    for (int j = 0; j < SCAN_K; ++j) tot += c0 + j < n ? v[c0 + j] : 0u;
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0u;
+    for (int i = 0; i < SCANP_THREADS / 64; ++i) t += wsum[i];
+    part[blockIdx.x] = t;
+  }
+}
+__global__ void __launch_bounds__(SCANP_THREADS) k_scan_tiles(uint32_t* __restrict__ v, int64_t n,
+                                                             const uint32_t* __restrict__ part) {
+  __shared__ uint32_t wsum[SCANP_THREADS / 64];
+  __shared__ uint32_t carry_s;
+  uint32_t c = 0u;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += SCANP_THREADS) c += part[b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0u;
+    for (int i = 0; i < SCANP_THREADS / 64; ++i) t += wsum[i];
+    carry_s = t;
+  }
+  __syncthreads();
+  const uint32_t carry = carry_s;
+  __syncthreads();   // wsum is reused by the tile scan
+  scan_tile<SCANP_THREADS>(v, n, (int64_t)blockIdx.x * SCANP_TILE, carry, wsum);
 }
 
 // Stable scatter.  The tile is processed in rounds of SORT_THREADS consecutive
