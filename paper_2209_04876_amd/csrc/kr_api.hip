@@ -935,6 +935,11 @@ static bool launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
     }
 #undef KR_ROWS_LAUNCH
     for (int k = g.N - 1; k >= 2; --k) {
+      if (!f32 && g.R[k - 1] <= 16) {
+        const int64_t tasks = tr.ncnt[k - 1] * ((g.rsuf[k] * g.nrhs + 15) / 16);
+        KL(h, k_adj_level_mfma, dim3((unsigned)tasks), dim3(256), 0, s, g, tr, k, (const double*)Q[k], (double*)Q[k - 1]);
+        continue;
+      }
       const int64_t CE = adj_cols((int)g.R[k - 1]);
       const int64_t tasks = tr.ncnt[k - 1] * ((g.rsuf[k] * g.nrhs + CE - 1) / CE);
       KLN(h, f32 ? "k_adj_level<f32>" : "k_adj_level", k_adj_level<T>, dim3(grid_for(tasks, 1, 2048)), dim3(ADJ_THREADS), 0,

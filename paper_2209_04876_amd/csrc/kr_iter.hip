@@ -843,6 +843,66 @@ __global__ void __launch_bounds__(ADJ_THREADS) k_adj_level(ModeTables TT, Geom g
   }
 }
 
+// Adjoint level k on v_mfma_f64_16x16x4 for R_{k-1} <= 16 (float64): one
+// workgroup of 4 waves per (parent p, block of 16 columns), Q_{k-1}[p][r][c] =
+// sum over the children s of p of a_{k-1}[i(s)][r] Q_k[s][c], an (R x children)
+// (children x 16) product taken four children per matrix step.  Wave w takes the
+// steps w, w + 4, ... (two per trip, their loads issued together); the waves'
+// 16 x 16 accumulators are added in wave order through LDS.  Rows r >= R and
+// columns c >= W are zero padding.  Against the one-workgroup-per-task VALU
+// kernel this moves the contraction onto the matrix cores and shortens each
+// task's chain of LDS staging steps.
+typedef double it_f64x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_adj_level_mfma(Geom g, Tree tr, int k, const double* __restrict__ Qk,
+                                                        double* __restrict__ Qout) {
+  __shared__ double accs[3][4][64];
+  const int Rk = g.R[k - 1];
+  const int64_t W = g.rsuf[k] * g.nrhs;
+  const int64_t ncb = (W + 15) / 16;
+  const int64_t p = blockIdx.x / ncb;
+  const int64_t c0 = (blockIdx.x - p * ncb) * 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t s0 = tr.fchild[k - 1][p], s1 = tr.fchild[k - 1][p + 1];
+  const double* __restrict__ arow = tr.arow[k];
+  const int64_t cq = c0 + col;
+  const bool rok = col < Rk, cok = cq < W;
+  it_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  int64_t sb = s0 + 4 * w;
+  for (; sb + 20 <= s1; sb += 32) {   // steps sb and sb + 16, all four children present
+    const int64_t sa = sb + kq, sc = sb + 16 + kq;
+    const double a0 = rok ? arow[sa * Rk + col] : 0.0;
+    const double b0 = cok ? Qk[sa * W + cq] : 0.0;
+    const double a1 = rok ? arow[sc * Rk + col] : 0.0;
+    const double b1 = cok ? Qk[sc * W + cq] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
+  }
+  for (; sb < s1; sb += 16) {
+    const int64_t sl = sb + kq;
+    const double a = (sl < s1 && rok) ? arow[sl * Rk + col] : 0.0;
+    const double b = (sl < s1 && cok) ? Qk[sl * W + cq] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) accs[w - 1][u][lane] = acc[u];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += accs[q][u][lane];
+    double* __restrict__ Qo = Qout + p * Rk * W;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = kq + 4 * u;
+      if (r < Rk && cok) Qo[(int64_t)r * W + cq] = acc[u];
+    }
+  }
+}
+
 // Root adjoint, split over blocks of npb level-1 nodes (npb a multiple of
 // RA_NODES): partial[b][r0][c] = sum_{s in block b} a_0[i(s)][r0] Q_1[s][c].
 template <typename T>
