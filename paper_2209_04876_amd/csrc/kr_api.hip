@@ -899,6 +899,9 @@ static bool launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
   {
     // forward levels 1..N-2; the rows kernel forms level N-1 itself
     for (int k = 1; k < g.N - 1; ++k) {
+      // segment roots whose level-1 nodes are the segments in order: P_1 is the
+      // iterate itself (the caller passes it as P[1])
+      if (k == 1 && g.seg_root && P[1] == P[0]) continue;
       const int64_t work = tr.ncnt[k] * g.rsuf[k] * g.nrhs;
       KL(h, k_fwd_level, dim3(grid_for(work, 256, 2048)), dim3(256), 0, s, TT, g, tr, k, (const double*)P[k - 1],
          P[k], state);
@@ -2760,6 +2763,9 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   for (int k = 0; k <= KR_MAXN; ++k) tr.ncnt[k] = (int64_t)h->h_small[8 + k];
+  // every row drawn (level-1 node s is row s): the forward level 1, a copy of the
+  // rows' iterates, is Z itself
+  if (g.N >= 3 && tr.ncnt[1] == In) P[1] = Z;
   // the rows' own factor rows are materialised only when the rows kernel does not
   // read them from the LDS-staged factor
   KL(h, k_node_rows, dim3(grid_for(Dcap * g.R[g.N - 1], 256, 2048)), dim3(256), 0, s, T, g, tr,
