@@ -502,7 +502,10 @@ __global__ void __launch_bounds__(KR_LANE_TPB) __attribute__((amdgpu_waves_per_e
   };
   const unsigned nrhs8 = (unsigned)nrhs * 8u;
   fetch(blockIdx.x * wpb + w);
-  for (int64_t task = blockIdx.x * wpb + w; task < ntask; task += tstride) {
+  for (int64_t task_v = blockIdx.x * wpb + w; task_v < ntask; task_v += tstride) {
+    // the task index in scalar registers (tasks number below 2^31), so that the
+    // node's addresses are formed by scalar arithmetic
+    const int64_t task = __builtin_amdgcn_readfirstlane((int)task_v);
     const int64_t p = node_of(task);
     const int q = (int)(task - p * nrhs);
     // the bounds and parent are wave-uniform: in scalar registers they make the
