@@ -763,6 +763,12 @@ static int64_t part_blocks(const Geom& g) {
 // Workspace of one solve.  lean: the batched team's layout, which never forms
 // the level-(N-1) products (N >= 3) nor the single-problem iteration's row and
 // partial-sum buffers.
+// Key tiles up to which each scatter workgroup forms its own offsets from the
+// raw histogram (reading all of it) instead of a scan launch.
+#ifndef SORT_OWN_SCAN_TILES
+#define SORT_OWN_SCAN_TILES 128
+#endif
+
 // Words of the sort's histogram buffer for nblocks key tiles: SORT_DIGITS_MAX
 // counts per tile, then the tile totals of the many-workgroup scan.
 static size_t hist_words(int64_t nblocks) {
@@ -821,12 +827,23 @@ static void launch_sort_tree(kr_handle h, const Geom& g, uint64_t* keys, uint64_
       KL(h, k_scan_tiles, dim3(nt), dim3(SCANP_THREADS), 0, s, hist, nh, (const uint32_t*)part);
     }
   };
+  // With few tiles every scatter workgroup reads the whole histogram and forms
+  // its own offsets, in place of a scan launch.
+  const bool own = nblocks <= SORT_OWN_SCAN_TILES;
   for (int sh = 0; sh < g.keybits; sh += rb) {
-    if (rb == 9) {
+    if (rb == 9 && own) {
+      KLN(h, "k_radix_hist", (k_radix_hist<9, true>), dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
+      KLN(h, "k_radix_scatter", (k_radix_scatter<9, true>), dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh,
+          hist, nblocks);
+    } else if (rb == 9) {
       KLN(h, "k_radix_hist", k_radix_hist<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
       scan((int64_t)512 * nblocks);
       KLN(h, "k_radix_scatter", k_radix_scatter<9>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh, hist,
           nblocks);
+    } else if (own) {
+      KLN(h, "k_radix_hist", (k_radix_hist<8, true>), dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
+      KLN(h, "k_radix_scatter", (k_radix_scatter<8, true>), dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, kout, m, sh,
+          hist, nblocks);
     } else {
       KLN(h, "k_radix_hist", k_radix_hist<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, kin, m, sh, hist, nblocks);
       scan((int64_t)256 * nblocks);

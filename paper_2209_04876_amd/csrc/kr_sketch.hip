@@ -142,7 +142,9 @@ __global__ void __launch_bounds__(256) k_sample_batched(const SampleJob* __restr
 // bits instead of four of 8).  hist is digit-major: hist[d * nblocks + b], with
 // room for SORT_DIGITS_MAX digits.
 // ---------------------------------------------------------------------------
-template <int RB>
+// BMAJ: the counts are stored tile-major (hist[tile NB + digit]) for the scatter
+// that forms its own offsets; else digit-major, the order of the global scan.
+template <int RB, bool BMAJ = false>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
                                                             int shift, uint32_t* __restrict__ hist,
                                                             int nblocks) {
@@ -157,7 +159,8 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint64_t* __r
     if (t < m) atomicAdd(&cnt[(keys[t] >> shift) & (uint64_t)(NB - 1)], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < NB; d += SORT_THREADS) hist[(size_t)d * nblocks + blockIdx.x] = cnt[d];
+  for (int d = threadIdx.x; d < NB; d += SORT_THREADS)
+    hist[BMAJ ? (size_t)blockIdx.x * NB + d : (size_t)d * nblocks + blockIdx.x] = cnt[d];
 }
 
 // Exclusive scan of n uint32 values in place, in tiles of NT SCAN_K entries:
@@ -293,7 +296,13 @@ __global__ void __launch_bounds__(SCANP_THREADS) k_scan_tiles(uint32_t* __restri
 // keys; in a round, a key's rank among equal digits is (earlier waves' counts) +
 // (earlier lanes in its wave with the same digit, found by ballot matching over
 // the RB + 1 bits of the digit, NB marking an absent key).
-template <int RB>
+// OWN: hist holds the raw per-tile counts, tile-major, and every workgroup forms
+// its own offsets (used for few tiles, where reading the whole histogram per
+// workgroup costs less than a separate scan launch): thread t owns the digits
+// d = t NB / SORT_THREADS + i, sums each digit's counts over all tiles and over
+// the tiles before its own (one coalesced read of a tile's row per step), and an
+// exclusive scan of the digit totals across the workgroup adds the digits before d.
+template <int RB, bool OWN = false>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t* __restrict__ in,
                                                                uint64_t* __restrict__ out, int64_t m,
                                                                int shift, const uint32_t* __restrict__ hist,
@@ -303,9 +312,55 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint64_t* 
   __shared__ uint32_t base_[NB];
   __shared__ uint32_t wcnt[NW][NB + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < NB; d += SORT_THREADS) {
-    base_[d] = hist[(size_t)d * nblocks + blockIdx.x];
-    for (int k = 0; k < NW; ++k) wcnt[k][d] = 0;
+  if constexpr (OWN) {
+    constexpr int DPT = NB / SORT_THREADS;   // digits per thread
+    uint32_t tot[DPT], bef[DPT], sum = 0u;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) tot[i] = bef[i] = 0u;
+    const uint32_t* __restrict__ col = hist + threadIdx.x * DPT;
+#pragma unroll 4
+    for (int k = 0; k < nblocks; ++k) {
+      uint32_t c[DPT];
+      if constexpr (DPT == 2) {
+        const uint2 v = *reinterpret_cast<const uint2*>(col + (size_t)k * NB);
+        c[0] = v.x;
+        c[1] = v.y;
+      } else {
+#pragma unroll
+        for (int i = 0; i < DPT; ++i) c[i] = col[(size_t)k * NB + i];
+      }
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) {
+        tot[i] += c[i];
+        bef[i] += k < (int)blockIdx.x ? c[i] : 0u;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) sum += tot[i];
+    // exclusive scan of the threads' digit totals: within the wave, then the waves
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t up = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += up;
+    }
+    if (lane == 63) wcnt[w][0] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int k = 0; k < w; ++k) run += wcnt[k][0];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      base_[threadIdx.x * DPT + i] = run + bef[i];
+      run += tot[i];
+    }
+    for (int d = threadIdx.x; d < NB; d += SORT_THREADS)
+      for (int k = 0; k < NW; ++k) wcnt[k][d] = 0;
+  } else {
+    for (int d = threadIdx.x; d < NB; d += SORT_THREADS) {
+      base_[d] = hist[(size_t)d * nblocks + blockIdx.x];
+      for (int k = 0; k < NW; ++k) wcnt[k][d] = 0;
+    }
   }
   if (threadIdx.x < NW) wcnt[threadIdx.x][NB] = 0;
   __syncthreads();
