@@ -2766,11 +2766,14 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
     T.A[k] = To.A[k - 1]; T.V[k] = To.V[k - 1]; T.evals[k] = To.evals[k - 1]; T.Ginv[k] = To.Ginv[k - 1];
     T.lev[k] = To.lev[k - 1]; T.Q[k] = To.Q[k - 1]; T.C[k] = To.C[k - 1];
   }
-  KL(h, k_tucker_setup, dim3(1), dim3(256), 0, s, T, g, tg, (const double*)d_core, lambda, eps, Gn, GtP, Vw, wbuf,
-     S.flags);
+  // the row-independent matrices staged in LDS while one of them fits 32 KB
+  const int tstage = (int64_t)Rn * Rr <= 4096 ? 1 : 0;
+  KL(h, k_tucker_setup, dim3(1), dim3(256), tstage ? 8 * (size_t)Rn * Rr : 0, s, T, g, tg, (const double*)d_core,
+     lambda, eps, Gn, GtP, Vw, wbuf, S.flags, tstage);
   KL(h, k_tucker_ainvu, dim3(Rn), dim3(256), 2 * 8 * (size_t)Rr, s, T, g, tg, (const double*)GtP,
      (const double*)wbuf, AinvU);
-  KL(h, k_tucker_cinv, dim3(1), dim3(256), 0, s, tg, (const double*)Vw, (const double*)AinvU, Cinv, S.flags);
+  KL(h, k_tucker_cinv, dim3(1), dim3(256), tstage ? 2 * 8 * (size_t)Rn * Rr : 0, s, tg, (const double*)Vw,
+     (const double*)AinvU, Cinv, S.flags, tstage);
   KL(h, k_sample_rows, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, T, g, tg, o.seed, o.stream, keys);
   launch_sort_tree(h, g, keys, keys_alt, hist, tiletot, nblocks, tr);
   KL(h, k_rows_tucker, dim3(grid_for(Dcap, 256, 2048)), dim3(256), 0, s, T, g, tg, tr, p->b, p->b_dtype, Omega, bD,

@@ -132,14 +132,19 @@ __device__ void wg_apply_Ainv(const Geom& g, const ModeTables& T, double w, doub
 //   GtP  R_n x Rr   (G^T)^+ = (G G^T)^-1 G
 //   Vw   R_n x Rr   lam (G^T)^+ - w G
 //   *w_out          the penalty weight
+// stage: the unfolding is also kept in dynamic LDS (Rn Rr doubles) and read from
+// there by the products below, instead of from global memory inside their loops.
 __global__ void __launch_bounds__(256) k_tucker_setup(ModeTables T, Geom g, TuckerGeom tg, const double* __restrict__ core,
                                                      double lambda, double eps, double* __restrict__ Gn,
                                                      double* __restrict__ GtP, double* __restrict__ Vw,
-                                                     double* __restrict__ w_out, int32_t* __restrict__ flags) {
+                                                     double* __restrict__ w_out, int32_t* __restrict__ flags,
+                                                     int stage) {
   __shared__ double GG[64 * 64];
   __shared__ double Gi[64 * 64];
   __shared__ int piv;
   __shared__ double scl;
+  extern __shared__ double ts_dyn[];
+  const double* Gr = stage ? (const double*)ts_dyn : (const double*)Gn;
   const int Rn = tg.Rn, Rr = tg.Rr, Nx = tg.Nx, n = tg.mode;
   // core dims R_0..R_{Nx-1} of X order: tree mode k >= 1 carries X mode tmode[k]
   int Rx[KR_MAXN];
@@ -158,13 +163,15 @@ __global__ void __launch_bounds__(256) k_tucker_setup(ModeTables T, Geom g, Tuck
       lin += im * mul;
       mul *= Rx[m];
     }
-    Gn[e] = core[lin];
+    const double v = core[lin];
+    Gn[e] = v;
+    if (stage) ts_dyn[e] = v;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < Rn * Rn; e += blockDim.x) {
     const int a = e / Rn, b = e % Rn;
     double s = 0.0;
-    for (int c = 0; c < Rr; ++c) s = fma(Gn[a * Rr + c], Gn[b * Rr + c], s);
+    for (int c = 0; c < Rr; ++c) s = fma(Gr[a * Rr + c], Gr[b * Rr + c], s);
     GG[e] = s;
   }
   __syncthreads();
@@ -183,9 +190,9 @@ __global__ void __launch_bounds__(256) k_tucker_setup(ModeTables T, Geom g, Tuck
   for (int e = threadIdx.x; e < Rn * Rr; e += blockDim.x) {
     const int r = e / Rr, c = e - r * Rr;
     double s = 0.0;
-    for (int b = 0; b < Rn; ++b) s = fma(Gi[r * Rn + b], Gn[b * Rr + c], s);
+    for (int b = 0; b < Rn; ++b) s = fma(Gi[r * Rn + b], Gr[b * Rr + c], s);
     GtP[e] = s;
-    Vw[e] = lambda * s - w * Gn[e];
+    Vw[e] = lambda * s - w * Gr[e];
   }
 }
 
@@ -204,18 +211,32 @@ __global__ void __launch_bounds__(256) k_tucker_ainvu(ModeTables T, Geom g, Tuck
 }
 
 // Cinv = (I + V A^-1 U)^-1, R_n x R_n; one workgroup.
+// stage: Vw and AinvU are first copied to dynamic LDS (2 Rn Rr doubles) with
+// coalesced loads, and the product reads them there.
 __global__ void __launch_bounds__(256) k_tucker_cinv(TuckerGeom tg, const double* __restrict__ Vw,
                                                     const double* __restrict__ AinvU, double* __restrict__ Cinv,
-                                                    int32_t* __restrict__ flags) {
+                                                    int32_t* __restrict__ flags, int stage) {
   __shared__ double C[64 * 64];
   __shared__ double Ci[64 * 64];
   __shared__ int piv;
   __shared__ double scl;
+  extern __shared__ double tc_dyn[];
   const int Rn = tg.Rn, Rr = tg.Rr;
+  const double* Vr = Vw;
+  const double* Ar = AinvU;
+  if (stage) {
+    for (int e = threadIdx.x; e < Rn * Rr; e += blockDim.x) {
+      tc_dyn[e] = Vw[e];
+      tc_dyn[Rn * Rr + e] = AinvU[e];
+    }
+    __syncthreads();
+    Vr = tc_dyn;
+    Ar = tc_dyn + Rn * Rr;
+  }
   for (int e = threadIdx.x; e < Rn * Rn; e += blockDim.x) {
     const int a = e / Rn, b = e % Rn;
     double s = (a == b) ? 1.0 : 0.0;
-    for (int c = 0; c < Rr; ++c) s = fma(Vw[a * Rr + c], AinvU[c * Rn + b], s);
+    for (int c = 0; c < Rr; ++c) s = fma(Vr[a * Rr + c], Ar[c * Rn + b], s);
     C[e] = s;
   }
   __syncthreads();
