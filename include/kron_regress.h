@@ -304,6 +304,25 @@ kr_status tucker_factor_update(kr_handle h, const kr_problem* p, const void* d_c
 kr_status tucker_factor_exact(kr_handle h, const kr_problem* p, const void* d_core, int32_t mode,
                               double lambda, void* d_A_out);
 
+/* Algorithm 1 (TuckerALS) with the sketched updates, as one call: for each of
+ * `sweeps` sweeps, the factor updates of modes 0..N-1 by Algorithm 3
+ * (tucker_factor_update with *factor_opts, Philox stream (sweep << 8) | mode),
+ * then the core update by Algorithm 2 with b = vec(X) (kron_ridge with
+ * *core_opts, stream (sweep << 8) | N), then the relative reconstruction error
+ * ||K vec(G) - vec(X)||^2 / ||X||^2 (kron_loss with lambda = 0).  p->b is the
+ * tensor X (FP64 or FP32, row-major I_1..I_N, nrhs = 1); p->A[n] are float64
+ * device factors, overwritten in place by their updates (a_dtype must be F64);
+ * d_core (float64, row-major R_1..R_N) is read by the factor updates and
+ * overwritten by each core update.  The streams in the options are ignored.
+ * Host outputs (each may be NULL): h_rre[sweeps]; h_iters[sweeps (N + 1)], the
+ * iterations of each update in order; *h_failed_step, the index (sweep (N + 1) +
+ * step) of an update that did not end in KR_OK, else -1.  The call stops at such
+ * an update and returns its status (a positive status such as KR_WMAXITER
+ * included: the factors and core then hold that update's result). */
+kr_status kr_tucker_als(kr_handle h, const kr_problem* p, void* d_core, double lambda, double eps,
+                        double delta, int32_t sweeps, const kr_opts* factor_opts, const kr_opts* core_opts,
+                        double* h_rre, int32_t* h_iters, int32_t* h_failed_step);
+
 /* Test support: copy the last solve's sketch to host memory.  Any pointer may be
  * NULL.  h_Q: sum_n I_n uint64 integer weights (mode-major); h_rows: distinct
  * rows as per-mode indices, D x N int32 (sorted by linear row index); h_Omega: D

@@ -131,6 +131,8 @@ def load_library(path=LIB_PATH):
     lib.kron_loss_opt.argtypes = [c_p, P, c_d, c_p, ctypes.POINTER(c_d), ctypes.POINTER(c_d)]
     lib.tucker_factor_update.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_d, c_d, O, c_p, IN]
     lib.tucker_factor_exact.argtypes = [c_p, P, c_p, ctypes.c_int32, c_d, c_p]
+    lib.kr_tucker_als.argtypes = [c_p, P, c_p, c_d, c_d, c_d, ctypes.c_int32, O, O, ctypes.POINTER(c_d),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.kr_export_sketch.argtypes = [c_p, c_p, c_p, c_p, c_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.kr_export_batched_sketch.argtypes = [c_p, ctypes.c_int32, c_p, c_p, c_p, c_p, ctypes.c_int64,
                                              ctypes.POINTER(ctypes.c_int64)]
@@ -141,7 +143,7 @@ def load_library(path=LIB_PATH):
     lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
     for name in ("kr_batched_config", "kron_ridge_batched", "kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_ridge_noalloc", "kron_loss",
                  "kron_loss_opt", "kron_exact", "kr_export_sketch", "kr_export_batched_sketch", "kr_export_leverage",
-                 "tucker_factor_update", "tucker_factor_exact"):
+                 "tucker_factor_update", "tucker_factor_exact", "kr_tucker_als"):
         getattr(lib, name).restype = c_i
     _lib = lib
     return lib
@@ -523,6 +525,35 @@ def tucker_als(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, han
         G = g.reshape(G.shape)
         trace.append(kron_loss(As, Xv, g, 0.0, handle=h)[0] / xx)
     return G, As, trace
+
+
+def tucker_als_native(X, G, As, lam, sweeps, eps=0.1, m_core=0, m_factor=0, seed=0, handle=None, tol=1e-12,
+                      max_iter=400, core_precision="f64", core_tol=None, delta=0.01):
+    """Algorithm 1 with the sketched updates through kr_tucker_als: the same
+    updates, streams and order as tucker_als(factor_update="sketched",
+    core_update="sketched"), looped inside the library.  Returns (G, As, [rre per
+    sweep], [iterations per update]); raises KronRegressError at the first update
+    that does not end in OK."""
+    torch = _torch()
+    h = handle or default_handle()
+    As = [A.clone() for A in As]
+    G = G.clone()
+    if G.dtype != torch.float64 or any(A.dtype != torch.float64 for A in As):
+        raise ValueError("the core and the factors must be float64")
+    N = len(As)
+    p, _keep = _problem(As, X.reshape(-1))
+    ctol = core_tol if core_tol is not None else (tol if core_precision == "f64" else max(tol, 1e-6))
+    fo = _opts(m_factor, max_iter, tol, seed, 0, 8)
+    co = _opts(m_core, max_iter, ctol, seed, 0, 0, 0, 0, core_precision)
+    rre = (ctypes.c_double * max(1, sweeps))()
+    iters = (ctypes.c_int32 * max(1, sweeps * (N + 1)))()
+    failed = ctypes.c_int32(-1)
+    st = h.lib.kr_tucker_als(h.ptr, ctypes.byref(p), ctypes.c_void_p(G.data_ptr()), lam, eps, delta, sweeps,
+                             ctypes.byref(fo), ctypes.byref(co), rre, iters, ctypes.byref(failed))
+    h._check(st)
+    if st != KR_OK:
+        raise KronRegressError(st, "ALS update %d ended with status %s" % (failed.value, STATUS_NAMES.get(st, st)))
+    return G, As, [rre[s] for s in range(sweeps)], [iters[k] for k in range(sweeps * (N + 1))]
 
 
 def profile_enable(enable=True, kernel_filter="", handle=None):

@@ -64,6 +64,8 @@ struct kr_handle_s {
   size_t ws_bytes = 0;
   void* aux = nullptr;
   size_t aux_bytes = 0;
+  void* als_zero = nullptr;       // zero core of kr_tucker_als's ||X||^2
+  size_t als_zero_bytes = 0;
   IterState* h_state = nullptr;   // pinned
   int64_t* h_small = nullptr;     // pinned scratch (flags, counts)
   void* h_batch = nullptr;         // pinned staging of batched descriptors and results
@@ -341,6 +343,7 @@ kr_status kr_destroy(kr_handle h) {
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   if (h->ws) hipFree(h->ws);
   if (h->aux) hipFree(h->aux);
+  if (h->als_zero) hipFree(h->als_zero);
   if (h->h_state) hipHostFree(h->h_state);
   if (h->h_small) hipHostFree(h->h_small);
   if (h->h_batch) hipHostFree(h->h_batch);
@@ -2977,6 +2980,70 @@ kr_status tucker_factor_exact(kr_handle h, const kr_problem* p, const void* d_co
   const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
   if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in the factors");
   if (fl & KR_FLAG_CORE) KR_FAIL(h, KR_ESINGULAR, "G_(n) K^T K G_(n)^T + lambda I is singular");
+  return KR_OK;
+}
+
+
+// Algorithm 1 (TuckerALS) behind the boundary: per sweep the factor updates of
+// modes 0..N-1 (Algorithm 3) and the core update (Algorithm 2 with b = vec(X)),
+// then the relative reconstruction error.
+kr_status kr_tucker_als(kr_handle h, const kr_problem* p, void* d_core, double lambda, double eps, double delta,
+                        int32_t sweeps, const kr_opts* factor_opts, const kr_opts* core_opts, double* h_rre,
+                        int32_t* h_iters, int32_t* h_failed_step) {
+  if (!h) return KR_EINVAL;
+  if (h_failed_step) *h_failed_step = -1;
+  if (!p || !d_core || !factor_opts || !core_opts || sweeps < 0) KR_FAIL(h, KR_EINVAL, "NULL argument or sweeps < 0");
+  if (p->a_dtype != KR_F64) KR_FAIL(h, KR_EINVAL, "the factors are updated in place and must be float64");
+  for (int n = 0; n < p->N; ++n)
+    if (!p->A[n]) KR_FAIL(h, KR_EINVAL, "factor %d is NULL", n);
+  Geom g;
+  kr_status st = make_geom(h, p, &g);
+  if (st != KR_OK) return st;
+  // ||X||^2 = the loss of the zero core
+  const size_t zb = 8 * (size_t)g.Rtot;
+  if (h->als_zero_bytes < zb) {
+    if (h->als_zero) {
+      hipStreamSynchronize(h->stream);
+      hipFree(h->als_zero);
+      h->als_zero = nullptr;
+      h->als_zero_bytes = 0;
+    }
+    if (hipMalloc(&h->als_zero, zb) != hipSuccess) {
+      h->als_zero = nullptr;
+      KR_FAIL(h, KR_ENOMEM, "zero core of %zu bytes could not be allocated", zb);
+    }
+    h->als_zero_bytes = zb;
+  }
+  KL(h, k_fill, dim3(grid_for(g.Rtot, 256, 1024)), dim3(256), 0, h->stream, (double*)h->als_zero, g.Rtot, 0.0);
+  HIPCHK(h, hipGetLastError());
+  double xx = 0.0;
+  st = kron_loss(h, p, 0.0, h->als_zero, &xx);
+  if (st != KR_OK) return st;
+  if (!(xx > 0.0)) KR_FAIL(h, KR_EINVAL, "||X|| is zero or not finite");
+  kr_opts fo = *factor_opts, co = *core_opts;
+  const int N = p->N;
+  for (int s = 0; s < sweeps; ++s) {
+    for (int step = 0; step <= N; ++step) {
+      kr_info info{};
+      if (step < N) {
+        fo.stream = ((uint64_t)s << 8) | (uint64_t)step;
+        st = tucker_factor_update(h, p, d_core, step, lambda, eps, delta, &fo, const_cast<void*>(p->A[step]), &info);
+      } else {
+        co.stream = ((uint64_t)s << 8) | (uint64_t)N;
+        st = kron_ridge(h, p, lambda, eps, delta, &co, d_core, &info);
+      }
+      if (h_iters) h_iters[(size_t)s * (N + 1) + step] = info.iters;
+      if (st != KR_OK) {
+        if (h_failed_step) *h_failed_step = s * (N + 1) + step;
+        if (st > 0) KR_FAIL(h, st, "ALS sweep %d step %d ended with status %d", s, step, (int)st);
+        return st;
+      }
+    }
+    double l = 0.0;
+    st = kron_loss(h, p, 0.0, d_core, &l);
+    if (st != KR_OK) return st;
+    if (h_rre) h_rre[s] = l / xx;
+  }
   return KR_OK;
 }
 

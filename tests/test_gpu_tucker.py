@@ -181,6 +181,53 @@ def test_als_matches_oracle_small(gpu_lib):
         assert rel_l2(a.cpu().numpy(), b) < 1e-7
 
 
+def test_als_native_loop_matches_python_loop(gpu_lib):
+    """kr_tucker_als (Algorithm 1 looped inside the library) against tucker_als's
+    Python loop over the same C-ABI updates, on the small tensor: the same
+    updates, streams and order, so the factors, core, errors and iteration counts
+    are identical bit for bit; and both against the oracle's sketched ALS."""
+    import torch
+    from oracle.tucker import tucker_als
+    print("case ALS native loop", flush=True)
+    rng = np.random.default_rng(41)
+    I, R = (24, 20, 18), (3, 3, 2)
+    Qs = [np.linalg.qr(rng.standard_normal((i, r)))[0] for i, r in zip(I, R)]
+    X = tucker_reconstruct(rng.standard_normal(R), Qs) + 0.01 * rng.standard_normal(I)
+    G0 = rng.standard_normal(R)
+    A0 = [rng.standard_normal((i, r)) for i, r in zip(I, R)]
+    lam, eps, mc, mf = 1e-3, 0.1, 3000, 400
+    tX = torch.tensor(X, device="cuda")
+    tG = torch.tensor(G0, device="cuda")
+    tA = [torch.tensor(A, device="cuda") for A in A0]
+    stats = []
+    Gp, Ap, tp = gpu_lib.tucker_als(tX, tG, tA, lam, 2, eps=eps, m_core=mc, m_factor=mf, seed=0, stats=stats)
+    Gn, An, tn, iters = gpu_lib.tucker_als_native(tX, tG, tA, lam, 2, eps=eps, m_core=mc, m_factor=mf, seed=0)
+    print("rre python", tp, "native", tn, "iters", iters, flush=True)
+    assert tn == tp
+    assert iters == [st["iters"] for st in stats]
+    assert torch.equal(Gn, Gp)
+    for a, b in zip(An, Ap):
+        assert torch.equal(a, b)
+    Go, Ao, to = tucker_als(X, G0, A0, lam, 2, sketched=True, eps=eps, m_factor=mf, m_core=mc, seed=0)
+    np.testing.assert_allclose(tn, to, rtol=1e-7)
+    assert rel_l2(Gn.cpu().numpy(), Go) < 1e-7
+
+
+def test_als_native_loop_reports_a_failed_update(gpu_lib):
+    """Updates held to one Richardson iteration end in WMAXITER: the native loop
+    stops at the first one (sweep 0, the factor update of mode 0) and names it."""
+    import torch
+    from paper_2209_04876_amd import KronRegressError
+    print("case ALS native loop failure", flush=True)
+    rng = np.random.default_rng(5)
+    I, R = (12, 10, 9), (2, 2, 2)
+    X = torch.tensor(rng.standard_normal(I), device="cuda")
+    G0 = torch.tensor(rng.standard_normal(R), device="cuda")
+    A0 = [torch.tensor(rng.standard_normal((i, r)), device="cuda") for i, r in zip(I, R)]
+    with pytest.raises(KronRegressError, match="update 0 "):
+        gpu_lib.tucker_als_native(X, G0, A0, 1e-3, 1, m_core=500, m_factor=200, max_iter=1)
+
+
 @pytest.mark.parametrize("prec", ["bf16", "f32"])
 def test_als_refined_core_small(gpu_lib, prec):
     """Two sketched ALS sweeps with the core update in a refined precision (float64
