@@ -341,6 +341,14 @@ kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* 
  * rows).  KR_EINVAL for a problem outside the last call, or for a problem that
  * took the single-problem path (its sketch is not kept).  Valid until the
  * handle's next call. */
+/* Test support: the samples t = first .. first + count - 1 of the last single
+ * solve (kron_regress, kron_ridge, kron_ridge_noalloc), drawn again from its kept
+ * sampling tables with its seed and stream, before any merging: h_idx receives
+ * count x N int32 per-mode indices in sample order (row t - first holds
+ * (i_1(t), .., i_N(t))), the draws of Algorithm 2's sampling step.  KR_EINVAL
+ * when the last call was not a single solve or the range is outside [0, m). */
+kr_status kr_export_samples(kr_handle h, int64_t first, int64_t count, int32_t* h_idx);
+
 kr_status kr_export_batched_sketch(kr_handle h, int32_t problem, uint64_t* h_Q, int32_t* h_rows,
                                    double* h_Omega, int32_t* h_counts, int64_t cap, int64_t* h_D);
 

@@ -137,13 +137,14 @@ def load_library(path=LIB_PATH):
     lib.kr_export_batched_sketch.argtypes = [c_p, ctypes.c_int32, c_p, c_p, c_p, c_p, ctypes.c_int64,
                                              ctypes.POINTER(ctypes.c_int64)]
     lib.kr_export_leverage.argtypes = [c_p, ctypes.c_int32, c_p, ctypes.c_int64]
+    lib.kr_export_samples.argtypes = [c_p, ctypes.c_int64, ctypes.c_int64, c_p]
     lib.kr_profile_enable.argtypes = [c_p, ctypes.c_int32, ctypes.c_char_p]
     lib.kr_profile_query.argtypes = [c_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(c_d)]
     lib.kr_profile_list.argtypes = [c_p, ctypes.c_char_p, ctypes.c_int64]
     for name in ("kr_batched_config", "kron_ridge_batched", "kr_profile_list", "kr_profile_enable", "kr_profile_query", "kr_create", "kr_destroy", "kr_set_stream", "kron_regress", "kron_ridge", "kron_ridge_noalloc", "kron_loss",
                  "kron_loss_opt", "kron_exact", "kr_export_sketch", "kr_export_batched_sketch", "kr_export_leverage",
-                 "tucker_factor_update", "tucker_factor_exact", "kr_tucker_als"):
+                 "tucker_factor_update", "tucker_factor_exact", "kr_tucker_als", "kr_export_samples"):
         getattr(lib, name).restype = c_i
     _lib = lib
     return lib
@@ -604,6 +605,17 @@ def export_sketch(sizes, handle=None):
     """The last solve's sketch: Q tables per mode, distinct rows (D x N), Omega, counts."""
     h = handle or default_handle()
     return _export(lambda *a: h._check(h.lib.kr_export_sketch(h.ptr, *a)), sizes)
+
+
+def export_samples(first, count, N, handle=None):
+    """Samples first .. first + count - 1 of the last single solve, drawn again from
+    its kept tables before merging: an int32 (count, N) array of per-mode indices
+    in sample order."""
+    import numpy as np
+    h = handle or default_handle()
+    idx = np.zeros((int(count), int(N)), dtype=np.int32)
+    h._check(h.lib.kr_export_samples(h.ptr, int(first), int(count), idx.ctypes.data))
+    return idx
 
 
 def export_batched_sketch(problem, sizes, handle=None):

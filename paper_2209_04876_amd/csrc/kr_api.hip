@@ -53,6 +53,8 @@ struct SketchRec {
   Tree tr{};
   double* Omega = nullptr;
   int32_t* counts = nullptr;
+  bool redraw = false;          // drawn by k_sample with (seed, stream), row 0
+  uint64_t seed = 0, stream = 0;
 };
 
 }  // namespace
@@ -1463,6 +1465,9 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
   h->last.tr = tr;
   h->last.Omega = B.Omega;
   h->last.counts = B.counts;
+  h->last.redraw = true;
+  h->last.seed = o.seed;
+  h->last.stream = o.stream;
   return result;
 }
 
@@ -2224,6 +2229,34 @@ kr_status kr_export_sketch(kr_handle h, uint64_t* h_Q, int32_t* h_rows, double* 
   return export_rec(h, h->last, h_Q, h_rows, h_Omega, h_counts, cap, h_D);
 }
 
+kr_status kr_export_samples(kr_handle h, int64_t first, int64_t count, int32_t* h_idx) {
+  if (!h) return KR_EINVAL;
+  const SketchRec& r = h->last;
+  if (!r.valid || !r.redraw) KR_FAIL(h, KR_EINVAL, "no single-solve sketch to redraw");
+  const Geom& g = r.g;
+  if (!h_idx || first < 0 || count < 0 || first + count > g.m)
+    KR_FAIL(h, KR_EINVAL, "samples [%lld, %lld) outside [0, %lld) or h_idx NULL", (long long)first,
+            (long long)(first + count), (long long)g.m);
+  if (count == 0) return KR_OK;
+  // the sampler again, from the kept tables, into a temporary buffer
+  uint64_t* d_keys = nullptr;
+  if (hipMalloc(&d_keys, (size_t)g.m * sizeof(uint64_t)) != hipSuccess)
+    KR_FAIL(h, KR_ENOMEM, "sample buffer of %lld keys", (long long)g.m);
+  KL(h, k_sample, dim3(grid_for(g.m, 256, 2048)), dim3(256), 0, h->stream, r.T, g, r.seed, r.stream, (uint64_t)0, 0,
+     d_keys);
+  std::vector<uint64_t> keys((size_t)count);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(keys.data(), d_keys + first, (size_t)count * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  hipFree(d_keys);
+  if (e != hipSuccess) KR_FAIL(h, KR_EHIP, "redraw failed: %s", hipGetErrorString(e));
+  for (int64_t t = 0; t < count; ++t)
+    for (int n = 0; n < g.N; ++n)
+      h_idx[t * g.N + g.orig[n]] = (int32_t)((keys[t] >> g.shift[n]) & ((1ull << g.bits[n]) - 1ull));
+  return KR_OK;
+}
+
 kr_status kr_export_batched_sketch(kr_handle h, int32_t problem, uint64_t* h_Q, int32_t* h_rows, double* h_Omega,
                                    int32_t* h_counts, int64_t cap, int64_t* h_D) {
   if (!h) return KR_EINVAL;
@@ -2873,6 +2906,7 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
     info->rel_update = relmax;
   }
   h->last.valid = true;
+  h->last.redraw = false;   // drawn per factor row by k_sample_rows
   h->last.g = g;
   h->last.T = T;
   h->last.tr = tr;

@@ -218,3 +218,27 @@ def test_info_loss_and_time(gpu_lib):
     xh = x.cpu().numpy()
     ref = max(loss(w["As"], b[:, q], xh[:, q], 0.01) for q in range(2))
     assert abs(info["loss"] - ref) <= 1e-10 * ref
+
+
+@pytest.mark.parametrize("case", [("N3", (9, 6, 5), (3, 2, 2), 4097), ("N4", (5, 4, 6, 3), (2, 2, 3, 1), 800),
+                                  ("N2 heavy", (40, 33), (4, 5), 20000)], ids=lambda c: c[0])
+def test_per_sample_draws_match_oracle(gpu_lib, case):
+    """Algorithm 2's draws before merging: every sample t's indices (i_1(t), ..,
+    i_N(t)) redrawn from the solve's kept tables equal the oracle sampler's, in
+    sample order, bit for bit; a window [first, first + count) equals the same
+    rows of the whole draw."""
+    import torch
+    from oracle.sampling import sample_product
+    name, I, R, m = case
+    print("case per-sample draws", name, I, R, m, flush=True)
+    w = workloads.random_problem(I, R, seed=zlib.crc32(name.encode()) % 1000, heavy=3 if "heavy" in name else 0)
+    tA = [torch.tensor(A, dtype=torch.float64, device="cuda") for A in w["As"]]
+    tb = torch.tensor(w["b"], dtype=torch.float64, device="cuda")
+    _, info = gpu_lib.kron_regress(tA, tb, eps=0.1, m=m, seed=23, stream=4)
+    sk = gpu_lib.export_sketch(list(I))
+    idx = gpu_lib.export_samples(0, m, len(I))
+    oidx, _ = sample_product(sk["Q"], m, 23, 4)
+    np.testing.assert_array_equal(idx, np.asarray(oidx, dtype=np.int32))
+    f, c = m // 3, min(257, m - m // 3)
+    np.testing.assert_array_equal(gpu_lib.export_samples(f, c, len(I)), idx[f:f + c])
+
