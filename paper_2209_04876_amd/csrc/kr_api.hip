@@ -2852,12 +2852,11 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
            (const double*)GtP, (const double*)Vw, (const double*)AinvU, (const double*)Cinv, (const double*)wbuf, eta,
            tol, enq + it, max_iter, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, counters, counters + 1,
            state);
-      KL(h, k_tucker_tick, dim3(1), dim3(64), 0, s, In, max_iter, (const int32_t*)counters,
-         (const int32_t*)(counters + 1), state);
     }
     enq += chunk;
     HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(h->h_state, state, sizeof(IterState), hipMemcpyDeviceToHost, s));
+    // rows done and the divergence flag (the updates test them themselves)
+    HIPCHK(h, hipMemcpyAsync(h->h_small + 4, counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (!checked) HIPCHK(h, hipMemcpyAsync(h->h_small, S.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (!checked) {
@@ -2867,7 +2866,8 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
       if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
       if (fl & KR_FLAG_CORE) KR_FAIL(h, KR_ESINGULAR, "G_(n) G_(n)^T or the Woodbury matrix is singular");
     }
-    if (h->h_state->all_done) break;
+    const int32_t* cnt = (const int32_t*)(h->h_small + 4);
+    if (cnt[0] >= In || cnt[1]) break;
   }
   KL(h, k_tucker_rows_out, dim3(grid_for((int64_t)In * Rn, 256, 1024)), dim3(256), 0, s, tg, (const double*)Z,
      (const double*)GtP, In, (double*)d_A_out);
@@ -2889,7 +2889,7 @@ static kr_status factor_update(kr_handle h, const kr_problem* p, const void* d_c
   for (int i = 0; i < In; ++i) {
     all = all && done[i];
     relmax = std::max(relmax, rel[i]);
-    itmax = std::max(itmax, done[i] ? its[i] : h->h_state->iters);
+    itmax = std::max(itmax, done[i] ? its[i] : enq);
   }
   if (cnt_h[1]) {
     result = KR_EDIVERGED;

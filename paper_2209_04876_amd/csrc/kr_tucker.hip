@@ -327,7 +327,8 @@ __global__ void __launch_bounds__(256) k_tucker_update(ModeTables T, Geom g, Tuc
   __shared__ double red[8];
   __shared__ double vv[64];
   __shared__ double uu[64];
-  if (st->all_done) return;
+  // every row done (one workgroup per row) or a row diverged: nothing to update
+  if (*ndone >= (int)gridDim.x || *diverged) return;
   const int i = blockIdx.x;
   if (seg_done[i]) return;
   const int Rr = tg.Rr, Rn = tg.Rn;
@@ -441,7 +442,8 @@ __global__ void __launch_bounds__(256) k_tucker_update_st(ModeTables T, Geom g, 
   __shared__ double red[8];
   __shared__ double vv[64];
   __shared__ double uu[64];
-  if (st->all_done) return;
+  // every row done (one workgroup per row) or a row diverged: nothing to update
+  if (*ndone >= (int)gridDim.x || *diverged) return;
   const int i = blockIdx.x;
   if (seg_done[i]) return;
   const int Rr = tg.Rr, Rn = tg.Rn;
@@ -564,15 +566,6 @@ __global__ void __launch_bounds__(256) k_tucker_update_st(ModeTables T, Geom g, 
   zz = block_sum(zz, red);
   if (threadIdx.x == 0)
     tucker_row_stop(i, dd, zz, eta, tol, it, seg_done, seg_iters, seg_rel, seg_d0, seg_best, seg_stall, ndone, diverged);
-}
-
-// After each update launch: iteration count and the all-done flag.
-__global__ void k_tucker_tick(int nrows, int max_iter, const int32_t* __restrict__ ndone,
-                              const int32_t* __restrict__ diverged, IterState* __restrict__ st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && !st->all_done) {
-    st->iters += 1;
-    if (*ndone >= nrows || *diverged || st->iters >= max_iter) st->all_done = 1;
-  }
 }
 
 // A_out[i][r] = sum_c GtP[r][c] z_i[c]
