@@ -892,6 +892,9 @@ static bool rows_ldsf(const Geom& g, const Tree& tr) {
   const int64_t IL = g.I[g.N - 1];
   return IL * g.R[g.N - 1] * 8 <= KR_ROWS_LDS_MAX && tr.ncnt[g.N] >= 16 * IL;
 }
+#ifndef KR_MULTI_ROWS
+#define KR_MULTI_ROWS 6
+#endif
 // Padded row width of the lane-per-row kernel (k_rows_lane), 0 where it does not
 // apply: R_{N-1} <= 16 and the factor zero-padded to 8 or 16 columns fits the
 // same LDS budget.
@@ -945,7 +948,16 @@ static bool launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
     const int RP = rows_lane_width(g, tr);
     const size_t flp = 8 * (size_t)g.I[g.N - 1] * RP;
     const dim3 rgp(grid_for(tr.ncnt[g.N - 1] * g.nrhs, KR_LANE_TPB / 64, KR_ROWS_LDS_GRID));
-    if (RP == 8)
+    // short nodes (under KR_MULTI_ROWS rows on average): blocks of nodes per wave
+    const bool multi = RP == 16 && g.N >= 3 && !g.seg_root && g.nrhs == 1 &&
+                       tr.ncnt[g.N] < (int64_t)KR_MULTI_ROWS * tr.ncnt[g.N - 1];
+    if (multi) {
+      const int64_t nblk = (tr.ncnt[g.N - 1] + MN_NODES - 1) / MN_NODES;
+      const size_t flm = flp + 8 * (size_t)(KR_LANE_TPB / 64) * MN_WAVE_LDS;
+      KLN(h, f32 ? "k_rows_multi<f32>" : "k_rows_multi", k_rows_multi<T>,
+          dim3(grid_for(nblk, KR_LANE_TPB / 64, KR_ROWS_LDS_GRID)), dim3(KR_LANE_TPB), flm, s, TT, g, tr, plast, Omega,
+          bD, qlast);
+    } else if (RP == 8)
       KLN(h, f32 ? "k_rows_lane<8,f32>" : "k_rows_lane<8>", (k_rows_lane<8, T>), rgp, dim3(KR_LANE_TPB), flp, s, TT, g,
           tr, plast, Omega, bD, qlast);
     else if (RP == 16)

@@ -571,6 +571,167 @@ __global__ void __launch_bounds__(KR_LANE_TPB) __attribute__((amdgpu_waves_per_e
   }
 }
 
+// The LDS-staged rows for short nodes (a few rows each; three or more modes,
+// R_{N-1} <= 16, one right-hand side): one wave takes a block of MN_NODES
+// consecutive level-(N-1) nodes, whose rows are contiguous.
+//   1. the block's forward values P_{N-1}[p] (16 per node), one node per 16-lane
+//      group and pass (the contraction of P_{N-2}[parent] with a_{N-2}[i(p)] in
+//      the same order as rows_pnode), into the wave's LDS;
+//   2. the block's rows 64 at a time, one per lane: its node (a search of the
+//      block's row bounds), u_j = Omega_j (<a_{N-1}[i(j)], P_{N-1}[node]> - b_j),
+//      with (u_j, i(j)) left in the wave's LDS;
+//   3. per node, lane r of its group adds u_j a_{N-1}[i(j)][r] over the node's
+//      rows of the chunk, in row order, into the node's accumulator (LDS);
+// and the nodes' accumulators are written as Q[p] at the end.  Compared with one
+// node per wave, a block of nodes shares each memory round trip.
+#define MN_NODES 8
+// a wave's LDS writes are seen by its later LDS reads (the hardware keeps a wave's
+// LDS operations in order); this keeps the compiler from moving them across
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+#define MN_WAVE_LDS (MN_NODES * 16 * 2 + 64 + 32 + 16)   // doubles per wave: pv, sums, u, indices, bounds, parents
+template <typename T>
+__global__ void __launch_bounds__(KR_LANE_TPB) __attribute__((amdgpu_waves_per_eu(KR_LANE_WPE, 8)))
+    k_rows_multi(ModeTables TT, Geom g, Tree tr, const double* __restrict__ Pprev, const double* __restrict__ Omega,
+                 const double* __restrict__ bD, T* __restrict__ Qout) {
+  constexpr int RP = 16, NGR = 4;
+  extern __shared__ double2 multi_fac2[];
+  double* rows_fac = (double*)multi_fac2;
+  const int N = g.N;
+  const int R = g.R[N - 1], Rp = g.R[N - 2];
+  const int IL = g.I[N - 1];
+  {
+    const double* __restrict__ A = TT.A[N - 1];
+    for (int e = threadIdx.x; e < IL * RP; e += blockDim.x) {
+      const int i = e / RP, r = e % RP;
+      rows_fac[e] = r < R ? A[(int64_t)i * R + r] : 0.0;
+    }
+    __syncthreads();
+  }
+  const int l64 = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = l64 & 15, gi = l64 >> 4;
+  double* wl = rows_fac + (size_t)IL * RP + (size_t)w * MN_WAVE_LDS;
+  double* pvl = wl;                          // MN_NODES x 16 forward values
+  double* accl = wl + MN_NODES * 16;         // MN_NODES x 16 adjoint sums
+  double* ul = accl + MN_NODES * 16;         // 64 u_j
+  int* ixl = (int*)(ul + 64);                // 64 row indices
+  int* bnd = ixl + 64;                       // MN_NODES + 1 row bounds
+  int* parl = bnd + MN_NODES + 1;            // MN_NODES parents
+  const int64_t S = tr.ncnt[N - 1];
+  const int64_t nblk = (S + MN_NODES - 1) / MN_NODES;
+  const int64_t wpb = blockDim.x >> 6;
+  const int64_t wg = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * wpb + w));
+  const int64_t wstride = (int64_t)gridDim.x * wpb;
+  const int32_t* __restrict__ idxL = tr.idx[N];
+  const int32_t* __restrict__ fch = tr.fchild[N - 1];
+  const int32_t* __restrict__ parL = tr.parent[N - 1];
+  const double* __restrict__ arow = tr.arow[N - 1];
+  const unsigned step8 = (unsigned)R * 8u;
+  for (int64_t b = wg; b < nblk; b += wstride) {
+    const int64_t p0 = __builtin_amdgcn_readfirstlane((int)(b * MN_NODES));
+    const int nn = (int)min((int64_t)MN_NODES, S - p0);
+    // row bounds and parents of the block's nodes (one round trip)
+    if (l64 <= nn) bnd[l64] = fch[p0 + l64];
+    if (l64 < nn) parl[l64] = parL[p0 + l64];
+    wave_sync();
+    const int r0 = bnd[0], r1 = bnd[nn];
+    // the first chunk's row data, requested with the forward values' operands
+    int ix0;
+    double om0, bb0;
+    {
+      const int j = r0 + l64;
+      const int jj = j < r1 ? j : r0;
+      ix0 = idxL[jj];
+      om0 = j < r1 ? Omega[jj] : 0.0;
+      bb0 = bD[jj];
+    }
+    // 1. forward values, node p0 + 4 pass + gi in group gi (all of a pass's
+    // operands requested together when R_{N-2} <= 16)
+#pragma unroll 1
+    for (int pass = 0; pass * NGR < nn; ++pass) {
+      const int nl = pass * NGR + gi;
+      double pv = 0.0;
+      if (nl < nn && lane < R) {
+        const int64_t pp = p0 + nl;
+        const double* __restrict__ a = arow + pp * Rp;
+        const double* __restrict__ src = Pprev + (int64_t)parl[nl] * Rp * R;
+        if (Rp <= 16) {
+          double av[16], sv[16];
+#pragma unroll
+          for (int s0 = 0; s0 < 16; ++s0) {
+            const bool ok = s0 < Rp;
+            av[s0] = ok ? a[s0] : 0.0;
+            sv[s0] = ok ? ld_at(src, (unsigned)s0 * step8 + (unsigned)lane * 8u) : 0.0;
+          }
+#pragma unroll
+          for (int s0 = 0; s0 < 16; ++s0) pv = fma(av[s0], sv[s0], pv);
+        } else {
+          for (int s0 = 0; s0 < Rp; ++s0) pv = fma(a[s0], ld_at(src, (unsigned)s0 * step8 + (unsigned)lane * 8u), pv);
+        }
+      }
+      if (nl < MN_NODES) {
+        pvl[nl * 16 + lane] = pv;
+        accl[nl * 16 + lane] = 0.0;
+      }
+    }
+    wave_sync();
+    for (int c = r0; c < r1; c += 64) {
+      // 2. one row per lane
+      const int j = c + l64;
+      const bool in = j < r1;
+      const int jj = in ? j : r0;
+      int nl = 0;
+#pragma unroll
+      for (int q = 1; q < MN_NODES; ++q) nl += (q < nn && bnd[q] <= jj) ? 1 : 0;
+      int ix;
+      double om, bb;
+      if (c == r0) {
+        ix = ix0;
+        om = om0;
+        bb = bb0;
+      } else {
+        ix = idxL[jj];
+        om = in ? Omega[jj] : 0.0;
+        bb = bD[jj];
+      }
+      const double2* __restrict__ row = (const double2*)(rows_fac + (int64_t)ix * RP);
+      const double2* __restrict__ pvr = (const double2*)(pvl + nl * 16);
+      double y = 0.0;
+#pragma unroll
+      for (int k = 0; k < RP / 2; ++k) {
+        const double2 a = row[k], v = pvr[k];
+        y = fma(a.x, v.x, y);
+        y = fma(a.y, v.y, y);
+      }
+      ul[l64] = in ? om * (y - bb) : 0.0;
+      ixl[l64] = ix;
+      wave_sync();
+      // 3. per node, lane r of its group over the node's rows of this chunk
+      for (int pass = 0; pass * NGR < nn; ++pass) {
+        const int nl2 = pass * NGR + gi;
+        if (nl2 < nn) {
+          const int a0 = max(bnd[nl2], c), a1 = min(bnd[nl2 + 1], min(c + 64, r1));
+          T acc = (T)accl[nl2 * 16 + lane];
+          for (int jr = a0; jr < a1; ++jr) {
+            const int t = jr - c;
+            acc = fma((T)ul[t], (T)rows_fac[(int64_t)ixl[t] * RP + lane], acc);
+          }
+          accl[nl2 * 16 + lane] = (double)acc;
+        }
+      }
+      wave_sync();
+    }
+    // the block's adjoints
+    for (int pass = 0; pass * NGR < nn; ++pass) {
+      const int nl = pass * NGR + gi;
+      if (nl < nn && lane < R) Qout[(p0 + nl) * R + lane] = (T)accl[nl * 16 + lane];
+    }
+    wave_sync();
+  }
+}
+
 // The chunk table of the fused three-mode pass: the children of level-1 node p
 // (n_p of them) split into k_p = ceil(n_p / ch) runs, run j starting at child
 // floor(j n_p / k_p), numbered in node order by an exclusive scan of k_p over
