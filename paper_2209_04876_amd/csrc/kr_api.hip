@@ -949,7 +949,7 @@ static bool launch_level_products(kr_handle h, const ModeTables& TT, const Geom&
     const size_t flp = 8 * (size_t)g.I[g.N - 1] * RP;
     const dim3 rgp(grid_for(tr.ncnt[g.N - 1] * g.nrhs, KR_LANE_TPB / 64, KR_ROWS_LDS_GRID));
     // short nodes (under KR_MULTI_ROWS rows on average): blocks of nodes per wave
-    const bool multi = RP == 16 && g.N >= 3 && !g.seg_root && g.nrhs == 1 &&
+    const bool multi = RP == 16 && g.N >= 3 && g.nrhs == 1 &&
                        tr.ncnt[g.N] < (int64_t)KR_MULTI_ROWS * tr.ncnt[g.N - 1];
     if (multi) {
       const int64_t nblk = (tr.ncnt[g.N - 1] + MN_NODES - 1) / MN_NODES;
