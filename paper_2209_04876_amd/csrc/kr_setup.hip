@@ -223,6 +223,14 @@ __global__ void __launch_bounds__(64) k_eig(ModeTables T, Geom g, const double* 
   }
 }
 
+// The value of lane l (uniform l) of a float64 register.
+__device__ __forceinline__ double chol_lane(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // lambda = 0 without the eigenvectors: one wave per mode factors G = L L^T
 // (right-looking Cholesky; a pivot at or below max(I,R) eps max_i G_ii -- the
 // resolution of G itself -- flags the factor singular and is clamped there),
@@ -247,24 +255,42 @@ __global__ void __launch_bounds__(64) k_chol(ModeTables T, Geom g, const double*
   double dmax = 0.0;
   for (int k = 0; k < R; ++k) dmax = fmax(dmax, a[k * R + k]);
   const double thr = (double)max(I, R) * 2.220446049250313e-16 * dmax;
-  for (int j = 0; j < R; ++j) {
-    if (lane == 0) {
-      double d = a[j * R + j];
-      if (!(d > thr)) { sing = 1; d = thr > 0.0 ? thr : 1.0; }
-      const double l = sqrt(d);
-      a[j * R + j] = l;
-      dinv[j] = 1.0 / l;
+  // Right-looking factorisation with lane i holding row i in registers (R <= RM
+  // <= 64): column j's diagonal and entries L_kj reach every lane by readlane, so
+  // the steps need neither LDS round trips nor barriers.  Each entry sees the same
+  // operations in the same order as a column-by-column update in memory.
+  {
+    double row[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) row[k] = (lane < R && k < R) ? a[lane * R + k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      if (j < R) {
+        double d = chol_lane(row[j], j);
+        if (!(d > thr)) {
+          if (lane == 0) sing = 1;
+          d = thr > 0.0 ? thr : 1.0;
+        }
+        const double l = sqrt(d);
+        const double di = 1.0 / l;
+        if (lane == j) row[j] = l;
+        if (lane > j) row[j] *= di;
+        if (lane == 0) dinv[j] = di;
+#pragma unroll
+        for (int k = j + 1; k < RM; ++k) {
+          if (k < R) {
+            const double lkj = chol_lane(row[j], k);
+            if (lane > j && k <= lane) row[k] -= row[j] * lkj;
+          }
+        }
+      }
     }
-    __syncthreads();
-    for (int i = j + 1 + lane; i < R; i += 64) a[i * R + j] *= dinv[j];
-    __syncthreads();
-    const int m = R - j - 1;
-    for (int e = lane; e < m * m; e += 64) {
-      const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) a[i * R + k] -= a[i * R + j] * a[k * R + j];
-    }
-    __syncthreads();
+    if (lane < R)
+#pragma unroll
+      for (int k = 0; k < RM; ++k)
+        if (k < R) a[lane * R + k] = row[k];
   }
+  __syncthreads();
   // column c of L^{-1}: x_i = 0 (i < c), x_c = 1 / L_cc, x_i = -(sum_{k<i} L_ik x_k) / L_ii
   if (lane < R) {
     const int c = lane;
