@@ -521,9 +521,9 @@ static void launch_factor(kr_handle h, const Geom& g, const ModeTables& T, const
   } else if (maxR <= 16) {
     KLN(h, "k_chol<16>", k_chol<16>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
   } else if (maxR <= 32) {
-    KLN(h, "k_chol<32>", k_chol<32>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+    KLN(h, "k_chol_wide<32>", k_chol_wide<32>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
   } else {
-    KLN(h, "k_chol<64>", k_chol<64>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
+    KLN(h, "k_chol_wide<64>", k_chol_wide<64>, dim3(g.N), dim3(64), 0, h->stream, T, g, (const double*)s.gram, s.flags);
   }
 }
 

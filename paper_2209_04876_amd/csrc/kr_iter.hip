@@ -780,12 +780,33 @@ __global__ void __launch_bounds__(CH_THREADS) k_chunk_table(Tree tr, Chunks ck, 
   }
   if (running > ck.cap) return;
   __syncthreads();
+  // the runs' factor rows, CH_U entries per thread per trip with every trip's
+  // loads issued before its stores (the stores could alias ck.par as far as the
+  // compiler knows, so it would not hoist them itself)
   const double* __restrict__ a0 = tr.arow[1];
-  for (int e = threadIdx.x; e < running * R0; e += CH_THREADS) {
-    const int c = e / R0;
-    const double a = a0[(int64_t)ck.par[c] * R0 + (e - c * R0)];
-    ck.arow[e] = a;
-    if (f32) ck.arow32[e] = (float)a;
+  const int total = running * R0;
+  constexpr int CH_U = 8;
+  for (int e0 = threadIdx.x; e0 < total; e0 += CH_U * CH_THREADS) {
+    int pr[CH_U];
+    double a[CH_U];
+#pragma unroll
+    for (int u = 0; u < CH_U; ++u) {
+      const int e = e0 + u * CH_THREADS;
+      pr[u] = e < total ? ck.par[e / R0] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < CH_U; ++u) {
+      const int e = e0 + u * CH_THREADS;
+      a[u] = e < total ? a0[(int64_t)pr[u] * R0 + (e % R0)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CH_U; ++u) {
+      const int e = e0 + u * CH_THREADS;
+      if (e < total) {
+        ck.arow[e] = a[u];
+        if (f32) ck.arow32[e] = (float)a[u];
+      }
+    }
   }
 }
 

@@ -241,6 +241,98 @@ __device__ __forceinline__ double chol_lane(double v, int l) {
 template <int RM>
 __global__ void __launch_bounds__(64) k_chol(ModeTables T, Geom g, const double* __restrict__ gram,
                                              int32_t* __restrict__ flags) {
+  static_assert(RM <= 16, "k_chol holds a row per lane for R <= 16");
+  __shared__ double li[RM * RM];
+  const int n = blockIdx.x;
+  const int R = g.R[n], I = g.I[n];
+  const int lane = threadIdx.x;
+  const double* G = gram + (size_t)n * KR_RMAX * KR_RMAX;
+  // Lane i holds row i of G padded to RM x RM with the identity (R <= RM <= 16).
+  // Every loop runs RM steps, so the code unrolls into straight-line selects with
+  // compile-time register indices; the padding leaves the leading R x R block's
+  // operations exactly those of the unpadded factorisation (padded entries meet
+  // the real ones only through exact zeros) and is never stored.
+  double row[RM];
+  {
+    const int li0 = lane < R ? lane : R - 1;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+      const double gv = G[li0 * R + (k < R ? k : R - 1)];   // unconditional loads
+      row[k] = (lane < R && k < R) ? gv : (k == lane ? 1.0 : 0.0);
+    }
+  }
+  double dmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < RM; ++k) {
+    const double dk = chol_lane(row[k], k);
+    dmax = k < R ? fmax(dmax, dk) : dmax;
+  }
+  const double thr = (double)max(I, R) * 2.220446049250313e-16 * dmax;
+  // Right-looking factorisation: column j's diagonal and entries L_kj reach every
+  // lane by readlane.  Each entry sees the same operations in the same order as a
+  // column-by-column update in memory.
+  bool sing = false;
+  double dinv[RM];
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    double d = chol_lane(row[j], j);
+    const bool bad = j < R && !(d > thr);
+    sing = sing || bad;
+    d = bad ? (thr > 0.0 ? thr : 1.0) : d;
+    const double l = sqrt(d);
+    const double di = 1.0 / l;
+    dinv[j] = di;
+    const double sc = row[j] * di;
+    row[j] = lane == j ? l : (lane > j ? sc : row[j]);
+#pragma unroll
+    for (int k = j + 1; k < RM; ++k) {
+      const double lkj = chol_lane(row[j], k);
+      const double upd = row[k] - row[j] * lkj;
+      row[k] = (lane > j && k <= lane) ? upd : row[k];
+    }
+  }
+  // column c = lane of L^{-1}: x_i = 0 (i < c), x_c = 1 / L_cc,
+  // x_i = -(sum_{k<i} L_ik x_k) / L_ii, with L_ik = row[k] of lane i
+  double x[RM];
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) acc = fma(chol_lane(row[k], i), x[k], acc);
+    x[i] = i < R ? (i < lane ? 0.0 : (i == lane ? dinv[i] : -acc * dinv[i])) : 0.0;
+  }
+  if (lane < RM)
+#pragma unroll
+    for (int i = 0; i < RM; ++i) li[i * RM + lane] = x[i];
+  __syncthreads();
+  // lane p: V[p][q] = (L^{-1})_qp and G^{-1}[p][q] = sum_{k >= max(p,q)} (L^{-1})_kp (L^{-1})_kq,
+  // summed in increasing k (the terms below max(p,q) are exact zeros, so acc
+  // meets its first nonzero term at k = max(p,q); the terms k >= R are skipped)
+  double* V = T.V[n];
+  double* ev = T.evals[n];
+  double* Gi = T.Ginv[n];
+#pragma unroll
+  for (int q = 0; q < RM; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+      const double t = fma(x[k], li[k * RM + q], acc);
+      acc = k < R ? t : acc;
+    }
+    if (lane < R && q < R) {
+      V[lane * R + q] = x[q];
+      Gi[lane * R + q] = acc;
+    }
+  }
+  for (int k = lane; k < R; k += 64) ev[k] = 1.0;
+  if (lane == 0 && sing) atomicOr(flags, KR_FLAG_SINGULAR);
+}
+
+// The same factorisation for 16 < R <= RM (32 or 64), with the row's updates
+// under lane conditions: unrolled straight-line code would not fit the registers there.
+template <int RM>
+__global__ void __launch_bounds__(64) k_chol_wide(ModeTables T, Geom g, const double* __restrict__ gram,
+                                             int32_t* __restrict__ flags) {
   __shared__ double a[KR_RMAX * KR_RMAX];
   __shared__ double li[KR_RMAX * KR_RMAX];
   __shared__ double dinv[KR_RMAX];
@@ -321,116 +413,193 @@ __global__ void __launch_bounds__(64) k_chol(ModeTables T, Geom g, const double*
   if (lane == 0 && sing) atomicOr(flags, KR_FLAG_SINGULAR);
 }
 
-// One workgroup (256 threads) per mode.
+// One workgroup (256 threads) per mode.  A thread takes rows tid, tid + 256, ...;
+// when every row of the mode fits LV rows per thread, its rows' scores and
+// weights stay in registers from the leverage through the CDF (no global round
+// trips between the stages), and the CDF is a wave-shuffle scan.
 template <int RM>
 __global__ void __launch_bounds__(256) k_leverage(ModeTables T, Geom g, int32_t* __restrict__ flags) {
+  constexpr int LV = RM <= 8 ? 4 : (RM <= 16 ? 2 : 1);
   __shared__ double vs[KR_RMAX * KR_RMAX];
   __shared__ double inv[2 * KR_RMAX];
   __shared__ double red[8];
   __shared__ unsigned long long ured[4];
   __shared__ unsigned long long umax[4];
-  __shared__ unsigned long long carry;
-  __shared__ unsigned long long scan[256];
+  __shared__ unsigned long long wtot[4];
+  __shared__ long long fixv[2];
   const int n = blockIdx.x;
   const int I = g.I[n], R = g.R[n];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double* A = T.A[n];
   double* lev = T.lev[n];
   uint64_t* Q = T.Q[n];
   uint64_t* C = T.C[n];
   copy_to_lds<16>(vs, T.V[n], R * R);
-  if (threadIdx.x < R) inv[threadIdx.x] = T.evals[n][threadIdx.x];
+  if (tid < R) inv[tid] = T.evals[n][tid];
   __syncthreads();
-  if (threadIdx.x < R) {
+  if (tid < R) {
     double lmax = 0.0;
     for (int k = 0; k < R; ++k) lmax = fmax(lmax, inv[k]);
     const double eps_r = (double)max(I, R) * 2.220446049250313e-16;
-    const double lk = inv[threadIdx.x];
-    inv[threadIdx.x + KR_RMAX] = lk > eps_r * eps_r * lmax ? 1.0 / lk : 0.0;
+    const double lk = inv[tid];
+    inv[tid + KR_RMAX] = lk > eps_r * eps_r * lmax ? 1.0 / lk : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x < R) inv[threadIdx.x] = inv[threadIdx.x + KR_RMAX];
+  if (tid < R) inv[tid] = inv[tid + KR_RMAX];
   __syncthreads();
-  // leverage per row (the row held in registers); thread-local partial sums in
-  // increasing row order
+  const bool one = I <= LV * 256;   // one trip: every row of this thread in registers
+  // leverage per row; thread-local partial sums in increasing row order
+  double lr[LV];
   double part = 0.0;
-  for (int i = threadIdx.x; i < I; i += blockDim.x) {
-    const double* ai = A + (size_t)i * R;
-    double x[RM];
-    bool zero = true;
 #pragma unroll
-    for (int r = 0; r < RM; ++r) {
-      x[r] = r < R ? ai[r] : 0.0;
-      zero &= (x[r] == 0.0);
+  for (int u = 0; u < LV; ++u) lr[u] = 0.0;
+  for (int i0 = tid; i0 < I; i0 += LV * 256) {
+    // every load unconditional (clamped indices), so the trip's rows are in flight together
+    double x[LV][RM];
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      const int i = i0 + u * 256;
+      const double* ai = A + (size_t)(i < I ? i : I - 1) * R;
+#pragma unroll
+      for (int r = 0; r < RM; ++r) x[u][r] = ai[r < R ? r : R - 1];
     }
-    double l = 0.0;
+    bool zero[LV];
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      zero[u] = true;
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        x[u][r] = r < R ? x[u][r] : 0.0;
+        zero[u] &= (x[u][r] == 0.0);
+      }
+    }
+    double l[LV];
+#pragma unroll
+    for (int u = 0; u < LV; ++u) l[u] = 0.0;
     for (int k = 0; k < R; ++k) {
-      double dot = 0.0;
+      double dot[LV];
 #pragma unroll
-      for (int r = 0; r < RM; ++r)
-        if (r < R) dot = fma(x[r], vs[r * R + k], dot);
-      l = fma(dot * dot, inv[k], l);
+      for (int u = 0; u < LV; ++u) dot[u] = 0.0;
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        const double v = vs[(r < R ? r : 0) * R + k];
+#pragma unroll
+        for (int u = 0; u < LV; ++u) {
+          const double t = fma(x[u][r], v, dot[u]);
+          dot[u] = r < R ? t : dot[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LV; ++u) l[u] = fma(dot[u] * dot[u], inv[k], l[u]);
     }
-    if (zero) l = 0.0;
-    lev[i] = l;
-    part += l;
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      const int i = i0 + u * 256;
+      const double li = zero[u] ? 0.0 : l[u];
+      lr[u] = li;
+      if (i < I) {
+        lev[i] = li;
+        part += li;
+      }
+    }
   }
   const double S = block_sum(part, red);
   if (!(S > 0.0) || !isfinite(S)) {
-    if (threadIdx.x == 0) atomicOr(flags, KR_FLAG_QUANT);
+    if (tid == 0) atomicOr(flags, KR_FLAG_QUANT);
     return;
   }
   // Q_i = max(1, nearest integer to 2^32 l_i / S) for l_i > 0; exact integer sum and argmax
   unsigned long long qsum = 0ull, best = 0ull;
-  for (int i = threadIdx.x; i < I; i += blockDim.x) {
-    const double l = lev[i];
-    uint64_t q = 0;
-    if (l > 0.0) {
-      q = (uint64_t)floor((l / S) * 4294967296.0 + 0.5);
-      if (q < 1) q = 1;
+  uint64_t qr[LV];
+#pragma unroll
+  for (int u = 0; u < LV; ++u) qr[u] = 0ull;
+  for (int i0 = tid; i0 < I; i0 += LV * 256) {
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      const int i = i0 + u * 256;
+      if (i < I) {
+        const double l = one ? lr[u] : lev[i];
+        uint64_t q = 0;
+        if (l > 0.0) {
+          q = (uint64_t)floor((l / S) * 4294967296.0 + 0.5);
+          if (q < 1) q = 1;
+        }
+        Q[i] = q;
+        qr[u] = q;
+        qsum += q;
+        // pack (q, lowest index wins on ties) into a comparable key: q high, ~i low
+        const unsigned long long key = ((unsigned long long)q << 24) | (unsigned long long)(0xFFFFFF - i);
+        best = key > best ? key : best;
+      }
     }
-    Q[i] = q;
-    qsum += q;
-    // pack (q, lowest index wins on ties) into a comparable key: q high, ~i low
-    const unsigned long long key = ((unsigned long long)q << 24) | (unsigned long long)(0xFFFFFF - i);
-    best = key > best ? key : best;
   }
-  // reductions (integer: order-independent)
-  {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int o = 32; o > 0; o >>= 1) {
-      qsum += __shfl_xor(qsum, o, 64);
-      const unsigned long long ob = __shfl_xor(best, o, 64);
-      best = ob > best ? ob : best;
-    }
-    if (lane == 0) { ured[w] = qsum; umax[w] = best; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long s = 0, b = 0;
-      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { s += ured[k]; b = umax[k] > b ? umax[k] : b; }
-      const int j = 0xFFFFFF - (int)(b & 0xFFFFFFull);
-      const long long deficit = (long long)(1ull << 32) - (long long)s;
+  // reductions (integer: order-independent); the deficit 2^32 - sum goes to the
+  // largest weight (lowest index on ties)
+  for (int o = 32; o > 0; o >>= 1) {
+    qsum += __shfl_xor(qsum, o, 64);
+    const unsigned long long ob = __shfl_xor(best, o, 64);
+    best = ob > best ? ob : best;
+  }
+  if (lane == 0) { ured[w] = qsum; umax[w] = best; }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long s2 = 0, b2 = 0;
+    for (int k = 0; k < 4; ++k) { s2 += ured[k]; b2 = umax[k] > b2 ? umax[k] : b2; }
+    const int j = 0xFFFFFF - (int)(b2 & 0xFFFFFFull);
+    const long long deficit = (long long)(1ull << 32) - (long long)s2;
+    fixv[0] = j;
+    fixv[1] = deficit;
+    if (!one) {
       const long long qj = (long long)Q[j] + deficit;
       if (qj < 1) atomicOr(flags, KR_FLAG_QUANT);
       else Q[j] = (uint64_t)qj;
-      carry = 0ull;
     }
-    __syncthreads();
   }
-  // inclusive CDF, 256 entries per step with a running carry
-  for (int base = 0; base < I; base += blockDim.x) {
-    const int i = base + threadIdx.x;
-    scan[threadIdx.x] = i < I ? Q[i] : 0ull;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-      const unsigned long long add = threadIdx.x >= (unsigned)o ? scan[threadIdx.x - o] : 0ull;
-      __syncthreads();
-      scan[threadIdx.x] += add;
-      __syncthreads();
+  __syncthreads();
+  if (one) {
+    const int j = (int)fixv[0];
+    if ((j & 255) == tid) {
+#pragma unroll
+      for (int u = 0; u < LV; ++u)
+        if (u == (j >> 8)) {
+          const long long qj = (long long)qr[u] + fixv[1];
+          if (qj < 1) {
+            atomicOr(flags, KR_FLAG_QUANT);
+          } else {
+            qr[u] = (uint64_t)qj;
+            Q[j] = (uint64_t)qj;
+          }
+        }
     }
-    if (i < I) C[i] = carry + scan[threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) carry += scan[blockDim.x - 1];
-    __syncthreads();
+  }
+  // inclusive CDF over 256-entry blocks (block b: entries 256 b + tid), each a
+  // wave-shuffle scan plus the preceding waves' totals, with a running carry
+  unsigned long long carry = 0ull;
+  for (int c0 = 0; c0 < I; c0 += LV * 256) {
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      const int base = c0 + u * 256;
+      if (base < I) {   // uniform
+        const int i = base + tid;
+        unsigned long long v = i < I ? (one ? qr[u] : Q[i]) : 0ull;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const unsigned long long t = __shfl_up(v, o, 64);
+          if (lane >= o) v += t;
+        }
+        if (lane == 63) wtot[w] = v;
+        __syncthreads();
+        unsigned long long before = 0ull, total = 0ull;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          before += k < w ? wtot[k] : 0ull;
+          total += wtot[k];
+        }
+        if (i < I) C[i] = carry + before + v;
+        carry += total;
+        __syncthreads();   // wtot is rewritten by the next block
+      }
+    }
   }
 }
 
