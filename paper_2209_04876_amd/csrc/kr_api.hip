@@ -1369,7 +1369,6 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     // reach tol (plus one), so a solve usually needs two checks and launches few
     // iterations that find the state already converged.
     int iters_enqueued = 0;
-    bool flags_checked = false;
     int chunk = std::min(check_every, max_iter);
     // a solve of the same shape and parameters took iter_hint iterations last
     // time: enqueue that many before the first host check (one round trip per
@@ -1413,19 +1412,9 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
       }
       iters_enqueued += chunk;
       HIPCHK(h, hipGetLastError());
+      // (the setup flags were checked at the setup round trip; no iteration kernel sets them)
       HIPCHK(h, hipMemcpyAsync(h->h_state, B.state, sizeof(IterState), hipMemcpyDeviceToHost, s));
-      if (!flags_checked) {
-        HIPCHK(h, hipMemcpyAsync(h->h_small, B.s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      }
       HIPCHK(h, hipStreamSynchronize(s));
-      if (!flags_checked) {
-        flags_checked = true;
-        const int32_t fl = (int32_t)(h->h_small[0] & 0xFFFFFFFF);
-        if (fl & KR_FLAG_NONFINITE) KR_FAIL(h, KR_EINVAL, "non-finite entries in A or b");
-        if (fl & KR_FLAG_QUANT) KR_FAIL(h, KR_EINVAL, "a factor has no non-zero leverage to sample from");
-        if ((fl & KR_FLAG_SINGULAR) && lambda == 0.0)
-          KR_FAIL(h, KR_ESINGULAR, "a factor Gram matrix is singular and lambda = 0");
-      }
       if (h->h_state->all_done) break;
       const IterState& S0 = *h->h_state;
       int predict = 0;
@@ -1448,7 +1437,8 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
       h->iter_hint[hint_key] = h->h_state->iters;
     }
   }
-  HIPCHK(h, hipMemcpyAsync(h->h_small + 8, tr.cnt, (KR_MAXN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  // the tree's level counts were read at the setup round trip (the tree does not
+  // change while iterating); the last check already synchronised the stream
   HIPCHK(h, hipStreamSynchronize(s));
   const IterState& S = *h->h_state;
   double rel = 0.0;
@@ -1468,7 +1458,7 @@ static kr_status solve(kr_handle h, const kr_problem* p, double lambda, double e
     info->iters = S.iters;
     info->status = result;
     info->m = m;
-    info->distinct_rows = h->h_small[8 + g.N];
+    info->distinct_rows = tr.ncnt[g.N];
     info->rel_update = rel;
   }
   h->last.valid = true;
